@@ -1,0 +1,270 @@
+"""Pins of the oracle decoders.
+
+* Tree codes: flooding sum-product equals brute-force bitwise MAP.
+* Single parity check: one check pass is exact MAP.
+* Degree-2 checks pass the other input through (minus the offset for OMS).
+* phi form equals the tanh form; both equal a per-edge Python loop.
+* Offset min-sum with offset 0 and no saturation equals a per-check loop.
+* Codeword symmetry: flipping the LLR signs on a codeword's ones flips
+  every posterior the same way.
+* Pruned and full graphs give identical posteriors.
+* Layered min-sum equals a check-by-check Python loop and, on a single row,
+  one flooding min-sum round.
+* Noiseless codewords are fixed points and decode with zero syndrome.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from inputs import rand
+from inputs.workloads import BG2, SMALL
+from oracle import decoders as D
+from oracle import philox, qc
+
+
+def tiny_graph(base, Z):
+    base = np.array(base)
+    mb, nb = base.shape
+    return qc.make_graph(base, nb - mb, Z, 0, nb * Z, family="11n")
+
+
+def codewords(g):
+    H = qc.dense_H(g.base, g.Z).astype(np.int64)
+    n = H.shape[1]
+    allv = np.array(list(itertools.product((0, 1), repeat=n)), dtype=np.int64)
+    return allv[~((allv @ H.T) % 2).any(axis=1)]
+
+
+def map_llr(g, L):
+    """Bitwise MAP LLRs (boundary convention) by enumerating the code."""
+    C = codewords(g).astype(np.float64)
+    out = np.empty_like(L)
+    for b in range(L.shape[0]):
+        s = C @ L[b]
+        for i in range(C.shape[1]):
+            one = C[:, i] == 1
+            out[b, i] = np.logaddexp.reduce(s[one]) - np.logaddexp.reduce(s[~one])
+    return out
+
+
+@pytest.mark.parametrize("base,Z", [([[0, 0, -1], [-1, 0, 0]], 1),
+                                    ([[3, 1, -1], [-1, 4, 2]], 5),
+                                    ([[0, 0, 0, -1, -1], [-1, -1, 0, 0, 0]], 2)])
+def test_tree_bp_equals_map(base, Z):
+    g = tiny_graph(base, Z)
+    L = rand.gaussian(1, (6, g.n_dec), scale=1.5)
+    app = D.spa_flood(g, -L, iters=6)
+    assert np.allclose(-app, map_llr(g, L), rtol=1e-10, atol=1e-10)
+
+
+def test_spc_one_pass_is_map():
+    g = tiny_graph([[0, 0, 0, 0, 0]], 1)
+    L = rand.gaussian(2, (8, 5), scale=2.0)
+    app = D.spa_flood(g, -L, iters=1)
+    assert np.allclose(-app, map_llr(g, L), rtol=1e-10, atol=1e-10)
+
+
+def test_degree2_passthrough():
+    q = rand.gaussian(3, (4, 2, 7), scale=5.0)
+    r = D.cn_spa_phi(q)
+    assert np.allclose(r[:, 0], q[:, 1], rtol=1e-9, atol=1e-9)
+    assert np.allclose(r[:, 1], q[:, 0], rtol=1e-9, atol=1e-9)
+    qi = rand.int8_uniform(4, (4, 2, 7), -31, 31).astype(np.int64)
+    ro = D.cn_oms(qi, offset=1)
+    exp0 = np.sign(np.where(qi[:, 1] < 0, -1, 1)) * np.maximum(np.abs(qi[:, 1]) - 1, 0)
+    assert np.array_equal(ro[:, 0], exp0)
+
+
+def test_phi_tanh_and_loop_agree():
+    q = rand.gaussian(5, (3, 6, 4), scale=3.0)
+    a = D.cn_spa_phi(q)
+    b = D.cn_spa_tanh(q)
+    assert np.allclose(a, b, rtol=1e-10, atol=1e-10)
+    # per-edge loop in the tanh form
+    for bb in range(3):
+        for z in range(4):
+            for v in range(6):
+                p = 1.0
+                for u in range(6):
+                    if u != v:
+                        p *= math.tanh(q[bb, u, z] / 2)
+                assert abs(a[bb, v, z] - 2 * math.atanh(p)) < 1e-10
+
+
+def test_phi_special_values():
+    assert D.phi(np.array([0.0]))[0] == np.inf
+    assert D.phi(np.array([np.inf]))[0] == 0.0
+    x = np.array([0.1, 1.0, 5.0, 20.0])
+    assert np.allclose(D.phi(D.phi(x)), x, rtol=1e-12)
+    assert np.allclose(D.phi(x), -np.log(np.tanh(x / 2)), rtol=1e-12)
+
+
+def test_oms_offset0_equals_minsum_loop():
+    q = rand.int8_uniform(6, (5, 7, 3), -40, 40).astype(np.int64)
+    r = D.cn_oms(q, offset=0)
+    for b in range(5):
+        for z in range(3):
+            for v in range(7):
+                others = [q[b, u, z] for u in range(7) if u != v]
+                s = 1
+                for x in others:
+                    s *= -1 if x < 0 else 1
+                assert r[b, v, z] == s * min(abs(x) for x in others)
+
+
+def _flood_loop_spa(g, lam, iters):
+    """Per-edge Python loop, tanh rule, for a tiny graph."""
+    ev, ec = g.edge_vn(), g.edge_check()
+    B = lam.shape[0]
+    q = np.clip(lam[:, ev], -20, 20)
+    app = lam.copy()
+    for _ in range(iters):
+        r = np.zeros_like(q)
+        for b in range(B):
+            for e in range(g.E):
+                p = 1.0
+                for f in range(g.E):
+                    if f != e and ec[f] == ec[e]:
+                        p *= math.tanh(q[b, f] / 2)
+                r[b, e] = min(max(2 * math.atanh(p), -20), 20)
+        app = lam.copy()
+        for e in range(g.E):
+            app[:, ev[e]] += r[:, e]
+        q = np.clip(app[:, ev] - r, -20, 20)
+    return app
+
+
+def test_spa_flood_equals_loop_on_cyclic_code():
+    g = tiny_graph([[0, 1, 2, 0, -1], [2, -1, 1, 0, 0], [1, 0, -1, -1, 0]], 3)
+    lam = rand.gaussian(7, (2, g.n_dec), scale=1.2, mean=0.3)
+    assert np.allclose(D.spa_flood(g, lam, 4), _flood_loop_spa(g, lam, 4), rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("algo", ["spa", "oms"])
+def test_codeword_symmetry(algo):
+    qb = SMALL.load()
+    g = qc.graph_from_qcbase(qb, 648)
+    u = philox.source_bits(8, 0, 3, g.k)
+    c = qc.encode(qb.base, qb.kb, qb.Z, qb.family, u)[:, :g.n_dec].astype(np.int64)
+    sgn = 1 - 2 * c
+    if algo == "spa":
+        lam = rand.gaussian(9, (3, g.n_dec), scale=2.0, mean=0.5)
+        a0 = D.spa_flood(g, lam, 7)
+        a1 = D.spa_flood(g, lam * sgn, 7)
+        assert np.allclose(a1, a0 * sgn, rtol=1e-12, atol=1e-12)
+    else:
+        lam = rand.int8_uniform(9, (3, g.n_dec), -12, 20).astype(np.int64)
+        a0 = D.oms_flood(g, lam, 7)
+        a1 = D.oms_flood(g, lam * sgn, 7)
+        assert np.array_equal(a1, a0 * sgn)
+
+
+@pytest.mark.parametrize("algo", ["spa", "oms"])
+def test_pruned_equals_full(algo):
+    qb = BG2.load()
+    gp = qc.graph_from_qcbase(qb, 3840)
+    gf = qc.graph_from_qcbase(qb, 3840, full=True)
+    assert gf.rows == 42 and gp.rows == 22
+    L = rand.gaussian(10, (3, 3840), scale=2.0, mean=-1.0)
+    if algo == "spa":
+        ap = D.spa_flood(gp, D.channel_lam(gp, L), 6)
+        af = D.spa_flood(gf, D.channel_lam(gf, L), 6)
+        assert np.array_equal(ap, af[:, :gp.n_dec])
+    else:
+        Lq = np.clip(np.rint(2 * L), -31, 31)
+        ap = D.oms_flood(gp, D.channel_lam(gp, Lq, np.int64), 6)
+        af = D.oms_flood(gf, D.channel_lam(gf, Lq, np.int64), 6)
+        assert np.array_equal(ap, af[:, :gp.n_dec])
+
+
+def _layered_loop(g, lam, iters, alpha):
+    ev = g.edge_vn()
+    B = lam.shape[0]
+    app = lam.astype(np.float64).copy()
+    r = np.zeros((B, g.E))
+    Z = g.Z
+    for _ in range(iters):
+        for i in range(g.rows):
+            es = g.row_entries(i)
+            for z in range(Z):
+                ids = [e * Z + z for e in es]
+                for b in range(B):
+                    t = [app[b, ev[x]] - r[b, x] for x in ids]
+                    for a, x in enumerate(ids):
+                        others = [t[u] for u in range(len(ids)) if u != a]
+                        s = 1.0
+                        for y in others:
+                            s *= -1.0 if y < 0 else 1.0
+                        rn = s * alpha * min(abs(y) for y in others)
+                        r[b, x] = rn
+                        app[b, ev[x]] = t[a] + rn
+    return app
+
+
+def test_layered_equals_check_loop():
+    g = tiny_graph([[0, 1, 2, 0, -1], [2, -1, 1, 0, 0], [1, 0, -1, -1, 0]], 3)
+    lam = rand.gaussian(11, (3, g.n_dec), scale=1.5, mean=0.4)
+    got = D.nms_layered(g, lam, 3, alpha=0.75)
+    assert np.allclose(got, _layered_loop(g, lam, 3, 0.75), rtol=1e-12, atol=1e-12)
+
+
+def test_layered_single_row_is_one_flood_round():
+    g = tiny_graph([[0, 2, 1, 3, 0, 4]], 5)
+    lam = rand.gaussian(12, (4, g.n_dec), scale=2.0)
+    got = D.nms_layered(g, lam, 1, alpha=1.0)
+    # one flooding min-sum round with no offset, written with the OMS update
+    # on an exact scaling: multiply by 2^20 and round to integers
+    q = lam[:, g.edge_vn()]
+    ids = g.row_edge_ids(0)
+    scale = 2.0 ** 20
+    qi = np.rint(q[:, ids] * scale).astype(np.int64)
+    rm = D.cn_oms(qi, offset=0) / scale
+    exp = lam.copy()
+    for a, e in enumerate(g.row_entries(0)):
+        for z in range(g.Z):
+            exp[:, g.edge_vn()[e * g.Z + z]] += rm[:, a, z]
+    assert np.allclose(got, exp, atol=1e-5)
+
+
+def test_layered_fp32_mode_is_float32_arithmetic():
+    g = tiny_graph([[0, 1, 2, 0, -1], [2, -1, 1, 0, 0], [1, 0, -1, -1, 0]], 3)
+    lam = rand.gaussian(13, (2, g.n_dec), scale=1.5, dtype=np.float32)
+    got = D.nms_layered(g, lam, 3, alpha=0.75, mode="fp32")
+    assert got.dtype == np.float32
+    ref = D.nms_layered(g, lam.astype(np.float64), 3, alpha=0.75, mode="fp64")
+    assert np.allclose(got, ref, rtol=1e-5, atol=1e-5)
+
+
+@pytest.mark.parametrize("algo", ["spa", "oms", "nms"])
+def test_noiseless_codewords_decode(algo):
+    qb = BG2.load()
+    g = qc.graph_from_qcbase(qb, 3840)
+    u = philox.source_bits(14, 0, 2, g.k)
+    c = qc.encode(qb.base, qb.kb, qb.Z, qb.family, u)
+    t = c[:, g.tx_lo:g.tx_lo + g.e_tx].astype(np.int64)
+    L = 8.0 * (2 * t - 1)
+    if algo == "spa":
+        app = D.spa_flood(g, D.channel_lam(g, L), 20)
+    elif algo == "oms":
+        app = D.oms_flood(g, D.channel_lam(g, np.clip(2 * L, -31, 31), np.int64), 20)
+    else:
+        app = D.nms_layered(g, D.channel_lam(g, L), 20)
+    hard = (app < 0).astype(np.uint8)
+    assert np.array_equal(hard, c[:, :g.n_dec])
+    assert np.array_equal(D.hard_bits(app, g.k), u)
+    sub = qc.syndrome(qb.base[:g.rows, :g.cols], qb.Z, hard)
+    assert not sub.any()
+
+
+def test_oms_saturated_inputs():
+    qb = SMALL.load()
+    g = qc.graph_from_qcbase(qb, 648)
+    u = philox.source_bits(15, 0, 2, g.k)
+    c = qc.encode(qb.base, qb.kb, qb.Z, qb.family, u).astype(np.int64)
+    lam = 31 * (1 - 2 * c)
+    app, rs, qs = D.oms_flood(g, lam, 3, trace=True)
+    assert (np.abs(rs[-1]) == 30).all()
+    assert (np.abs(qs[-1]) == 31).all()
+    assert np.array_equal((app < 0).astype(np.int64), c)
