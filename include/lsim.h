@@ -1,0 +1,308 @@
+/*
+ * lsim.h — C-ABI of liblsim, a gfx950 (MI355X) implementation of the LDPC
+ * link-level simulation hot path: binary source -> QC-LDPC encoder -> Gray
+ * QAM mapper -> AWGN -> LLR demapper -> belief-propagation decoder -> error
+ * count, in the order of the Sionna white paper's "Hello, World!" example
+ * (arXiv 2203.11854, Sec. III-C, Listing 1), plus a persistent mixed-shape
+ * decoder and a differentiable weighted-BP / neural-demapper pair
+ * (Sec. II-A "Native support of NNs", Sec. III-A, Listings 2-3, Sec. IV-A).
+ *
+ * Conventions (every entry point):
+ *  - Status codes only; nothing crosses the ABI as an exception.  Arguments
+ *    are validated on the host before any launch; a non-OK status means no
+ *    work was enqueued.  lsim_last_error() returns a thread-local message.
+ *  - Every d_* pointer is device memory owned by the caller.  Calls enqueue
+ *    asynchronously on `stream` (a hipStream_t; NULL = the null stream) and
+ *    never synchronize.  Decode-path calls allocate nothing; code and plan
+ *    creation allocate device tables and may synchronize.
+ *  - Row-major, batch-first layouts (Sec. III-A: the first dimension is the
+ *    batch of independent Monte-Carlo trials).  Complex values are
+ *    interleaved (re, im) float pairs.
+ *  - Boundary LLRs are logits of bit = 1, L = ln P(b=1)/P(b=0) (Listing 2
+ *    feeds them to a binary cross-entropy with the code bits as labels).
+ *    Hard decision: bit = [L_post > 0].
+ *  - Codeword index: the Philox counters of bits and noise include the
+ *    global codeword index cw0 + b, so a batch can be split anywhere and
+ *    reproduce the same data.
+ */
+#ifndef LSIM_H
+#define LSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LSIM_OK = 0,
+  LSIM_E_INVAL = 1,        /* bad argument: null pointer, bad size, bad table */
+  LSIM_E_NOMEM = 2,        /* workspace too small or device allocation failed */
+  LSIM_E_UNSUPPORTED = 3,  /* valid but not implemented (e.g. odd-m QAM) */
+  LSIM_E_DEVICE = 4        /* a HIP call failed */
+} lsim_status;
+
+typedef struct lsim_code lsim_code; /* opaque, immutable after create */
+typedef struct lsim_plan lsim_plan; /* opaque mixed-batch plan */
+typedef void* lsim_stream;          /* hipStream_t */
+
+/* ---------------------------------------------------------------- codes */
+
+enum { LSIM_FAMILY_11N = 0, LSIM_FAMILY_BG = 1 };
+
+/*
+ * Build a quasi-cyclic LDPC code (Sec. III-B lists 5G LDPC codes with rate
+ * matching; the base matrices here are synthetic dual-diagonal QC codes).
+ *  base          host int16[mb*nb], row-major; -1 = zero block, s in [0,Z) =
+ *                identity shifted right by s (check (i,r) joins variable node
+ *                (j, (r+s) mod Z)).  Copied; the caller keeps ownership.
+ *  family        LSIM_FAMILY_11N: parity part dual-diagonal over all mb rows
+ *                (weight-3 column kb with shifts 1/0/1 at rows 0, mb/2, mb-1);
+ *                LSIM_FAMILY_BG: 4 dual-diagonal core rows, extension rows r
+ *                with an identity at column kb+r.  kb = nb - mb.
+ *  n_punct_cols  leading information blocks never transmitted (0 or 2).
+ *  e_tx          transmitted bits: mother-code bits n_punct_cols*Z ..
+ *                n_punct_cols*Z + e_tx - 1 (column-order rate matching).  The
+ *                decoder keeps the core rows plus every extension row whose own
+ *                column carries a transmitted bit; untransmitted and punctured
+ *                variable nodes get LLR 0.
+ * Errors: LSIM_E_INVAL on a table that is not of the stated family, a shift
+ * out of range, a decoded row of degree < 2, e_tx out of range or not
+ * positive; LSIM_E_UNSUPPORTED when Z > 1024 or a decoded degree > 27;
+ * LSIM_E_DEVICE / LSIM_E_NOMEM on device-table upload failure.  The code's
+ * device tables live on the device current at creation.
+ */
+lsim_status lsim_code_create(const int16_t* base, int mb, int nb, int Z, int family,
+                             int n_punct_cols, int64_t e_tx, lsim_code** out);
+void lsim_code_destroy(lsim_code* code);
+
+typedef struct {
+  int64_t k;          /* information bits, kb*Z (punctured ones included) */
+  int64_t n_mother;   /* nb*Z */
+  int64_t e_tx;       /* transmitted bits */
+  int64_t n_dec;      /* decoded variable nodes */
+  int64_t m_dec;      /* decoded checks */
+  int64_t n_edges;    /* edges of the decoded graph, E */
+  int32_t Z, mb, nb, kb, rows, cols, n_punct_cols, max_row_deg, max_col_deg;
+} lsim_code_info;
+
+lsim_status lsim_code_query(const lsim_code* code, lsim_code_info* info);
+
+/* ------------------------------------------------------------- pipeline */
+
+/*
+ * BinarySource (Listing 1): d_u u8[B][k], bit i of codeword cw0+b is bit
+ * i%32 of word (i/32)%4 of Philox4x32-10(key=(seed lo, seed hi),
+ * counter=(i/128, cw lo, cw hi, 0)) (Salmon et al., SC'11).
+ */
+lsim_status lsim_source_bits(uint64_t seed, int64_t cw0, int64_t B, int64_t k, uint8_t* d_u,
+                             lsim_stream stream);
+
+/*
+ * LDPC encoder (Listing 1): systematic back-substitution through the
+ * dual-diagonal parity part, then the extension parities.
+ * d_u u8[B][k] (values 0/1) -> d_c u8[B][n_mother].
+ */
+lsim_status lsim_encode(const lsim_code* code, const uint8_t* d_u, int64_t B, uint8_t* d_c,
+                        lsim_stream stream);
+
+/*
+ * Mapper + AWGN (Listing 1, AWGN takes the noise variance N0): takes the
+ * transmitted slice of d_c u8[B][n_mother], maps m = bits_per_sym bits per
+ * symbol (1 = BPSK x = 1-2c; 2, 4, 6 = square Gray QAM of 3GPP TS 38.211
+ * Sec. 5.1, unit energy; I bits c0,c2,.. Q bits c1,c3,..) and adds
+ * sqrt(N0/2)(g_re + j g_im) with Box-Muller normals from Philox counter
+ * (j, cw lo, cw hi, 1) for symbols 2j, 2j+1.  d_no f32[B] per-codeword N0.
+ * d_y f32[B][S][2], S = e_tx / m.  e_tx % m != 0 -> LSIM_E_INVAL; m not in
+ * {1,2,4,6} -> LSIM_E_UNSUPPORTED.
+ */
+lsim_status lsim_map_awgn(const lsim_code* code, int bits_per_sym, const uint8_t* d_c,
+                          const float* d_no, uint64_t seed, int64_t cw0, int64_t B, float* d_y,
+                          lsim_stream stream);
+
+enum { LSIM_DEMAP_EXACT = 0, LSIM_DEMAP_MAXLOG = 1 };
+
+/*
+ * Demapper (Listing 1, "app" = exact; max-log): per-bit LLRs of each symbol
+ * given N0.  d_y f32[B][S][2], d_no f32[B] -> d_llr f32[B][S*m].  Both
+ * methods separate per I/Q axis for this labelling.  No clipping.
+ */
+lsim_status lsim_demap(int bits_per_sym, int method, const float* d_y, const float* d_no,
+                       int64_t B, int64_t S, float* d_llr, lsim_stream stream);
+
+/* Demapper fused with the int8 quantizer below: d_q i8[B][S*m]. */
+lsim_status lsim_demap_q8(int bits_per_sym, int method, const float* d_y, const float* d_no,
+                          int64_t B, int64_t S, float scale, int sat, int8_t* d_q,
+                          lsim_stream stream);
+
+/*
+ * LLR quantizer: q = clamp(rint(L*scale), -sat, sat), round half to even.
+ * scale must be a power of two (so L*scale is exact) and 1 <= sat <= 127.
+ */
+lsim_status lsim_quantize(const float* d_llr, int64_t count, float scale, int sat, int8_t* d_q,
+                          lsim_stream stream);
+
+/* ------------------------------------------------------------- decoders */
+
+enum {
+  LSIM_SPA_F32 = 0, /* flooding sum-product, FP32, messages clamped to +-llr_max */
+  LSIM_OMS_I8 = 1,  /* flooding offset min-sum on int8 LLRs (offset, sat) */
+  LSIM_NMS_F32 = 2  /* layered normalized min-sum, FP32, scale alpha */
+};
+
+typedef struct {
+  int algo;      /* LSIM_SPA_F32 | LSIM_OMS_I8 | LSIM_NMS_F32 */
+  int iters;     /* full iterations, no early stop, 1..1000 */
+  float offset;  /* OMS offset (integer-valued, >= 0) */
+  float alpha;   /* NMS normalization, (0, 1] */
+  float llr_max; /* SPA clamp, > 0 */
+  int sat;       /* OMS saturation, 1..127 */
+  int threads;   /* workgroup size; 0 = library default */
+} lsim_decode_params;
+
+/*
+ * Belief-propagation decoder (Sec. III-B "BP decoder and variants";
+ * Sec. IV-A names the min-sum BP decoder).  d_llr is f32[B][e_tx]
+ * (SPA, NMS) or i8[B][e_tx] (OMS, quantized LLRs).  Outputs: d_bits
+ * u8[B][k] hard decisions [L_post > 0] of the information bits (nullable),
+ * d_app f32[B][n_dec] posteriors L_post (nullable; integers for OMS).
+ * d_work: device workspace of at least lsim_decode_workspace() bytes (the
+ * layered decoder keeps its per-check state there; others need 0 bytes).
+ */
+lsim_status lsim_decode_workspace(const lsim_code* code, const lsim_decode_params* p, int64_t B,
+                                  size_t* bytes);
+lsim_status lsim_decode(const lsim_code* code, const lsim_decode_params* p, const void* d_llr,
+                        int64_t B, uint8_t* d_bits, float* d_app, void* d_work,
+                        size_t work_bytes, lsim_stream stream);
+
+/*
+ * Decoder state in canonical edge order (base nonzeros row-major, edge
+ * e*Z + r for lift index r), for per-iteration parity checks.  Flooding
+ * decoders: d_q_in (nullable, f32 or i8 [B][E]) replaces the initial
+ * variable-to-check messages; after p->iters rounds d_r_out holds the last
+ * check-to-variable messages and d_q_out the variable-to-check messages
+ * (both nullable, message type).  Layered: d_q_in and d_q_out must be NULL;
+ * d_r_out f32[B][E] gets the stored check messages.  d_app (nullable) as
+ * in lsim_decode (L_post).  The decoder input d_q_in is taken as given (no
+ * clamp); OMS channel LLRs are clamped to +-sat.
+ */
+lsim_status lsim_decode_state(const lsim_code* code, const lsim_decode_params* p,
+                              const void* d_llr, int64_t B, const void* d_q_in, void* d_r_out,
+                              void* d_q_out, float* d_app, void* d_work, size_t work_bytes,
+                              lsim_stream stream);
+
+/*
+ * Error count (compute_ber, Listing 1): per codeword, bit errors between
+ * d_ref (row stride ref_stride bytes) and d_hat u8[B][k]; adds (bit errors,
+ * block errors, codewords) into d_counts i64[nbins][3] at bin d_bin[b]
+ * (d_bin nullable = bin 0).  The caller zeroes d_counts.  Integer atomics:
+ * deterministic.
+ */
+lsim_status lsim_count_errors(const uint8_t* d_ref, int64_t ref_stride, const uint8_t* d_hat,
+                              int64_t B, int64_t k, const int32_t* d_bin, int nbins,
+                              int64_t* d_counts, lsim_stream stream);
+
+/*
+ * Syndrome weight of hard decisions over the decoded graph: d_c u8[B][n_dec]
+ * (row stride `stride` bytes) -> d_unsat i32[B] unsatisfied checks.
+ */
+lsim_status lsim_syndrome(const lsim_code* code, const uint8_t* d_c, int64_t stride, int64_t B,
+                          int32_t* d_unsat, lsim_stream stream);
+
+/* ------------------------------------------------- mixed-shape batching */
+
+/*
+ * Plan for decoding codewords of several codes in one persistent launch
+ * (layered NMS or flooding OMS).  counts[s] codewords of codes[s].  The
+ * plan owns a device work list and descriptor table.  `codewords_per_tile`
+ * (nullable) fixes, per shape, how many codewords share one workgroup
+ * (0 = choose from Z and LDS); `threads` (0 = default) the workgroup size.
+ * LLRs and bits are concatenated by shape: shape s starts at
+ * sum_{t<s} counts[t]*e_tx[t] LLRs and sum_{t<s} counts[t]*k[t] bits.
+ */
+lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t* counts,
+                                   int nshapes, const lsim_decode_params* p,
+                                   const int32_t* codewords_per_tile, int threads,
+                                   lsim_plan** out);
+void lsim_mixed_plan_destroy(lsim_plan* plan);
+/* Bytes of device workspace the plan's decode needs. */
+lsim_status lsim_mixed_workspace(const lsim_plan* plan, size_t* bytes);
+/*
+ * One persistent launch over the plan's work list: a small kernel resets the
+ * work counter (kept in d_work), then workgroups pull tiles until the list is
+ * drained.  No allocation and no memset node: graph-capturable.
+ * persistent = 0 launches one workgroup per tile instead (same results).
+ */
+lsim_status lsim_mixed_decode(lsim_plan* plan, const void* d_llr_concat, uint8_t* d_bits_concat,
+                              float* d_app_concat, void* d_work, size_t work_bytes,
+                              int persistent, lsim_stream stream);
+
+/* ------------------------------------------------ differentiable forms */
+
+/*
+ * Weighted BP forward (trainable decoder; Sec. II-A "gradients can be
+ * backpropagated through an entire system"): flooding sum-product, T rounds,
+ * check-to-variable message of edge e in round t scaled by d_w[t][e].
+ * d_llr f32[B][e_tx] channel LLRs; d_app f32[B][n_dec] -> L_post.
+ * d_ckpt f32[T][B][E] (nullable) receives the variable-to-check messages
+ * entering each round, which the backward pass reads.
+ */
+lsim_status lsim_wbp_forward(const lsim_code* code, int T, const float* d_w, const float* d_llr,
+                             int64_t B, float llr_max, float* d_ckpt, float* d_lpost,
+                             lsim_stream stream);
+/*
+ * Weighted BP backward (custom gradient, Sec. IV-A): given d_gpost =
+ * dLoss/dL_post f32[B][n_dec] and the forward checkpoints, writes
+ * d_gllr = dLoss/dL f32[B][e_tx] and d_gw = dLoss/dw f32[T][E]
+ * (overwritten; reduced over the batch in a fixed order).  d_work needs
+ * lsim_wbp_workspace() bytes.
+ */
+lsim_status lsim_wbp_workspace(const lsim_code* code, int T, int64_t B, size_t* bytes);
+lsim_status lsim_wbp_backward(const lsim_code* code, int T, const float* d_w, const float* d_llr,
+                              const float* d_ckpt, int64_t B, float llr_max, const float* d_gpost,
+                              float* d_gllr, float* d_gw, void* d_work, size_t work_bytes,
+                              lsim_stream stream);
+
+/*
+ * Neural demapper (Listing 3): per symbol, input [Re y, Im y, ln N0] ->
+ * Dense 64 ReLU -> Dense 64 ReLU -> Dense 4 (LLRs of the symbol's 4 bits).
+ * d_params f32[4676]: W1[64][3], b1[64], W2[64][64], b2[64], W3[4][64], b3[4].
+ * d_y f32[B][S][2], d_no f32[B] -> d_llr f32[B][S*4].
+ */
+#define LSIM_NDM_PARAMS 4676
+lsim_status lsim_ndm_forward(const float* d_params, const float* d_y, const float* d_no,
+                             int64_t B, int64_t S, float* d_llr, lsim_stream stream);
+/* dLoss/dparams for upstream d_gllr f32[B][S*4]; d_gparams overwritten
+ * (fixed-order reduction); d_work needs lsim_ndm_workspace() bytes. */
+lsim_status lsim_ndm_workspace(int64_t B, int64_t S, size_t* bytes);
+lsim_status lsim_ndm_backward(const float* d_params, const float* d_y, const float* d_no,
+                              const float* d_gllr, int64_t B, int64_t S, float* d_gparams,
+                              void* d_work, size_t work_bytes, lsim_stream stream);
+
+/*
+ * Binary cross-entropy on logits (Listing 2 loss) against code bits:
+ * d_g[b][v] = scale*(sigmoid(L[b][v]) - c[b][v]) for L = d_lpost f32[B][n]
+ * and c = d_c u8 (row stride c_stride bytes); d_loss (nullable, f32[1])
+ * receives scale * sum(softplus(L) - c L), reduced in a fixed order.
+ * d_work needs lsim_bce_workspace() bytes when d_loss is given.
+ */
+lsim_status lsim_bce_workspace(int64_t B, int64_t n, size_t* bytes);
+lsim_status lsim_bce_grad(const float* d_lpost, const uint8_t* d_c, int64_t c_stride, int64_t B,
+                          int64_t n, float scale, float* d_g, float* d_loss, void* d_work,
+                          size_t work_bytes, lsim_stream stream);
+
+/* Adam (Kingma & Ba 2015) on n parameters; step >= 1 (bias correction). */
+lsim_status lsim_adam_step(float* d_p, const float* d_g, float* d_m, float* d_v, int64_t n,
+                           float lr, float beta1, float beta2, float eps, int step,
+                           lsim_stream stream);
+
+/* ---------------------------------------------------------------- misc */
+
+const char* lsim_last_error(void);
+const char* lsim_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSIM_H */

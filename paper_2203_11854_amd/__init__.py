@@ -1,0 +1,292 @@
+"""Python binding of ``liblsim.so`` (include/lsim.h).
+
+Argument marshalling only: every function checks tensor devices, dtypes and
+shapes, passes raw device pointers and torch's current HIP stream to the
+C-ABI, and raises ``LsimError`` on a non-OK status.  All computation happens
+in the library's HIP kernels; torch provides device memory and streams.
+There is no CPU fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblsim.so")
+
+SPA_F32, OMS_I8, NMS_F32 = 0, 1, 2
+DEMAP_EXACT, DEMAP_MAXLOG = 0, 1
+FAMILY_11N, FAMILY_BG = 0, 1
+NDM_PARAMS = 4676
+
+_lib = None
+
+
+class LsimError(RuntimeError):
+    pass
+
+
+class CodeInfo(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int64), ("n_mother", ctypes.c_int64), ("e_tx", ctypes.c_int64),
+                ("n_dec", ctypes.c_int64), ("m_dec", ctypes.c_int64), ("n_edges", ctypes.c_int64),
+                ("Z", ctypes.c_int32), ("mb", ctypes.c_int32), ("nb", ctypes.c_int32),
+                ("kb", ctypes.c_int32), ("rows", ctypes.c_int32), ("cols", ctypes.c_int32),
+                ("n_punct_cols", ctypes.c_int32), ("max_row_deg", ctypes.c_int32),
+                ("max_col_deg", ctypes.c_int32)]
+
+
+class DecodeParams(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int), ("iters", ctypes.c_int), ("offset", ctypes.c_float),
+                ("alpha", ctypes.c_float), ("llr_max", ctypes.c_float), ("sat", ctypes.c_int),
+                ("threads", ctypes.c_int)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+_U64 = ctypes.c_uint64
+_F = ctypes.c_float
+_SZ = ctypes.c_size_t
+
+_SIGS = {
+    "lsim_code_create": [_P, _I, _I, _I, _I, _I, _I64, ctypes.POINTER(_P)],
+    "lsim_code_destroy": [_P],
+    "lsim_code_query": [_P, ctypes.POINTER(CodeInfo)],
+    "lsim_source_bits": [_U64, _I64, _I64, _I64, _P, _P],
+    "lsim_encode": [_P, _P, _I64, _P, _P],
+    "lsim_map_awgn": [_P, _I, _P, _P, _U64, _I64, _I64, _P, _P],
+    "lsim_demap": [_I, _I, _P, _P, _I64, _I64, _P, _P],
+    "lsim_demap_q8": [_I, _I, _P, _P, _I64, _I64, _F, _I, _P, _P],
+    "lsim_quantize": [_P, _I64, _F, _I, _P, _P],
+    "lsim_decode_workspace": [_P, ctypes.POINTER(DecodeParams), _I64, ctypes.POINTER(_SZ)],
+    "lsim_decode": [_P, ctypes.POINTER(DecodeParams), _P, _I64, _P, _P, _P, _SZ, _P],
+    "lsim_decode_state": [_P, ctypes.POINTER(DecodeParams), _P, _I64, _P, _P, _P, _P, _P, _SZ, _P],
+    "lsim_count_errors": [_P, _I64, _P, _I64, _I64, _P, _I, _P, _P],
+    "lsim_syndrome": [_P, _P, _I64, _I64, _P, _P],
+    "lsim_mixed_plan_create": [_P, _P, _I, ctypes.POINTER(DecodeParams), _P, _I, ctypes.POINTER(_P)],
+    "lsim_mixed_plan_destroy": [_P],
+    "lsim_mixed_workspace": [_P, ctypes.POINTER(_SZ)],
+    "lsim_mixed_decode": [_P, _P, _P, _P, _P, _SZ, _I, _P],
+    "lsim_wbp_forward": [_P, _I, _P, _P, _I64, _F, _P, _P, _P],
+    "lsim_wbp_workspace": [_P, _I, _I64, ctypes.POINTER(_SZ)],
+    "lsim_wbp_backward": [_P, _I, _P, _P, _P, _I64, _F, _P, _P, _P, _P, _SZ, _P],
+    "lsim_ndm_forward": [_P, _P, _P, _I64, _I64, _P, _P],
+    "lsim_ndm_workspace": [_I64, _I64, ctypes.POINTER(_SZ)],
+    "lsim_ndm_backward": [_P, _P, _P, _P, _I64, _I64, _P, _P, _SZ, _P],
+    "lsim_bce_workspace": [_I64, _I64, ctypes.POINTER(_SZ)],
+    "lsim_bce_grad": [_P, _P, _I64, _I64, _I64, _F, _P, _P, _P, _SZ, _P],
+    "lsim_adam_step": [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I, _P],
+    "lsim_last_error": [],
+    "lsim_version": [],
+}
+
+
+def lib():
+    """Load the library once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LsimError(f"{LIB_PATH} is missing: run paper_2203_11854_amd.build.build() first")
+    L = ctypes.CDLL(LIB_PATH)
+    for name, args in _SIGS.items():
+        fn = getattr(L, name, None)
+        if fn is None:
+            continue
+        fn.argtypes = args
+        fn.restype = None if name.endswith(("_destroy",)) else (
+            ctypes.c_char_p if name in ("lsim_last_error", "lsim_version") else ctypes.c_int)
+    _lib = L
+    return L
+
+
+def _call(name, *args):
+    st = getattr(lib(), name)(*args)
+    if st != 0:
+        msg = lib().lsim_last_error().decode()
+        raise LsimError(f"{name}: status {st}: {msg}")
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise LsimError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise LsimError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise LsimError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _empty(shape, dtype, device):
+    return torch.empty(shape, dtype=dtype, device=device)
+
+
+# ------------------------------------------------------------------ codes
+
+class Code:
+    """A QC-LDPC code on the current device (lsim_code_create)."""
+
+    def __init__(self, base, Z: int, family: str, n_punct_cols: int, e_tx: int):
+        import numpy as np
+        arr = np.ascontiguousarray(np.asarray(base, dtype=np.int16))
+        mb, nb = arr.shape
+        fam = FAMILY_11N if family == "11n" else FAMILY_BG
+        h = ctypes.c_void_p()
+        _call("lsim_code_create", arr.ctypes.data_as(ctypes.c_void_p), mb, nb, Z, fam,
+              n_punct_cols, e_tx, ctypes.byref(h))
+        self._h = h
+        info = CodeInfo()
+        _call("lsim_code_query", h, ctypes.byref(info))
+        self.info = info
+        for f, _ in CodeInfo._fields_:
+            setattr(self, f, getattr(info, f))
+        self.E = info.n_edges
+
+    @classmethod
+    def from_qcbase(cls, qb, e_tx: int) -> "Code":
+        return cls(qb.base, qb.Z, qb.family, qb.n_punct_cols, e_tx)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.lsim_code_destroy(h)
+            self._h = None
+
+
+# --------------------------------------------------------------- pipeline
+
+def source_bits(seed: int, cw0: int, B: int, k: int, device="cuda", out=None):
+    u = out if out is not None else _empty((B, k), torch.uint8, device)
+    _call("lsim_source_bits", seed, cw0, B, k, _ptr(u, torch.uint8, "u"), _stream())
+    return u
+
+
+def encode(code: Code, u, out=None):
+    B = u.shape[0]
+    c = out if out is not None else _empty((B, code.n_mother), torch.uint8, u.device)
+    _call("lsim_encode", code.handle, _ptr(u, torch.uint8, "u"), B, _ptr(c, torch.uint8, "c"), _stream())
+    return c
+
+
+def map_awgn(code: Code, m: int, c, no, seed: int, cw0: int, out=None):
+    B = c.shape[0]
+    S = code.e_tx // m
+    y = out if out is not None else _empty((B, S, 2), torch.float32, c.device)
+    _call("lsim_map_awgn", code.handle, m, _ptr(c, torch.uint8, "c"), _ptr(no, torch.float32, "no"),
+          seed, cw0, B, _ptr(y, torch.float32, "y"), _stream())
+    return y
+
+
+def demap(m: int, method: int, y, no, out=None):
+    B, S = y.shape[0], y.shape[1]
+    L = out if out is not None else _empty((B, S * m), torch.float32, y.device)
+    _call("lsim_demap", m, method, _ptr(y, torch.float32, "y"), _ptr(no, torch.float32, "no"), B, S,
+          _ptr(L, torch.float32, "llr"), _stream())
+    return L
+
+
+def demap_q8(m: int, method: int, y, no, scale: float = 2.0, sat: int = 31, out=None):
+    B, S = y.shape[0], y.shape[1]
+    q = out if out is not None else _empty((B, S * m), torch.int8, y.device)
+    _call("lsim_demap_q8", m, method, _ptr(y, torch.float32, "y"), _ptr(no, torch.float32, "no"), B,
+          S, scale, sat, _ptr(q, torch.int8, "q"), _stream())
+    return q
+
+
+def quantize(L, scale: float = 2.0, sat: int = 31, out=None):
+    q = out if out is not None else torch.empty(L.shape, dtype=torch.int8, device=L.device)
+    _call("lsim_quantize", _ptr(L, torch.float32, "llr"), L.numel(), scale, sat,
+          _ptr(q, torch.int8, "q"), _stream())
+    return q
+
+
+# --------------------------------------------------------------- decoders
+
+def params(algo: int, iters: int = 20, offset: float = 1.0, alpha: float = 0.75,
+           llr_max: float = 20.0, sat: int = 31, threads: int = 0) -> DecodeParams:
+    return DecodeParams(algo, iters, offset, alpha, llr_max, sat, threads)
+
+
+def decode_workspace(code: Code, p: DecodeParams, B: int) -> int:
+    n = ctypes.c_size_t()
+    _call("lsim_decode_workspace", code.handle, ctypes.byref(p), B, ctypes.byref(n))
+    return n.value
+
+
+def _work(nbytes, device, work):
+    if nbytes == 0:
+        return None, 0
+    if work is None:
+        work = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    return work, work.numel() * work.element_size()
+
+
+def decode(code: Code, llr, p: DecodeParams, want_bits=True, want_app=False, bits=None,
+           app=None, work=None):
+    """Hard information bits u8[B][k] and/or posteriors L_post f32[B][n_dec]."""
+    B = llr.shape[0]
+    dt = torch.int8 if p.algo == OMS_I8 else torch.float32
+    if want_bits and bits is None:
+        bits = _empty((B, code.k), torch.uint8, llr.device)
+    if want_app and app is None:
+        app = _empty((B, code.n_dec), torch.float32, llr.device)
+    work, nbytes = _work(decode_workspace(code, p, B), llr.device, work)
+    _call("lsim_decode", code.handle, ctypes.byref(p), _ptr(llr, dt, "llr"), B,
+          _ptr(bits, torch.uint8, "bits") if want_bits else None,
+          _ptr(app, torch.float32, "app") if want_app else None,
+          _ptr(work, None, "work"), nbytes, _stream())
+    return bits, app
+
+
+def decode_state(code: Code, llr, p: DecodeParams, q_in=None, want_q=True, want_r=True):
+    """(r, q, L_post) after p.iters rounds, messages in canonical edge order."""
+    B = llr.shape[0]
+    mt = torch.int8 if p.algo == OMS_I8 else torch.float32
+    r = _empty((B, code.E), mt, llr.device) if want_r else None
+    q = _empty((B, code.E), mt, llr.device) if (want_q and p.algo != NMS_F32) else None
+    app = _empty((B, code.n_dec), torch.float32, llr.device)
+    work, nbytes = _work(decode_workspace(code, p, B), llr.device, None)
+    _call("lsim_decode_state", code.handle, ctypes.byref(p), _ptr(llr, mt, "llr"), B,
+          _ptr(q_in, mt, "q_in"), _ptr(r, mt, "r_out"), _ptr(q, mt, "q_out"),
+          _ptr(app, torch.float32, "app"), _ptr(work, None, "work"), nbytes, _stream())
+    return r, q, app
+
+
+def count_errors(ref, hat, bins=None, nbins: int = 1, counts=None):
+    B, k = hat.shape
+    if counts is None:
+        counts = torch.zeros((nbins, 3), dtype=torch.int64, device=hat.device)
+    stride = ref.stride(0)
+    if ref.stride(1) != 1 or ref.dtype != torch.uint8:
+        raise LsimError("ref must be u8 with unit column stride")
+    _call("lsim_count_errors", ctypes.c_void_p(ref.data_ptr()), stride, _ptr(hat, torch.uint8, "hat"),
+          B, k, _ptr(bins, torch.int32, "bins"), nbins, _ptr(counts, torch.int64, "counts"), _stream())
+    return counts
+
+
+def syndrome(code: Code, hard):
+    B = hard.shape[0]
+    out = _empty((B,), torch.int32, hard.device)
+    if hard.stride(1) != 1 or hard.dtype != torch.uint8:
+        raise LsimError("hard decisions must be u8 with unit column stride")
+    _call("lsim_syndrome", code.handle, ctypes.c_void_p(hard.data_ptr()), hard.stride(0), B,
+          _ptr(out, torch.int32, "unsat"), _stream())
+    return out
+
+
+def ebn0_to_n0(ebn0_db, rate: float, m: int):
+    """N0 = 1 / (R m 10^(EbN0/10)) for unit-energy symbols (host helper)."""
+    import numpy as np
+    return 1.0 / (rate * m * 10.0 ** (np.asarray(ebn0_db, dtype=np.float64) / 10.0))

@@ -1,0 +1,341 @@
+// Flooding belief-propagation decoders on a QC Tanner graph:
+//   SPA  FP32 sum-product (messages clamped to +-llr_max)
+//   OMS  int8 offset min-sum (offset, saturation)
+//
+// One workgroup decodes one codeword with its whole message state in LDS:
+// M[E] holds, per edge in canonical order (base nonzero e, lift r -> e*Z+r),
+// the variable-to-check message q before a check phase and the
+// check-to-variable message r after it; lam[n_dec] holds the channel LLRs.
+// A round is two phases separated by barriers:
+//   check phase     lane = check (i, r); reads the d_i messages of its row
+//                   (addresses e*Z + r: consecutive lanes, no bank conflict),
+//                   writes r in place;
+//   variable phase  lane = variable node (j, c); gathers the column's r
+//                   (addresses e*Z + (c - s) mod Z: rotated contiguous
+//                   segments), forms APP = lam + sum r and writes
+//                   q = clamp(APP - r).
+// Work items are (base row or column, 64-lift block); every wavefront works
+// on a single row or column at a time, so the degree loop is uniform.  Items
+// are sorted heaviest first and dealt round-robin to the wavefronts.
+#include <hip/hip_runtime.h>
+
+#include "lsim_internal.h"
+
+namespace lsim {
+
+namespace {
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+struct FloodArgs {
+  const void* llr;
+  int64_t B;
+  uint8_t* bits;
+  float* lpost;
+  const void* q_in;
+  void* r_out;
+  void* q_out;
+  int iters;
+  float llr_max;
+  int offset;
+  int sat;
+};
+
+// Small graph tables staged in LDS (read with wave-uniform addresses).
+struct Tables {
+  int* cn_tasks;
+  int* vn_tasks;
+  int* row_ptr;
+  int* col_ptr;
+  int2* col_edge;  // per column entry: (e * Z, shift)
+};
+
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+template <int ALG>
+struct Traits;
+template <>
+struct Traits<LSIM_SPA_F32> {
+  using Msg = float;
+  using In = float;
+};
+template <>
+struct Traits<LSIM_OMS_I8> {
+  using Msg = int8_t;
+  using In = int8_t;
+};
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+__host__ __device__ inline size_t table_bytes(const DevCode& c) {
+  return align16((size_t)(c.n_cn_tasks + c.n_vn_tasks + c.rows + 1 + c.cols + 1) * 4) +
+         (size_t)c.nnz * 8;
+}
+
+template <int ALG>
+__host__ __device__ inline size_t lds_bytes_for(const DevCode& c) {
+  using M = typename Traits<ALG>::Msg;
+  return align16((size_t)c.E * sizeof(M)) + align16((size_t)c.n_dec * sizeof(M)) + table_bytes(c);
+}
+
+template <int NT, int DMAX, int ALG>
+__global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
+  using M = typename Traits<ALG>::Msg;
+  using In = typename Traits<ALG>::In;
+  constexpr int NW = NT / 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  M* msg = reinterpret_cast<M*>(smem);
+  M* lam = reinterpret_cast<M*>(smem + align16((size_t)c.E * sizeof(M)));
+  unsigned char* tb = smem + align16((size_t)c.E * sizeof(M)) + align16((size_t)c.n_dec * sizeof(M));
+  Tables t;
+  t.cn_tasks = reinterpret_cast<int*>(tb);
+  t.vn_tasks = t.cn_tasks + c.n_cn_tasks;
+  t.row_ptr = t.vn_tasks + c.n_vn_tasks;
+  t.col_ptr = t.row_ptr + c.rows + 1;
+  t.col_edge = reinterpret_cast<int2*>(
+      tb + align16((size_t)(c.n_cn_tasks + c.n_vn_tasks + c.rows + 1 + c.cols + 1) * 4));
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = uni(tid >> 6);
+  const int Z = c.Z;
+  const int64_t b = blockIdx.x;
+
+  // ---- stage tables, channel LLRs, zero messages
+  for (int i = tid; i < c.n_cn_tasks; i += NT) t.cn_tasks[i] = c.cn_tasks[i];
+  for (int i = tid; i < c.n_vn_tasks; i += NT) t.vn_tasks[i] = c.vn_tasks[i];
+  for (int i = tid; i <= c.rows; i += NT) t.row_ptr[i] = c.row_ptr[i];
+  for (int i = tid; i <= c.cols; i += NT) t.col_ptr[i] = c.col_ptr[i];
+  for (int i = tid; i < c.nnz; i += NT) {
+    const int e = c.col_ent[i];
+    t.col_edge[i] = make_int2(e * Z, c.ent_shift[e]);
+  }
+  const In* llr = reinterpret_cast<const In*>(a.llr) + b * (int64_t)c.e_tx;
+  for (int v = tid; v < c.n_dec; v += NT) {
+    const int x = v - c.tx_lo;
+    M l = 0;
+    if (x >= 0 && x < c.e_tx) {
+      if constexpr (ALG == LSIM_SPA_F32) {
+        l = fminf(fmaxf(-llr[x], -a.llr_max), a.llr_max);
+      } else {
+        l = (M)min(max(-(int)llr[x], -a.sat), a.sat);
+      }
+    }
+    lam[v] = l;
+  }
+  if (a.q_in) {
+    const M* qi = reinterpret_cast<const M*>(a.q_in) + b * (int64_t)c.E;
+    for (int e = tid; e < c.E; e += NT) msg[e] = qi[e];
+  } else {
+    for (int e = tid; e < c.E; e += NT) msg[e] = 0;
+  }
+  __syncthreads();
+
+  // variable phase; mode 0: q <- clamp(lam + sum r - r), 1: last round
+  auto var_phase = [&](bool write_q, bool final_round) {
+    for (int ti = wave; ti < c.n_vn_tasks; ti += NW) {
+      const int task = uni(t.vn_tasks[ti]);
+      const int j = task >> 16;
+      const int cc = (task & 0xffff) + lane;
+      const int cb = uni(t.col_ptr[j]);
+      const int dc = uni(t.col_ptr[j + 1]) - cb;
+      if (cc < Z) {
+        const int v = j * Z + cc;
+        int idx[DMAX];
+        if constexpr (ALG == LSIM_SPA_F32) {
+          float rv[DMAX];
+          float acc = lam[v];
+#pragma unroll
+          for (int q = 0; q < DMAX; ++q) {
+            if (q < dc) {
+              const int2 ce = t.col_edge[cb + q];
+              int x = cc - ce.y;
+              x += x < 0 ? Z : 0;
+              idx[q] = ce.x + x;
+              rv[q] = msg[idx[q]];
+              acc += rv[q];
+            }
+          }
+          if (write_q) {
+#pragma unroll
+            for (int q = 0; q < DMAX; ++q)
+              if (q < dc) msg[idx[q]] = fminf(fmaxf(acc - rv[q], -a.llr_max), a.llr_max);
+          }
+          if (final_round) {
+            if (a.bits && v < c.k) a.bits[b * (int64_t)c.k + v] = acc < 0.f;
+            if (a.lpost) a.lpost[b * (int64_t)c.n_dec + v] = -acc;
+          }
+        } else {
+          int rv[DMAX];
+          int acc = lam[v];
+#pragma unroll
+          for (int q = 0; q < DMAX; ++q) {
+            if (q < dc) {
+              const int2 ce = t.col_edge[cb + q];
+              int x = cc - ce.y;
+              x += x < 0 ? Z : 0;
+              idx[q] = ce.x + x;
+              rv[q] = msg[idx[q]];
+              acc += rv[q];
+            }
+          }
+          if (write_q) {
+#pragma unroll
+            for (int q = 0; q < DMAX; ++q)
+              if (q < dc) msg[idx[q]] = (M)min(max(acc - rv[q], -a.sat), a.sat);
+          }
+          if (final_round) {
+            if (a.bits && v < c.k) a.bits[b * (int64_t)c.k + v] = acc < 0;
+            if (a.lpost) a.lpost[b * (int64_t)c.n_dec + v] = (float)(-acc);
+          }
+        }
+      }
+    }
+  };
+
+  auto check_phase = [&]() {
+    for (int ti = wave; ti < c.n_cn_tasks; ti += NW) {
+      const int task = uni(t.cn_tasks[ti]);
+      const int i = task >> 16;
+      const int r = (task & 0xffff) + lane;
+      const int e0 = uni(t.row_ptr[i]);
+      const int d = uni(t.row_ptr[i + 1]) - e0;
+      if (r < Z) {
+        M* row = msg + (size_t)e0 * Z + r;
+        uint32_t neg = 0;
+        if constexpr (ALG == LSIM_SPA_F32) {
+          // sum-product in the "1 - prod tanh" domain: with
+          // m_v = 1 - tanh(|q_v|/2) = 2e/(1+e), e = exp(-|q_v|), the
+          // extrinsic D_v = 1 - prod_{v' != v}(1 - m_v') is built from
+          // exclusive prefix and suffix combinations x (+) y = x + y - xy,
+          // and |r_v| = ln((2 - D_v) / D_v) = 2 atanh(1 - D_v).
+          float mm[DMAX], pre[DMAX];
+          float dp = 0.f;
+#pragma unroll
+          for (int q = 0; q < DMAX; ++q) {
+            if (q < d) {
+              const float x = row[q * Z];
+              neg |= (x < 0.f ? 1u : 0u) << q;
+              const float e = __builtin_amdgcn_exp2f(-fabsf(x) * kLog2e);
+              const float m = 2.f * e * __builtin_amdgcn_rcpf(1.f + e);
+              mm[q] = m;
+              pre[q] = dp;
+              dp = dp + m - dp * m;
+            }
+          }
+          const uint32_t par = __popc(neg) & 1u;
+          float ds = 0.f;
+#pragma unroll
+          for (int q = DMAX - 1; q >= 0; --q) {
+            if (q < d) {
+              const float p = pre[q];
+              const float dx = p + ds - p * ds;
+              float rv = kLn2 * __builtin_amdgcn_logf((2.f - dx) * __builtin_amdgcn_rcpf(dx));
+              rv = fminf(rv, a.llr_max);
+              row[q * Z] = (par ^ ((neg >> q) & 1u)) ? -rv : rv;
+              const float m = mm[q];
+              ds = ds + m - ds * m;
+            }
+          }
+        } else {
+          int m1 = 255, m2 = 255, i1 = 0;
+#pragma unroll
+          for (int q = 0; q < DMAX; ++q) {
+            if (q < d) {
+              const int x = row[q * Z];
+              neg |= (x < 0 ? 1u : 0u) << q;
+              const int ax = x < 0 ? -x : x;
+              m2 = min(m2, max(m1, ax));
+              i1 = ax < m1 ? q : i1;
+              m1 = min(m1, ax);
+            }
+          }
+          const uint32_t par = __popc(neg) & 1u;
+#pragma unroll
+          for (int q = 0; q < DMAX; ++q) {
+            if (q < d) {
+              const int mag = max((q == i1 ? m2 : m1) - a.offset, 0);
+              row[q * Z] = (M)((par ^ ((neg >> q) & 1u)) ? -mag : mag);
+            }
+          }
+        }
+      }
+    }
+  };
+
+  if (!a.q_in) {
+    var_phase(true, false);  // q = lam on every edge
+    __syncthreads();
+  }
+  for (int it = 0; it < a.iters; ++it) {
+    const bool last = it + 1 == a.iters;
+    check_phase();
+    __syncthreads();
+    if (last && a.r_out) {
+      M* ro = reinterpret_cast<M*>(a.r_out) + b * (int64_t)c.E;
+      for (int e = tid; e < c.E; e += NT) ro[e] = msg[e];
+      __syncthreads();
+    }
+    var_phase(!last || a.q_out != nullptr, last);
+    __syncthreads();
+  }
+  if (a.q_out) {
+    M* qo = reinterpret_cast<M*>(a.q_out) + b * (int64_t)c.E;
+    for (int e = tid; e < c.E; e += NT) qo[e] = msg[e];
+  }
+}
+
+template <int NT, int DMAX, int ALG>
+hipError_t launch_t(const DevCode& c, const FloodArgs& a, size_t lds, hipStream_t s) {
+  static bool attr_done = false;
+  if (!attr_done) {
+    hipError_t e = hipFuncSetAttribute((const void*)flood_kernel<NT, DMAX, ALG>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_done = true;
+  }
+  flood_kernel<NT, DMAX, ALG><<<(unsigned)a.B, NT, lds, s>>>(c, a);
+  return hipGetLastError();
+}
+
+template <int ALG>
+hipError_t dispatch(const DevCode& c, int nt, const FloodArgs& a, size_t lds, hipStream_t s) {
+  const int dmax = c.max_row_deg > c.max_col_deg ? c.max_row_deg : c.max_col_deg;
+#define LSIM_FLOOD_CASE(NT_, D_) \
+  if (nt == NT_ && dmax <= D_) return launch_t<NT_, D_, ALG>(c, a, lds, s);
+  LSIM_FLOOD_CASE(256, 8)
+  LSIM_FLOOD_CASE(256, 16)
+  LSIM_FLOOD_CASE(256, 32)
+  LSIM_FLOOD_CASE(512, 8)
+  LSIM_FLOOD_CASE(512, 16)
+  LSIM_FLOOD_CASE(512, 32)
+  LSIM_FLOOD_CASE(1024, 8)
+  LSIM_FLOOD_CASE(1024, 16)
+  LSIM_FLOOD_CASE(1024, 32)
+#undef LSIM_FLOOD_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+size_t flood_lds_bytes(const DevCode& c, int algo) {
+  return algo == LSIM_SPA_F32 ? lds_bytes_for<LSIM_SPA_F32>(c) : lds_bytes_for<LSIM_OMS_I8>(c);
+}
+
+hipError_t launch_flood(const DevCode& c, const lsim_decode_params& p, const void* llr, int64_t B,
+                        uint8_t* bits, float* lpost, const void* q_in, void* r_out, void* q_out,
+                        hipStream_t s, std::string* why) {
+  const size_t lds = flood_lds_bytes(c, p.algo);
+  if (lds > 160 * 1024) {
+    *why = "flooding decoder state (" + std::to_string(lds) + " B) exceeds the 160 KiB LDS";
+    return hipSuccess;
+  }
+  FloodArgs a{llr, B, bits, lpost, q_in, r_out, q_out, p.iters, p.llr_max,
+              (int)p.offset, p.sat};
+  const int nt = p.threads ? p.threads : (p.algo == LSIM_SPA_F32 ? 512 : 256);
+  if (p.algo == LSIM_SPA_F32) return dispatch<LSIM_SPA_F32>(c, nt, a, lds, s);
+  return dispatch<LSIM_OMS_I8>(c, nt, a, lds, s);
+}
+
+}  // namespace lsim

@@ -1,0 +1,351 @@
+// Link kernels around the decoder: binary source, QC encoder, Gray QAM
+// mapper + AWGN, demappers, quantizer, error counting and syndrome.
+#include <hip/hip_runtime.h>
+
+#include "lsim_internal.h"
+#include "philox.h"
+
+namespace lsim {
+
+namespace {
+
+constexpr float kTwoPow32Inv = 2.3283064365386963e-10f;  // 2^-32
+
+// ----------------------------------------------------------------- source
+
+__global__ void source_bits_kernel(uint64_t seed, int64_t cw0, int64_t B, int64_t k,
+                                   int64_t words_per_cw, uint8_t* __restrict__ u) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B * words_per_cw) return;
+  const int64_t b = t / words_per_cw;
+  const int64_t w = t - b * words_per_cw;  // 32-bit word index within the codeword
+  const U4 r = philox_at(seed, (uint32_t)(w >> 2), (uint64_t)(cw0 + b), kStreamBits);
+  const uint32_t sel = (uint32_t)(w & 3);
+  const uint32_t word = sel == 0 ? r.x : sel == 1 ? r.y : sel == 2 ? r.z : r.w;
+  const int64_t i0 = w * 32;
+  const int n = (int)min<int64_t>(32, k - i0);
+  uint8_t* dst = u + b * k + i0;
+  if (n == 32 && (((uintptr_t)dst) & 3) == 0) {
+    uint32_t* d4 = reinterpret_cast<uint32_t*>(dst);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const uint32_t nib = word >> (4 * q);
+      d4[q] = (nib & 1u) | ((nib >> 1) & 1u) << 8 | ((nib >> 2) & 1u) << 16 | ((nib >> 3) & 1u) << 24;
+    }
+  } else {
+    for (int i = 0; i < n; ++i) dst[i] = (uint8_t)((word >> i) & 1u);
+  }
+}
+
+// ---------------------------------------------------------------- encoder
+
+// One workgroup per codeword; the whole mother codeword sits in LDS.
+// lambda_i (core rows) = XOR over information blocks of rotated u_j;
+// p_0 = XOR of all lambda_i; p_1 = lambda_0 ^ P^1 p_0;
+// p_{i+1} = lambda_i ^ p_i (^ p_0 at the middle row); extension rows (BG
+// shape) then set their own block from columns < kb + 4.
+__global__ __launch_bounds__(256) void encode_kernel(DevCode c, const uint8_t* __restrict__ u,
+                                                     uint8_t* __restrict__ cw) {
+  extern __shared__ uint8_t sm[];
+  const int Z = c.Z, kb = c.kb, nb = c.nb, mb = c.mb;
+  const int m = c.family == LSIM_FAMILY_11N ? mb : 4;
+  const int mid = m / 2;
+  uint8_t* cb = sm;                        // n_mother bits
+  uint8_t* lam = sm + c.n_mother;          // m * Z
+  const int64_t b = blockIdx.x;
+  const uint8_t* ub = u + b * (int64_t)c.k;
+  for (int i = threadIdx.x; i < c.k; i += blockDim.x) cb[i] = ub[i] & 1;
+  __syncthreads();
+  for (int t = threadIdx.x; t < m * Z; t += blockDim.x) {
+    const int i = t / Z, r = t - i * Z;
+    uint8_t acc = 0;
+    for (int j = 0; j < kb; ++j) {
+      const int s = c.base[i * nb + j];
+      if (s < 0) continue;
+      int x = r + s;
+      x -= x >= Z ? Z : 0;
+      acc ^= cb[j * Z + x];
+    }
+    lam[t] = acc;
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < Z; r += blockDim.x) {
+    uint8_t p0 = 0;
+    for (int i = 0; i < m; ++i) p0 ^= lam[i * Z + r];
+    cb[kb * Z + r] = p0;
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < Z; r += blockDim.x) {
+    const int r1 = r + 1 == Z ? 0 : r + 1;
+    const uint8_t p0r = cb[kb * Z + r];
+    uint8_t p = lam[r] ^ cb[kb * Z + r1];
+    cb[(kb + 1) * Z + r] = p;
+    for (int i = 1; i < m - 1; ++i) {
+      p = lam[i * Z + r] ^ p ^ (i == mid ? p0r : 0);
+      cb[(kb + i + 1) * Z + r] = p;
+    }
+  }
+  __syncthreads();
+  if (c.family == LSIM_FAMILY_BG) {
+    const int ext = mb - 4;
+    for (int t = threadIdx.x; t < ext * Z; t += blockDim.x) {
+      const int row = 4 + t / Z, r = t % Z;
+      uint8_t acc = 0;
+      for (int j = 0; j < kb + 4; ++j) {
+        const int s = c.base[row * nb + j];
+        if (s < 0) continue;
+        int x = r + s;
+        x -= x >= Z ? Z : 0;
+        acc ^= cb[j * Z + x];
+      }
+      cb[(kb + row) * Z + r] = acc;
+    }
+    __syncthreads();
+  }
+  uint8_t* out = cw + b * (int64_t)c.n_mother;
+  for (int i = threadIdx.x; i < c.n_mother; i += blockDim.x) out[i] = cb[i];
+}
+
+// ------------------------------------------------------- mapper + channel
+
+// Gray PAM level of h bits (a0 first): (1-2a0)(2^{h-1} - (1-2a1)(...)).
+__device__ __forceinline__ float pam_level(const uint32_t* a, int h) {
+  int v = 1;
+  for (int l = h - 1; l >= 1; --l) v = (1 << (h - l)) - (1 - 2 * (int)a[l]) * v;
+  return (float)((1 - 2 * (int)a[0]) * v);
+}
+
+__device__ __forceinline__ float qam_inv_scale(int h) {
+  return h == 1 ? 0.70710678118654752f : h == 2 ? 0.31622776601683794f : 0.15430334996209191f;
+}
+
+__global__ void map_awgn_kernel(DevCode c, int m, const uint8_t* __restrict__ cw,
+                                const float* __restrict__ no, uint64_t seed, int64_t cw0,
+                                int64_t B, int S, float* __restrict__ y) {
+  const int npair = (S + 1) >> 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B * npair) return;
+  const int64_t b = t / npair;
+  const int j = (int)(t - b * npair);
+  const U4 r = philox_at(seed, (uint32_t)j, (uint64_t)(cw0 + b), kStreamNoise);
+  const float sig = sqrtf(no[b] * 0.5f);
+  const uint8_t* bits = cw + b * (int64_t)c.n_mother + c.tx_lo;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int s = 2 * j + h;
+    if (s >= S) break;
+    const uint32_t xa = h ? r.z : r.x, xb = h ? r.w : r.y;
+    const float ua = fmaf((float)xa, kTwoPow32Inv, kTwoPow32Inv);
+    const float ub = (float)xb * kTwoPow32Inv;
+    const float rho = sqrtf(-2.0f * logf(ua));
+    float sn, cs;
+    sincospif(2.0f * ub, &sn, &cs);
+    float xr, xi;
+    if (m == 1) {
+      xr = 1.0f - 2.0f * (float)bits[s];
+      xi = 0.0f;
+    } else {
+      const int hb = m >> 1;
+      uint32_t ai[3], aq[3];
+      for (int q = 0; q < hb; ++q) {
+        ai[q] = bits[s * m + 2 * q];
+        aq[q] = bits[s * m + 2 * q + 1];
+      }
+      const float inv = qam_inv_scale(hb);
+      xr = pam_level(ai, hb) * inv;
+      xi = pam_level(aq, hb) * inv;
+    }
+    float2 out;
+    out.x = xr + sig * rho * cs;
+    out.y = xi + sig * rho * sn;
+    reinterpret_cast<float2*>(y)[b * (int64_t)S + s] = out;
+  }
+}
+
+// --------------------------------------------------------------- demapper
+
+// Per-axis LLRs of h Gray bits for coordinate v (unit-energy scale `inv`):
+// max-log: (min_{b=0} d^2 - min_{b=1} d^2) / N0; exact: log-sum-exp of
+// -d^2/N0 over the levels with bit 1 minus that over bit 0.
+__device__ __forceinline__ void axis_llr(float v, float inv_no, int h, float inv, bool exact,
+                                         float* out) {
+  const int nl = 1 << h;
+  float d2[8];
+  for (int l = 0; l < nl; ++l) {
+    uint32_t a[3];
+    for (int q = 0; q < h; ++q) a[q] = (l >> (h - 1 - q)) & 1u;
+    const float lv = pam_level(a, h) * inv;
+    const float dv = v - lv;
+    d2[l] = dv * dv * inv_no;
+  }
+  for (int q = 0; q < h; ++q) {
+    const int sh = h - 1 - q;
+    if (!exact) {
+      float m0 = INFINITY, m1 = INFINITY;
+      for (int l = 0; l < nl; ++l) {
+        if ((l >> sh) & 1) m1 = fminf(m1, d2[l]);
+        else m0 = fminf(m0, d2[l]);
+      }
+      out[q] = m0 - m1;
+    } else {
+      float m0 = INFINITY, m1 = INFINITY;
+      for (int l = 0; l < nl; ++l) {
+        if ((l >> sh) & 1) m1 = fminf(m1, d2[l]);
+        else m0 = fminf(m0, d2[l]);
+      }
+      float s0 = 0.f, s1 = 0.f;
+      for (int l = 0; l < nl; ++l) {
+        if ((l >> sh) & 1) s1 += expf(m1 - d2[l]);
+        else s0 += expf(m0 - d2[l]);
+      }
+      out[q] = (m0 - m1) + logf(s1) - logf(s0);
+    }
+  }
+}
+
+__global__ void demap_kernel(int m, int method, const float* __restrict__ y,
+                             const float* __restrict__ no, int64_t B, int64_t S,
+                             float* __restrict__ llr, int8_t* __restrict__ q, float scale,
+                             int sat) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B * S) return;
+  const int64_t b = t / S;
+  const float2 yy = reinterpret_cast<const float2*>(y)[t];
+  const float n0 = no[b];
+  float L[6];
+  if (m == 1) {
+    L[0] = -4.0f * yy.x / n0;
+  } else {
+    const int h = m >> 1;
+    const float inv_no = 1.0f / n0;
+    float li[3], lq[3];
+    const bool exact = method == LSIM_DEMAP_EXACT;
+    axis_llr(yy.x, inv_no, h, qam_inv_scale(h), exact, li);
+    axis_llr(yy.y, inv_no, h, qam_inv_scale(h), exact, lq);
+    for (int i = 0; i < h; ++i) {
+      L[2 * i] = li[i];
+      L[2 * i + 1] = lq[i];
+    }
+  }
+  if (llr) {
+    for (int i = 0; i < m; ++i) llr[t * m + i] = L[i];
+  } else {
+    for (int i = 0; i < m; ++i) {
+      const float v = fminf(fmaxf(rintf(L[i] * scale), (float)-sat), (float)sat);
+      q[t * m + i] = (int8_t)v;
+    }
+  }
+}
+
+__global__ void quantize_kernel(const float* __restrict__ L, int64_t n, float scale, int sat,
+                                int8_t* __restrict__ q) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const float v = fminf(fmaxf(rintf(L[t] * scale), (float)-sat), (float)sat);
+  q[t] = (int8_t)v;
+}
+
+// ------------------------------------------------------------ error count
+
+__global__ __launch_bounds__(256) void count_errors_kernel(const uint8_t* __restrict__ ref,
+                                                           int64_t ref_stride,
+                                                           const uint8_t* __restrict__ hat,
+                                                           int64_t k, const int32_t* __restrict__ bin,
+                                                           int nbins, int64_t* __restrict__ counts) {
+  __shared__ int part[4];
+  const int64_t b = blockIdx.x;
+  const uint8_t* rr = ref + b * ref_stride;
+  const uint8_t* hh = hat + b * k;
+  int err = 0;
+  for (int64_t i = threadIdx.x; i < k; i += blockDim.x) err += (rr[i] & 1) != (hh[i] & 1);
+  for (int off = 32; off > 0; off >>= 1) err += __shfl_down(err, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = err;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += part[w];
+    const int bb = bin ? bin[b] : 0;
+    if (bb < 0 || bb >= nbins) return;  // codewords outside every bin are not counted
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counts) + 3 * (int64_t)bb;
+    atomicAdd(cnt + 0, (unsigned long long)tot);
+    atomicAdd(cnt + 1, (unsigned long long)(tot > 0));
+    atomicAdd(cnt + 2, 1ull);
+  }
+}
+
+__global__ __launch_bounds__(256) void syndrome_kernel(DevCode c, const uint8_t* __restrict__ cw,
+                                                       int64_t stride, int32_t* __restrict__ unsat) {
+  __shared__ int part[4];
+  const int64_t b = blockIdx.x;
+  const uint8_t* x = cw + b * stride;
+  const int Z = c.Z;
+  int bad = 0;
+  for (int chk = threadIdx.x; chk < c.m_dec; chk += blockDim.x) {
+    const int i = chk / Z, r = chk - i * Z;
+    uint8_t acc = 0;
+    for (int e = c.row_ptr[i]; e < c.row_ptr[i + 1]; ++e) {
+      int v = r + c.ent_shift[e];
+      v -= v >= Z ? Z : 0;
+      acc ^= x[c.ent_col[e] * Z + v] & 1;
+    }
+    bad += acc;
+  }
+  for (int off = 32; off > 0; off >>= 1) bad += __shfl_down(bad, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = bad;
+  __syncthreads();
+  if (threadIdx.x == 0) unsat[b] = part[0] + part[1] + part[2] + part[3];
+}
+
+inline unsigned grid_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_source_bits(uint64_t seed, int64_t cw0, int64_t B, int64_t k, uint8_t* u,
+                              hipStream_t s) {
+  const int64_t wpc = (k + 31) / 32;
+  source_bits_kernel<<<grid_for(B * wpc, 256), 256, 0, s>>>(seed, cw0, B, k, wpc, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode(const DevCode& c, const uint8_t* u, int64_t B, uint8_t* cw,
+                         hipStream_t s) {
+  const int m = c.family == LSIM_FAMILY_11N ? c.mb : 4;
+  const size_t lds = (size_t)c.n_mother + (size_t)m * c.Z;
+  encode_kernel<<<(unsigned)B, 256, lds, s>>>(c, u, cw);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_awgn(const DevCode& c, int m, const uint8_t* cw, const float* no,
+                           uint64_t seed, int64_t cw0, int64_t B, float* y, hipStream_t s) {
+  const int S = c.e_tx / m;
+  const int64_t n = B * ((S + 1) / 2);
+  map_awgn_kernel<<<grid_for(n, 256), 256, 0, s>>>(c, m, cw, no, seed, cw0, B, S, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_demap(int m, int method, const float* y, const float* no, int64_t B, int64_t S,
+                        float* llr, int8_t* q, float scale, int sat, hipStream_t s) {
+  demap_kernel<<<grid_for(B * S, 256), 256, 0, s>>>(m, method, y, no, B, S, llr, q, scale, sat);
+  return hipGetLastError();
+}
+
+hipError_t launch_quantize(const float* llr, int64_t n, float scale, int sat, int8_t* q,
+                           hipStream_t s) {
+  quantize_kernel<<<grid_for(n, 256), 256, 0, s>>>(llr, n, scale, sat, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_errors(const uint8_t* ref, int64_t ref_stride, const uint8_t* hat,
+                               int64_t B, int64_t k, const int32_t* bin, int nbins,
+                               int64_t* counts, hipStream_t s) {
+  count_errors_kernel<<<(unsigned)B, 256, 0, s>>>(ref, ref_stride, hat, k, bin, nbins, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_syndrome(const DevCode& c, const uint8_t* cw, int64_t stride, int64_t B,
+                           int32_t* unsat, hipStream_t s) {
+  syndrome_kernel<<<(unsigned)B, 256, 0, s>>>(c, cw, stride, unsat);
+  return hipGetLastError();
+}
+
+}  // namespace lsim

@@ -1,0 +1,112 @@
+// Internal declarations shared by the host API (api.cpp) and the kernel
+// translation units.  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lsim.h"
+
+namespace lsim {
+
+// Device view of a code: the decoded Tanner graph plus encoder tables.  All
+// pointers are device memory owned by the lsim_code.
+struct DevCode {
+  int Z, mb, nb, kb, rows, cols, nnz, E, n_dec, m_dec, k, n_mother, tx_lo, e_tx, family;
+  int max_row_deg, max_col_deg, n_cn_tasks, n_vn_tasks;
+  const int* row_ptr;    // rows+1; entries of base row i: row_ptr[i]..row_ptr[i+1]-1 (row-major)
+  const int* ent_col;    // nnz
+  const int* ent_shift;  // nnz
+  const int* col_ptr;    // cols+1
+  const int* col_ent;    // entry ids of each column, rows ascending
+  const int* cn_tasks;   // (row << 16) | lift0, heaviest first
+  const int* vn_tasks;   // (col << 16) | lift0, heaviest first
+  const int16_t* base;   // full mb x nb base matrix (encoder)
+};
+
+}  // namespace lsim
+
+struct lsim_code {
+  lsim::DevCode dev;
+  lsim_code_info info;
+  std::vector<int16_t> base;
+  std::vector<int> row_ptr, ent_col, ent_shift, col_ptr, col_ent;
+  void* dmem = nullptr;
+  int device = 0;
+};
+
+namespace lsim {
+
+void set_error(const std::string& msg);
+
+// Flooding decoders (k_flood.hip)
+hipError_t launch_flood(const DevCode& c, const lsim_decode_params& p, const void* llr, int64_t B,
+                        uint8_t* bits, float* lpost, const void* q_in, void* r_out, void* q_out,
+                        hipStream_t s, std::string* why);
+size_t flood_lds_bytes(const DevCode& c, int algo);
+
+// Layered decoder and mixed batches (k_layered.hip)
+struct LayerShape {
+  DevCode code;
+  int G;               // codewords per tile
+  int64_t count;       // codewords of this shape
+  int64_t tile0;       // first global tile index of this shape
+  int64_t llr_off;     // offset (elements) of the shape's LLRs in the concatenated input
+  int64_t bits_off;    // offset of the shape's bits
+  int64_t app_off;     // offset of the shape's posteriors
+  int64_t state_off;   // offset (in 32-bit words) of the shape's check state
+};
+size_t layered_state_words(const DevCode& c, int64_t B);
+size_t layered_tile_lds(const DevCode& c, int G);
+hipError_t launch_layered(const DevCode& c, const lsim_decode_params& p, const float* llr,
+                          int64_t B, uint8_t* bits, float* lpost, float* r_out, uint32_t* state,
+                          hipStream_t s, std::string* why);
+hipError_t launch_mixed(const LayerShape* d_shapes, int nshapes, const int* d_tile_shape,
+                        const int64_t* d_tile_local, int64_t ntiles, int threads,
+                        size_t lds_bytes, const lsim_decode_params& p, const void* llr,
+                        uint8_t* bits, float* lpost, uint32_t* state, int* counter,
+                        int persistent, int grid, hipStream_t s);
+
+// Pipeline kernels (k_pipeline.hip)
+hipError_t launch_source_bits(uint64_t seed, int64_t cw0, int64_t B, int64_t k, uint8_t* u,
+                              hipStream_t s);
+hipError_t launch_encode(const DevCode& c, const uint8_t* u, int64_t B, uint8_t* cw,
+                         hipStream_t s);
+hipError_t launch_map_awgn(const DevCode& c, int m, const uint8_t* cw, const float* no,
+                           uint64_t seed, int64_t cw0, int64_t B, float* y, hipStream_t s);
+hipError_t launch_demap(int m, int method, const float* y, const float* no, int64_t B, int64_t S,
+                        float* llr, int8_t* q, float scale, int sat, hipStream_t s);
+hipError_t launch_quantize(const float* llr, int64_t n, float scale, int sat, int8_t* q,
+                           hipStream_t s);
+hipError_t launch_count_errors(const uint8_t* ref, int64_t ref_stride, const uint8_t* hat,
+                               int64_t B, int64_t k, const int32_t* bin, int nbins,
+                               int64_t* counts, hipStream_t s);
+hipError_t launch_syndrome(const DevCode& c, const uint8_t* cw, int64_t stride, int64_t B,
+                           int32_t* unsat, hipStream_t s);
+
+// Differentiable forms (k_wbp.hip, k_ndm.hip)
+size_t wbp_work_bytes(const DevCode& c, int T, int64_t B);
+hipError_t launch_wbp_forward(const DevCode& c, int T, const float* w, const float* llr,
+                              int64_t B, float llr_max, float* ckpt, float* lpost, hipStream_t s,
+                              std::string* why);
+hipError_t launch_wbp_backward(const DevCode& c, int T, const float* w, const float* llr,
+                               const float* ckpt, int64_t B, float llr_max, const float* gpost,
+                               float* gllr, float* gw, void* work, hipStream_t s,
+                               std::string* why);
+size_t ndm_work_bytes(int64_t B, int64_t S);
+hipError_t launch_ndm_forward(const float* params, const float* y, const float* no, int64_t B,
+                              int64_t S, float* llr, hipStream_t s);
+hipError_t launch_ndm_backward(const float* params, const float* y, const float* no,
+                               const float* gllr, int64_t B, int64_t S, float* gparams,
+                               void* work, hipStream_t s);
+size_t bce_work_bytes(int64_t B, int64_t n);
+hipError_t launch_bce_grad(const float* lpost, const uint8_t* c, int64_t c_stride, int64_t B,
+                           int64_t n, float scale, float* g, float* loss, void* work,
+                           hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                       float b1, float b2, float eps, int step, hipStream_t s);
+
+}  // namespace lsim

@@ -1,0 +1,136 @@
+"""GPU decoder parity against the oracle.
+
+int8 offset min-sum: bit-exact r and q after every round, posteriors, hard
+decisions.  Layered normalized min-sum (FP32): bit-exact (float equality)
+against the oracle's single-precision mode.  FP32 sum-product: one round
+from the same state (oracle state, cast to float32) within 1e-4 relative,
+and after 20 rounds on every frame the oracle decodes to a codeword.
+Inputs are LLRs of the oracle's own link at a waterfall Eb/N0, so every
+regime (saturated, weak, punctured) is exercised.
+"""
+import numpy as np
+import pytest
+import torch
+
+from helpers import graph, oracle_llrs, rel_close
+from oracle import decoders as D
+from oracle import modem, qc
+
+pytestmark = pytest.mark.gpu
+
+lsim = pytest.importorskip("paper_2203_11854_amd")
+dev = "cuda"
+
+
+def gcode(name):
+    qb, g = graph(name)
+    return qb, g, lsim.Code.from_qcbase(qb, g.e_tx)
+
+
+def q8_inputs(name, B, ebn0, seed):
+    tx = oracle_llrs(name, B, ebn0, seed)
+    return tx, modem.quantize(tx["L"].astype(np.float32))
+
+
+@pytest.mark.parametrize("name,B,ebn0", [("bg2", 37, 3.0), ("small", 29, 1.5)])
+def test_oms_bit_exact_every_round(name, B, ebn0):
+    qb, g, code = gcode(name)
+    tx, q = q8_inputs(name, B, ebn0, 41)
+    lam = D.channel_lam(g, q, np.int64)
+    app, rs, qs = D.oms_flood(g, lam, 20, offset=1, sat=31, trace=True)
+    tq = torch.from_numpy(q).to(dev)
+    for t in (1, 2, 3, 7, 20):
+        p = lsim.params(lsim.OMS_I8, iters=t, offset=1, sat=31)
+        r, qq, lp = lsim.decode_state(code, tq, p)
+        assert np.array_equal(r.cpu().numpy(), rs[t - 1]), t
+        assert np.array_equal(qq.cpu().numpy(), qs[t - 1]), t
+    p = lsim.params(lsim.OMS_I8, iters=20, offset=1, sat=31)
+    bits, lpost = lsim.decode(code, tq, p, want_app=True)
+    assert np.array_equal(lpost.cpu().numpy(), -app)
+    assert np.array_equal(bits.cpu().numpy(), D.hard_bits(app, g.k))
+
+
+@pytest.mark.parametrize("name,B,ebn0", [("bg2", 23, 3.0), ("small", 17, 1.5), ("bg1", 3, 2.5)])
+def test_nms_layered_bit_exact(name, B, ebn0):
+    qb, g, code = gcode(name)
+    tx = oracle_llrs(name, B, ebn0, 43)
+    L32 = tx["L"].astype(np.float32)
+    lam = D.channel_lam(g, L32, dtype=np.float32)
+    app, hist = D.nms_layered(g, lam, 20, alpha=0.75, mode="fp32", trace=True)
+    tl = torch.from_numpy(L32).to(dev)
+    for t in (1, 2, 20):
+        p = lsim.params(lsim.NMS_F32, iters=t, alpha=0.75)
+        r, _, lp = lsim.decode_state(code, tl, p)
+        assert np.array_equal(r.cpu().numpy(), hist[t - 1][0]), t
+        assert np.array_equal(lp.cpu().numpy(), -hist[t - 1][1]), t
+    bits, _ = lsim.decode(code, tl, lsim.params(lsim.NMS_F32, iters=20, alpha=0.75))
+    assert np.array_equal(bits.cpu().numpy(), D.hard_bits(app, g.k))
+
+
+@pytest.mark.parametrize("name,B,ebn0", [("bg2", 21, 3.0), ("small", 17, 1.5)])
+def test_spa_one_round_from_oracle_state(name, B, ebn0):
+    qb, g, code = gcode(name)
+    tx = oracle_llrs(name, B, ebn0, 47)
+    L32 = tx["L"].astype(np.float32)
+    lam = np.clip(D.channel_lam(g, L32.astype(np.float64)), -20, 20)
+    _, rs, qs = D.spa_flood(g, lam, 19, trace=True)
+    tl = torch.from_numpy(L32).to(dev)
+    states = [lam[:, g.edge_vn()]] + [qs[t] for t in (0, 4, 9, 18)]
+    p = lsim.params(lsim.SPA_F32, iters=1, llr_max=20.0)
+    worst = 0.0
+    for q0 in states:
+        q32 = q0.astype(np.float32)
+        r_ref, app_ref, q_ref = D.spa_iteration(g, lam, q32.astype(np.float64))
+        r, qq, lp = lsim.decode_state(code, tl, p, q_in=torch.from_numpy(q32).to(dev))
+        for got, ref in ((r, r_ref), (qq, q_ref), (lp, -app_ref)):
+            ok, w = rel_close(got.cpu().numpy(), ref, 1e-4)
+            worst = max(worst, w)
+            assert ok, w
+    print("worst relative error", worst)
+
+
+@pytest.mark.parametrize("name,B,ebn0", [("bg2", 64, 3.5), ("small", 64, 2.0)])
+def test_spa_end_to_end_on_converged_frames(name, B, ebn0):
+    qb, g, code = gcode(name)
+    tx = oracle_llrs(name, B, ebn0, 53)
+    L32 = tx["L"].astype(np.float32)
+    app = D.spa_flood(g, D.channel_lam(g, L32.astype(np.float64)), 20)
+    hard = (app < 0).astype(np.uint8)
+    conv = ~qc.syndrome(qb.base[:g.rows, :g.cols], qb.Z, hard).any(axis=1)
+    assert conv.sum() >= B // 4
+    bits, lp = lsim.decode(code, torch.from_numpy(L32).to(dev),
+                           lsim.params(lsim.SPA_F32, iters=20), want_app=True)
+    bits, lp = bits.cpu().numpy(), lp.cpu().numpy()
+    ok, w = rel_close(lp[conv], -app[conv], 1e-4)
+    assert ok, w
+    assert np.array_equal(bits[conv], D.hard_bits(app, g.k)[conv])
+
+
+@pytest.mark.parametrize("algo", ["spa", "oms", "nms"])
+def test_deterministic(algo):
+    qb, g, code = gcode("bg2")
+    tx = oracle_llrs("bg2", 40, 3.0, 59)
+    if algo == "oms":
+        llr = torch.from_numpy(modem.quantize(tx["L"].astype(np.float32))).to(dev)
+        p = lsim.params(lsim.OMS_I8)
+    else:
+        llr = torch.from_numpy(tx["L"].astype(np.float32)).to(dev)
+        p = lsim.params(lsim.SPA_F32 if algo == "spa" else lsim.NMS_F32)
+    a = lsim.decode(code, llr, p, want_app=True)[1]
+    b = lsim.decode(code, llr, p, want_app=True)[1]
+    assert torch.equal(a, b)
+
+
+def test_workgroup_size_invariance():
+    qb, g, code = gcode("bg2")
+    tx = oracle_llrs("bg2", 16, 3.0, 61)
+    llr = torch.from_numpy(tx["L"].astype(np.float32)).to(dev)
+    q8 = torch.from_numpy(modem.quantize(tx["L"].astype(np.float32))).to(dev)
+    for algo, x in ((lsim.SPA_F32, llr), (lsim.OMS_I8, q8)):
+        outs = [lsim.decode(code, x, lsim.params(algo, threads=t), want_app=True)[1]
+                for t in (256, 512, 1024)]
+        assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    outs = [lsim.decode(code, llr, lsim.params(lsim.NMS_F32, threads=t), want_app=True)[1]
+            for t in (256, 384, 512, 1024)]
+    for o in outs[1:]:
+        assert torch.equal(outs[0], o)

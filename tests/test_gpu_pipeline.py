@@ -1,0 +1,142 @@
+"""GPU parity of the link kernels against the oracle (bit-exact for bits,
+codewords, quantized LLRs and counts; float tolerances derived from FP32
+rounding for the noise and the demapper)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import CODES, graph, rel_close
+from inputs import rand
+from inputs.workloads import mixed_specs
+from oracle import modem, philox, qc, stats
+
+pytestmark = pytest.mark.gpu
+
+lsim = pytest.importorskip("paper_2203_11854_amd")
+dev = "cuda"
+
+
+def code_for(name):
+    spec, e_tx, m = CODES[name]
+    qb = spec.load()
+    return qb, lsim.Code.from_qcbase(qb, e_tx), m
+
+
+@pytest.mark.parametrize("k,cw0", [(300, 3), (1280, 0), (8448, 2 ** 32 + 5), (5, 7)])
+def test_source_bits_exact(k, cw0):
+    seed = 0x2203118500000102
+    u = lsim.source_bits(seed, cw0, 37, k, dev).cpu().numpy()
+    assert np.array_equal(u, philox.source_bits(seed, cw0, 37, k))
+
+
+@pytest.mark.parametrize("name", ["small", "bg2", "bg1"])
+def test_encode_exact(name):
+    qb, code, _ = code_for(name)
+    B = 19
+    u = philox.source_bits(5, 0, B, qb.k)
+    c = lsim.encode(code, torch.from_numpy(u).to(dev)).cpu().numpy()
+    ref = qc.encode(qb.base, qb.kb, qb.Z, qb.family, u)
+    assert np.array_equal(c, ref)
+
+
+def test_encode_mixed_shapes_exact():
+    for spec, e_tx in mixed_specs():
+        qb = spec.load()
+        code = lsim.Code.from_qcbase(qb, e_tx)
+        u = philox.source_bits(6, 0, 5, qb.k)
+        c = lsim.encode(code, torch.from_numpy(u).to(dev)).cpu().numpy()
+        assert np.array_equal(c, qc.encode(qb.base, qb.kb, qb.Z, qb.family, u)), spec.name
+
+
+@pytest.mark.parametrize("name,m", [("small", 1), ("bg2", 2), ("bg2", 4), ("bg1", 6)])
+def test_map_awgn_vs_oracle(name, m):
+    qb, code, _ = code_for(name)
+    g = qc.graph_from_qcbase(qb, code.e_tx)
+    B = 9
+    seed, cw0 = 1234, 11
+    u = philox.source_bits(seed, cw0, B, qb.k)
+    c = qc.encode(qb.base, qb.kb, qb.Z, qb.family, u)
+    n0 = rand.uniform(3, B, 0.1, 1.5).astype(np.float32)
+    y = lsim.map_awgn(code, m, torch.from_numpy(c).to(dev), torch.from_numpy(n0).to(dev),
+                      seed, cw0).cpu().numpy()
+    t = c[:, g.tx_lo:g.tx_lo + g.e_tx]
+    x = modem.map_bits(t, m)
+    ref = modem.awgn(x, n0.astype(np.float64), philox.normals(seed, cw0, B, x.shape[1]))
+    got = y[..., 0] + 1j * y[..., 1]
+    # |dg| <= 1e-5 on the unit normals, scaled by sqrt(N0/2)
+    err = np.abs(got - ref) / np.sqrt(n0[:, None] / 2)
+    assert err.max() < 1e-5
+
+
+@pytest.mark.parametrize("m", [1, 2, 4, 6])
+@pytest.mark.parametrize("method", [lsim.DEMAP_EXACT, lsim.DEMAP_MAXLOG])
+def test_demap_vs_bruteforce(m, method):
+    B, S = 13, 257
+    y = (1.3 * (rand.gaussian(m, (B, S)) + 1j * rand.gaussian(m + 10, (B, S)))).astype(np.complex64)
+    n0 = rand.uniform(m + 20, B, 0.05, 2.0).astype(np.float32)
+    yy = np.stack([y.real, y.imag], axis=-1).astype(np.float32)
+    L = lsim.demap(m, method, torch.from_numpy(yy).to(dev), torch.from_numpy(n0).to(dev)).cpu().numpy()
+    y64 = y.astype(np.complex128)
+    n64 = n0.astype(np.float64)
+    if m == 1:
+        ref = modem.demap_bpsk(y64, n64)
+    else:
+        ref = modem.demap_bruteforce(y64, n64, m, "exact" if method == lsim.DEMAP_EXACT else "maxlog")
+    # FP32 rounding of the squared distances |y - x|^2 / N0 bounds the error
+    scale = (np.abs(y64) + 2.0) ** 2 / n64[:, None]
+    tol = 1e-5 * np.maximum(1.0, np.abs(ref)) + 2e-6 * np.repeat(scale, m, axis=1)
+    assert (np.abs(L - ref) <= tol).all(), float((np.abs(L - ref) / tol).max())
+
+
+def test_quantize_exact():
+    L = np.concatenate([rand.gaussian(1, 5000, scale=20.0),
+                        np.arange(-40, 40) * 0.25, [0.0, -0.0, 1e30, -1e30]]).astype(np.float32)
+    q = lsim.quantize(torch.from_numpy(L).to(dev)).cpu().numpy()
+    assert np.array_equal(q, modem.quantize(L))
+
+
+def test_demap_q8_is_quantized_demap():
+    B, S = 7, 301
+    yy = rand.gaussian(3, (B, S, 2)).astype(np.float32)
+    n0 = rand.uniform(4, B, 0.1, 1.0).astype(np.float32)
+    ty, tn = torch.from_numpy(yy).to(dev), torch.from_numpy(n0).to(dev)
+    q = lsim.demap_q8(4, lsim.DEMAP_MAXLOG, ty, tn).cpu().numpy()
+    L = lsim.demap(4, lsim.DEMAP_MAXLOG, ty, tn).cpu().numpy()
+    assert np.array_equal(q, modem.quantize(L))
+
+
+def test_count_errors_exact():
+    B, k = 301, 133
+    u = rand.bits(1, (B, k))
+    h = u.copy()
+    r = rand.rng(2)
+    flips = r.random((B, k)) < 0.01
+    h[flips] ^= 1
+    bins = r.integers(0, 5, B).astype(np.int32)
+    cnt = lsim.count_errors(torch.from_numpy(u).to(dev), torch.from_numpy(h).to(dev),
+                            torch.from_numpy(bins).to(dev), 5).cpu().numpy()
+    assert np.array_equal(cnt, stats.count_errors(u, h, bins, 5))
+
+
+def test_syndrome_exact():
+    qb, code, _ = code_for("bg2")
+    g = qc.graph_from_qcbase(qb, code.e_tx)
+    u = philox.source_bits(8, 0, 6, qb.k)
+    c = qc.encode(qb.base, qb.kb, qb.Z, qb.family, u)[:, :g.n_dec].copy()
+    c[1, 5] ^= 1
+    c[2, 100:110] ^= 1
+    got = lsim.syndrome(code, torch.from_numpy(c).to(dev)).cpu().numpy()
+    ref = qc.syndrome(qb.base[:g.rows, :g.cols], qb.Z, c).sum(axis=1)
+    assert np.array_equal(got, ref)
+    assert got[0] == 0 and got[1] > 0
+
+
+def test_invalid_arguments_raise():
+    qb, code, _ = code_for("bg2")
+    with pytest.raises(lsim.LsimError):
+        lsim.map_awgn(code, 3, torch.zeros((1, code.n_mother), dtype=torch.uint8, device=dev),
+                      torch.ones(1, device=dev), 1, 0)
+    with pytest.raises(lsim.LsimError):
+        lsim.quantize(torch.zeros(4, device=dev), scale=3.0)
