@@ -52,6 +52,8 @@ bool check_family(const std::vector<int16_t>& H, int mb, int nb, int family, std
     for (int j = kb; j < nb; ++j) {
       int want = -1;
       const int pj = j - kb;
+      // extension rows of the BG shape may touch the core parity columns
+      if (family == LSIM_FAMILY_BG && i >= 4 && pj < 4) continue;
       if (pj == 0) {
         if (i == 0 || i == m - 1) want = 1;
         else if (i == mid) want = 0;

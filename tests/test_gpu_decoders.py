@@ -22,6 +22,11 @@ lsim = pytest.importorskip("paper_2203_11854_amd")
 dev = "cuda"
 
 
+def T(x):
+    """Host array -> contiguous host tensor (moved to the device by the caller)."""
+    return torch.from_numpy(np.ascontiguousarray(x))
+
+
 def gcode(name):
     qb, g = graph(name)
     return qb, g, lsim.Code.from_qcbase(qb, g.e_tx)
@@ -38,7 +43,7 @@ def test_oms_bit_exact_every_round(name, B, ebn0):
     tx, q = q8_inputs(name, B, ebn0, 41)
     lam = D.channel_lam(g, q, np.int64)
     app, rs, qs = D.oms_flood(g, lam, 20, offset=1, sat=31, trace=True)
-    tq = torch.from_numpy(q).to(dev)
+    tq = T(q).to(dev)
     for t in (1, 2, 3, 7, 20):
         p = lsim.params(lsim.OMS_I8, iters=t, offset=1, sat=31)
         r, qq, lp = lsim.decode_state(code, tq, p)
@@ -57,7 +62,7 @@ def test_nms_layered_bit_exact(name, B, ebn0):
     L32 = tx["L"].astype(np.float32)
     lam = D.channel_lam(g, L32, dtype=np.float32)
     app, hist = D.nms_layered(g, lam, 20, alpha=0.75, mode="fp32", trace=True)
-    tl = torch.from_numpy(L32).to(dev)
+    tl = T(L32).to(dev)
     for t in (1, 2, 20):
         p = lsim.params(lsim.NMS_F32, iters=t, alpha=0.75)
         r, _, lp = lsim.decode_state(code, tl, p)
@@ -74,14 +79,14 @@ def test_spa_one_round_from_oracle_state(name, B, ebn0):
     L32 = tx["L"].astype(np.float32)
     lam = np.clip(D.channel_lam(g, L32.astype(np.float64)), -20, 20)
     _, rs, qs = D.spa_flood(g, lam, 19, trace=True)
-    tl = torch.from_numpy(L32).to(dev)
+    tl = T(L32).to(dev)
     states = [lam[:, g.edge_vn()]] + [qs[t] for t in (0, 4, 9, 18)]
     p = lsim.params(lsim.SPA_F32, iters=1, llr_max=20.0)
     worst = 0.0
     for q0 in states:
         q32 = q0.astype(np.float32)
         r_ref, app_ref, q_ref = D.spa_iteration(g, lam, q32.astype(np.float64))
-        r, qq, lp = lsim.decode_state(code, tl, p, q_in=torch.from_numpy(q32).to(dev))
+        r, qq, lp = lsim.decode_state(code, tl, p, q_in=T(q32).to(dev))
         for got, ref in ((r, r_ref), (qq, q_ref), (lp, -app_ref)):
             ok, w = rel_close(got.cpu().numpy(), ref, 1e-4)
             worst = max(worst, w)
@@ -98,7 +103,7 @@ def test_spa_end_to_end_on_converged_frames(name, B, ebn0):
     hard = (app < 0).astype(np.uint8)
     conv = ~qc.syndrome(qb.base[:g.rows, :g.cols], qb.Z, hard).any(axis=1)
     assert conv.sum() >= B // 4
-    bits, lp = lsim.decode(code, torch.from_numpy(L32).to(dev),
+    bits, lp = lsim.decode(code, T(L32).to(dev),
                            lsim.params(lsim.SPA_F32, iters=20), want_app=True)
     bits, lp = bits.cpu().numpy(), lp.cpu().numpy()
     ok, w = rel_close(lp[conv], -app[conv], 1e-4)
@@ -111,10 +116,10 @@ def test_deterministic(algo):
     qb, g, code = gcode("bg2")
     tx = oracle_llrs("bg2", 40, 3.0, 59)
     if algo == "oms":
-        llr = torch.from_numpy(modem.quantize(tx["L"].astype(np.float32))).to(dev)
+        llr = T(modem.quantize(tx["L"].astype(np.float32))).to(dev)
         p = lsim.params(lsim.OMS_I8)
     else:
-        llr = torch.from_numpy(tx["L"].astype(np.float32)).to(dev)
+        llr = T(tx["L"].astype(np.float32)).to(dev)
         p = lsim.params(lsim.SPA_F32 if algo == "spa" else lsim.NMS_F32)
     a = lsim.decode(code, llr, p, want_app=True)[1]
     b = lsim.decode(code, llr, p, want_app=True)[1]
@@ -124,8 +129,8 @@ def test_deterministic(algo):
 def test_workgroup_size_invariance():
     qb, g, code = gcode("bg2")
     tx = oracle_llrs("bg2", 16, 3.0, 61)
-    llr = torch.from_numpy(tx["L"].astype(np.float32)).to(dev)
-    q8 = torch.from_numpy(modem.quantize(tx["L"].astype(np.float32))).to(dev)
+    llr = T(tx["L"].astype(np.float32)).to(dev)
+    q8 = T(modem.quantize(tx["L"].astype(np.float32))).to(dev)
     for algo, x in ((lsim.SPA_F32, llr), (lsim.OMS_I8, q8)):
         outs = [lsim.decode(code, x, lsim.params(algo, threads=t), want_app=True)[1]
                 for t in (256, 512, 1024)]

@@ -18,6 +18,11 @@ lsim = pytest.importorskip("paper_2203_11854_amd")
 dev = "cuda"
 
 
+def T(x):
+    """Host array -> contiguous host tensor (moved to the device by the caller)."""
+    return torch.from_numpy(np.ascontiguousarray(x))
+
+
 def code_for(name):
     spec, e_tx, m = CODES[name]
     qb = spec.load()
@@ -36,7 +41,7 @@ def test_encode_exact(name):
     qb, code, _ = code_for(name)
     B = 19
     u = philox.source_bits(5, 0, B, qb.k)
-    c = lsim.encode(code, torch.from_numpy(u).to(dev)).cpu().numpy()
+    c = lsim.encode(code, T(u).to(dev)).cpu().numpy()
     ref = qc.encode(qb.base, qb.kb, qb.Z, qb.family, u)
     assert np.array_equal(c, ref)
 
@@ -46,7 +51,7 @@ def test_encode_mixed_shapes_exact():
         qb = spec.load()
         code = lsim.Code.from_qcbase(qb, e_tx)
         u = philox.source_bits(6, 0, 5, qb.k)
-        c = lsim.encode(code, torch.from_numpy(u).to(dev)).cpu().numpy()
+        c = lsim.encode(code, T(u).to(dev)).cpu().numpy()
         assert np.array_equal(c, qc.encode(qb.base, qb.kb, qb.Z, qb.family, u)), spec.name
 
 
@@ -59,7 +64,7 @@ def test_map_awgn_vs_oracle(name, m):
     u = philox.source_bits(seed, cw0, B, qb.k)
     c = qc.encode(qb.base, qb.kb, qb.Z, qb.family, u)
     n0 = rand.uniform(3, B, 0.1, 1.5).astype(np.float32)
-    y = lsim.map_awgn(code, m, torch.from_numpy(c).to(dev), torch.from_numpy(n0).to(dev),
+    y = lsim.map_awgn(code, m, T(c).to(dev), T(n0).to(dev),
                       seed, cw0).cpu().numpy()
     t = c[:, g.tx_lo:g.tx_lo + g.e_tx]
     x = modem.map_bits(t, m)
@@ -77,7 +82,7 @@ def test_demap_vs_bruteforce(m, method):
     y = (1.3 * (rand.gaussian(m, (B, S)) + 1j * rand.gaussian(m + 10, (B, S)))).astype(np.complex64)
     n0 = rand.uniform(m + 20, B, 0.05, 2.0).astype(np.float32)
     yy = np.stack([y.real, y.imag], axis=-1).astype(np.float32)
-    L = lsim.demap(m, method, torch.from_numpy(yy).to(dev), torch.from_numpy(n0).to(dev)).cpu().numpy()
+    L = lsim.demap(m, method, T(yy).to(dev), T(n0).to(dev)).cpu().numpy()
     y64 = y.astype(np.complex128)
     n64 = n0.astype(np.float64)
     if m == 1:
@@ -93,7 +98,7 @@ def test_demap_vs_bruteforce(m, method):
 def test_quantize_exact():
     L = np.concatenate([rand.gaussian(1, 5000, scale=20.0),
                         np.arange(-40, 40) * 0.25, [0.0, -0.0, 1e30, -1e30]]).astype(np.float32)
-    q = lsim.quantize(torch.from_numpy(L).to(dev)).cpu().numpy()
+    q = lsim.quantize(T(L).to(dev)).cpu().numpy()
     assert np.array_equal(q, modem.quantize(L))
 
 
@@ -101,7 +106,7 @@ def test_demap_q8_is_quantized_demap():
     B, S = 7, 301
     yy = rand.gaussian(3, (B, S, 2)).astype(np.float32)
     n0 = rand.uniform(4, B, 0.1, 1.0).astype(np.float32)
-    ty, tn = torch.from_numpy(yy).to(dev), torch.from_numpy(n0).to(dev)
+    ty, tn = T(yy).to(dev), T(n0).to(dev)
     q = lsim.demap_q8(4, lsim.DEMAP_MAXLOG, ty, tn).cpu().numpy()
     L = lsim.demap(4, lsim.DEMAP_MAXLOG, ty, tn).cpu().numpy()
     assert np.array_equal(q, modem.quantize(L))
@@ -115,8 +120,8 @@ def test_count_errors_exact():
     flips = r.random((B, k)) < 0.01
     h[flips] ^= 1
     bins = r.integers(0, 5, B).astype(np.int32)
-    cnt = lsim.count_errors(torch.from_numpy(u).to(dev), torch.from_numpy(h).to(dev),
-                            torch.from_numpy(bins).to(dev), 5).cpu().numpy()
+    cnt = lsim.count_errors(T(u).to(dev), T(h).to(dev),
+                            T(bins).to(dev), 5).cpu().numpy()
     assert np.array_equal(cnt, stats.count_errors(u, h, bins, 5))
 
 
@@ -127,7 +132,7 @@ def test_syndrome_exact():
     c = qc.encode(qb.base, qb.kb, qb.Z, qb.family, u)[:, :g.n_dec].copy()
     c[1, 5] ^= 1
     c[2, 100:110] ^= 1
-    got = lsim.syndrome(code, torch.from_numpy(c).to(dev)).cpu().numpy()
+    got = lsim.syndrome(code, T(c).to(dev)).cpu().numpy()
     ref = qc.syndrome(qb.base[:g.rows, :g.cols], qb.Z, c).sum(axis=1)
     assert np.array_equal(got, ref)
     assert got[0] == 0 and got[1] > 0
