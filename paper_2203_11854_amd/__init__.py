@@ -290,3 +290,176 @@ def ebn0_to_n0(ebn0_db, rate: float, m: int):
     """N0 = 1 / (R m 10^(EbN0/10)) for unit-energy symbols (host helper)."""
     import numpy as np
     return 1.0 / (rate * m * 10.0 ** (np.asarray(ebn0_db, dtype=np.float64) / 10.0))
+
+
+# ----------------------------------------------------------- mixed batches
+
+class MixedPlan:
+    """Persistent decode of several codes in one launch (lsim_mixed_plan_*).
+
+    LLRs, bits and posteriors are concatenated by shape in the order of
+    ``codes``."""
+
+    def __init__(self, codes, counts, p: DecodeParams, codewords_per_tile=None, threads: int = 0):
+        n = len(codes)
+        self.codes = list(codes)          # keep the codes alive as long as the plan
+        self.counts = [int(x) for x in counts]
+        arr = (ctypes.c_void_p * n)(*[c.handle.value for c in codes])
+        cnt = (ctypes.c_int64 * n)(*self.counts)
+        cpt = None if codewords_per_tile is None else (ctypes.c_int32 * n)(*codewords_per_tile)
+        h = ctypes.c_void_p()
+        self.p = p
+        _call("lsim_mixed_plan_create", ctypes.cast(arr, ctypes.c_void_p),
+              ctypes.cast(cnt, ctypes.c_void_p), n, ctypes.byref(p),
+              None if cpt is None else ctypes.cast(cpt, ctypes.c_void_p), threads, ctypes.byref(h))
+        self._h = h
+        nb = ctypes.c_size_t()
+        _call("lsim_mixed_workspace", h, ctypes.byref(nb))
+        self.work_bytes = nb.value
+        self.llr_offsets, self.bits_offsets, self.app_offsets = [], [], []
+        lo = bo = ao = 0
+        for c, k in zip(codes, self.counts):
+            self.llr_offsets.append(lo)
+            self.bits_offsets.append(bo)
+            self.app_offsets.append(ao)
+            lo += k * c.e_tx
+            bo += k * c.k
+            ao += k * c.n_dec
+        self.n_llr, self.n_bits, self.n_app = lo, bo, ao
+
+    def workspace(self, device="cuda"):
+        return torch.empty(self.work_bytes, dtype=torch.uint8, device=device)
+
+    def decode(self, llr, bits=None, app=None, work=None, persistent=True):
+        if llr.numel() != self.n_llr:
+            raise LsimError("concatenated LLRs have the wrong length")
+        if work is None:
+            work = self.workspace(llr.device)
+        _call("lsim_mixed_decode", self._h, _ptr(llr, torch.float32, "llr"),
+              _ptr(bits, torch.uint8, "bits"), _ptr(app, torch.float32, "app"),
+              _ptr(work, None, "work"), work.numel(), 1 if persistent else 0, _stream())
+        return bits, app
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.lsim_mixed_plan_destroy(h)
+            self._h = None
+
+
+# ----------------------------------------------------- differentiable forms
+
+def wbp_forward(code: Code, w, llr, T: int, llr_max: float = 20.0, ckpt=None, lpost=None,
+                want_ckpt: bool = True):
+    """Weighted BP forward: L_post f32[B][n_dec] and checkpoints f32[T][B][E]."""
+    B = llr.shape[0]
+    if lpost is None:
+        lpost = _empty((B, code.n_dec), torch.float32, llr.device)
+    if want_ckpt and ckpt is None:
+        ckpt = _empty((T, B, code.E), torch.float32, llr.device)
+    _call("lsim_wbp_forward", code.handle, T, _ptr(w, torch.float32, "w"),
+          _ptr(llr, torch.float32, "llr"), B, llr_max, _ptr(ckpt, torch.float32, "ckpt"),
+          _ptr(lpost, torch.float32, "lpost"), _stream())
+    return lpost, ckpt
+
+
+def wbp_workspace(code: Code, T: int, B: int) -> int:
+    n = ctypes.c_size_t()
+    _call("lsim_wbp_workspace", code.handle, T, B, ctypes.byref(n))
+    return n.value
+
+
+def wbp_backward(code: Code, w, llr, ckpt, gpost, T: int, llr_max: float = 20.0, work=None,
+                 gllr=None, gw=None):
+    """(dLoss/dL_ch f32[B][e_tx], dLoss/dw f32[T][E]) from dLoss/dL_post."""
+    B = llr.shape[0]
+    if gllr is None:
+        gllr = _empty((B, code.e_tx), torch.float32, llr.device)
+    if gw is None:
+        gw = _empty((T, code.E), torch.float32, llr.device)
+    work, nbytes = _work(wbp_workspace(code, T, B), llr.device, work)
+    _call("lsim_wbp_backward", code.handle, T, _ptr(w, torch.float32, "w"),
+          _ptr(llr, torch.float32, "llr"), _ptr(ckpt, torch.float32, "ckpt"), B, llr_max,
+          _ptr(gpost, torch.float32, "gpost"), _ptr(gllr, torch.float32, "gllr"),
+          _ptr(gw, torch.float32, "gw"), _ptr(work, None, "work"), nbytes, _stream())
+    return gllr, gw
+
+
+def ndm_forward(params, y, no, out=None):
+    B, S = y.shape[0], y.shape[1]
+    L = out if out is not None else _empty((B, S * 4), torch.float32, y.device)
+    _call("lsim_ndm_forward", _ptr(params, torch.float32, "params"), _ptr(y, torch.float32, "y"),
+          _ptr(no, torch.float32, "no"), B, S, _ptr(L, torch.float32, "llr"), _stream())
+    return L
+
+
+def ndm_backward(params, y, no, gllr, out=None, work=None):
+    B, S = y.shape[0], y.shape[1]
+    g = out if out is not None else _empty((NDM_PARAMS,), torch.float32, y.device)
+    n = ctypes.c_size_t()
+    _call("lsim_ndm_workspace", B, S, ctypes.byref(n))
+    work, nbytes = _work(n.value, y.device, work)
+    _call("lsim_ndm_backward", _ptr(params, torch.float32, "params"), _ptr(y, torch.float32, "y"),
+          _ptr(no, torch.float32, "no"), _ptr(gllr, torch.float32, "gllr"), B, S,
+          _ptr(g, torch.float32, "gparams"), _ptr(work, None, "work"), nbytes, _stream())
+    return g
+
+
+def bce_grad(lpost, c, scale: float, want_loss: bool = True, g=None, loss=None, work=None):
+    """scale*(sigmoid(L) - c) and scale*sum(softplus(L) - c L); c u8 rows may
+    be wider than L (only the first n columns are read)."""
+    B, n = lpost.shape
+    if g is None:
+        g = torch.empty_like(lpost)
+    if want_loss and loss is None:
+        loss = _empty((1,), torch.float32, lpost.device)
+    if c.dtype != torch.uint8 or c.stride(1) != 1:
+        raise LsimError("labels must be u8 with unit column stride")
+    nb = ctypes.c_size_t()
+    _call("lsim_bce_workspace", B, n, ctypes.byref(nb))
+    work, nbytes = _work(nb.value if want_loss else 0, lpost.device, work)
+    _call("lsim_bce_grad", _ptr(lpost, torch.float32, "lpost"), ctypes.c_void_p(c.data_ptr()),
+          c.stride(0), B, n, scale, _ptr(g, torch.float32, "g"),
+          _ptr(loss, torch.float32, "loss") if want_loss else None, _ptr(work, None, "work"),
+          nbytes, _stream())
+    return g, loss
+
+
+def adam_step(p, g, m, v, step: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8):
+    _call("lsim_adam_step", _ptr(p, torch.float32, "p"), _ptr(g, torch.float32, "g"),
+          _ptr(m, torch.float32, "m"), _ptr(v, torch.float32, "v"), p.numel(), lr, beta1, beta2,
+          eps, step, _stream())
+
+
+class WBPFunction(torch.autograd.Function):
+    """Weighted BP as an autograd function: (L_ch, w) -> L_post, with the
+    hand-written adjoint of liblsim and per-round checkpoints."""
+
+    @staticmethod
+    def forward(ctx, llr, w, code, T, llr_max):
+        lpost, ckpt = wbp_forward(code, w.contiguous(), llr.contiguous(), T, llr_max)
+        ctx.save_for_backward(llr, w, ckpt)
+        ctx.code, ctx.T, ctx.llr_max = code, T, llr_max
+        return lpost
+
+    @staticmethod
+    def backward(ctx, gpost):
+        llr, w, ckpt = ctx.saved_tensors
+        gllr, gw = wbp_backward(ctx.code, w, llr, ckpt, gpost.contiguous(), ctx.T, ctx.llr_max)
+        return gllr, gw, None, None, None
+
+
+class NDMFunction(torch.autograd.Function):
+    """Neural demapper as an autograd function: (params, y, N0) -> LLRs."""
+
+    @staticmethod
+    def forward(ctx, params, y, no):
+        out = ndm_forward(params.contiguous(), y.contiguous(), no.contiguous())
+        ctx.save_for_backward(params, y, no)
+        return out
+
+    @staticmethod
+    def backward(ctx, gllr):
+        params, y, no = ctx.saved_tensors
+        return ndm_backward(params, y, no, gllr.contiguous()), None, None

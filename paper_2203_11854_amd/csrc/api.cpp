@@ -414,3 +414,278 @@ lsim_status lsim_syndrome(const lsim_code* code, const uint8_t* d_c, int64_t str
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------- mixed-shape plans
+
+struct lsim_plan {
+  std::vector<lsim::LayerShape> shapes;
+  lsim_decode_params p;
+  int threads = 0;
+  size_t lds = 0;
+  int grid = 0;
+  int64_t ntiles = 0;
+  size_t state_words = 0;
+  void* dmem = nullptr;
+  lsim::LayerShape* d_shapes = nullptr;
+  int* d_tile_shape = nullptr;
+  int64_t* d_tile_local = nullptr;
+};
+
+namespace {
+constexpr size_t kCounterBytes = 256;
+}
+
+extern "C" {
+
+lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t* counts,
+                                   int nshapes, const lsim_decode_params* p,
+                                   const int32_t* codewords_per_tile, int threads,
+                                   lsim_plan** out) {
+  if (!codes || !counts || !p || !out || nshapes < 1 || nshapes > 4096)
+    return fail(LSIM_E_INVAL, "bad mixed plan arguments");
+  *out = nullptr;
+  lsim_status st = check_params(codes[0], p);
+  if (st != LSIM_OK) return st;
+  if (p->algo != LSIM_NMS_F32)
+    return fail(LSIM_E_UNSUPPORTED, "mixed batches decode with the layered NMS decoder");
+  int zmax = 0, dmax = 0;
+  for (int s = 0; s < nshapes; ++s) {
+    if (!codes[s] || counts[s] < 0) return fail(LSIM_E_INVAL, "null code or negative count");
+    zmax = std::max(zmax, codes[s]->dev.Z);
+    dmax = std::max(dmax, codes[s]->dev.max_row_deg);
+  }
+  if (threads == 0) {
+    const int cand[5] = {256, 384, 512, 768, 1024};
+    threads = 1024;
+    for (int x : cand)
+      if (x >= zmax) {
+        threads = x;
+        break;
+      }
+  }
+  if (threads != 256 && threads != 384 && threads != 512 && threads != 768 && threads != 1024)
+    return fail(LSIM_E_INVAL, "threads must be 256, 384, 512, 768 or 1024");
+  if (threads < zmax) return fail(LSIM_E_INVAL, "threads < largest Z");
+  const size_t lds_cap = 160 * 1024 - 64;  // room for the kernel's static LDS
+  auto* plan = new lsim_plan();
+  plan->p = *p;
+  plan->threads = threads;
+  int64_t llr_off = 0, bits_off = 0, app_off = 0, state_off = 0, tile0 = 0;
+  for (int s = 0; s < nshapes; ++s) {
+    const DevCode& c = codes[s]->dev;
+    int G = codewords_per_tile && codewords_per_tile[s] > 0 ? codewords_per_tile[s]
+                                                            : threads / c.Z;
+    if (!codewords_per_tile || codewords_per_tile[s] <= 0)
+      while (G > 1 && lsim::layered_tile_lds(c, G) > lds_cap) --G;
+    if (G < 1 || G * c.Z > threads || lsim::layered_tile_lds(c, G) > lds_cap) {
+      delete plan;
+      return fail(LSIM_E_INVAL, "codewords_per_tile does not fit the workgroup or the LDS");
+    }
+    lsim::LayerShape sh;
+    sh.code = c;
+    sh.G = G;
+    sh.count = counts[s];
+    sh.tile0 = tile0;
+    sh.llr_off = llr_off;
+    sh.bits_off = bits_off;
+    sh.app_off = app_off;
+    sh.state_off = state_off;
+    plan->lds = std::max(plan->lds, lsim::layered_tile_lds(c, G));
+    llr_off += counts[s] * c.e_tx;
+    bits_off += counts[s] * c.k;
+    app_off += counts[s] * c.n_dec;
+    state_off += (int64_t)lsim::layered_state_words(c, counts[s]);
+    tile0 += (counts[s] + G - 1) / G;
+    plan->shapes.push_back(sh);
+  }
+  plan->ntiles = tile0;
+  plan->state_words = (size_t)state_off;
+  // work list, heaviest tiles first: a tile costs about one pass over the
+  // base nonzeros plus one barrier per layer, per iteration
+  std::vector<int> order(nshapes);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const DevCode &ca = plan->shapes[a].code, &cb = plan->shapes[b].code;
+    return ca.nnz + 2 * ca.rows > cb.nnz + 2 * cb.rows;
+  });
+  std::vector<int> tile_shape;
+  std::vector<int64_t> tile_local;
+  for (int s : order) {
+    const lsim::LayerShape& sh = plan->shapes[s];
+    const int64_t nt = (sh.count + sh.G - 1) / sh.G;
+    for (int64_t t = 0; t < nt; ++t) {
+      tile_shape.push_back(s);
+      tile_local.push_back(t);
+    }
+  }
+  int dev = 0, ncu = 256;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int by_lds = std::max(1, (int)((160 * 1024) / (plan->lds + 64)));
+  const int by_waves = std::max(1, 32 / (threads / 64));
+  plan->grid = ncu * std::min(by_lds, by_waves);
+  const size_t b_shapes = nshapes * sizeof(lsim::LayerShape);
+  const size_t b_ts = tile_shape.size() * sizeof(int);
+  const size_t b_tl = tile_local.size() * sizeof(int64_t);
+  const size_t o_ts = (b_shapes + 255) & ~(size_t)255;
+  const size_t o_tl = (o_ts + b_ts + 255) & ~(size_t)255;
+  if (e == hipSuccess) e = hipMalloc(&plan->dmem, o_tl + b_tl + 8);
+  if (e == hipSuccess) {
+    char* d = (char*)plan->dmem;
+    plan->d_shapes = (lsim::LayerShape*)d;
+    plan->d_tile_shape = (int*)(d + o_ts);
+    plan->d_tile_local = (int64_t*)(d + o_tl);
+    e = hipMemcpy(plan->d_shapes, plan->shapes.data(), b_shapes, hipMemcpyHostToDevice);
+    if (e == hipSuccess && b_ts)
+      e = hipMemcpy(plan->d_tile_shape, tile_shape.data(), b_ts, hipMemcpyHostToDevice);
+    if (e == hipSuccess && b_tl)
+      e = hipMemcpy(plan->d_tile_local, tile_local.data(), b_tl, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    if (plan->dmem) (void)hipFree(plan->dmem);
+    delete plan;
+    return dev_status(e, "mixed plan upload");
+  }
+  *out = plan;
+  return LSIM_OK;
+}
+
+void lsim_mixed_plan_destroy(lsim_plan* plan) {
+  if (!plan) return;
+  if (plan->dmem) (void)hipFree(plan->dmem);
+  delete plan;
+}
+
+lsim_status lsim_mixed_workspace(const lsim_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return fail(LSIM_E_INVAL, "null plan or bytes");
+  *bytes = kCounterBytes + plan->state_words * 4;
+  return LSIM_OK;
+}
+
+lsim_status lsim_mixed_decode(lsim_plan* plan, const void* d_llr_concat, uint8_t* d_bits_concat,
+                              float* d_app_concat, void* d_work, size_t work_bytes,
+                              int persistent, lsim_stream stream) {
+  if (!plan || !d_llr_concat || (!d_bits_concat && !d_app_concat))
+    return fail(LSIM_E_INVAL, "bad mixed decode arguments");
+  const size_t need = kCounterBytes + plan->state_words * 4;
+  if (!d_work || work_bytes < need)
+    return fail(LSIM_E_NOMEM, "workspace smaller than lsim_mixed_workspace()");
+  if (plan->ntiles == 0) return LSIM_OK;
+  char* w = (char*)d_work;
+  hipError_t e = lsim::launch_mixed(
+      plan->d_shapes, (int)plan->shapes.size(), plan->d_tile_shape, plan->d_tile_local,
+      plan->ntiles, plan->threads, plan->lds, plan->p, d_llr_concat, d_bits_concat, d_app_concat,
+      (uint32_t*)(w + kCounterBytes), (int*)w, persistent ? 1 : 0, plan->grid,
+      as_stream(stream));
+  return dev_status(e, "mixed decode");
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------ differentiable forms
+
+extern "C" {
+
+static lsim_status check_wbp(const lsim_code* code, int T, const float* w, const float* llr,
+                             int64_t B, float llr_max) {
+  if (!code || !w || !llr || B < 1 || B > ((int64_t)1 << 31))
+    return fail(LSIM_E_INVAL, "bad weighted BP arguments");
+  if (T < 1 || T > 100) return fail(LSIM_E_INVAL, "T must be in 1..100");
+  if (!(llr_max > 0.f)) return fail(LSIM_E_INVAL, "llr_max must be > 0");
+  return LSIM_OK;
+}
+
+lsim_status lsim_wbp_forward(const lsim_code* code, int T, const float* d_w, const float* d_llr,
+                             int64_t B, float llr_max, float* d_ckpt, float* d_lpost,
+                             lsim_stream stream) {
+  lsim_status st = check_wbp(code, T, d_w, d_llr, B, llr_max);
+  if (st != LSIM_OK) return st;
+  if (!d_lpost) return fail(LSIM_E_INVAL, "null lpost");
+  std::string why;
+  hipError_t e = lsim::launch_wbp_forward(code->dev, T, d_w, d_llr, B, llr_max, d_ckpt, d_lpost,
+                                          as_stream(stream), &why);
+  if (!why.empty()) return fail(LSIM_E_UNSUPPORTED, why);
+  return dev_status(e, "wbp_forward");
+}
+
+lsim_status lsim_wbp_workspace(const lsim_code* code, int T, int64_t B, size_t* bytes) {
+  if (!code || !bytes || T < 1 || B < 1) return fail(LSIM_E_INVAL, "bad workspace query");
+  *bytes = lsim::wbp_work_bytes(code->dev, T, B);
+  return LSIM_OK;
+}
+
+lsim_status lsim_wbp_backward(const lsim_code* code, int T, const float* d_w, const float* d_llr,
+                              const float* d_ckpt, int64_t B, float llr_max, const float* d_gpost,
+                              float* d_gllr, float* d_gw, void* d_work, size_t work_bytes,
+                              lsim_stream stream) {
+  lsim_status st = check_wbp(code, T, d_w, d_llr, B, llr_max);
+  if (st != LSIM_OK) return st;
+  if (!d_ckpt || !d_gpost || !d_gllr || !d_gw)
+    return fail(LSIM_E_INVAL, "null checkpoint or gradient buffer");
+  if (!d_work || work_bytes < lsim::wbp_work_bytes(code->dev, T, B))
+    return fail(LSIM_E_NOMEM, "workspace smaller than lsim_wbp_workspace()");
+  std::string why;
+  hipError_t e = lsim::launch_wbp_backward(code->dev, T, d_w, d_llr, d_ckpt, B, llr_max, d_gpost,
+                                           d_gllr, d_gw, d_work, as_stream(stream), &why);
+  if (!why.empty()) return fail(LSIM_E_UNSUPPORTED, why);
+  return dev_status(e, "wbp_backward");
+}
+
+lsim_status lsim_ndm_forward(const float* d_params, const float* d_y, const float* d_no,
+                             int64_t B, int64_t S, float* d_llr, lsim_stream stream) {
+  if (!d_params || !d_y || !d_no || !d_llr || B < 1 || S < 1)
+    return fail(LSIM_E_INVAL, "bad ndm_forward arguments");
+  if (((uintptr_t)d_llr) & 15) return fail(LSIM_E_INVAL, "d_llr must be 16-byte aligned");
+  return dev_status(lsim::launch_ndm_forward(d_params, d_y, d_no, B, S, d_llr, as_stream(stream)),
+                    "ndm_forward");
+}
+
+lsim_status lsim_ndm_workspace(int64_t B, int64_t S, size_t* bytes) {
+  if (!bytes || B < 1 || S < 1) return fail(LSIM_E_INVAL, "bad workspace query");
+  *bytes = lsim::ndm_work_bytes(B, S);
+  return LSIM_OK;
+}
+
+lsim_status lsim_ndm_backward(const float* d_params, const float* d_y, const float* d_no,
+                              const float* d_gllr, int64_t B, int64_t S, float* d_gparams,
+                              void* d_work, size_t work_bytes, lsim_stream stream) {
+  if (!d_params || !d_y || !d_no || !d_gllr || !d_gparams || B < 1 || S < 1)
+    return fail(LSIM_E_INVAL, "bad ndm_backward arguments");
+  if (!d_work || work_bytes < lsim::ndm_work_bytes(B, S))
+    return fail(LSIM_E_NOMEM, "workspace smaller than lsim_ndm_workspace()");
+  return dev_status(lsim::launch_ndm_backward(d_params, d_y, d_no, d_gllr, B, S, d_gparams,
+                                              d_work, as_stream(stream)),
+                    "ndm_backward");
+}
+
+lsim_status lsim_bce_workspace(int64_t B, int64_t n, size_t* bytes) {
+  if (!bytes || B < 1 || n < 1) return fail(LSIM_E_INVAL, "bad workspace query");
+  *bytes = lsim::bce_work_bytes(B, n);
+  return LSIM_OK;
+}
+
+lsim_status lsim_bce_grad(const float* d_lpost, const uint8_t* d_c, int64_t c_stride, int64_t B,
+                          int64_t n, float scale, float* d_g, float* d_loss, void* d_work,
+                          size_t work_bytes, lsim_stream stream) {
+  if (!d_lpost || !d_c || !d_g || B < 1 || n < 1 || c_stride < n)
+    return fail(LSIM_E_INVAL, "bad bce_grad arguments");
+  if (d_loss && (!d_work || work_bytes < lsim::bce_work_bytes(B, n)))
+    return fail(LSIM_E_NOMEM, "workspace smaller than lsim_bce_workspace()");
+  return dev_status(lsim::launch_bce_grad(d_lpost, d_c, c_stride, B, n, scale, d_g, d_loss,
+                                          d_work, as_stream(stream)),
+                    "bce_grad");
+}
+
+lsim_status lsim_adam_step(float* d_p, const float* d_g, float* d_m, float* d_v, int64_t n,
+                           float lr, float beta1, float beta2, float eps, int step,
+                           lsim_stream stream) {
+  if (!d_p || !d_g || !d_m || !d_v || n < 1 || step < 1)
+    return fail(LSIM_E_INVAL, "bad adam arguments");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f))
+    return fail(LSIM_E_INVAL, "bad adam hyper-parameters");
+  return dev_status(lsim::launch_adam(d_p, d_g, d_m, d_v, n, lr, beta1, beta2, eps, step,
+                                      as_stream(stream)),
+                    "adam_step");
+}
+
+}  // extern "C"

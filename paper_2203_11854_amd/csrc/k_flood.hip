@@ -20,13 +20,11 @@
 #include <hip/hip_runtime.h>
 
 #include "lsim_internal.h"
+#include "spa_math.h"
 
 namespace lsim {
 
 namespace {
-
-constexpr float kLog2e = 1.4426950408889634f;
-constexpr float kLn2 = 0.6931471805599453f;
 
 struct FloodArgs {
   const void* llr;
@@ -205,11 +203,7 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
         M* row = msg + (size_t)e0 * Z + r;
         uint32_t neg = 0;
         if constexpr (ALG == LSIM_SPA_F32) {
-          // sum-product in the "1 - prod tanh" domain: with
-          // m_v = 1 - tanh(|q_v|/2) = 2e/(1+e), e = exp(-|q_v|), the
-          // extrinsic D_v = 1 - prod_{v' != v}(1 - m_v') is built from
-          // exclusive prefix and suffix combinations x (+) y = x + y - xy,
-          // and |r_v| = ln((2 - D_v) / D_v) = 2 atanh(1 - D_v).
+          // sum-product in the "1 - prod tanh" domain (spa_math.h)
           float mm[DMAX], pre[DMAX];
           float dp = 0.f;
 #pragma unroll
@@ -217,11 +211,10 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
             if (q < d) {
               const float x = row[q * Z];
               neg |= (x < 0.f ? 1u : 0u) << q;
-              const float e = __builtin_amdgcn_exp2f(-fabsf(x) * kLog2e);
-              const float m = 2.f * e * __builtin_amdgcn_rcpf(1.f + e);
+              const float m = spa_m(x);
               mm[q] = m;
               pre[q] = dp;
-              dp = dp + m - dp * m;
+              dp = spa_combine(dp, m);
             }
           }
           const uint32_t par = __popc(neg) & 1u;
@@ -229,13 +222,9 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
 #pragma unroll
           for (int q = DMAX - 1; q >= 0; --q) {
             if (q < d) {
-              const float p = pre[q];
-              const float dx = p + ds - p * ds;
-              float rv = kLn2 * __builtin_amdgcn_logf((2.f - dx) * __builtin_amdgcn_rcpf(dx));
-              rv = fminf(rv, a.llr_max);
+              const float rv = fminf(spa_mag(spa_combine(pre[q], ds)), a.llr_max);
               row[q * Z] = (par ^ ((neg >> q) & 1u)) ? -rv : rv;
-              const float m = mm[q];
-              ds = ds + m - ds * m;
+              ds = spa_combine(ds, mm[q]);
             }
           }
         } else {

@@ -1,0 +1,426 @@
+// Weighted belief propagation (trainable flooding sum-product) and its
+// hand-written adjoint.
+//
+// Forward, T rounds, weights w[t][e] on the check-to-variable messages:
+//   r = clamp(CN_SPA(q), +-L);  APP = lam + sum_e w r;  q' = clamp(APP - w r, +-L)
+// with q^(1) = lam = clamp(-L_ch, +-L) and output L_post = -APP^(T).  The
+// variable-to-check messages entering each round are checkpointed to device
+// memory, ckpt[t][b][e]; the backward pass recomputes every check from them.
+//
+// Backward of round t, given the adjoint of APP^(t) (only for t = T: minus
+// dLoss/dL_post) and the adjoint qb' of q^(t+1):
+//   g_e   = qb'_e [|APP_v - s_e| <= L]             (s_e = w_e r_e)
+//   A_v   = abar_v + sum_{e at v} g_e ;  lam_bar_v += A_v
+//   sb_e  = A_v - g_e ;  dw_e = sb_e r_e ;  rb_e = sb_e w_e
+//   c_e   = rb_e [|r_e unclamped| <= L]
+//   qb_k  = sech^2(q_k/2) sum_{v != k} c_v cosh^2(r_v/2) prod_{j not in {v,k}} tanh(q_j/2)
+// The last sum is formed in O(d) per check from prefix/suffix products of
+// t_j = tanh(q_j/2) and prefix/suffix sums A of c_v cosh^2 times partial
+// products.  After round 1, lam_bar_v += sum_e qb_e (q^(1) = lam), and
+// dLoss/dL_ch = -lam_bar [|L_ch| <= L].
+//
+// The weight gradient is summed over the batch in a fixed order: every
+// codeword writes its own contribution, a second kernel adds them up.
+#include <hip/hip_runtime.h>
+
+#include "lsim_internal.h"
+#include "spa_math.h"
+
+namespace lsim {
+
+namespace {
+
+constexpr int kNT = 512;
+constexpr int kNW = kNT / 64;
+constexpr int kDMAX = 16;
+
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+struct Tab {
+  int* cn_tasks;
+  int* vn_tasks;
+  int* row_ptr;
+  int* col_ptr;
+  int2* col_edge;  // (e * Z, shift) per column entry
+};
+
+__host__ __device__ inline size_t tab_bytes(const DevCode& c) {
+  return align16((size_t)(c.n_cn_tasks + c.n_vn_tasks + c.rows + 1 + c.cols + 1) * 4) +
+         (size_t)c.nnz * 8;
+}
+
+__device__ inline Tab stage_tables(const DevCode& c, unsigned char* tb) {
+  Tab t;
+  t.cn_tasks = reinterpret_cast<int*>(tb);
+  t.vn_tasks = t.cn_tasks + c.n_cn_tasks;
+  t.row_ptr = t.vn_tasks + c.n_vn_tasks;
+  t.col_ptr = t.row_ptr + c.rows + 1;
+  t.col_edge = reinterpret_cast<int2*>(
+      tb + align16((size_t)(c.n_cn_tasks + c.n_vn_tasks + c.rows + 1 + c.cols + 1) * 4));
+  const int tid = threadIdx.x;
+  for (int i = tid; i < c.n_cn_tasks; i += kNT) t.cn_tasks[i] = c.cn_tasks[i];
+  for (int i = tid; i < c.n_vn_tasks; i += kNT) t.vn_tasks[i] = c.vn_tasks[i];
+  for (int i = tid; i <= c.rows; i += kNT) t.row_ptr[i] = c.row_ptr[i];
+  for (int i = tid; i <= c.cols; i += kNT) t.col_ptr[i] = c.col_ptr[i];
+  for (int i = tid; i < c.nnz; i += kNT) {
+    const int e = c.col_ent[i];
+    t.col_edge[i] = make_int2(e * c.Z, c.ent_shift[e]);
+  }
+  return t;
+}
+
+__device__ __forceinline__ float chan_lam(const DevCode& c, const float* llr_b, int v,
+                                          float lmax) {
+  const int x = v - c.tx_lo;
+  return (x >= 0 && x < c.e_tx) ? fminf(fmaxf(-llr_b[x], -lmax), lmax) : 0.f;
+}
+
+// Check update of one check from its d inputs q (row stride Z), writing the
+// clamped outputs to `out` (same layout).
+__device__ __forceinline__ void cn_forward(const float* in, float* out, int d, int Z, float lmax) {
+  float mm[kDMAX], pre[kDMAX];
+  uint32_t neg = 0;
+  float dp = 0.f;
+#pragma unroll
+  for (int q = 0; q < kDMAX; ++q) {
+    if (q < d) {
+      const float x = in[q * Z];
+      neg |= (x < 0.f ? 1u : 0u) << q;
+      const float m = spa_m(x);
+      mm[q] = m;
+      pre[q] = dp;
+      dp = spa_combine(dp, m);
+    }
+  }
+  const uint32_t par = __popc(neg) & 1u;
+  float ds = 0.f;
+#pragma unroll
+  for (int q = kDMAX - 1; q >= 0; --q) {
+    if (q < d) {
+      const float rv = fminf(spa_mag(spa_combine(pre[q], ds)), lmax);
+      out[q * Z] = (par ^ ((neg >> q) & 1u)) ? -rv : rv;
+      ds = spa_combine(ds, mm[q]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kNT) void wbp_forward_kernel(DevCode c, int T,
+                                                          const float* __restrict__ w,
+                                                          const float* __restrict__ llr,
+                                                          float lmax, float* __restrict__ ckpt,
+                                                          float* __restrict__ lpost, int64_t B) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* msg = reinterpret_cast<float*>(smem);
+  float* lam = reinterpret_cast<float*>(smem + align16((size_t)c.E * 4));
+  const Tab t = stage_tables(c, smem + align16((size_t)c.E * 4) + align16((size_t)c.n_dec * 4));
+  const int tid = threadIdx.x, lane = tid & 63, wave = uni(tid >> 6);
+  const int Z = c.Z;
+  const int64_t b = blockIdx.x;
+  const float* llr_b = llr + b * (int64_t)c.e_tx;
+  for (int v = tid; v < c.n_dec; v += kNT) lam[v] = chan_lam(c, llr_b, v, lmax);
+  __syncthreads();
+  // q^(1) = lam on every edge
+  for (int ti = wave; ti < c.n_vn_tasks; ti += kNW) {
+    const int task = uni(t.vn_tasks[ti]);
+    const int j = task >> 16, cc = (task & 0xffff) + lane;
+    const int cb = uni(t.col_ptr[j]), dc = uni(t.col_ptr[j + 1]) - cb;
+    if (cc < Z) {
+      const float l = lam[j * Z + cc];
+      for (int q = 0; q < dc; ++q) {
+        const int2 ce = t.col_edge[cb + q];
+        int x = cc - ce.y;
+        x += x < 0 ? Z : 0;
+        msg[ce.x + x] = l;
+      }
+    }
+  }
+  __syncthreads();
+  for (int it = 0; it < T; ++it) {
+    const bool last = it + 1 == T;
+    if (ckpt) {
+      float* ck = ckpt + ((int64_t)it * B + b) * c.E;
+      for (int e = tid; e < c.E; e += kNT) ck[e] = msg[e];
+    }
+    for (int ti = wave; ti < c.n_cn_tasks; ti += kNW) {
+      const int task = uni(t.cn_tasks[ti]);
+      const int i = task >> 16, r = (task & 0xffff) + lane;
+      const int e0 = uni(t.row_ptr[i]), d = uni(t.row_ptr[i + 1]) - e0;
+      if (r < Z) {
+        float* row = msg + (size_t)e0 * Z + r;
+        cn_forward(row, row, d, Z, lmax);
+      }
+    }
+    __syncthreads();
+    const float* wt = w + (int64_t)it * c.E;
+    for (int ti = wave; ti < c.n_vn_tasks; ti += kNW) {
+      const int task = uni(t.vn_tasks[ti]);
+      const int j = task >> 16, cc = (task & 0xffff) + lane;
+      const int cb = uni(t.col_ptr[j]), dc = uni(t.col_ptr[j + 1]) - cb;
+      if (cc < Z) {
+        const int v = j * Z + cc;
+        float s[kDMAX];
+        int idx[kDMAX];
+        float acc = lam[v];
+#pragma unroll
+        for (int q = 0; q < kDMAX; ++q) {
+          if (q < dc) {
+            const int2 ce = t.col_edge[cb + q];
+            int x = cc - ce.y;
+            x += x < 0 ? Z : 0;
+            idx[q] = ce.x + x;
+            s[q] = wt[idx[q]] * msg[idx[q]];
+            acc += s[q];
+          }
+        }
+        if (!last) {
+#pragma unroll
+          for (int q = 0; q < kDMAX; ++q)
+            if (q < dc) msg[idx[q]] = fminf(fmaxf(acc - s[q], -lmax), lmax);
+        } else {
+          lpost[b * (int64_t)c.n_dec + v] = -acc;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// LDS: R[E] (recomputed clamped check outputs), QB[E] (adjoints of the
+// variable-to-check messages, then of the check outputs), LB[n_dec].
+__global__ __launch_bounds__(kNT) void wbp_backward_kernel(
+    DevCode c, int T, const float* __restrict__ w, const float* __restrict__ llr,
+    const float* __restrict__ ckpt, float lmax, const float* __restrict__ gpost,
+    float* __restrict__ gllr, float* __restrict__ gw_part, int64_t B) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  float* R = reinterpret_cast<float*>(smem);
+  float* QB = R + c.E;
+  float* LB = reinterpret_cast<float*>(smem + align16((size_t)2 * c.E * 4));
+  const Tab t =
+      stage_tables(c, smem + align16((size_t)2 * c.E * 4) + align16((size_t)c.n_dec * 4));
+  const int tid = threadIdx.x, lane = tid & 63, wave = uni(tid >> 6);
+  const int Z = c.Z;
+  const int64_t b = blockIdx.x;
+  const float* llr_b = llr + b * (int64_t)c.e_tx;
+  for (int v = tid; v < c.n_dec; v += kNT) LB[v] = 0.f;
+  for (int e = tid; e < c.E; e += kNT) QB[e] = 0.f;
+  __syncthreads();
+
+  for (int it = T - 1; it >= 0; --it) {
+    const float* ck = ckpt + ((int64_t)it * B + b) * c.E;
+    // A: recompute the clamped check outputs of round it
+    for (int ti = wave; ti < c.n_cn_tasks; ti += kNW) {
+      const int task = uni(t.cn_tasks[ti]);
+      const int i = task >> 16, r = (task & 0xffff) + lane;
+      const int e0 = uni(t.row_ptr[i]), d = uni(t.row_ptr[i + 1]) - e0;
+      if (r < Z) cn_forward(ck + (size_t)e0 * Z + r, R + (size_t)e0 * Z + r, d, Z, lmax);
+    }
+    __syncthreads();
+    // B: variable-side adjoint
+    const float* wt = w + (int64_t)it * c.E;
+    float* gwb = gw_part + (b * (int64_t)T + it) * c.E;
+    const bool last = it + 1 == T;
+    for (int ti = wave; ti < c.n_vn_tasks; ti += kNW) {
+      const int task = uni(t.vn_tasks[ti]);
+      const int j = task >> 16, cc = (task & 0xffff) + lane;
+      const int cb = uni(t.col_ptr[j]), dc = uni(t.col_ptr[j + 1]) - cb;
+      if (cc < Z) {
+        const int v = j * Z + cc;
+        float s[kDMAX], g[kDMAX], ww[kDMAX];
+        int idx[kDMAX];
+        float acc = chan_lam(c, llr_b, v, lmax);
+#pragma unroll
+        for (int q = 0; q < kDMAX; ++q) {
+          if (q < dc) {
+            const int2 ce = t.col_edge[cb + q];
+            int x = cc - ce.y;
+            x += x < 0 ? Z : 0;
+            idx[q] = ce.x + x;
+            ww[q] = wt[idx[q]];
+            s[q] = ww[q] * R[idx[q]];
+            acc += s[q];
+          }
+        }
+        float A = last ? -gpost[b * (int64_t)c.n_dec + v] : 0.f;
+#pragma unroll
+        for (int q = 0; q < kDMAX; ++q) {
+          if (q < dc) {
+            const float qv = acc - s[q];
+            g[q] = (!last && fabsf(qv) <= lmax) ? QB[idx[q]] : 0.f;
+            A += g[q];
+          }
+        }
+        LB[v] += A;
+#pragma unroll
+        for (int q = 0; q < kDMAX; ++q) {
+          if (q < dc) {
+            const float sb = A - g[q];
+            gwb[idx[q]] = sb * R[idx[q]];
+            QB[idx[q]] = sb * ww[q];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // C: check-side adjoint from the checkpointed inputs
+    for (int ti = wave; ti < c.n_cn_tasks; ti += kNW) {
+      const int task = uni(t.cn_tasks[ti]);
+      const int i = task >> 16, r = (task & 0xffff) + lane;
+      const int e0 = uni(t.row_ptr[i]), d = uni(t.row_ptr[i + 1]) - e0;
+      if (r < Z) {
+        const float* qin = ck + (size_t)e0 * Z + r;
+        float* qb = QB + (size_t)e0 * Z + r;
+        float mm[kDMAX], tt[kDMAX], pre[kDMAX], av[kDMAX];
+        float dp = 0.f;
+#pragma unroll
+        for (int q = 0; q < kDMAX; ++q) {
+          if (q < d) {
+            const float x = qin[q * Z];
+            const float m = spa_m(x);
+            mm[q] = m;
+            tt[q] = x < 0.f ? -(1.f - m) : (1.f - m);
+            pre[q] = dp;
+            dp = spa_combine(dp, m);
+          }
+        }
+        // a_v = c_v cosh^2(r_v/2) with cosh^2 = 1/(D (2 - D)); zero where clamped
+        float ds = 0.f;
+#pragma unroll
+        for (int q = kDMAX - 1; q >= 0; --q) {
+          if (q < d) {
+            const float D = spa_combine(pre[q], ds);
+            const float mag = spa_mag(D);
+            const float cb = mag <= lmax ? qb[q * Z] : 0.f;
+            av[q] = cb == 0.f ? 0.f : cb * __builtin_amdgcn_rcpf(D * (2.f - D));
+            ds = spa_combine(ds, mm[q]);
+          }
+        }
+        // S_k = Apre_k Psuf_k + Ppre_k Asuf_k; forward pass stores Apre, Ppre
+        float ap[kDMAX], pp[kDMAX];
+        float P = 1.f, Aacc = 0.f;
+#pragma unroll
+        for (int q = 0; q < kDMAX; ++q) {
+          if (q < d) {
+            ap[q] = Aacc;
+            pp[q] = P;
+            Aacc = Aacc * tt[q] + av[q] * P;
+            P *= tt[q];
+          }
+        }
+        float Ps = 1.f, As = 0.f;
+#pragma unroll
+        for (int q = kDMAX - 1; q >= 0; --q) {
+          if (q < d) {
+            const float S = ap[q] * Ps + pp[q] * As;
+            qb[q * Z] = mm[q] * (2.f - mm[q]) * S;
+            As = As * tt[q] + av[q] * Ps;
+            Ps *= tt[q];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // D: q^(1) = lam, then the channel clamp
+  for (int ti = wave; ti < c.n_vn_tasks; ti += kNW) {
+    const int task = uni(t.vn_tasks[ti]);
+    const int j = task >> 16, cc = (task & 0xffff) + lane;
+    const int cb = uni(t.col_ptr[j]), dc = uni(t.col_ptr[j + 1]) - cb;
+    if (cc < Z) {
+      const int v = j * Z + cc;
+      float acc = LB[v];
+      for (int q = 0; q < dc; ++q) {
+        const int2 ce = t.col_edge[cb + q];
+        int x = cc - ce.y;
+        x += x < 0 ? Z : 0;
+        acc += QB[ce.x + x];
+      }
+      const int xx = v - c.tx_lo;
+      if (xx >= 0 && xx < c.e_tx) {
+        const float L = llr_b[xx];
+        gllr[b * (int64_t)c.e_tx + xx] = fabsf(L) <= lmax ? -acc : 0.f;
+      }
+    }
+  }
+}
+
+// gw[t][e] = sum over b (in order) of part[b][t][e]
+__global__ void sum_over_batch_kernel(const float* __restrict__ part, int64_t B, int64_t n,
+                                      float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float acc = 0.f;
+  for (int64_t b = 0; b < B; ++b) acc += part[b * n + i];
+  out[i] = acc;
+}
+
+size_t fwd_lds(const DevCode& c) {
+  return align16((size_t)c.E * 4) + align16((size_t)c.n_dec * 4) + tab_bytes(c);
+}
+size_t bwd_lds(const DevCode& c) {
+  return align16((size_t)2 * c.E * 4) + align16((size_t)c.n_dec * 4) + tab_bytes(c);
+}
+
+hipError_t set_attr(const void* fn) {
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+}  // namespace
+
+size_t wbp_work_bytes(const DevCode& c, int T, int64_t B) { return (size_t)B * T * c.E * 4; }
+
+hipError_t launch_wbp_forward(const DevCode& c, int T, const float* w, const float* llr,
+                              int64_t B, float llr_max, float* ckpt, float* lpost, hipStream_t s,
+                              std::string* why) {
+  const int dmax = c.max_row_deg > c.max_col_deg ? c.max_row_deg : c.max_col_deg;
+  if (dmax > kDMAX) {
+    *why = "weighted BP supports degrees up to 16";
+    return hipSuccess;
+  }
+  const size_t lds = fwd_lds(c);
+  if (lds > 160 * 1024) {
+    *why = "weighted BP state exceeds the 160 KiB LDS";
+    return hipSuccess;
+  }
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = set_attr((const void*)wbp_forward_kernel);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  wbp_forward_kernel<<<(unsigned)B, kNT, lds, s>>>(c, T, w, llr, llr_max, ckpt, lpost, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_wbp_backward(const DevCode& c, int T, const float* w, const float* llr,
+                               const float* ckpt, int64_t B, float llr_max, const float* gpost,
+                               float* gllr, float* gw, void* work, hipStream_t s,
+                               std::string* why) {
+  const int dmax = c.max_row_deg > c.max_col_deg ? c.max_row_deg : c.max_col_deg;
+  if (dmax > kDMAX) {
+    *why = "weighted BP supports degrees up to 16";
+    return hipSuccess;
+  }
+  const size_t lds = bwd_lds(c);
+  if (lds > 160 * 1024) {
+    *why = "weighted BP adjoint state exceeds the 160 KiB LDS";
+    return hipSuccess;
+  }
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = set_attr((const void*)wbp_backward_kernel);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  float* part = reinterpret_cast<float*>(work);
+  wbp_backward_kernel<<<(unsigned)B, kNT, lds, s>>>(c, T, w, llr, ckpt, llr_max, gpost, gllr,
+                                                    part, B);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n = (int64_t)T * c.E;
+  sum_over_batch_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(part, B, n, gw);
+  return hipGetLastError();
+}
+
+}  // namespace lsim

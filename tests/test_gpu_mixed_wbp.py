@@ -1,0 +1,204 @@
+"""GPU parity of the mixed-shape persistent decoder and of the
+differentiable forms (weighted BP forward/adjoint, neural demapper, BCE,
+Adam)."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import rel_close
+from inputs import rand
+from inputs.workloads import BG2, mixed_specs
+from oracle import decoders as D
+from oracle import ndm as ondm
+from oracle import pipeline, qc, wbp
+
+pytestmark = pytest.mark.gpu
+
+lsim = pytest.importorskip("paper_2203_11854_amd")
+dev = "cuda"
+
+
+def T(x):
+    return torch.from_numpy(np.ascontiguousarray(x))
+
+
+def mixed_inputs(counts, seed=71):
+    shapes, llrs, graphs, qbs = [], [], [], []
+    for s, ((spec, e_tx), cnt) in enumerate(zip(mixed_specs(), counts)):
+        qb = spec.load()
+        g = qc.graph_from_qcbase(qb, e_tx)
+        m = 2 if s % 2 == 0 else 4
+        eb = rand.uniform(seed + s, cnt, 0.0, 6.0)
+        n0 = pipeline.n0_for(g, eb, m)
+        tx = pipeline.transmit(g, qb.family, seed + 100 + s, 0, cnt, n0, m, "maxlog")
+        llrs.append(tx["L"].astype(np.float32))
+        graphs.append(g)
+        qbs.append(qb)
+        shapes.append(lsim.Code.from_qcbase(qb, e_tx))
+    return shapes, llrs, graphs, qbs
+
+
+def test_mixed_persistent_equals_per_shape_and_oracle():
+    counts = [5, 9, 3, 7, 4, 6, 2, 3]
+    codes, llrs, graphs, _ = mixed_inputs(counts)
+    p = lsim.params(lsim.NMS_F32, iters=20, alpha=0.75)
+    plan = lsim.MixedPlan(codes, counts, p)
+    cat = T(np.concatenate([x.reshape(-1) for x in llrs])).to(dev)
+    bits = torch.zeros(plan.n_bits, dtype=torch.uint8, device=dev)
+    app = torch.zeros(plan.n_app, dtype=torch.float32, device=dev)
+    plan.decode(cat, bits=bits, app=app, persistent=True)
+    bits2 = torch.zeros_like(bits)
+    app2 = torch.zeros_like(app)
+    plan.decode(cat, bits=bits2, app=app2, persistent=False)
+    assert torch.equal(bits, bits2) and torch.equal(app, app2)
+    for s, (code, L, g) in enumerate(zip(codes, llrs, graphs)):
+        b1, a1 = lsim.decode(code, T(L).to(dev), p, want_app=True)
+        lo, n = plan.app_offsets[s], counts[s] * code.n_dec
+        assert torch.equal(app[lo:lo + n].view(counts[s], -1), a1), s
+        bo = plan.bits_offsets[s]
+        assert torch.equal(bits[bo:bo + counts[s] * code.k].view(counts[s], -1), b1), s
+        ref = D.nms_layered(g, D.channel_lam(g, L, dtype=np.float32), 20, 0.75, mode="fp32")
+        assert np.array_equal(a1.cpu().numpy(), -ref), s
+
+
+def test_mixed_graph_replay():
+    counts = [4, 3, 5, 2, 3, 2, 1, 2]
+    codes, llrs, _, _ = mixed_inputs(counts, seed=90)
+    p = lsim.params(lsim.NMS_F32, iters=20, alpha=0.75)
+    plan = lsim.MixedPlan(codes, counts, p)
+    cat = T(np.concatenate([x.reshape(-1) for x in llrs])).to(dev)
+    work = plan.workspace(dev)
+    ref = torch.zeros(plan.n_app, dtype=torch.float32, device=dev)
+    plan.decode(cat, app=ref, work=work)
+    torch.cuda.synchronize()
+    out = torch.zeros_like(ref)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.decode(cat, app=out, work=work)     # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.decode(cat, app=out, work=work)
+    for rep in range(3):
+        out.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), rep
+        _ = (cat * 2).sum()                        # unrelated eager work between replays
+        torch.cuda.synchronize()
+
+
+def wbp_case(B=5, Tn=3, ebn0=1.0, seed=81):
+    qb = BG2.load()
+    g = qc.graph_from_qcbase(qb, 3840)
+    n0 = float(pipeline.n0_for(g, ebn0, 4))
+    tx = pipeline.transmit(g, qb.family, seed, 0, B, np.full(B, n0), 4, "maxlog")
+    L32 = tx["L"].astype(np.float32)
+    w = rand.uniform(seed + 1, (Tn, g.E), 0.7, 1.3).astype(np.float32)
+    c = tx["c"][:, :g.n_dec]
+    return qb, g, L32, w, c
+
+
+def test_wbp_forward_vs_oracle():
+    qb, g, L32, w, c = wbp_case()
+    code = lsim.Code.from_qcbase(qb, 3840)
+    lp, ck = lsim.wbp_forward(code, T(w).to(dev), T(L32).to(dev), 3)
+    ref = wbp.forward_numpy(g, D.channel_lam(g, L32.astype(np.float64)), w.astype(np.float64))
+    ok, worst = rel_close(lp.cpu().numpy(), -ref, 1e-4)
+    assert ok, worst
+    # unit weights: the plain sum-product decoder
+    ones = torch.ones((3, code.E), device=dev)
+    lp1, _ = lsim.wbp_forward(code, ones, T(L32).to(dev), 3, want_ckpt=False)
+    _, lp2 = lsim.decode(code, T(L32).to(dev), lsim.params(lsim.SPA_F32, iters=3), want_bits=False,
+                         want_app=True)
+    assert torch.equal(lp1, lp2)
+
+
+def test_wbp_gradient_vs_autograd():
+    qb, g, L32, w, c = wbp_case()
+    code = lsim.Code.from_qcbase(qb, 3840)
+    B, Tn = L32.shape[0], w.shape[0]
+    tl, tw = T(L32).to(dev), T(w).to(dev)
+    lp, ck = lsim.wbp_forward(code, tw, tl, Tn)
+    tc = T(c.astype(np.uint8)).to(dev)
+    gpost, loss = lsim.bce_grad(lp, tc, 1.0 / (B * g.n_dec))
+    gllr, gw = lsim.wbp_backward(code, tw, tl, ck, gpost, Tn)
+    Lch = np.zeros((B, g.n_dec))
+    Lch[:, g.tx_lo:g.tx_lo + g.e_tx] = L32
+    loss_ref, gL_ref, gw_ref, hits = wbp.grad_autograd(g, Lch, w.astype(np.float64), c.astype(np.float64))
+    assert abs(loss.item() - loss_ref) <= 1e-4 * abs(loss_ref)
+    for got, ref in ((gllr.cpu().numpy(), gL_ref[:, g.tx_lo:g.tx_lo + g.e_tx]), (gw.cpu().numpy(), gw_ref)):
+        rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        cos = float((got * ref).sum() / (np.linalg.norm(got) * np.linalg.norm(ref)))
+        print(f"rel {rel:.2e} cos {cos:.8f} clamp hits {hits}")
+        assert rel <= 1e-3 and cos >= 0.99999
+
+
+def test_wbp_autograd_function_and_determinism():
+    qb, g, L32, w, c = wbp_case(B=4, Tn=2)
+    code = lsim.Code.from_qcbase(qb, 3840)
+    tl = T(L32).to(dev).requires_grad_(True)
+    tw = T(w).to(dev).requires_grad_(True)
+    out = lsim.WBPFunction.apply(tl, tw, code, 2, 20.0)
+    (out ** 2).mean().backward()
+    g1 = (tl.grad.clone(), tw.grad.clone())
+    tl.grad, tw.grad = None, None
+    out = lsim.WBPFunction.apply(tl, tw, code, 2, 20.0)
+    (out ** 2).mean().backward()
+    assert torch.equal(g1[0], tl.grad) and torch.equal(g1[1], tw.grad)
+
+
+def glorot(seed):
+    r = rand.rng(seed)
+    out = []
+    for shape in ondm.SIZES:
+        if len(shape) == 2:
+            lim = np.sqrt(6.0 / (shape[0] + shape[1]))
+            out.append(r.uniform(-lim, lim, shape).reshape(-1))
+        else:
+            out.append(r.uniform(-0.1, 0.1, shape))
+    return np.concatenate(out)
+
+
+def test_ndm_forward_backward_vs_oracle():
+    params = glorot(5).astype(np.float32)
+    B, S = 7, 301
+    y = (rand.gaussian(6, (B, S)) + 1j * rand.gaussian(7, (B, S))).astype(np.complex64)
+    n0 = rand.uniform(8, B, 0.1, 1.0).astype(np.float32)
+    yy = np.stack([y.real, y.imag], -1).astype(np.float32)
+    tp, ty, tn = T(params).to(dev), T(yy).to(dev), T(n0).to(dev)
+    out = lsim.ndm_forward(tp, ty, tn).cpu().numpy()
+    ref = ondm.forward_numpy(params.astype(np.float64), y.astype(np.complex128), n0.astype(np.float64))
+    assert np.abs(out - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+    gl = rand.gaussian(9, (B, S * 4)).astype(np.float32)
+    gp = lsim.ndm_backward(tp, ty, tn, T(gl).to(dev)).cpu().numpy()
+    gref = ondm.grad_params(params.astype(np.float64), y.astype(np.complex128), n0.astype(np.float64),
+                            gl.astype(np.float64))
+    rel = np.linalg.norm(gp - gref) / np.linalg.norm(gref)
+    assert rel <= 1e-5, rel
+
+
+def test_bce_and_adam():
+    L = rand.gaussian(10, (6, 100), scale=4.0).astype(np.float32)
+    c = rand.bits(11, (6, 120))
+    g, loss = lsim.bce_grad(T(L).to(dev), T(c).to(dev), 0.01)
+    cc = c[:, :100].astype(np.float64)
+    L64 = L.astype(np.float64)
+    assert np.allclose(g.cpu().numpy(), 0.01 * (1 / (1 + np.exp(-L64)) - cc), atol=1e-7)
+    assert abs(loss.item() - 0.01 * float(np.sum(np.logaddexp(0, L64) - cc * L64))) < 1e-5
+    p = rand.gaussian(12, 1000).astype(np.float32)
+    gr = rand.gaussian(13, 1000).astype(np.float32)
+    tp, tg = T(p.copy()).to(dev), T(gr).to(dev)
+    tm, tv = torch.zeros_like(tp), torch.zeros_like(tp)
+    m = np.zeros(1000)
+    v = np.zeros(1000)
+    pp = p.astype(np.float64)
+    for step in (1, 2, 3):
+        lsim.adam_step(tp, tg, tm, tv, step, lr=1e-2)
+        m = 0.9 * m + 0.1 * gr
+        v = 0.999 * v + 0.001 * gr.astype(np.float64) ** 2
+        pp -= 1e-2 * (m / (1 - 0.9 ** step)) / (np.sqrt(v / (1 - 0.999 ** step)) + 1e-8)
+    assert np.allclose(tp.cpu().numpy(), pp, atol=1e-5)
