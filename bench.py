@@ -56,8 +56,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=256,
                     help="codewords of the oracle CPU baseline sample (0 = skip)")
-    ap.add_argument("--legs", default="oms,nms",
-                    help="secondary legs to time: oms,nms (empty = none)")
+    ap.add_argument("--legs", default="oms,nms,mixed,wbp",
+                    help="secondary legs to time: oms,nms,mixed,wbp (empty = none)")
     return ap.parse_args()
 
 
@@ -210,6 +210,13 @@ def main():
             "state_stream_gbs": round(state_bytes / (ms * 1e-3) / 1e9, 1)}
         log(f"[bench] nms layered bg1 decoder {ms:.3f} ms")
 
+    if "mixed" in legs:
+        extra["mixed_persistent"] = mixed_leg(torch, lsim, dev)
+        log(f"[bench] mixed: {extra['mixed_persistent']}")
+    if "wbp" in legs:
+        extra["wbp_ndm_bg2"] = wbp_leg(torch, lsim, dev, code, qb)
+        log(f"[bench] wbp: {extra['wbp_ndm_bg2']}")
+
     cpu = None
     if args.cpu_sample > 0:
         cpu = cpu_baseline(qb, args.cpu_sample)
@@ -227,6 +234,151 @@ def main():
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def _elapsed(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def mixed_leg(torch, lsim, dev):
+    """Eight BG-shaped codes (Z 16..384, rates 1/3..8/9), counts drawn
+    log-uniform in [16, 4096], QPSK/16-QAM per codeword, Eb/N0 ~ U[0, 6] dB:
+    one persistent graph-replayed launch vs one launch per shape."""
+    from inputs import rand
+    from inputs.workloads import data_seed, mixed_counts, mixed_specs
+
+    specs = mixed_specs()
+    counts = mixed_counts()
+    codes, parts = [], []
+    p = lsim.params(lsim.NMS_F32, iters=20, alpha=0.75)
+    for s, ((spec, e_tx), cnt) in enumerate(zip(specs, counts)):
+        qb = spec.load()
+        code = lsim.Code.from_qcbase(qb, e_tx)
+        codes.append(code)
+        r = rand.rng(4000 + s)
+        n_qpsk = int((r.random(cnt) < 0.5).sum())
+        ebn0 = r.uniform(0.0, 6.0, cnt)
+        seed = data_seed(4, s)
+        u = lsim.source_bits(seed, 0, cnt, code.k, dev)
+        c = lsim.encode(code, u)
+        llr = torch.empty((cnt, code.e_tx), dtype=torch.float32, device=dev)
+        for lo, hi, m in ((0, n_qpsk, 2), (n_qpsk, cnt, 4)):
+            if hi <= lo:
+                continue
+            no = torch.tensor(lsim.ebn0_to_n0(ebn0[lo:hi], code.k / code.e_tx, m),
+                              dtype=torch.float32, device=dev)
+            y = lsim.map_awgn(code, m, c[lo:hi].contiguous(), no, seed, lo)
+            llr[lo:hi] = lsim.demap(m, lsim.DEMAP_MAXLOG, y, no)
+        parts.append(llr)
+    cat = torch.cat([x.reshape(-1) for x in parts])
+    plan = lsim.MixedPlan(codes, counts, p)
+    work = plan.workspace(dev)
+    bits = torch.empty(plan.n_bits, dtype=torch.uint8, device=dev)
+    plan.decode(cat, bits=bits, work=work)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.decode(cat, bits=bits, work=work)
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.decode(cat, bits=bits, work=work)
+    ms_graph = _elapsed(torch, g.replay, 5)
+    ms_pers = _elapsed(torch, lambda: plan.decode(cat, bits=bits, work=work), 5)
+    sep_bits = [torch.empty((cnt, cd.k), dtype=torch.uint8, device=dev) for cd, cnt in zip(codes, counts)]
+    sep_work = [torch.empty(max(1, lsim.decode_workspace(cd, p, cnt)), dtype=torch.uint8, device=dev)
+                for cd, cnt in zip(codes, counts)]
+
+    def per_shape():
+        for cd, x, bb, ww in zip(codes, parts, sep_bits, sep_work):
+            lsim.decode(cd, x, p, bits=bb, work=ww)
+
+    ms_sep = _elapsed(torch, per_shape, 5)
+    same = all(torch.equal(bits[o:o + bb.numel()], bb.reshape(-1))
+               for o, bb in zip(plan.bits_offsets, sep_bits))
+    info = sum(cnt * cd.k for cd, cnt in zip(codes, counts))
+    return {"codewords": int(sum(counts)), "counts": counts, "info_bits": int(info),
+            "graph_ms": round(ms_graph, 4), "persistent_ms": round(ms_pers, 4),
+            "per_shape_ms": round(ms_sep, 4),
+            "graph_gbps": round(info / (ms_graph * 1e-3) / 1e9, 3),
+            "per_shape_gbps": round(info / (ms_sep * 1e-3) / 1e9, 3),
+            "bit_identical_to_per_shape": bool(same)}
+
+
+def wbp_leg(torch, lsim, dev, code, qb):
+    """Weighted BP (10 rounds, per-edge per-round weights) fed by the neural
+    demapper on 16-QAM, batch 2048, Eb/N0 ~ U[1, 4] dB: one training step
+    (forward; forward + backward + Adam) vs the plain sum-product decoder."""
+    from inputs import rand
+    from inputs.workloads import data_seed
+
+    B, T, m = 2048, 10, 4
+    S = code.e_tx // m
+    r = rand.rng(5005)
+    ebn0 = r.uniform(1.0, 4.0, B)
+    no = torch.tensor(lsim.ebn0_to_n0(ebn0, code.k / code.e_tx, m), dtype=torch.float32, device=dev)
+    seed = data_seed(5, 0)
+    u = lsim.source_bits(seed, 0, B, code.k, dev)
+    c = lsim.encode(code, u)
+    y = lsim.map_awgn(code, m, c, no, seed, 0)
+    params = torch.tensor(glorot_params(5006), dtype=torch.float32, device=dev)
+    w = torch.ones((T, code.E), dtype=torch.float32, device=dev)
+    pm, pv = torch.zeros_like(params), torch.zeros_like(params)
+    wm, wv = torch.zeros_like(w), torch.zeros_like(w)
+    llr = torch.empty((B, code.e_tx), dtype=torch.float32, device=dev)
+    lpost = torch.empty((B, code.n_dec), dtype=torch.float32, device=dev)
+    ckpt = torch.empty((T, B, code.E), dtype=torch.float32, device=dev)
+    gwork = torch.empty(lsim.wbp_workspace(code, T, B), dtype=torch.uint8, device=dev)
+    scale = 1.0 / (B * code.n_dec)
+    state = {"step": 0}
+
+    def fwd():
+        lsim.ndm_forward(params, y, no, out=llr)
+        lsim.wbp_forward(code, w, llr, T, 20.0, ckpt=ckpt, lpost=lpost)
+        return lsim.bce_grad(lpost, c, scale)
+
+    def fwd_bwd():
+        gpost, loss = fwd()
+        gllr, gw = lsim.wbp_backward(code, w, llr, ckpt, gpost, T, 20.0, work=gwork)
+        gp = lsim.ndm_backward(params, y, no, gllr)
+        state["step"] += 1
+        lsim.adam_step(w, gw, wm, wv, state["step"])
+        lsim.adam_step(params, gp, pm, pv, state["step"])
+        return loss
+
+    ms_f = _elapsed(torch, fwd, 5)
+    ms_fb = _elapsed(torch, fwd_bwd, 5)
+    l0 = float(fwd()[1].item())
+    spa = lsim.params(lsim.SPA_F32, iters=T)
+    ms_plain = _elapsed(torch, lambda: lsim.decode(code, llr, spa), 5)
+    info = B * code.k
+    return {"batch": B, "iters": T, "fwd_ms": round(ms_f, 4), "fwd_bwd_ms": round(ms_fb, 4),
+            "fwd_gbps": round(info / (ms_f * 1e-3) / 1e9, 3),
+            "fwd_bwd_gbps": round(info / (ms_fb * 1e-3) / 1e9, 3),
+            "plain_spa_T10_ms": round(ms_plain, 4),
+            "plain_spa_T10_gbps": round(info / (ms_plain * 1e-3) / 1e9, 3),
+            "loss_after_timing_steps": round(l0, 6)}
+
+
+def glorot_params(seed):
+    """Glorot-uniform weights, zero biases, flat in the library's order."""
+    from inputs import rand
+    r = rand.rng(seed)
+    out = []
+    for fan_out, fan_in in ((64, 3), (64, 64), (4, 64)):
+        lim = math.sqrt(6.0 / (fan_in + fan_out))
+        out.append(r.uniform(-lim, lim, fan_out * fan_in))
+        out.append(np.zeros(fan_out))
+    return np.concatenate(out)
 
 
 def cpu_baseline(qb, ncw):

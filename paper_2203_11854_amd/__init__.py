@@ -333,8 +333,14 @@ class MixedPlan:
     def decode(self, llr, bits=None, app=None, work=None, persistent=True):
         if llr.numel() != self.n_llr:
             raise LsimError("concatenated LLRs have the wrong length")
+        if bits is not None and bits.numel() != self.n_bits:
+            raise LsimError("concatenated bits have the wrong length")
+        if app is not None and app.numel() != self.n_app:
+            raise LsimError("concatenated posteriors have the wrong length")
         if work is None:
             work = self.workspace(llr.device)
+        if work.numel() * work.element_size() < self.work_bytes:
+            raise LsimError("workspace too small")
         _call("lsim_mixed_decode", self._h, _ptr(llr, torch.float32, "llr"),
               _ptr(bits, torch.uint8, "bits"), _ptr(app, torch.float32, "app"),
               _ptr(work, None, "work"), work.numel(), 1 if persistent else 0, _stream())
