@@ -19,6 +19,8 @@
 // are sorted heaviest first and dealt round-robin to the wavefronts.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lsim_internal.h"
 #include "spa_math.h"
 
@@ -50,6 +52,25 @@ struct Tables {
 };
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+template <int N>
+struct Deg {
+  static constexpr int value = N;
+};
+
+// Calls f(Deg<d>{}) for the wave-uniform degree d in [1, D]: every degree
+// gets its own straight-line body, so all of a check's (or a variable
+// node's) LDS reads are issued back to back before the first use.
+template <int D, class F>
+__device__ __forceinline__ void with_degree(int d, F&& f) {
+  if constexpr (D >= 1) {
+    if (d == D) {
+      f(Deg<D>{});
+      return;
+    }
+    with_degree<D - 1>(d, f);
+  }
+}
 
 template <int ALG>
 struct Traits;
@@ -140,54 +161,37 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
       const int dc = uni(t.col_ptr[j + 1]) - cb;
       if (cc < Z) {
         const int v = j * Z + cc;
-        int idx[DMAX];
-        if constexpr (ALG == LSIM_SPA_F32) {
-          float rv[DMAX];
-          float acc = lam[v];
+        with_degree<DMAX>(dc, [&](auto deg) {
+          constexpr int DC = decltype(deg)::value;
+          int idx[DC];
+          using Acc = typename std::conditional<ALG == LSIM_SPA_F32, float, int>::type;
+          Acc rv[DC];
 #pragma unroll
-          for (int q = 0; q < DMAX; ++q) {
-            if (q < dc) {
-              const int2 ce = t.col_edge[cb + q];
-              int x = cc - ce.y;
-              x += x < 0 ? Z : 0;
-              idx[q] = ce.x + x;
-              rv[q] = msg[idx[q]];
-              acc += rv[q];
-            }
+          for (int q = 0; q < DC; ++q) {
+            const int2 ce = t.col_edge[cb + q];
+            int x = cc - ce.y;
+            x += x < 0 ? Z : 0;
+            idx[q] = ce.x + x;
           }
+#pragma unroll
+          for (int q = 0; q < DC; ++q) rv[q] = msg[idx[q]];
+          Acc acc = lam[v];
+#pragma unroll
+          for (int q = 0; q < DC; ++q) acc += rv[q];
           if (write_q) {
 #pragma unroll
-            for (int q = 0; q < DMAX; ++q)
-              if (q < dc) msg[idx[q]] = fminf(fmaxf(acc - rv[q], -a.llr_max), a.llr_max);
-          }
-          if (final_round) {
-            if (a.bits && v < c.k) a.bits[b * (int64_t)c.k + v] = acc < 0.f;
-            if (a.lpost) a.lpost[b * (int64_t)c.n_dec + v] = -acc;
-          }
-        } else {
-          int rv[DMAX];
-          int acc = lam[v];
-#pragma unroll
-          for (int q = 0; q < DMAX; ++q) {
-            if (q < dc) {
-              const int2 ce = t.col_edge[cb + q];
-              int x = cc - ce.y;
-              x += x < 0 ? Z : 0;
-              idx[q] = ce.x + x;
-              rv[q] = msg[idx[q]];
-              acc += rv[q];
+            for (int q = 0; q < DC; ++q) {
+              if constexpr (ALG == LSIM_SPA_F32)
+                msg[idx[q]] = fminf(fmaxf(acc - rv[q], -a.llr_max), a.llr_max);
+              else
+                msg[idx[q]] = (M)min(max(acc - rv[q], -a.sat), a.sat);
             }
-          }
-          if (write_q) {
-#pragma unroll
-            for (int q = 0; q < DMAX; ++q)
-              if (q < dc) msg[idx[q]] = (M)min(max(acc - rv[q], -a.sat), a.sat);
           }
           if (final_round) {
             if (a.bits && v < c.k) a.bits[b * (int64_t)c.k + v] = acc < 0;
             if (a.lpost) a.lpost[b * (int64_t)c.n_dec + v] = (float)(-acc);
           }
-        }
+        });
       }
     }
   };
@@ -201,54 +205,48 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
       const int d = uni(t.row_ptr[i + 1]) - e0;
       if (r < Z) {
         M* row = msg + (size_t)e0 * Z + r;
-        uint32_t neg = 0;
-        if constexpr (ALG == LSIM_SPA_F32) {
-          // sum-product in the "1 - prod tanh" domain (spa_math.h)
-          float mm[DMAX], pre[DMAX];
-          float dp = 0.f;
+        with_degree<DMAX>(d, [&](auto deg) {
+          constexpr int D = decltype(deg)::value;
+          M x[D];
 #pragma unroll
-          for (int q = 0; q < DMAX; ++q) {
-            if (q < d) {
-              const float x = row[q * Z];
-              neg |= (x < 0.f ? 1u : 0u) << q;
-              const float m = spa_m(x);
-              mm[q] = m;
-              pre[q] = dp;
-              dp = spa_combine(dp, m);
-            }
-          }
+          for (int q = 0; q < D; ++q) x[q] = row[q * Z];
+          uint32_t neg = 0;
+#pragma unroll
+          for (int q = 0; q < D; ++q) neg |= (x[q] < 0 ? 1u : 0u) << q;
           const uint32_t par = __popc(neg) & 1u;
-          float ds = 0.f;
+          if constexpr (ALG == LSIM_SPA_F32) {
+            // sum-product in the "1 - prod tanh" domain (spa_math.h)
+            float mm[D], pre[D];
+            float dp = 0.f;
 #pragma unroll
-          for (int q = DMAX - 1; q >= 0; --q) {
-            if (q < d) {
+            for (int q = 0; q < D; ++q) {
+              mm[q] = spa_m(x[q]);
+              pre[q] = dp;
+              dp = spa_combine(dp, mm[q]);
+            }
+            float ds = 0.f;
+#pragma unroll
+            for (int q = D - 1; q >= 0; --q) {
               const float rv = fminf(spa_mag(spa_combine(pre[q], ds)), a.llr_max);
               row[q * Z] = (par ^ ((neg >> q) & 1u)) ? -rv : rv;
               ds = spa_combine(ds, mm[q]);
             }
-          }
-        } else {
-          int m1 = 255, m2 = 255, i1 = 0;
+          } else {
+            int m1 = 255, m2 = 255, i1 = 0;
 #pragma unroll
-          for (int q = 0; q < DMAX; ++q) {
-            if (q < d) {
-              const int x = row[q * Z];
-              neg |= (x < 0 ? 1u : 0u) << q;
-              const int ax = x < 0 ? -x : x;
+            for (int q = 0; q < D; ++q) {
+              const int ax = x[q] < 0 ? -(int)x[q] : (int)x[q];
               m2 = min(m2, max(m1, ax));
               i1 = ax < m1 ? q : i1;
               m1 = min(m1, ax);
             }
-          }
-          const uint32_t par = __popc(neg) & 1u;
 #pragma unroll
-          for (int q = 0; q < DMAX; ++q) {
-            if (q < d) {
+            for (int q = 0; q < D; ++q) {
               const int mag = max((q == i1 ? m2 : m1) - a.offset, 0);
               row[q * Z] = (M)((par ^ ((neg >> q) & 1u)) ? -mag : mag);
             }
           }
-        }
+        });
       }
     }
   };
