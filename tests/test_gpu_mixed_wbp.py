@@ -109,12 +109,14 @@ def test_wbp_forward_vs_oracle():
     ref = wbp.forward_numpy(g, D.channel_lam(g, L32.astype(np.float64)), w.astype(np.float64))
     ok, worst = rel_close(lp.cpu().numpy(), -ref, 1e-4)
     assert ok, worst
-    # unit weights: the plain sum-product decoder
+    # unit weights: the plain sum-product decoder (the two kernels may
+    # contract multiply-adds differently, hence a few-ulp tolerance)
     ones = torch.ones((3, code.E), device=dev)
     lp1, _ = lsim.wbp_forward(code, ones, T(L32).to(dev), 3, want_ckpt=False)
     _, lp2 = lsim.decode(code, T(L32).to(dev), lsim.params(lsim.SPA_F32, iters=3), want_bits=False,
                          want_app=True)
-    assert torch.equal(lp1, lp2)
+    ok, worst = rel_close(lp1.cpu().numpy(), lp2.cpu().numpy(), 1e-5)
+    assert ok, worst
 
 
 def test_wbp_gradient_vs_autograd():
