@@ -56,34 +56,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=256,
                     help="codewords of the oracle CPU baseline sample (0 = skip)")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="MiB of a plain device copy run first (reference for HBM counters)")
     ap.add_argument("--legs", default="oms,nms,mixed,wbp",
                     help="secondary legs to time: oms,nms,mixed,wbp (empty = none)")
     return ap.parse_args()
-
-
-class Timer:
-    """HIP events on torch's current stream (the stream every lsim call uses)."""
-
-    def __init__(self, torch):
-        self.torch = torch
-        self.total = 0.0
-        self.n = 0
-
-    def __enter__(self):
-        self.a = self.torch.cuda.Event(enable_timing=True)
-        self.b = self.torch.cuda.Event(enable_timing=True)
-        self.a.record()
-        return self
-
-    def __exit__(self, *exc):
-        self.b.record()
-        self.pending = (self.a, self.b)
-        return False
-
-    def collect(self):
-        self.torch.cuda.synchronize()
-        self.total += self.pending[0].elapsed_time(self.pending[1])
-        self.n += 1
 
 
 def main():
@@ -101,6 +78,14 @@ def main():
     torch.cuda.set_device(0)
     dev = "cuda:0"
 
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # ---------------- workload: BG2-shaped code, 16-QAM, batch 4096
     qb = BG2.load()
     code = lsim.Code.from_qcbase(qb, 3840)
@@ -111,48 +96,32 @@ def main():
     bins = np.arange(B) % 9
     no = torch.tensor(n0_pts[bins], dtype=torch.float32, device=dev)
     tbins = torch.tensor(bins, dtype=torch.int32, device=dev)
-    u = torch.empty((B, k), dtype=torch.uint8, device=dev)
-    c = torch.empty((B, code.n_mother), dtype=torch.uint8, device=dev)
-    y = torch.empty((B, S, 2), dtype=torch.float32, device=dev)
-    llr = torch.empty((B, code.e_tx), dtype=torch.float32, device=dev)
-    bits = torch.empty((B, k), dtype=torch.uint8, device=dev)
-    counts = torch.zeros((9, 3), dtype=torch.int64, device=dev)
     p_spa = lsim.params(lsim.SPA_F32, iters=20, llr_max=20.0)
-    dec_timer = Timer(torch)
+    link = lsim.Link(code, m, lsim.DEMAP_MAXLOG, p_spa, B, no, bins=tbins, nbins=9, device=dev)
 
-    def step(i, timed):
-        seed = data_seed(2, i)
-        lsim.source_bits(seed, 0, B, k, out=u)
-        lsim.encode(code, u, out=c)
-        lsim.map_awgn(code, m, c, no, seed, 0, out=y)
-        lsim.demap(m, lsim.DEMAP_MAXLOG, y, no, out=llr)
-        if timed:
-            with dec_timer:
-                lsim.decode(code, llr, p_spa, bits=bits)
-        else:
-            lsim.decode(code, llr, p_spa, bits=bits)
-        lsim.count_errors(u, bits, tbins, 9, counts=counts)
+    def step(i):
+        link.run(data_seed(2, i), 0)
 
     log(f"[bench] warmup {args.warmup} steps")
     for i in range(args.warmup):
-        step(i, False)
+        step(i)
     torch.cuda.synchronize()
-    counts.zero_()
+    link.counts.zero_()
     log(f"[bench] timing {args.steps} steps")
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(1000 + i, False)
+        step(1000 + i)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
     value = B * k / (ms_step * 1e-3) / 1e9
-    cnt = counts.cpu().numpy()
+    cnt = link.counts.cpu().numpy()
 
-    # decoder kernel alone, HIP events on its stream
-    for i in range(max(5, min(args.steps, 20))):
-        step(2000 + i, True)
-        dec_timer.collect()
-    dec_ms = dec_timer.total / dec_timer.n
+    # decoder kernel alone: back-to-back launches between two HIP events on
+    # the stream the kernels run on
+    llr, bits = link.llr, link.bits
+    nrep = 10
+    dec_ms = _elapsed(torch, lambda: lsim.decode(code, llr, p_spa, bits=bits), nrep)
     E = code.E
     slots = B * 20 * E * SPA_SLOTS_PER_EDGE
     achieved = slots / (dec_ms * 1e-3) / 1e12
@@ -172,14 +141,9 @@ def main():
     legs = [x for x in args.legs.split(",") if x]
     if "oms" in legs:
         q8 = torch.empty((B, code.e_tx), dtype=torch.int8, device=dev)
+        lsim.demap_q8(m, lsim.DEMAP_MAXLOG, link.y, no, out=q8)
         p = lsim.params(lsim.OMS_I8, iters=20, offset=1, sat=31)
-        tm = Timer(torch)
-        for i in range(10):
-            lsim.demap_q8(m, lsim.DEMAP_MAXLOG, y, no, out=q8)
-            with tm:
-                lsim.decode(code, q8, p, bits=bits)
-            tm.collect()
-        ms = tm.total / tm.n
+        ms = _elapsed(torch, lambda: lsim.decode(code, q8, p, bits=bits), nrep)
         a = B * 20 * E * OMS_SLOTS_PER_EDGE / (ms * 1e-3) / 1e12
         extra["oms_i8_bg2"] = {"decoder_ms": round(ms, 4), "gbps": round(B * k / (ms * 1e-3) / 1e9, 3),
                                "alu_frac": round(a / VALU_PEAK_TOPS, 4)}
@@ -197,12 +161,7 @@ def main():
         p = lsim.params(lsim.NMS_F32, iters=20, alpha=0.75)
         work = torch.empty(lsim.decode_workspace(code1, p, B1), dtype=torch.uint8, device=dev)
         b1 = torch.empty((B1, code1.k), dtype=torch.uint8, device=dev)
-        tm = Timer(torch)
-        for i in range(6):
-            with tm:
-                lsim.decode(code1, l1, p, bits=b1, work=work)
-            tm.collect()
-        ms = tm.total / tm.n
+        ms = _elapsed(torch, lambda: lsim.decode(code1, l1, p, bits=b1, work=work), 5)
         state_bytes = B1 * 20 * code1.m_dec * 12 * 2
         extra["nms_layered_bg1"] = {
             "decoder_ms": round(ms, 4), "gbps": round(B1 * code1.k / (ms * 1e-3) / 1e9, 3),

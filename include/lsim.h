@@ -210,6 +210,42 @@ lsim_status lsim_count_errors(const uint8_t* d_ref, int64_t ref_stride, const ui
 lsim_status lsim_syndrome(const lsim_code* code, const uint8_t* d_c, int64_t stride, int64_t B,
                           int32_t* d_unsat, lsim_stream stream);
 
+/* ------------------------------------------------------- whole link */
+
+/*
+ * One Monte-Carlo batch through the whole link of Listing 1 in a single
+ * call: source bits (seed, cw0) -> encoder -> mapper + AWGN (d_no) ->
+ * demapper (fused with the quantizer for LSIM_OMS_I8, scale q_scale and
+ * saturation dec.sat) -> decoder -> error count.  Buffers are the ones of
+ * the individual calls; d_llr is f32[B][e_tx] or, for LSIM_OMS_I8,
+ * i8[B][e_tx].  d_work / work_bytes as for lsim_decode.  d_counts receives
+ * (bit errors, block errors, codewords) per bin (d_bin nullable = bin 0),
+ * accumulated.  Equivalent to issuing the six calls in order on `stream`.
+ */
+typedef struct {
+  const lsim_code* code;
+  int bits_per_sym;
+  int demap_method;
+  lsim_decode_params dec;
+  float q_scale;
+  uint64_t seed;
+  int64_t cw0;
+  int64_t B;
+  const float* d_no;
+  uint8_t* d_u;
+  uint8_t* d_c;
+  float* d_y;
+  void* d_llr;
+  uint8_t* d_bits;
+  void* d_work;
+  size_t work_bytes;
+  const int32_t* d_bin;
+  int nbins;
+  int64_t* d_counts;
+} lsim_link_args;
+
+lsim_status lsim_link_run(const lsim_link_args* args, lsim_stream stream);
+
 /* ------------------------------------------------- mixed-shape batching */
 
 /*

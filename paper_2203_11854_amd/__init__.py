@@ -78,6 +78,7 @@ _SIGS = {
     "lsim_bce_workspace": [_I64, _I64, ctypes.POINTER(_SZ)],
     "lsim_bce_grad": [_P, _P, _I64, _I64, _I64, _F, _P, _P, _P, _SZ, _P],
     "lsim_adam_step": [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I, _P],
+    "lsim_link_run": [_P, _P],
     "lsim_last_error": [],
     "lsim_version": [],
 }
@@ -469,3 +470,40 @@ class NDMFunction(torch.autograd.Function):
     def backward(ctx, gllr):
         params, y, no = ctx.saved_tensors
         return ndm_backward(params, y, no, gllr.contiguous()), None, None
+
+
+class LinkArgs(ctypes.Structure):
+    _fields_ = [("code", _P), ("bits_per_sym", _I), ("demap_method", _I), ("dec", DecodeParams),
+                ("q_scale", _F), ("seed", _U64), ("cw0", _I64), ("B", _I64), ("d_no", _P),
+                ("d_u", _P), ("d_c", _P), ("d_y", _P), ("d_llr", _P), ("d_bits", _P),
+                ("d_work", _P), ("work_bytes", _SZ), ("d_bin", _P), ("nbins", _I),
+                ("d_counts", _P)]
+
+
+class Link:
+    """Pre-allocated buffers for lsim_link_run: one call per Monte-Carlo
+    batch through source, encoder, mapper + AWGN, demapper, decoder and
+    error count."""
+
+    def __init__(self, code: Code, m: int, method: int, p: DecodeParams, B: int, no, bins=None,
+                 nbins: int = 1, q_scale: float = 2.0, device="cuda"):
+        self.code, self.B = code, B
+        self.no = no
+        self.u = _empty((B, code.k), torch.uint8, device)
+        self.c = _empty((B, code.n_mother), torch.uint8, device)
+        self.y = _empty((B, code.e_tx // m, 2), torch.float32, device)
+        self.llr = _empty((B, code.e_tx), torch.int8 if p.algo == OMS_I8 else torch.float32, device)
+        self.bits = _empty((B, code.k), torch.uint8, device)
+        self.counts = torch.zeros((nbins, 3), dtype=torch.int64, device=device)
+        nb = decode_workspace(code, p, B)
+        self.work = torch.empty(max(nb, 1), dtype=torch.uint8, device=device)
+        self.bins = bins
+        self.args = LinkArgs(code.handle, m, method, p, q_scale, 0, 0, B, _ptr(no, torch.float32, "no"),
+                             _ptr(self.u), _ptr(self.c), _ptr(self.y), _ptr(self.llr), _ptr(self.bits),
+                             _ptr(self.work), nb, _ptr(bins, torch.int32, "bins"), nbins,
+                             _ptr(self.counts))
+
+    def run(self, seed: int, cw0: int = 0):
+        self.args.seed = seed
+        self.args.cw0 = cw0
+        _call("lsim_link_run", ctypes.byref(self.args), _stream())

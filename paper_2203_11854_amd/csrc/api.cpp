@@ -476,7 +476,7 @@ lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t*
     int G = codewords_per_tile && codewords_per_tile[s] > 0 ? codewords_per_tile[s]
                                                             : threads / c.Z;
     if (!codewords_per_tile || codewords_per_tile[s] <= 0)
-      while (G > 1 && lsim::layered_tile_lds(c, G) > lds_cap) --G;
+      while (G > 1 && lsim::layered_tile_lds(c, G) > lds_cap / 2) --G;  // two workgroups per CU
     if (G < 1 || G * c.Z > threads || lsim::layered_tile_lds(c, G) > lds_cap) {
       delete plan;
       return fail(LSIM_E_INVAL, "codewords_per_tile does not fit the workgroup or the LDS");
@@ -689,3 +689,55 @@ lsim_status lsim_adam_step(float* d_p, const float* d_g, float* d_m, float* d_v,
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------- whole link
+
+extern "C" lsim_status lsim_link_run(const lsim_link_args* a, lsim_stream stream) {
+  if (!a) return fail(LSIM_E_INVAL, "null link arguments");
+  const lsim_code* code = a->code;
+  lsim_status st = check_params(code, &a->dec);
+  if (st != LSIM_OK) return st;
+  const int m = a->bits_per_sym;
+  if (!a->d_no || !a->d_u || !a->d_c || !a->d_y || !a->d_llr || !a->d_bits || !a->d_counts ||
+      a->B < 1 || a->cw0 < 0 || a->nbins < 1)
+    return fail(LSIM_E_INVAL, "bad link arguments");
+  if (m != 1 && m != 2 && m != 4 && m != 6)
+    return fail(LSIM_E_UNSUPPORTED, "bits_per_sym must be 1, 2, 4 or 6");
+  if (a->demap_method != LSIM_DEMAP_EXACT && a->demap_method != LSIM_DEMAP_MAXLOG)
+    return fail(LSIM_E_INVAL, "unknown demap method");
+  const DevCode& c = code->dev;
+  if (c.e_tx % m) return fail(LSIM_E_INVAL, "e_tx is not a multiple of bits_per_sym");
+  if ((int64_t)c.n_mother > 48 * 1024)
+    return fail(LSIM_E_UNSUPPORTED, "mother code too long for the encoder's LDS tile");
+  const bool q8 = a->dec.algo == LSIM_OMS_I8;
+  if (q8 && !is_pow2_scale(a->q_scale)) return fail(LSIM_E_INVAL, "q_scale must be a power of two");
+  if (a->dec.algo == LSIM_NMS_F32) {
+    const size_t need = lsim::layered_state_words(c, a->B) * 4;
+    if (!a->d_work || a->work_bytes < need)
+      return fail(LSIM_E_NOMEM, "workspace smaller than lsim_decode_workspace()");
+  }
+  hipStream_t s = as_stream(stream);
+  const int64_t S = c.e_tx / m;
+  hipError_t e = lsim::launch_source_bits(a->seed, a->cw0, a->B, c.k, a->d_u, s);
+  if (e == hipSuccess) e = lsim::launch_encode(c, a->d_u, a->B, a->d_c, s);
+  if (e == hipSuccess)
+    e = lsim::launch_map_awgn(c, m, a->d_c, a->d_no, a->seed, a->cw0, a->B, a->d_y, s);
+  if (e == hipSuccess)
+    e = lsim::launch_demap(m, a->demap_method, a->d_y, a->d_no, a->B, S,
+                           q8 ? nullptr : (float*)a->d_llr, q8 ? (int8_t*)a->d_llr : nullptr,
+                           a->q_scale, a->dec.sat, s);
+  std::string why;
+  if (e == hipSuccess) {
+    if (a->dec.algo == LSIM_NMS_F32)
+      e = lsim::launch_layered(c, a->dec, (const float*)a->d_llr, a->B, a->d_bits, nullptr,
+                               nullptr, (uint32_t*)a->d_work, s, &why);
+    else
+      e = lsim::launch_flood(c, a->dec, a->d_llr, a->B, a->d_bits, nullptr, nullptr, nullptr,
+                             nullptr, s, &why);
+  }
+  if (!why.empty()) return fail(LSIM_E_UNSUPPORTED, why);
+  if (e == hipSuccess)
+    e = lsim::launch_count_errors(a->d_u, c.k, a->d_bits, a->B, c.k, a->d_bin, a->nbins,
+                                  a->d_counts, s);
+  return dev_status(e, "link_run");
+}

@@ -291,13 +291,10 @@ hipError_t dispatch(const DevCode& c, int nt, const FloodArgs& a, size_t lds, hi
   const int dmax = c.max_row_deg > c.max_col_deg ? c.max_row_deg : c.max_col_deg;
 #define LSIM_FLOOD_CASE(NT_, D_) \
   if (nt == NT_ && dmax <= D_) return launch_t<NT_, D_, ALG>(c, a, lds, s);
-  LSIM_FLOOD_CASE(256, 8)
   LSIM_FLOOD_CASE(256, 16)
   LSIM_FLOOD_CASE(256, 32)
-  LSIM_FLOOD_CASE(512, 8)
   LSIM_FLOOD_CASE(512, 16)
   LSIM_FLOOD_CASE(512, 32)
-  LSIM_FLOOD_CASE(1024, 8)
   LSIM_FLOOD_CASE(1024, 16)
   LSIM_FLOOD_CASE(1024, 32)
 #undef LSIM_FLOOD_CASE

@@ -24,6 +24,24 @@ namespace {
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+template <int N>
+struct Deg {
+  static constexpr int value = N;
+};
+
+// Calls f(Deg<d>{}) for the wave-uniform degree d in [1, D], so each degree
+// runs a straight-line body whose LDS reads issue back to back.
+template <int D, class F>
+__device__ __forceinline__ void with_degree(int d, F&& f) {
+  if constexpr (D >= 1) {
+    if (d == D) {
+      f(Deg<D>{});
+      return;
+    }
+    with_degree<D - 1>(d, f);
+  }
+}
+
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 __host__ __device__ inline size_t tile_lds_bytes(const DevCode& c, int G) {
@@ -68,35 +86,60 @@ __device__ void decode_tile(const DevCode& c, int G, int64_t tile, const TileIO&
   float* myapp = app + (size_t)(active ? g : 0) * c.n_dec;
   uint32_t* st = io.state + (size_t)(cw0 + (active ? g : 0)) * c.rows * 3 * Z + r;
 
+  // The check state of the next layer is loaded one layer ahead so its
+  // memory latency overlaps the current layer.  A decoded graph has at
+  // least three layers, so a prefetched layer was stored at least two
+  // layers earlier.
+  const int rows = c.rows;
+  float n1 = 0.f, n2 = 0.f;
+  uint32_t npk_in = 0;
   for (int it = 0; it < iters; ++it) {
-    for (int i = 0; i < c.rows; ++i) {
+    for (int i = 0; i < rows; ++i) {
       const int e0 = uni(row_ptr[i]);
       const int d = uni(row_ptr[i + 1]) - e0;
+      const float a1 = n1, a2 = n2;
+      const uint32_t pk = npk_in;
+      {
+        int ni = i + 1, nit = it;
+        if (ni == rows) {
+          ni = 0;
+          ++nit;
+        }
+        if (active && nit >= 1 && nit < iters) {
+          const uint32_t* s2 = st + (size_t)ni * 3 * Z;
+          n1 = __uint_as_float(s2[0]);
+          n2 = __uint_as_float(s2[Z]);
+          npk_in = s2[2 * Z];
+        } else {
+          n1 = 0.f;
+          n2 = 0.f;
+          npk_in = 0;
+        }
+      }
       if (active) {
         uint32_t* sti = st + (size_t)i * 3 * Z;
-        float a1 = 0.f, a2 = 0.f;
-        uint32_t pk = 0;
-        if (it > 0) {
-          a1 = __uint_as_float(sti[0]);
-          a2 = __uint_as_float(sti[Z]);
-          pk = sti[2 * Z];
-        }
-        const int i1_old = (int)(pk >> 27);
-        float tv[DMAX];
-        int addr[DMAX];
-        uint32_t neg = 0;
-        float m1 = INFINITY, m2 = INFINITY;
-        int i1 = 0;
+        with_degree<DMAX>(d, [&](auto deg) {
+          constexpr int D = decltype(deg)::value;
+          int addr[D];
+          float tv[D];
 #pragma unroll
-        for (int q = 0; q < DMAX; ++q) {
-          if (q < d) {
+          for (int q = 0; q < D; ++q) {
             const int2 en = ent[e0 + q];
             int x = r + en.y;
             x -= x >= Z ? Z : 0;
             addr[q] = en.x + x;
+          }
+#pragma unroll
+          for (int q = 0; q < D; ++q) tv[q] = myapp[addr[q]];
+          const int i1_old = (int)(pk >> 27);
+          uint32_t neg = 0;
+          float m1 = INFINITY, m2 = INFINITY;
+          int i1 = 0;
+#pragma unroll
+          for (int q = 0; q < D; ++q) {
             const float mag = q == i1_old ? a2 : a1;
             const float rold = ((pk >> q) & 1u) ? -mag : mag;
-            const float t = __fsub_rn(myapp[addr[q]], rold);
+            const float t = __fsub_rn(tv[q], rold);
             tv[q] = t;
             neg |= (t < 0.f ? 1u : 0u) << q;
             const float at = fabsf(t);
@@ -104,23 +147,21 @@ __device__ void decode_tile(const DevCode& c, int G, int64_t tile, const TileIO&
             i1 = at < m1 ? q : i1;
             m1 = fminf(m1, at);
           }
-        }
-        const uint32_t par = __popc(neg) & 1u;
-        const float b1 = __fmul_rn(alpha, m1);
-        const float b2 = __fmul_rn(alpha, m2);
-        uint32_t npk = (uint32_t)i1 << 27;
+          const uint32_t par = __popc(neg) & 1u;
+          const float b1 = __fmul_rn(alpha, m1);
+          const float b2 = __fmul_rn(alpha, m2);
+          uint32_t npk = (uint32_t)i1 << 27;
 #pragma unroll
-        for (int q = 0; q < DMAX; ++q) {
-          if (q < d) {
+          for (int q = 0; q < D; ++q) {
             const float mag = q == i1 ? b2 : b1;
             const uint32_t sg = par ^ ((neg >> q) & 1u);
             myapp[addr[q]] = __fadd_rn(tv[q], sg ? -mag : mag);
             npk |= sg << q;
           }
-        }
-        sti[0] = __float_as_uint(b1);
-        sti[Z] = __float_as_uint(b2);
-        sti[2 * Z] = npk;
+          sti[0] = __float_as_uint(b1);
+          sti[Z] = __float_as_uint(b2);
+          sti[2 * Z] = npk;
+        });
       }
       __syncthreads();
     }
@@ -242,18 +283,14 @@ hipError_t launch_layered(const DevCode& c, const lsim_decode_params& p, const f
     layered_kernel<NT_, D_><<<grid, NT_, lds, s>>>(c, G, io, p.iters, p.alpha);    \
     return hipGetLastError();                                                      \
   }
-  LSIM_LAYER_CASE(256, 8)
   LSIM_LAYER_CASE(256, 16)
   LSIM_LAYER_CASE(256, 27)
-  LSIM_LAYER_CASE(384, 8)
   LSIM_LAYER_CASE(384, 16)
   LSIM_LAYER_CASE(384, 27)
-  LSIM_LAYER_CASE(512, 8)
   LSIM_LAYER_CASE(512, 16)
   LSIM_LAYER_CASE(512, 27)
   LSIM_LAYER_CASE(768, 16)
   LSIM_LAYER_CASE(768, 27)
-  LSIM_LAYER_CASE(1024, 8)
   LSIM_LAYER_CASE(1024, 16)
   LSIM_LAYER_CASE(1024, 27)
 #undef LSIM_LAYER_CASE

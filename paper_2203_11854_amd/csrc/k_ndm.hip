@@ -149,12 +149,27 @@ __global__ __launch_bounds__(64) void ndm_backward_kernel(const float* __restric
   if (lane < 4) out[OB3 + lane] = gb3;
 }
 
-__global__ void sum_rows_kernel(const float* __restrict__ part, int rows, int n,
-                                float* __restrict__ out) {
+// out[i] = sum over rows of part[r][i] in a fixed order: pass 1 sums
+// kSlices row slices, pass 2 adds the slices in order.
+constexpr int kSlices = 32;
+
+__global__ void sum_slices_kernel(const float* __restrict__ part, int rows, int n,
+                                  float* __restrict__ slices) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int per = (rows + kSlices - 1) / kSlices;
+  const int r0 = blockIdx.y * per;
+  const int r1 = min(rows, r0 + per);
+  float acc = 0.f;
+  for (int r = r0; r < r1; ++r) acc += part[(int64_t)r * n + i];
+  slices[(int64_t)blockIdx.y * n + i] = acc;
+}
+
+__global__ void sum_final_kernel(const float* __restrict__ slices, int n, float* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   float acc = 0.f;
-  for (int r = 0; r < rows; ++r) acc += part[(int64_t)r * n + i];
+  for (int k = 0; k < kSlices; ++k) acc += slices[(int64_t)k * n + i];
   out[i] = acc;
 }
 
@@ -212,7 +227,9 @@ inline int ndm_bwd_blocks(int64_t n) {
 
 }  // namespace
 
-size_t ndm_work_bytes(int64_t B, int64_t S) { return (size_t)ndm_bwd_blocks(B * S) * NP * 4; }
+size_t ndm_work_bytes(int64_t B, int64_t S) {
+  return ((size_t)ndm_bwd_blocks(B * S) + kSlices) * NP * 4;
+}
 
 hipError_t launch_ndm_forward(const float* params, const float* y, const float* no, int64_t B,
                               int64_t S, float* llr, hipStream_t s) {
@@ -229,7 +246,12 @@ hipError_t launch_ndm_backward(const float* params, const float* y, const float*
   ndm_backward_kernel<<<nb, 64, 0, s>>>(params, y, no, gllr, B, S, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  sum_rows_kernel<<<(NP + 255) / 256, 256, 0, s>>>(part, nb, NP, gparams);
+  float* slices = part + (size_t)nb * NP;
+  dim3 grid((NP + 255) / 256, kSlices);
+  sum_slices_kernel<<<grid, 256, 0, s>>>(part, nb, NP, slices);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  sum_final_kernel<<<(NP + 255) / 256, 256, 0, s>>>(slices, NP, gparams);
   return hipGetLastError();
 }
 

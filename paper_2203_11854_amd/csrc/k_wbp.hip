@@ -345,13 +345,29 @@ __global__ __launch_bounds__(kNT) void wbp_backward_kernel(
   }
 }
 
-// gw[t][e] = sum over b (in order) of part[b][t][e]
-__global__ void sum_over_batch_kernel(const float* __restrict__ part, int64_t B, int64_t n,
-                                      float* __restrict__ out) {
+// gw[t][e] = sum over b of part[b][t][e], in a fixed order: pass 1 sums
+// kSlices contiguous batch slices into slice partials (every block reads
+// coalesced rows), pass 2 adds the slices in order.
+constexpr int kSlices = 32;
+
+__global__ void sum_slices_kernel(const float* __restrict__ part, int64_t B, int64_t n,
+                                  float* __restrict__ slices) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t per = (B + kSlices - 1) / kSlices;
+  const int64_t b0 = (int64_t)blockIdx.y * per;
+  const int64_t b1 = min(B, b0 + per);
+  float acc = 0.f;
+  for (int64_t b = b0; b < b1; ++b) acc += part[b * n + i];
+  slices[(int64_t)blockIdx.y * n + i] = acc;
+}
+
+__global__ void sum_final_kernel(const float* __restrict__ slices, int64_t n,
+                                 float* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   float acc = 0.f;
-  for (int64_t b = 0; b < B; ++b) acc += part[b * n + i];
+  for (int k = 0; k < kSlices; ++k) acc += slices[(int64_t)k * n + i];
   out[i] = acc;
 }
 
@@ -368,7 +384,9 @@ hipError_t set_attr(const void* fn) {
 
 }  // namespace
 
-size_t wbp_work_bytes(const DevCode& c, int T, int64_t B) { return (size_t)B * T * c.E * 4; }
+size_t wbp_work_bytes(const DevCode& c, int T, int64_t B) {
+  return ((size_t)B + kSlices) * T * c.E * 4;
+}
 
 hipError_t launch_wbp_forward(const DevCode& c, int T, const float* w, const float* llr,
                               int64_t B, float llr_max, float* ckpt, float* lpost, hipStream_t s,
@@ -419,7 +437,12 @@ hipError_t launch_wbp_backward(const DevCode& c, int T, const float* w, const fl
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n = (int64_t)T * c.E;
-  sum_over_batch_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(part, B, n, gw);
+  float* slices = part + (size_t)B * n;
+  dim3 grid((unsigned)((n + 255) / 256), kSlices);
+  sum_slices_kernel<<<grid, 256, 0, s>>>(part, B, n, slices);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  sum_final_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(slices, n, gw);
   return hipGetLastError();
 }
 

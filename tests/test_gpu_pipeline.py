@@ -145,3 +145,25 @@ def test_invalid_arguments_raise():
                       torch.ones(1, device=dev), 1, 0)
     with pytest.raises(lsim.LsimError):
         lsim.quantize(torch.zeros(4, device=dev), scale=3.0)
+
+
+@pytest.mark.parametrize("algo", ["spa", "oms", "nms"])
+def test_link_run_equals_separate_calls(algo):
+    qb, code, m = code_for("bg2")
+    B = 37
+    no = T(np.full(B, 0.4, dtype=np.float32)).to(dev)
+    bins = T((np.arange(B) % 3).astype(np.int32)).to(dev)
+    p = lsim.params({"spa": lsim.SPA_F32, "oms": lsim.OMS_I8, "nms": lsim.NMS_F32}[algo])
+    link = lsim.Link(code, m, lsim.DEMAP_MAXLOG, p, B, no, bins=bins, nbins=3, device=dev)
+    link.run(1234, 5)
+    u = lsim.source_bits(1234, 5, B, code.k, dev)
+    c = lsim.encode(code, u)
+    y = lsim.map_awgn(code, m, c, no, 1234, 5)
+    if algo == "oms":
+        llr = lsim.demap_q8(m, lsim.DEMAP_MAXLOG, y, no)
+    else:
+        llr = lsim.demap(m, lsim.DEMAP_MAXLOG, y, no)
+    bits, _ = lsim.decode(code, llr, p)
+    cnt = lsim.count_errors(u, bits, bins, 3)
+    assert torch.equal(link.u, u) and torch.equal(link.c, c) and torch.equal(link.llr, llr)
+    assert torch.equal(link.bits, bits) and torch.equal(link.counts, cnt)
