@@ -126,7 +126,9 @@ enum { LSIM_DEMAP_EXACT = 0, LSIM_DEMAP_MAXLOG = 1 };
 /*
  * Demapper (Listing 1, "app" = exact; max-log): per-bit LLRs of each symbol
  * given N0.  d_y f32[B][S][2], d_no f32[B] -> d_llr f32[B][S*m].  Both
- * methods separate per I/Q axis for this labelling.  No clipping.
+ * methods separate per I/Q axis for this labelling.  No clipping.  d_y must
+ * be 8-byte aligned and d_llr aligned to 16 bytes for m = 4, 8 bytes for
+ * m = 2 and 6 (vector stores), else LSIM_E_INVAL.
  */
 lsim_status lsim_demap(int bits_per_sym, int method, const float* d_y, const float* d_no,
                        int64_t B, int64_t S, float* d_llr, lsim_stream stream);

@@ -316,10 +316,17 @@ static lsim_status check_demap(int m, int method, const void* y, const float* no
   return LSIM_OK;
 }
 
+static bool llr_aligned(int m, const void* p) {
+  const uintptr_t a = (uintptr_t)p;
+  return m == 4 ? (a & 15) == 0 : (m == 2 || m == 6) ? (a & 7) == 0 : (a & 3) == 0;
+}
+
 lsim_status lsim_demap(int bits_per_sym, int method, const float* d_y, const float* d_no,
                        int64_t B, int64_t S, float* d_llr, lsim_stream stream) {
   lsim_status st = check_demap(bits_per_sym, method, d_y, d_no, B, S, d_llr);
   if (st != LSIM_OK) return st;
+  if (!llr_aligned(bits_per_sym, d_llr) || ((uintptr_t)d_y & 7))
+    return fail(LSIM_E_INVAL, "d_llr must be aligned to 4*m bytes (16 for m=4, 8 for m=2,6), d_y to 8");
   return dev_status(lsim::launch_demap(bits_per_sym, method, d_y, d_no, B, S, d_llr, nullptr,
                                        0.f, 0, as_stream(stream)),
                     "demap");
@@ -421,6 +428,7 @@ struct lsim_plan {
   std::vector<lsim::LayerShape> shapes;
   lsim_decode_params p;
   int threads = 0;
+  int dmax = 0;
   size_t lds = 0;
   int grid = 0;
   int64_t ntiles = 0;
@@ -500,6 +508,7 @@ lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t*
   }
   plan->ntiles = tile0;
   plan->state_words = (size_t)state_off;
+  plan->dmax = dmax;
   // work list, heaviest tiles first: a tile costs about one pass over the
   // base nonzeros plus one barrier per layer, per iteration
   std::vector<int> order(nshapes);
@@ -575,7 +584,7 @@ lsim_status lsim_mixed_decode(lsim_plan* plan, const void* d_llr_concat, uint8_t
   hipError_t e = lsim::launch_mixed(
       plan->d_shapes, (int)plan->shapes.size(), plan->d_tile_shape, plan->d_tile_local,
       plan->ntiles, plan->threads, plan->lds, plan->p, d_llr_concat, d_bits_concat, d_app_concat,
-      (uint32_t*)(w + kCounterBytes), (int*)w, persistent ? 1 : 0, plan->grid,
+      (uint32_t*)(w + kCounterBytes), (int*)w, persistent ? 1 : 0, plan->grid, plan->dmax,
       as_stream(stream));
   return dev_status(e, "mixed decode");
 }
@@ -710,6 +719,8 @@ extern "C" lsim_status lsim_link_run(const lsim_link_args* a, lsim_stream stream
   if ((int64_t)c.n_mother > 48 * 1024)
     return fail(LSIM_E_UNSUPPORTED, "mother code too long for the encoder's LDS tile");
   const bool q8 = a->dec.algo == LSIM_OMS_I8;
+  if ((!q8 && !llr_aligned(m, a->d_llr)) || ((uintptr_t)a->d_y & 7))
+    return fail(LSIM_E_INVAL, "d_llr must be aligned to 4*m bytes (16 for m=4, 8 for m=2,6), d_y to 8");
   if (q8 && !is_pow2_scale(a->q_scale)) return fail(LSIM_E_INVAL, "q_scale must be a power of two");
   if (a->dec.algo == LSIM_NMS_F32) {
     const size_t need = lsim::layered_state_words(c, a->B) * 4;

@@ -210,12 +210,14 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
           M x[D];
 #pragma unroll
           for (int q = 0; q < D; ++q) x[q] = row[q * Z];
-          uint32_t neg = 0;
-#pragma unroll
-          for (int q = 0; q < D; ++q) neg |= (x[q] < 0 ? 1u : 0u) << q;
-          const uint32_t par = __popc(neg) & 1u;
           if constexpr (ALG == LSIM_SPA_F32) {
-            // sum-product in the "1 - prod tanh" domain (spa_math.h)
+            // sum-product in the "1 - prod tanh" domain (spa_math.h); the
+            // output sign is the XOR of the other inputs' sign bits (a zero
+            // input only ever receives or sends zero magnitudes, so the sign
+            // of a zero is immaterial)
+            uint32_t sx = 0;
+#pragma unroll
+            for (int q = 0; q < D; ++q) sx ^= __float_as_uint(x[q]);
             float mm[D], pre[D];
             float dp = 0.f;
 #pragma unroll
@@ -228,10 +230,15 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
 #pragma unroll
             for (int q = D - 1; q >= 0; --q) {
               const float rv = fminf(spa_mag(spa_combine(pre[q], ds)), a.llr_max);
-              row[q * Z] = (par ^ ((neg >> q) & 1u)) ? -rv : rv;
+              const uint32_t sg = (sx ^ __float_as_uint(x[q])) & 0x80000000u;
+              row[q * Z] = __uint_as_float(__float_as_uint(rv) | sg);
               ds = spa_combine(ds, mm[q]);
             }
           } else {
+            uint32_t neg = 0;
+#pragma unroll
+            for (int q = 0; q < D; ++q) neg |= (x[q] < 0 ? 1u : 0u) << q;
+            const uint32_t par = __popc(neg) & 1u;
             int m1 = 255, m2 = 255, i1 = 0;
 #pragma unroll
             for (int q = 0; q < D; ++q) {
@@ -292,10 +299,13 @@ hipError_t dispatch(const DevCode& c, int nt, const FloodArgs& a, size_t lds, hi
 #define LSIM_FLOOD_CASE(NT_, D_) \
   if (nt == NT_ && dmax <= D_) return launch_t<NT_, D_, ALG>(c, a, lds, s);
   LSIM_FLOOD_CASE(256, 16)
+  LSIM_FLOOD_CASE(256, 24)
   LSIM_FLOOD_CASE(256, 32)
   LSIM_FLOOD_CASE(512, 16)
+  LSIM_FLOOD_CASE(512, 24)
   LSIM_FLOOD_CASE(512, 32)
   LSIM_FLOOD_CASE(1024, 16)
+  LSIM_FLOOD_CASE(1024, 24)
   LSIM_FLOOD_CASE(1024, 32)
 #undef LSIM_FLOOD_CASE
   return hipErrorInvalidValue;

@@ -58,7 +58,7 @@ struct TileIO {
 };
 
 template <int NT, int DMAX>
-__device__ void decode_tile(const DevCode& c, int G, int64_t tile, const TileIO& io, int iters,
+__device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t tile, const TileIO& io, int iters,
                             float alpha, unsigned char* smem) {
   float* app = reinterpret_cast<float*>(smem);
   int* row_ptr = reinterpret_cast<int*>(smem + align16((size_t)G * c.n_dec * 4));
@@ -284,14 +284,19 @@ hipError_t launch_layered(const DevCode& c, const lsim_decode_params& p, const f
     return hipGetLastError();                                                      \
   }
   LSIM_LAYER_CASE(256, 16)
+  LSIM_LAYER_CASE(256, 24)
   LSIM_LAYER_CASE(256, 27)
   LSIM_LAYER_CASE(384, 16)
+  LSIM_LAYER_CASE(384, 24)
   LSIM_LAYER_CASE(384, 27)
   LSIM_LAYER_CASE(512, 16)
+  LSIM_LAYER_CASE(512, 24)
   LSIM_LAYER_CASE(512, 27)
   LSIM_LAYER_CASE(768, 16)
+  LSIM_LAYER_CASE(768, 24)
   LSIM_LAYER_CASE(768, 27)
   LSIM_LAYER_CASE(1024, 16)
+  LSIM_LAYER_CASE(1024, 24)
   LSIM_LAYER_CASE(1024, 27)
 #undef LSIM_LAYER_CASE
   return hipErrorInvalidValue;
@@ -303,7 +308,7 @@ hipError_t launch_mixed(const LayerShape* d_shapes, int nshapes, const int* d_ti
                         const int64_t* d_tile_local, int64_t ntiles, int threads,
                         size_t lds_bytes, const lsim_decode_params& p, const void* llr,
                         uint8_t* bits, float* lpost, uint32_t* state, int* counter,
-                        int persistent, int grid, hipStream_t s) {
+                        int persistent, int grid, int dmax, hipStream_t s) {
   (void)nshapes;
   if (persistent) {
     reset_counter_kernel<<<1, 1, 0, s>>>(counter);
@@ -311,21 +316,31 @@ hipError_t launch_mixed(const LayerShape* d_shapes, int nshapes, const int* d_ti
     if (e != hipSuccess) return e;
   }
   const unsigned g = persistent ? (unsigned)grid : (unsigned)ntiles;
-#define LSIM_MIXED_CASE(NT_)                                                               \
-  if (threads == NT_) {                                                                    \
-    hipError_t e = set_attr_once<NT_, 27>((const void*)mixed_kernel<NT_, 27>);             \
+#define LSIM_MIXED_CASE(NT_, D_)                                                           \
+  if (threads == NT_ && dmax <= D_) {                                                      \
+    hipError_t e = set_attr_once<NT_, D_>((const void*)mixed_kernel<NT_, D_>);             \
     if (e != hipSuccess) return e;                                                         \
-    mixed_kernel<NT_, 27><<<g, NT_, lds_bytes, s>>>(d_shapes, d_tile_shape, d_tile_local,  \
+    mixed_kernel<NT_, D_><<<g, NT_, lds_bytes, s>>>(d_shapes, d_tile_shape, d_tile_local,  \
                                                     ntiles, (const float*)llr, bits, lpost, \
                                                     state, counter, persistent, p.iters,   \
                                                     p.alpha);                              \
     return hipGetLastError();                                                              \
   }
-  LSIM_MIXED_CASE(256)
-  LSIM_MIXED_CASE(384)
-  LSIM_MIXED_CASE(512)
-  LSIM_MIXED_CASE(768)
-  LSIM_MIXED_CASE(1024)
+  LSIM_MIXED_CASE(256, 16)
+  LSIM_MIXED_CASE(256, 24)
+  LSIM_MIXED_CASE(256, 27)
+  LSIM_MIXED_CASE(384, 16)
+  LSIM_MIXED_CASE(384, 24)
+  LSIM_MIXED_CASE(384, 27)
+  LSIM_MIXED_CASE(512, 16)
+  LSIM_MIXED_CASE(512, 24)
+  LSIM_MIXED_CASE(512, 27)
+  LSIM_MIXED_CASE(768, 16)
+  LSIM_MIXED_CASE(768, 24)
+  LSIM_MIXED_CASE(768, 27)
+  LSIM_MIXED_CASE(1024, 16)
+  LSIM_MIXED_CASE(1024, 24)
+  LSIM_MIXED_CASE(1024, 27)
 #undef LSIM_MIXED_CASE
   return hipErrorInvalidValue;
 }

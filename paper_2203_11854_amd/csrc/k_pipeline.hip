@@ -164,36 +164,42 @@ __global__ void map_awgn_kernel(DevCode c, int m, const uint8_t* __restrict__ cw
 
 // --------------------------------------------------------------- demapper
 
-// Per-axis LLRs of h Gray bits for coordinate v (unit-energy scale `inv`):
-// max-log: (min_{b=0} d^2 - min_{b=1} d^2) / N0; exact: log-sum-exp of
-// -d^2/N0 over the levels with bit 1 minus that over bit 0.
-__device__ __forceinline__ void axis_llr(float v, float inv_no, int h, float inv, bool exact,
-                                         float* out) {
-  const int nl = 1 << h;
-  float d2[8];
+// Unit-energy Gray PAM levels per axis, indexed by the axis label read
+// MSB-first (bits a0 a1 ...), for h = 1, 2, 3 bits per axis.
+__constant__ float kPam1[2] = {0.70710678118654752f, -0.70710678118654752f};
+__constant__ float kPam2[4] = {0.31622776601683794f, 0.94868329805051381f, -0.31622776601683794f,
+                               -0.94868329805051381f};
+__constant__ float kPam3[8] = {0.46291004988627573f, 0.15430334996209191f, 0.77151674981045953f,
+                               1.08012344973464337f, -0.46291004988627573f, -0.15430334996209191f,
+                               -0.77151674981045953f, -1.08012344973464337f};
+
+// Per-axis LLRs of h Gray bits for coordinate v: max-log
+// (min_{b=0} d^2 - min_{b=1} d^2) / N0, or exact: log-sum-exp of -d^2/N0
+// over the levels with bit 1 minus that over bit 0.
+template <int h>
+__device__ __forceinline__ void axis_llr(float v, float inv_no, bool exact, float* out) {
+  constexpr int nl = 1 << h;
+  const float* lv = h == 1 ? kPam1 : h == 2 ? kPam2 : kPam3;
+  float d2[nl];
+#pragma unroll
   for (int l = 0; l < nl; ++l) {
-    uint32_t a[3];
-    for (int q = 0; q < h; ++q) a[q] = (l >> (h - 1 - q)) & 1u;
-    const float lv = pam_level(a, h) * inv;
-    const float dv = v - lv;
+    const float dv = v - lv[l];
     d2[l] = dv * dv * inv_no;
   }
+#pragma unroll
   for (int q = 0; q < h; ++q) {
     const int sh = h - 1 - q;
+    float m0 = INFINITY, m1 = INFINITY;
+#pragma unroll
+    for (int l = 0; l < nl; ++l) {
+      if ((l >> sh) & 1) m1 = fminf(m1, d2[l]);
+      else m0 = fminf(m0, d2[l]);
+    }
     if (!exact) {
-      float m0 = INFINITY, m1 = INFINITY;
-      for (int l = 0; l < nl; ++l) {
-        if ((l >> sh) & 1) m1 = fminf(m1, d2[l]);
-        else m0 = fminf(m0, d2[l]);
-      }
       out[q] = m0 - m1;
     } else {
-      float m0 = INFINITY, m1 = INFINITY;
-      for (int l = 0; l < nl; ++l) {
-        if ((l >> sh) & 1) m1 = fminf(m1, d2[l]);
-        else m0 = fminf(m0, d2[l]);
-      }
       float s0 = 0.f, s1 = 0.f;
+#pragma unroll
       for (int l = 0; l < nl; ++l) {
         if ((l >> sh) & 1) s1 += expf(m1 - d2[l]);
         else s0 += expf(m0 - d2[l]);
@@ -203,37 +209,53 @@ __device__ __forceinline__ void axis_llr(float v, float inv_no, int h, float inv
   }
 }
 
-__global__ void demap_kernel(int m, int method, const float* __restrict__ y,
-                             const float* __restrict__ no, int64_t B, int64_t S,
-                             float* __restrict__ llr, int8_t* __restrict__ q, float scale,
-                             int sat) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= B * S) return;
-  const int64_t b = t / S;
-  const float2 yy = reinterpret_cast<const float2*>(y)[t];
-  const float n0 = no[b];
-  float L[6];
-  if (m == 1) {
+template <int M>
+__device__ __forceinline__ void symbol_llr(float2 yy, float n0, bool exact, float* L) {
+  if constexpr (M == 1) {
     L[0] = -4.0f * yy.x / n0;
   } else {
-    const int h = m >> 1;
+    constexpr int h = M / 2;
     const float inv_no = 1.0f / n0;
-    float li[3], lq[3];
-    const bool exact = method == LSIM_DEMAP_EXACT;
-    axis_llr(yy.x, inv_no, h, qam_inv_scale(h), exact, li);
-    axis_llr(yy.y, inv_no, h, qam_inv_scale(h), exact, lq);
+    float li[h], lq[h];
+    axis_llr<h>(yy.x, inv_no, exact, li);
+    axis_llr<h>(yy.y, inv_no, exact, lq);
+#pragma unroll
     for (int i = 0; i < h; ++i) {
       L[2 * i] = li[i];
       L[2 * i + 1] = lq[i];
     }
   }
+}
+
+template <int M>
+__global__ void demap_kernel(int method, const float* __restrict__ y, const float* __restrict__ no,
+                             int64_t B, int64_t S, float* __restrict__ llr,
+                             int8_t* __restrict__ q, float scale, int sat) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B * S) return;
+  const int64_t b = t / S;
+  float L[M];
+  symbol_llr<M>(reinterpret_cast<const float2*>(y)[t], no[b], method == LSIM_DEMAP_EXACT, L);
   if (llr) {
-    for (int i = 0; i < m; ++i) llr[t * m + i] = L[i];
-  } else {
-    for (int i = 0; i < m; ++i) {
-      const float v = fminf(fmaxf(rintf(L[i] * scale), (float)-sat), (float)sat);
-      q[t * m + i] = (int8_t)v;
+    float* o = llr + t * M;
+    if constexpr (M == 4) {
+      *reinterpret_cast<float4*>(o) = make_float4(L[0], L[1], L[2], L[3]);
+    } else if constexpr (M == 2) {
+      *reinterpret_cast<float2*>(o) = make_float2(L[0], L[1]);
+    } else if constexpr (M == 6) {
+      reinterpret_cast<float2*>(o)[0] = make_float2(L[0], L[1]);
+      reinterpret_cast<float2*>(o)[1] = make_float2(L[2], L[3]);
+      reinterpret_cast<float2*>(o)[2] = make_float2(L[4], L[5]);
+    } else {
+      o[0] = L[0];
     }
+  } else {
+    int8_t qq[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+      qq[i] = (int8_t)fminf(fmaxf(rintf(L[i] * scale), (float)-sat), (float)sat);
+#pragma unroll
+    for (int i = 0; i < M; ++i) q[t * M + i] = qq[i];
   }
 }
 
@@ -247,28 +269,37 @@ __global__ void quantize_kernel(const float* __restrict__ L, int64_t n, float sc
 
 // ------------------------------------------------------------ error count
 
+// One wavefront per codeword.  Bits are bytes holding 0/1, so the
+// population count of the XOR of two 32-bit words counts 4 bit errors at
+// a time; rows that are not 4-byte aligned fall back to bytes.
 __global__ __launch_bounds__(256) void count_errors_kernel(const uint8_t* __restrict__ ref,
                                                            int64_t ref_stride,
                                                            const uint8_t* __restrict__ hat,
-                                                           int64_t k, const int32_t* __restrict__ bin,
+                                                           int64_t k, int64_t B,
+                                                           const int32_t* __restrict__ bin,
                                                            int nbins, int64_t* __restrict__ counts) {
-  __shared__ int part[4];
-  const int64_t b = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (b >= B) return;
   const uint8_t* rr = ref + b * ref_stride;
   const uint8_t* hh = hat + b * k;
   int err = 0;
-  for (int64_t i = threadIdx.x; i < k; i += blockDim.x) err += (rr[i] & 1) != (hh[i] & 1);
+  if (((((uintptr_t)rr) | ((uintptr_t)hh)) & 3) == 0) {
+    const int64_t nw = k >> 2;
+    const uint32_t* r4 = reinterpret_cast<const uint32_t*>(rr);
+    const uint32_t* h4 = reinterpret_cast<const uint32_t*>(hh);
+    for (int64_t i = lane; i < nw; i += 64) err += __popc((r4[i] ^ h4[i]) & 0x01010101u);
+    for (int64_t i = nw * 4 + lane; i < k; i += 64) err += (rr[i] & 1) != (hh[i] & 1);
+  } else {
+    for (int64_t i = lane; i < k; i += 64) err += (rr[i] & 1) != (hh[i] & 1);
+  }
   for (int off = 32; off > 0; off >>= 1) err += __shfl_down(err, off, 64);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = err;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int tot = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += part[w];
+  if (lane == 0) {
     const int bb = bin ? bin[b] : 0;
     if (bb < 0 || bb >= nbins) return;  // codewords outside every bin are not counted
     unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counts) + 3 * (int64_t)bb;
-    atomicAdd(cnt + 0, (unsigned long long)tot);
-    atomicAdd(cnt + 1, (unsigned long long)(tot > 0));
+    atomicAdd(cnt + 0, (unsigned long long)err);
+    atomicAdd(cnt + 1, (unsigned long long)(err > 0));
     atomicAdd(cnt + 2, 1ull);
   }
 }
@@ -325,7 +356,13 @@ hipError_t launch_map_awgn(const DevCode& c, int m, const uint8_t* cw, const flo
 
 hipError_t launch_demap(int m, int method, const float* y, const float* no, int64_t B, int64_t S,
                         float* llr, int8_t* q, float scale, int sat, hipStream_t s) {
-  demap_kernel<<<grid_for(B * S, 256), 256, 0, s>>>(m, method, y, no, B, S, llr, q, scale, sat);
+  const unsigned g = grid_for(B * S, 256);
+  switch (m) {
+    case 1: demap_kernel<1><<<g, 256, 0, s>>>(method, y, no, B, S, llr, q, scale, sat); break;
+    case 2: demap_kernel<2><<<g, 256, 0, s>>>(method, y, no, B, S, llr, q, scale, sat); break;
+    case 4: demap_kernel<4><<<g, 256, 0, s>>>(method, y, no, B, S, llr, q, scale, sat); break;
+    default: demap_kernel<6><<<g, 256, 0, s>>>(method, y, no, B, S, llr, q, scale, sat); break;
+  }
   return hipGetLastError();
 }
 
@@ -338,7 +375,8 @@ hipError_t launch_quantize(const float* llr, int64_t n, float scale, int sat, in
 hipError_t launch_count_errors(const uint8_t* ref, int64_t ref_stride, const uint8_t* hat,
                                int64_t B, int64_t k, const int32_t* bin, int nbins,
                                int64_t* counts, hipStream_t s) {
-  count_errors_kernel<<<(unsigned)B, 256, 0, s>>>(ref, ref_stride, hat, k, bin, nbins, counts);
+  count_errors_kernel<<<(unsigned)((B + 3) / 4), 256, 0, s>>>(ref, ref_stride, hat, k, B, bin,
+                                                               nbins, counts);
   return hipGetLastError();
 }
 

@@ -68,7 +68,7 @@ hipError_t launch_mixed(const LayerShape* d_shapes, int nshapes, const int* d_ti
                         const int64_t* d_tile_local, int64_t ntiles, int threads,
                         size_t lds_bytes, const lsim_decode_params& p, const void* llr,
                         uint8_t* bits, float* lpost, uint32_t* state, int* counter,
-                        int persistent, int grid, hipStream_t s);
+                        int persistent, int grid, int dmax, hipStream_t s);
 
 // Pipeline kernels (k_pipeline.hip)
 hipError_t launch_source_bits(uint64_t seed, int64_t cw0, int64_t B, int64_t k, uint8_t* u,
