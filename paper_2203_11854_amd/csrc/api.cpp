@@ -204,6 +204,20 @@ lsim_status lsim_code_create(const int16_t* base, int mb, int nb, int Z, int fam
   };
   size_t o_row = push(c->row_ptr), o_col = push(c->ent_col), o_sh = push(c->ent_shift),
          o_cp = push(c->col_ptr), o_ce = push(c->col_ent), o_cn = push(cn), o_vn = push(vn);
+  std::vector<int> ce2(2 * (size_t)nnz);
+  for (int i = 0; i < nnz; ++i) {
+    const int e = c->col_ent[i];
+    ce2[2 * i] = e * Z;
+    ce2[2 * i + 1] = c->ent_shift[e];
+  }
+  std::vector<int> ecz(2 * (size_t)nnz);
+  for (int e = 0; e < nnz; ++e) {
+    ecz[2 * e] = c->ent_col[e] * Z;
+    ecz[2 * e + 1] = c->ent_shift[e];
+  }
+  if (blob.size() & 1) blob.push_back(0);  // 8-byte alignment of the int2 tables
+  size_t o_ce2 = push(ce2);
+  size_t o_ecz = push(ecz);
   size_t o_base = blob.size();
   blob.resize(blob.size() + ((size_t)mb * nb + 1) / 2, 0);
   std::memcpy(blob.data() + o_base, H.data(), H.size() * sizeof(int16_t));
@@ -245,6 +259,8 @@ lsim_status lsim_code_create(const int16_t* base, int mb, int nb, int Z, int fam
   dc.cn_tasks = d + o_cn;
   dc.vn_tasks = d + o_vn;
   dc.base = reinterpret_cast<const int16_t*>(d + o_base);
+  dc.col_edge = reinterpret_cast<const int2*>(d + o_ce2);
+  dc.ent_cz = reinterpret_cast<const int2*>(d + o_ecz);
   lsim_code_info& in = c->info;
   in.k = dc.k;
   in.n_mother = dc.n_mother;

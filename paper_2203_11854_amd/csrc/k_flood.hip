@@ -42,15 +42,6 @@ struct FloodArgs {
   int sat;
 };
 
-// Small graph tables staged in LDS (read with wave-uniform addresses).
-struct Tables {
-  int* cn_tasks;
-  int* vn_tasks;
-  int* row_ptr;
-  int* col_ptr;
-  int2* col_edge;  // per column entry: (e * Z, shift)
-};
-
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 template <int N>
@@ -87,15 +78,10 @@ struct Traits<LSIM_OMS_I8> {
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-__host__ __device__ inline size_t table_bytes(const DevCode& c) {
-  return align16((size_t)(c.n_cn_tasks + c.n_vn_tasks + c.rows + 1 + c.cols + 1) * 4) +
-         (size_t)c.nnz * 8;
-}
-
 template <int ALG>
 __host__ __device__ inline size_t lds_bytes_for(const DevCode& c) {
   using M = typename Traits<ALG>::Msg;
-  return align16((size_t)c.E * sizeof(M)) + align16((size_t)c.n_dec * sizeof(M)) + table_bytes(c);
+  return align16((size_t)c.E * sizeof(M)) + align16((size_t)c.n_dec * sizeof(M));
 }
 
 template <int NT, int DMAX, int ALG>
@@ -106,30 +92,16 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   M* msg = reinterpret_cast<M*>(smem);
   M* lam = reinterpret_cast<M*>(smem + align16((size_t)c.E * sizeof(M)));
-  unsigned char* tb = smem + align16((size_t)c.E * sizeof(M)) + align16((size_t)c.n_dec * sizeof(M));
-  Tables t;
-  t.cn_tasks = reinterpret_cast<int*>(tb);
-  t.vn_tasks = t.cn_tasks + c.n_cn_tasks;
-  t.row_ptr = t.vn_tasks + c.n_vn_tasks;
-  t.col_ptr = t.row_ptr + c.rows + 1;
-  t.col_edge = reinterpret_cast<int2*>(
-      tb + align16((size_t)(c.n_cn_tasks + c.n_vn_tasks + c.rows + 1 + c.cols + 1) * 4));
-
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = uni(tid >> 6);
   const int Z = c.Z;
   const int64_t b = blockIdx.x;
 
-  // ---- stage tables, channel LLRs, zero messages
-  for (int i = tid; i < c.n_cn_tasks; i += NT) t.cn_tasks[i] = c.cn_tasks[i];
-  for (int i = tid; i < c.n_vn_tasks; i += NT) t.vn_tasks[i] = c.vn_tasks[i];
-  for (int i = tid; i <= c.rows; i += NT) t.row_ptr[i] = c.row_ptr[i];
-  for (int i = tid; i <= c.cols; i += NT) t.col_ptr[i] = c.col_ptr[i];
-  for (int i = tid; i < c.nnz; i += NT) {
-    const int e = c.col_ent[i];
-    t.col_edge[i] = make_int2(e * Z, c.ent_shift[e]);
-  }
+  // ---- channel LLRs, zero messages (graph tables are read with scalar
+  // loads from the code's device tables)
+  const int zm = Z - 1;
+  const bool zpow2 = (Z & zm) == 0;
   const In* llr = reinterpret_cast<const In*>(a.llr) + b * (int64_t)c.e_tx;
   for (int v = tid; v < c.n_dec; v += NT) {
     const int x = v - c.tx_lo;
@@ -154,11 +126,11 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
   // variable phase; mode 0: q <- clamp(lam + sum r - r), 1: last round
   auto var_phase = [&](bool write_q, bool final_round) {
     for (int ti = wave; ti < c.n_vn_tasks; ti += NW) {
-      const int task = uni(t.vn_tasks[ti]);
+      const int task = uni(ld_const(c.vn_tasks, ti));
       const int j = task >> 16;
       const int cc = (task & 0xffff) + lane;
-      const int cb = uni(t.col_ptr[j]);
-      const int dc = uni(t.col_ptr[j + 1]) - cb;
+      const int cb = uni(ld_const(c.col_ptr, j));
+      const int dc = uni(ld_const(c.col_ptr, j + 1)) - cb;
       if (cc < Z) {
         const int v = j * Z + cc;
         with_degree<DMAX>(dc, [&](auto deg) {
@@ -166,15 +138,26 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
           int idx[DC];
           using Acc = typename std::conditional<ALG == LSIM_SPA_F32, float, int>::type;
           Acc rv[DC];
+          // byte offset of entry e's edge at lift c: (e*Z + (c - shift) mod Z) * sizeof(M)
+          constexpr int SZ = sizeof(M);
+          if (zpow2) {
 #pragma unroll
-          for (int q = 0; q < DC; ++q) {
-            const int2 ce = t.col_edge[cb + q];
-            int x = cc - ce.y;
-            x += x < 0 ? Z : 0;
-            idx[q] = ce.x + x;
+            for (int q = 0; q < DC; ++q) {
+              const int2 ce = ld_const(c.col_edge, cb + q);
+              idx[q] = ((cc * SZ - ce.y * SZ) & (zm * SZ)) | (ce.x * SZ);
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < DC; ++q) {
+              const int2 ce = ld_const(c.col_edge, cb + q);
+              int x = cc - ce.y;
+              x += x < 0 ? Z : 0;
+              idx[q] = (ce.x + x) * SZ;
+            }
           }
+          unsigned char* mb = reinterpret_cast<unsigned char*>(msg);
 #pragma unroll
-          for (int q = 0; q < DC; ++q) rv[q] = msg[idx[q]];
+          for (int q = 0; q < DC; ++q) rv[q] = *reinterpret_cast<M*>(mb + idx[q]);
           Acc acc = lam[v];
 #pragma unroll
           for (int q = 0; q < DC; ++q) acc += rv[q];
@@ -182,9 +165,10 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
 #pragma unroll
             for (int q = 0; q < DC; ++q) {
               if constexpr (ALG == LSIM_SPA_F32)
-                msg[idx[q]] = fminf(fmaxf(acc - rv[q], -a.llr_max), a.llr_max);
+                *reinterpret_cast<M*>(mb + idx[q]) =
+                    __builtin_amdgcn_fmed3f(acc - rv[q], -a.llr_max, a.llr_max);
               else
-                msg[idx[q]] = (M)min(max(acc - rv[q], -a.sat), a.sat);
+                *reinterpret_cast<M*>(mb + idx[q]) = (M)min(max(acc - rv[q], -a.sat), a.sat);
             }
           }
           if (final_round) {
@@ -198,11 +182,11 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
 
   auto check_phase = [&]() {
     for (int ti = wave; ti < c.n_cn_tasks; ti += NW) {
-      const int task = uni(t.cn_tasks[ti]);
+      const int task = uni(ld_const(c.cn_tasks, ti));
       const int i = task >> 16;
       const int r = (task & 0xffff) + lane;
-      const int e0 = uni(t.row_ptr[i]);
-      const int d = uni(t.row_ptr[i + 1]) - e0;
+      const int e0 = uni(ld_const(c.row_ptr, i));
+      const int d = uni(ld_const(c.row_ptr, i + 1)) - e0;
       if (r < Z) {
         M* row = msg + (size_t)e0 * Z + r;
         with_degree<DMAX>(d, [&](auto deg) {
@@ -218,21 +202,23 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
             uint32_t sx = 0;
 #pragma unroll
             for (int q = 0; q < D; ++q) sx ^= __float_as_uint(x[q]);
-            float mm[D], pre[D];
-            float dp = 0.f;
+            float mm[D], pD[D], pC[D];
+            SpaAcc pre;
 #pragma unroll
             for (int q = 0; q < D; ++q) {
               mm[q] = spa_m(x[q]);
-              pre[q] = dp;
-              dp = spa_combine(dp, mm[q]);
+              pD[q] = pre.D;
+              pC[q] = pre.C;
+              pre.add(mm[q]);
             }
-            float ds = 0.f;
+            SpaAcc suf;
 #pragma unroll
             for (int q = D - 1; q >= 0; --q) {
-              const float rv = fminf(spa_mag(spa_combine(pre[q], ds)), a.llr_max);
+              const float Dx = fmaf(suf.D, pC[q], pD[q]);
+              const float rv = fminf(spa_mag(Dx), a.llr_max);
               const uint32_t sg = (sx ^ __float_as_uint(x[q])) & 0x80000000u;
               row[q * Z] = __uint_as_float(__float_as_uint(rv) | sg);
-              ds = spa_combine(ds, mm[q]);
+              suf.add(mm[q]);
             }
           } else {
             uint32_t neg = 0;

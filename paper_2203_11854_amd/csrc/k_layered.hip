@@ -45,7 +45,7 @@ __device__ __forceinline__ void with_degree(int d, F&& f) {
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 __host__ __device__ inline size_t tile_lds_bytes(const DevCode& c, int G) {
-  return align16((size_t)G * c.n_dec * 4) + align16((size_t)(c.rows + 1) * 4) + (size_t)c.nnz * 8;
+  return align16((size_t)G * c.n_dec * 4);
 }
 
 struct TileIO {
@@ -61,16 +61,11 @@ template <int NT, int DMAX>
 __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t tile, const TileIO& io, int iters,
                             float alpha, unsigned char* smem) {
   float* app = reinterpret_cast<float*>(smem);
-  int* row_ptr = reinterpret_cast<int*>(smem + align16((size_t)G * c.n_dec * 4));
-  int2* ent = reinterpret_cast<int2*>(smem + align16((size_t)G * c.n_dec * 4) +
-                                      align16((size_t)(c.rows + 1) * 4));
   const int Z = c.Z;
   const int tid = threadIdx.x;
   const int64_t cw0 = tile * G;
   const int gmax = (int)min<int64_t>(G, io.count - cw0);
 
-  for (int i = tid; i <= c.rows; i += NT) row_ptr[i] = c.row_ptr[i];
-  for (int i = tid; i < c.nnz; i += NT) ent[i] = make_int2(c.ent_col[i] * Z, c.ent_shift[i]);
   for (int idx = tid; idx < G * c.n_dec; idx += NT) {
     const int g = idx / c.n_dec, v = idx - g * c.n_dec;
     const int x = v - c.tx_lo;
@@ -83,7 +78,9 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
   const int g = tid / Z;
   const int r = tid - g * Z;
   const bool active = g < gmax;
-  float* myapp = app + (size_t)(active ? g : 0) * c.n_dec;
+  unsigned char* myapp = reinterpret_cast<unsigned char*>(app + (size_t)(active ? g : 0) * c.n_dec);
+  const int zm4 = (Z - 1) * 4, r4 = r * 4;
+  const bool zpow2 = (Z & (Z - 1)) == 0;
   uint32_t* st = io.state + (size_t)(cw0 + (active ? g : 0)) * c.rows * 3 * Z + r;
 
   // The check state of the next layer is loaded one layer ahead so its
@@ -95,8 +92,8 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
   uint32_t npk_in = 0;
   for (int it = 0; it < iters; ++it) {
     for (int i = 0; i < rows; ++i) {
-      const int e0 = uni(row_ptr[i]);
-      const int d = uni(row_ptr[i + 1]) - e0;
+      const int e0 = uni(ld_const(c.row_ptr, i));
+      const int d = uni(ld_const(c.row_ptr, i + 1)) - e0;
       const float a1 = n1, a2 = n2;
       const uint32_t pk = npk_in;
       {
@@ -122,41 +119,53 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
           constexpr int D = decltype(deg)::value;
           int addr[D];
           float tv[D];
+          // byte offset of the variable node of entry e at lift r:
+          // (col*Z + (r + shift) mod Z) * 4
+          if (zpow2) {
 #pragma unroll
-          for (int q = 0; q < D; ++q) {
-            const int2 en = ent[e0 + q];
-            int x = r + en.y;
-            x -= x >= Z ? Z : 0;
-            addr[q] = en.x + x;
+            for (int q = 0; q < D; ++q) {
+              const int2 en = ld_const(c.ent_cz, e0 + q);
+              addr[q] = ((r4 + en.y * 4) & zm4) | (en.x * 4);
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+              const int2 en = ld_const(c.ent_cz, e0 + q);
+              int x = r + en.y;
+              x -= x >= Z ? Z : 0;
+              addr[q] = (en.x + x) * 4;
+            }
           }
 #pragma unroll
-          for (int q = 0; q < D; ++q) tv[q] = myapp[addr[q]];
+          for (int q = 0; q < D; ++q) tv[q] = *reinterpret_cast<const float*>(myapp + addr[q]);
           const int i1_old = (int)(pk >> 27);
-          uint32_t neg = 0;
+          // sign of a zero never reaches a nonzero value (a zero input forces
+          // every other output magnitude to zero), so sign bits are used as is
+          uint32_t sx = 0;
           float m1 = INFINITY, m2 = INFINITY;
           int i1 = 0;
 #pragma unroll
           for (int q = 0; q < D; ++q) {
             const float mag = q == i1_old ? a2 : a1;
-            const float rold = ((pk >> q) & 1u) ? -mag : mag;
+            const float rold = __uint_as_float(__float_as_uint(mag) | ((pk << (31 - q)) & 0x80000000u));
             const float t = __fsub_rn(tv[q], rold);
             tv[q] = t;
-            neg |= (t < 0.f ? 1u : 0u) << q;
+            sx ^= __float_as_uint(t);
             const float at = fabsf(t);
-            m2 = fminf(m2, fmaxf(m1, at));
+            m2 = __builtin_amdgcn_fmed3f(m1, at, m2);
             i1 = at < m1 ? q : i1;
             m1 = fminf(m1, at);
           }
-          const uint32_t par = __popc(neg) & 1u;
           const float b1 = __fmul_rn(alpha, m1);
           const float b2 = __fmul_rn(alpha, m2);
           uint32_t npk = (uint32_t)i1 << 27;
 #pragma unroll
           for (int q = 0; q < D; ++q) {
             const float mag = q == i1 ? b2 : b1;
-            const uint32_t sg = par ^ ((neg >> q) & 1u);
-            myapp[addr[q]] = __fadd_rn(tv[q], sg ? -mag : mag);
-            npk |= sg << q;
+            const uint32_t sg = (sx ^ __float_as_uint(tv[q])) & 0x80000000u;
+            *reinterpret_cast<float*>(myapp + addr[q]) =
+                __fadd_rn(tv[q], __uint_as_float(__float_as_uint(mag) | sg));
+            npk |= sg >> (31 - q);
           }
           sti[0] = __float_as_uint(b1);
           sti[Z] = __float_as_uint(b2);
@@ -180,8 +189,9 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
       const float a1 = __uint_as_float(sti[0]), a2 = __uint_as_float(sti[Z]);
       const uint32_t pk = sti[2 * Z];
       const int i1 = (int)(pk >> 27);
-      for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-        const int q = e - row_ptr[i];
+      const int rb = c.row_ptr[i];
+      for (int e = rb; e < c.row_ptr[i + 1]; ++e) {
+        const int q = e - rb;
         const float mag = q == i1 ? a2 : a1;
         io.r_out[(cw0 + g) * (int64_t)c.E + (int64_t)e * Z + r] = ((pk >> q) & 1u) ? -mag : mag;
       }

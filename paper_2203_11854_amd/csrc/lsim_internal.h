@@ -25,7 +25,20 @@ struct DevCode {
   const int* cn_tasks;   // (row << 16) | lift0, heaviest first
   const int* vn_tasks;   // (col << 16) | lift0, heaviest first
   const int16_t* base;   // full mb x nb base matrix (encoder)
+  const int2* col_edge;  // per column entry (col_ptr order): (e * Z, shift of e)
+  const int2* ent_cz;    // per entry (row-major): (col * Z, shift)
 };
+
+// Read-only device tables through the constant address space: with a
+// wave-uniform index the compiler emits scalar loads (no VALU, no LDS).
+__device__ __forceinline__ int ld_const(const int* p, int i) {
+  return ((const __attribute__((address_space(4))) int*)p)[i];
+}
+__device__ __forceinline__ int2 ld_const(const int2* p, int i) {
+  const __attribute__((address_space(4))) int* q =
+      (const __attribute__((address_space(4))) int*)p;
+  return make_int2(q[2 * i], q[2 * i + 1]);
+}
 
 }  // namespace lsim
 

@@ -20,11 +20,23 @@ constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 
 __device__ __forceinline__ float spa_m(float q) {
-  const float e = __builtin_amdgcn_exp2f(-fabsf(q) * kLog2e);
-  return 2.f * e * __builtin_amdgcn_rcpf(1.f + e);
+  // e2 = 2 exp(-|q|);  m = e2 / (1 + e2 / 2)
+  const float e2 = __builtin_amdgcn_exp2f(fmaf(fabsf(q), -kLog2e, 1.f));
+  return e2 * __builtin_amdgcn_rcpf(fmaf(e2, 0.5f, 1.f));
 }
 
 __device__ __forceinline__ float spa_combine(float x, float y) { return x + y - x * y; }
+
+// Running combination over a sequence: keeps D = 1 - prod(1 - m) and its
+// complement C = prod(1 - m); one step is two fused multiply-adds, and
+// (+)-ing another running value y onto it is D + y C (one more).
+struct SpaAcc {
+  float D = 0.f, C = 1.f;
+  __device__ __forceinline__ void add(float m) {
+    D = fmaf(m, C, D);
+    C = fmaf(-C, m, C);
+  }
+};
 
 // Unclamped output magnitude ln((2 - D) / D); +inf for D = 0.
 __device__ __forceinline__ float spa_mag(float D) {
