@@ -21,6 +21,7 @@
 
 #include <type_traits>
 
+#include "dispatch.h"
 #include "lsim_internal.h"
 #include "spa_math.h"
 
@@ -41,27 +42,6 @@ struct FloodArgs {
   int offset;
   int sat;
 };
-
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
-template <int N>
-struct Deg {
-  static constexpr int value = N;
-};
-
-// Calls f(Deg<d>{}) for the wave-uniform degree d in [1, D]: every degree
-// gets its own straight-line body, so all of a check's (or a variable
-// node's) LDS reads are issued back to back before the first use.
-template <int D, class F>
-__device__ __forceinline__ void with_degree(int d, F&& f) {
-  if constexpr (D >= 1) {
-    if (d == D) {
-      f(Deg<D>{});
-      return;
-    }
-    with_degree<D - 1>(d, f);
-  }
-}
 
 template <int ALG>
 struct Traits;

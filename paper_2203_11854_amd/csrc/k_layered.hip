@@ -14,6 +14,7 @@
 // r_new = sign * (alpha * (v == i1 ? m2 : m1)); APP = t + r_new.
 #include <hip/hip_runtime.h>
 
+#include "dispatch.h"
 #include "lsim_internal.h"
 
 #pragma clang fp contract(off)
@@ -21,26 +22,6 @@
 namespace lsim {
 
 namespace {
-
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
-template <int N>
-struct Deg {
-  static constexpr int value = N;
-};
-
-// Calls f(Deg<d>{}) for the wave-uniform degree d in [1, D], so each degree
-// runs a straight-line body whose LDS reads issue back to back.
-template <int D, class F>
-__device__ __forceinline__ void with_degree(int d, F&& f) {
-  if constexpr (D >= 1) {
-    if (d == D) {
-      f(Deg<D>{});
-      return;
-    }
-    with_degree<D - 1>(d, f);
-  }
-}
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 

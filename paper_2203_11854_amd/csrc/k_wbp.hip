@@ -23,6 +23,7 @@
 // codeword writes its own contribution, a second kernel adds them up.
 #include <hip/hip_runtime.h>
 
+#include "dispatch.h"
 #include "lsim_internal.h"
 #include "spa_math.h"
 
@@ -30,46 +31,9 @@ namespace lsim {
 
 namespace {
 
-constexpr int kNT = 512;
-constexpr int kNW = kNT / 64;
 constexpr int kDMAX = 16;
 
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
-
-struct Tab {
-  int* cn_tasks;
-  int* vn_tasks;
-  int* row_ptr;
-  int* col_ptr;
-  int2* col_edge;  // (e * Z, shift) per column entry
-};
-
-__host__ __device__ inline size_t tab_bytes(const DevCode& c) {
-  return align16((size_t)(c.n_cn_tasks + c.n_vn_tasks + c.rows + 1 + c.cols + 1) * 4) +
-         (size_t)c.nnz * 8;
-}
-
-__device__ inline Tab stage_tables(const DevCode& c, unsigned char* tb) {
-  Tab t;
-  t.cn_tasks = reinterpret_cast<int*>(tb);
-  t.vn_tasks = t.cn_tasks + c.n_cn_tasks;
-  t.row_ptr = t.vn_tasks + c.n_vn_tasks;
-  t.col_ptr = t.row_ptr + c.rows + 1;
-  t.col_edge = reinterpret_cast<int2*>(
-      tb + align16((size_t)(c.n_cn_tasks + c.n_vn_tasks + c.rows + 1 + c.cols + 1) * 4));
-  const int tid = threadIdx.x;
-  for (int i = tid; i < c.n_cn_tasks; i += kNT) t.cn_tasks[i] = c.cn_tasks[i];
-  for (int i = tid; i < c.n_vn_tasks; i += kNT) t.vn_tasks[i] = c.vn_tasks[i];
-  for (int i = tid; i <= c.rows; i += kNT) t.row_ptr[i] = c.row_ptr[i];
-  for (int i = tid; i <= c.cols; i += kNT) t.col_ptr[i] = c.col_ptr[i];
-  for (int i = tid; i < c.nnz; i += kNT) {
-    const int e = c.col_ent[i];
-    t.col_edge[i] = make_int2(e * c.Z, c.ent_shift[e]);
-  }
-  return t;
-}
 
 __device__ __forceinline__ float chan_lam(const DevCode& c, const float* llr_b, int v,
                                           float lmax) {
@@ -77,63 +41,92 @@ __device__ __forceinline__ float chan_lam(const DevCode& c, const float* llr_b, 
   return (x >= 0 && x < c.e_tx) ? fminf(fmaxf(-llr_b[x], -lmax), lmax) : 0.f;
 }
 
-// Check update of one check from its d inputs q (row stride Z), writing the
-// clamped outputs to `out` (same layout).
-__device__ __forceinline__ void cn_forward(const float* in, float* out, int d, int Z, float lmax) {
-  float mm[kDMAX], pre[kDMAX];
-  uint32_t neg = 0;
-  float dp = 0.f;
+// Byte offsets of the D edges of variable node (column j, lift cc), in the
+// column's entry order: (e*Z + (cc - shift) mod Z) * 4.
+template <int D>
+__device__ __forceinline__ void col_offsets(const DevCode& c, int cb, int cc, bool zpow2,
+                                            int* off) {
+  const int Z = c.Z;
+  if (zpow2) {
 #pragma unroll
-  for (int q = 0; q < kDMAX; ++q) {
-    if (q < d) {
-      const float x = in[q * Z];
-      neg |= (x < 0.f ? 1u : 0u) << q;
-      const float m = spa_m(x);
-      mm[q] = m;
-      pre[q] = dp;
-      dp = spa_combine(dp, m);
+    for (int q = 0; q < D; ++q) {
+      const int2 ce = ld_const(c.col_edge, cb + q);
+      off[q] = ((cc * 4 - ce.y * 4) & ((Z - 1) * 4)) | (ce.x * 4);
     }
-  }
-  const uint32_t par = __popc(neg) & 1u;
-  float ds = 0.f;
+  } else {
 #pragma unroll
-  for (int q = kDMAX - 1; q >= 0; --q) {
-    if (q < d) {
-      const float rv = fminf(spa_mag(spa_combine(pre[q], ds)), lmax);
-      out[q * Z] = (par ^ ((neg >> q) & 1u)) ? -rv : rv;
-      ds = spa_combine(ds, mm[q]);
+    for (int q = 0; q < D; ++q) {
+      const int2 ce = ld_const(c.col_edge, cb + q);
+      int x = cc - ce.y;
+      x += x < 0 ? Z : 0;
+      off[q] = (ce.x + x) * 4;
     }
   }
 }
 
-__global__ __launch_bounds__(kNT) void wbp_forward_kernel(DevCode c, int T,
-                                                          const float* __restrict__ w,
-                                                          const float* __restrict__ llr,
-                                                          float lmax, float* __restrict__ ckpt,
-                                                          float* __restrict__ lpost, int64_t B) {
+__device__ __forceinline__ float& at(float* base, int off) {
+  return *reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(base) + off);
+}
+
+// Check update of one check of degree D from inputs in[q*Z], clamped outputs
+// to out[q*Z] (spa_math.h).
+template <int D>
+__device__ __forceinline__ void cn_forward(const float* in, float* out, int Z, float lmax) {
+  float x[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) x[q] = in[q * Z];
+  uint32_t sx = 0;
+#pragma unroll
+  for (int q = 0; q < D; ++q) sx ^= __float_as_uint(x[q]);
+  float mm[D], pD[D], pC[D];
+  SpaAcc pre;
+#pragma unroll
+  for (int q = 0; q < D; ++q) {
+    mm[q] = spa_m(x[q]);
+    pD[q] = pre.D;
+    pC[q] = pre.C;
+    pre.add(mm[q]);
+  }
+  SpaAcc suf;
+#pragma unroll
+  for (int q = D - 1; q >= 0; --q) {
+    const float rv = fminf(spa_mag(fmaf(suf.D, pC[q], pD[q])), lmax);
+    out[q * Z] = __uint_as_float(__float_as_uint(rv) | ((sx ^ __float_as_uint(x[q])) & 0x80000000u));
+    suf.add(mm[q]);
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
+                                                         const float* __restrict__ w,
+                                                         const float* __restrict__ llr,
+                                                         float lmax, float* __restrict__ ckpt,
+                                                         float* __restrict__ lpost, int64_t B) {
+  constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   float* msg = reinterpret_cast<float*>(smem);
   float* lam = reinterpret_cast<float*>(smem + align16((size_t)c.E * 4));
-  const Tab t = stage_tables(c, smem + align16((size_t)c.E * 4) + align16((size_t)c.n_dec * 4));
   const int tid = threadIdx.x, lane = tid & 63, wave = uni(tid >> 6);
   const int Z = c.Z;
+  const bool zpow2 = (Z & (Z - 1)) == 0;
   const int64_t b = blockIdx.x;
   const float* llr_b = llr + b * (int64_t)c.e_tx;
-  for (int v = tid; v < c.n_dec; v += kNT) lam[v] = chan_lam(c, llr_b, v, lmax);
+  for (int v = tid; v < c.n_dec; v += NT) lam[v] = chan_lam(c, llr_b, v, lmax);
   __syncthreads();
   // q^(1) = lam on every edge
-  for (int ti = wave; ti < c.n_vn_tasks; ti += kNW) {
-    const int task = uni(t.vn_tasks[ti]);
+  for (int ti = wave; ti < c.n_vn_tasks; ti += NW) {
+    const int task = uni(ld_const(c.vn_tasks, ti));
     const int j = task >> 16, cc = (task & 0xffff) + lane;
-    const int cb = uni(t.col_ptr[j]), dc = uni(t.col_ptr[j + 1]) - cb;
+    const int cb = uni(ld_const(c.col_ptr, j)), dc = uni(ld_const(c.col_ptr, j + 1)) - cb;
     if (cc < Z) {
       const float l = lam[j * Z + cc];
-      for (int q = 0; q < dc; ++q) {
-        const int2 ce = t.col_edge[cb + q];
-        int x = cc - ce.y;
-        x += x < 0 ? Z : 0;
-        msg[ce.x + x] = l;
-      }
+      with_degree<kDMAX>(dc, [&](auto deg) {
+        constexpr int DC = decltype(deg)::value;
+        int off[DC];
+        col_offsets<DC>(c, cb, cc, zpow2, off);
+#pragma unroll
+        for (int q = 0; q < DC; ++q) at(msg, off[q]) = l;
+      });
     }
   }
   __syncthreads();
@@ -141,46 +134,54 @@ __global__ __launch_bounds__(kNT) void wbp_forward_kernel(DevCode c, int T,
     const bool last = it + 1 == T;
     if (ckpt) {
       float* ck = ckpt + ((int64_t)it * B + b) * c.E;
-      for (int e = tid; e < c.E; e += kNT) ck[e] = msg[e];
+      if ((c.E & 3) == 0) {
+        const float4* m4 = reinterpret_cast<const float4*>(msg);
+        for (int e = tid; e < c.E / 4; e += NT) reinterpret_cast<float4*>(ck)[e] = m4[e];
+      } else {
+        for (int e = tid; e < c.E; e += NT) ck[e] = msg[e];
+      }
     }
-    for (int ti = wave; ti < c.n_cn_tasks; ti += kNW) {
-      const int task = uni(t.cn_tasks[ti]);
+    for (int ti = wave; ti < c.n_cn_tasks; ti += NW) {
+      const int task = uni(ld_const(c.cn_tasks, ti));
       const int i = task >> 16, r = (task & 0xffff) + lane;
-      const int e0 = uni(t.row_ptr[i]), d = uni(t.row_ptr[i + 1]) - e0;
+      const int e0 = uni(ld_const(c.row_ptr, i)), d = uni(ld_const(c.row_ptr, i + 1)) - e0;
       if (r < Z) {
         float* row = msg + (size_t)e0 * Z + r;
-        cn_forward(row, row, d, Z, lmax);
+        with_degree<kDMAX>(d, [&](auto deg) {
+          cn_forward<decltype(deg)::value>(row, row, Z, lmax);
+        });
       }
     }
     __syncthreads();
     const float* wt = w + (int64_t)it * c.E;
-    for (int ti = wave; ti < c.n_vn_tasks; ti += kNW) {
-      const int task = uni(t.vn_tasks[ti]);
+    for (int ti = wave; ti < c.n_vn_tasks; ti += NW) {
+      const int task = uni(ld_const(c.vn_tasks, ti));
       const int j = task >> 16, cc = (task & 0xffff) + lane;
-      const int cb = uni(t.col_ptr[j]), dc = uni(t.col_ptr[j + 1]) - cb;
+      const int cb = uni(ld_const(c.col_ptr, j)), dc = uni(ld_const(c.col_ptr, j + 1)) - cb;
       if (cc < Z) {
         const int v = j * Z + cc;
-        float s[kDMAX];
-        int idx[kDMAX];
-        float acc = lam[v];
+        with_degree<kDMAX>(dc, [&](auto deg) {
+          constexpr int DC = decltype(deg)::value;
+          int off[DC];
+          col_offsets<DC>(c, cb, cc, zpow2, off);
+          float s[DC], wv[DC];
 #pragma unroll
-        for (int q = 0; q < kDMAX; ++q) {
-          if (q < dc) {
-            const int2 ce = t.col_edge[cb + q];
-            int x = cc - ce.y;
-            x += x < 0 ? Z : 0;
-            idx[q] = ce.x + x;
-            s[q] = wt[idx[q]] * msg[idx[q]];
+          for (int q = 0; q < DC; ++q) wv[q] = at(const_cast<float*>(wt), off[q]);
+#pragma unroll
+          for (int q = 0; q < DC; ++q) s[q] = at(msg, off[q]);
+          float acc = lam[v];
+#pragma unroll
+          for (int q = 0; q < DC; ++q) {
+            s[q] *= wv[q];
             acc += s[q];
           }
-        }
-        if (!last) {
+          if (!last) {
 #pragma unroll
-          for (int q = 0; q < kDMAX; ++q)
-            if (q < dc) msg[idx[q]] = fminf(fmaxf(acc - s[q], -lmax), lmax);
-        } else {
-          lpost[b * (int64_t)c.n_dec + v] = -acc;
-        }
+            for (int q = 0; q < DC; ++q) at(msg, off[q]) = __builtin_amdgcn_fmed3f(acc - s[q], -lmax, lmax);
+          } else {
+            lpost[b * (int64_t)c.n_dec + v] = -acc;
+          }
+        });
       }
     }
     __syncthreads();
@@ -189,153 +190,160 @@ __global__ __launch_bounds__(kNT) void wbp_forward_kernel(DevCode c, int T,
 
 // LDS: R[E] (recomputed clamped check outputs), QB[E] (adjoints of the
 // variable-to-check messages, then of the check outputs), LB[n_dec].
-__global__ __launch_bounds__(kNT) void wbp_backward_kernel(
+template <int NT>
+__global__ __launch_bounds__(NT) void wbp_backward_kernel(
     DevCode c, int T, const float* __restrict__ w, const float* __restrict__ llr,
     const float* __restrict__ ckpt, float lmax, const float* __restrict__ gpost,
     float* __restrict__ gllr, float* __restrict__ gw_part, int64_t B) {
+  constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   float* R = reinterpret_cast<float*>(smem);
   float* QB = R + c.E;
   float* LB = reinterpret_cast<float*>(smem + align16((size_t)2 * c.E * 4));
-  const Tab t =
-      stage_tables(c, smem + align16((size_t)2 * c.E * 4) + align16((size_t)c.n_dec * 4));
   const int tid = threadIdx.x, lane = tid & 63, wave = uni(tid >> 6);
   const int Z = c.Z;
+  const bool zpow2 = (Z & (Z - 1)) == 0;
   const int64_t b = blockIdx.x;
   const float* llr_b = llr + b * (int64_t)c.e_tx;
-  for (int v = tid; v < c.n_dec; v += kNT) LB[v] = 0.f;
-  for (int e = tid; e < c.E; e += kNT) QB[e] = 0.f;
+  for (int v = tid; v < c.n_dec; v += NT) LB[v] = 0.f;
+  for (int e = tid; e < c.E; e += NT) QB[e] = 0.f;
   __syncthreads();
 
   for (int it = T - 1; it >= 0; --it) {
     const float* ck = ckpt + ((int64_t)it * B + b) * c.E;
     // A: recompute the clamped check outputs of round it
-    for (int ti = wave; ti < c.n_cn_tasks; ti += kNW) {
-      const int task = uni(t.cn_tasks[ti]);
+    for (int ti = wave; ti < c.n_cn_tasks; ti += NW) {
+      const int task = uni(ld_const(c.cn_tasks, ti));
       const int i = task >> 16, r = (task & 0xffff) + lane;
-      const int e0 = uni(t.row_ptr[i]), d = uni(t.row_ptr[i + 1]) - e0;
-      if (r < Z) cn_forward(ck + (size_t)e0 * Z + r, R + (size_t)e0 * Z + r, d, Z, lmax);
+      const int e0 = uni(ld_const(c.row_ptr, i)), d = uni(ld_const(c.row_ptr, i + 1)) - e0;
+      if (r < Z) {
+        with_degree<kDMAX>(d, [&](auto deg) {
+          cn_forward<decltype(deg)::value>(ck + (size_t)e0 * Z + r, R + (size_t)e0 * Z + r, Z, lmax);
+        });
+      }
     }
     __syncthreads();
     // B: variable-side adjoint
     const float* wt = w + (int64_t)it * c.E;
     float* gwb = gw_part + (b * (int64_t)T + it) * c.E;
     const bool last = it + 1 == T;
-    for (int ti = wave; ti < c.n_vn_tasks; ti += kNW) {
-      const int task = uni(t.vn_tasks[ti]);
+    for (int ti = wave; ti < c.n_vn_tasks; ti += NW) {
+      const int task = uni(ld_const(c.vn_tasks, ti));
       const int j = task >> 16, cc = (task & 0xffff) + lane;
-      const int cb = uni(t.col_ptr[j]), dc = uni(t.col_ptr[j + 1]) - cb;
+      const int cb = uni(ld_const(c.col_ptr, j)), dc = uni(ld_const(c.col_ptr, j + 1)) - cb;
       if (cc < Z) {
         const int v = j * Z + cc;
-        float s[kDMAX], g[kDMAX], ww[kDMAX];
-        int idx[kDMAX];
-        float acc = chan_lam(c, llr_b, v, lmax);
+        with_degree<kDMAX>(dc, [&](auto deg) {
+          constexpr int DC = decltype(deg)::value;
+          int off[DC];
+          col_offsets<DC>(c, cb, cc, zpow2, off);
+          float rr[DC], ww[DC], s[DC], g[DC];
 #pragma unroll
-        for (int q = 0; q < kDMAX; ++q) {
-          if (q < dc) {
-            const int2 ce = t.col_edge[cb + q];
-            int x = cc - ce.y;
-            x += x < 0 ? Z : 0;
-            idx[q] = ce.x + x;
-            ww[q] = wt[idx[q]];
-            s[q] = ww[q] * R[idx[q]];
+          for (int q = 0; q < DC; ++q) ww[q] = at(const_cast<float*>(wt), off[q]);
+#pragma unroll
+          for (int q = 0; q < DC; ++q) rr[q] = at(R, off[q]);
+          float acc = chan_lam(c, llr_b, v, lmax);
+#pragma unroll
+          for (int q = 0; q < DC; ++q) {
+            s[q] = ww[q] * rr[q];
             acc += s[q];
           }
-        }
-        float A = last ? -gpost[b * (int64_t)c.n_dec + v] : 0.f;
+          float A = last ? -gpost[b * (int64_t)c.n_dec + v] : 0.f;
+          if (!last) {
 #pragma unroll
-        for (int q = 0; q < kDMAX; ++q) {
-          if (q < dc) {
-            const float qv = acc - s[q];
-            g[q] = (!last && fabsf(qv) <= lmax) ? QB[idx[q]] : 0.f;
-            A += g[q];
+            for (int q = 0; q < DC; ++q) {
+              const float qv = acc - s[q];
+              g[q] = fabsf(qv) <= lmax ? at(QB, off[q]) : 0.f;
+              A += g[q];
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < DC; ++q) g[q] = 0.f;
           }
-        }
-        LB[v] += A;
+          LB[v] += A;
 #pragma unroll
-        for (int q = 0; q < kDMAX; ++q) {
-          if (q < dc) {
+          for (int q = 0; q < DC; ++q) {
             const float sb = A - g[q];
-            gwb[idx[q]] = sb * R[idx[q]];
-            QB[idx[q]] = sb * ww[q];
+            at(gwb, off[q]) = sb * rr[q];
+            at(QB, off[q]) = sb * ww[q];
           }
-        }
+        });
       }
     }
     __syncthreads();
     // C: check-side adjoint from the checkpointed inputs
-    for (int ti = wave; ti < c.n_cn_tasks; ti += kNW) {
-      const int task = uni(t.cn_tasks[ti]);
+    for (int ti = wave; ti < c.n_cn_tasks; ti += NW) {
+      const int task = uni(ld_const(c.cn_tasks, ti));
       const int i = task >> 16, r = (task & 0xffff) + lane;
-      const int e0 = uni(t.row_ptr[i]), d = uni(t.row_ptr[i + 1]) - e0;
+      const int e0 = uni(ld_const(c.row_ptr, i)), d = uni(ld_const(c.row_ptr, i + 1)) - e0;
       if (r < Z) {
         const float* qin = ck + (size_t)e0 * Z + r;
         float* qb = QB + (size_t)e0 * Z + r;
-        float mm[kDMAX], tt[kDMAX], pre[kDMAX], av[kDMAX];
-        float dp = 0.f;
+        with_degree<kDMAX>(d, [&](auto deg) {
+          constexpr int D = decltype(deg)::value;
+          float x[D], cbar[D];
 #pragma unroll
-        for (int q = 0; q < kDMAX; ++q) {
-          if (q < d) {
-            const float x = qin[q * Z];
-            const float m = spa_m(x);
+          for (int q = 0; q < D; ++q) x[q] = qin[q * Z];
+#pragma unroll
+          for (int q = 0; q < D; ++q) cbar[q] = qb[q * Z];
+          float mm[D], tt[D], pD[D], pC[D], av[D];
+          SpaAcc pre;
+#pragma unroll
+          for (int q = 0; q < D; ++q) {
+            const float m = spa_m(x[q]);
             mm[q] = m;
-            tt[q] = x < 0.f ? -(1.f - m) : (1.f - m);
-            pre[q] = dp;
-            dp = spa_combine(dp, m);
+            tt[q] = __uint_as_float(__float_as_uint(1.f - m) | (__float_as_uint(x[q]) & 0x80000000u));
+            pD[q] = pre.D;
+            pC[q] = pre.C;
+            pre.add(m);
           }
-        }
-        // a_v = c_v cosh^2(r_v/2) with cosh^2 = 1/(D (2 - D)); zero where clamped
-        float ds = 0.f;
+          // a_v = c_v cosh^2(r_v/2) with cosh^2 = 1/(D (2 - D)); zero where clamped
+          SpaAcc suf;
 #pragma unroll
-        for (int q = kDMAX - 1; q >= 0; --q) {
-          if (q < d) {
-            const float D = spa_combine(pre[q], ds);
-            const float mag = spa_mag(D);
-            const float cb = mag <= lmax ? qb[q * Z] : 0.f;
-            av[q] = cb == 0.f ? 0.f : cb * __builtin_amdgcn_rcpf(D * (2.f - D));
-            ds = spa_combine(ds, mm[q]);
+          for (int q = D - 1; q >= 0; --q) {
+            const float Dx = fmaf(suf.D, pC[q], pD[q]);
+            const float cb = spa_mag(Dx) <= lmax ? cbar[q] : 0.f;
+            av[q] = cb == 0.f ? 0.f : cb * __builtin_amdgcn_rcpf(Dx * (2.f - Dx));
+            suf.add(mm[q]);
           }
-        }
-        // S_k = Apre_k Psuf_k + Ppre_k Asuf_k; forward pass stores Apre, Ppre
-        float ap[kDMAX], pp[kDMAX];
-        float P = 1.f, Aacc = 0.f;
+          // S_k = Apre_k Psuf_k + Ppre_k Asuf_k
+          float ap[D], pp[D];
+          float P = 1.f, Aacc = 0.f;
 #pragma unroll
-        for (int q = 0; q < kDMAX; ++q) {
-          if (q < d) {
+          for (int q = 0; q < D; ++q) {
             ap[q] = Aacc;
             pp[q] = P;
             Aacc = Aacc * tt[q] + av[q] * P;
             P *= tt[q];
           }
-        }
-        float Ps = 1.f, As = 0.f;
+          float Ps = 1.f, As = 0.f;
 #pragma unroll
-        for (int q = kDMAX - 1; q >= 0; --q) {
-          if (q < d) {
+          for (int q = D - 1; q >= 0; --q) {
             const float S = ap[q] * Ps + pp[q] * As;
             qb[q * Z] = mm[q] * (2.f - mm[q]) * S;
             As = As * tt[q] + av[q] * Ps;
             Ps *= tt[q];
           }
-        }
+        });
       }
     }
     __syncthreads();
   }
   // D: q^(1) = lam, then the channel clamp
-  for (int ti = wave; ti < c.n_vn_tasks; ti += kNW) {
-    const int task = uni(t.vn_tasks[ti]);
+  for (int ti = wave; ti < c.n_vn_tasks; ti += NW) {
+    const int task = uni(ld_const(c.vn_tasks, ti));
     const int j = task >> 16, cc = (task & 0xffff) + lane;
-    const int cb = uni(t.col_ptr[j]), dc = uni(t.col_ptr[j + 1]) - cb;
+    const int cb = uni(ld_const(c.col_ptr, j)), dc = uni(ld_const(c.col_ptr, j + 1)) - cb;
     if (cc < Z) {
       const int v = j * Z + cc;
       float acc = LB[v];
-      for (int q = 0; q < dc; ++q) {
-        const int2 ce = t.col_edge[cb + q];
-        int x = cc - ce.y;
-        x += x < 0 ? Z : 0;
-        acc += QB[ce.x + x];
-      }
+      with_degree<kDMAX>(dc, [&](auto deg) {
+        constexpr int DC = decltype(deg)::value;
+        int off[DC];
+        col_offsets<DC>(c, cb, cc, zpow2, off);
+#pragma unroll
+        for (int q = 0; q < DC; ++q) acc += at(QB, off[q]);
+      });
       const int xx = v - c.tx_lo;
       if (xx >= 0 && xx < c.e_tx) {
         const float L = llr_b[xx];
@@ -371,12 +379,13 @@ __global__ void sum_final_kernel(const float* __restrict__ slices, int64_t n,
   out[i] = acc;
 }
 
-size_t fwd_lds(const DevCode& c) {
-  return align16((size_t)c.E * 4) + align16((size_t)c.n_dec * 4) + tab_bytes(c);
-}
+size_t fwd_lds(const DevCode& c) { return align16((size_t)c.E * 4) + align16((size_t)c.n_dec * 4); }
 size_t bwd_lds(const DevCode& c) {
-  return align16((size_t)2 * c.E * 4) + align16((size_t)c.n_dec * 4) + tab_bytes(c);
+  return align16((size_t)2 * c.E * 4) + align16((size_t)c.n_dec * 4);
 }
+
+constexpr int kFwdNT = 512;
+constexpr int kBwdNT = 1024;
 
 hipError_t set_attr(const void* fn) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -403,11 +412,11 @@ hipError_t launch_wbp_forward(const DevCode& c, int T, const float* w, const flo
   }
   static bool attr = false;
   if (!attr) {
-    hipError_t e = set_attr((const void*)wbp_forward_kernel);
+    hipError_t e = set_attr((const void*)wbp_forward_kernel<kFwdNT>);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  wbp_forward_kernel<<<(unsigned)B, kNT, lds, s>>>(c, T, w, llr, llr_max, ckpt, lpost, B);
+  wbp_forward_kernel<kFwdNT><<<(unsigned)B, kFwdNT, lds, s>>>(c, T, w, llr, llr_max, ckpt, lpost, B);
   return hipGetLastError();
 }
 
@@ -427,13 +436,13 @@ hipError_t launch_wbp_backward(const DevCode& c, int T, const float* w, const fl
   }
   static bool attr = false;
   if (!attr) {
-    hipError_t e = set_attr((const void*)wbp_backward_kernel);
+    hipError_t e = set_attr((const void*)wbp_backward_kernel<kBwdNT>);
     if (e != hipSuccess) return e;
     attr = true;
   }
   float* part = reinterpret_cast<float*>(work);
-  wbp_backward_kernel<<<(unsigned)B, kNT, lds, s>>>(c, T, w, llr, ckpt, llr_max, gpost, gllr,
-                                                    part, B);
+  wbp_backward_kernel<kBwdNT><<<(unsigned)B, kBwdNT, lds, s>>>(c, T, w, llr, ckpt, llr_max, gpost,
+                                                               gllr, part, B);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n = (int64_t)T * c.E;
