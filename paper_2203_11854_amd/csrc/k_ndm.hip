@@ -6,8 +6,8 @@
 // second layer is consumed row by row straight into the 4 outputs.
 // Backward: one wavefront handles 64 symbols at a time; each lane recomputes
 // its symbol's activations, forms the deltas, and the wavefront reduces the
-// outer products through LDS with every lane owning one row of W2 (and of
-// W1, b1, b2, one column of W3).  Per-workgroup partial gradients are then
+// outer products through LDS tiles in two phases with every lane owning one
+// row of W2 (and of W1, b1, b2, one column of W3).  Per-workgroup partial gradients are then
 // summed over workgroups in a fixed order, so the result is deterministic.
 #include <hip/hip_runtime.h>
 
@@ -53,13 +53,18 @@ __global__ __launch_bounds__(256) void ndm_forward_kernel(const float* __restric
 
 constexpr int PAD = H + 1;
 
+// LDS per wavefront: three 64 x 65 float tiles (50 KB), so three
+// wavefronts fit on a CU.  delta1 = W2^T delta2 is accumulated while the
+// rows of delta2 are produced, so delta2 and h2 never sit in registers.
+// Phase 1 reduces dW2 = D2^T H1, db2, dW3 = D3^T H2, db3; phase 2 reuses
+// the H1 tile for dW1 = D1^T X and db1.
 __global__ __launch_bounds__(64) void ndm_backward_kernel(const float* __restrict__ P,
                                                           const float* __restrict__ y,
                                                           const float* __restrict__ no,
                                                           const float* __restrict__ gllr,
                                                           int64_t B, int64_t S,
                                                           float* __restrict__ part) {
-  __shared__ float sH1[64 * PAD], sD2[64 * PAD], sH2[64 * PAD], sD1[64 * PAD];
+  __shared__ float sA[64 * PAD], sB[64 * PAD], sC[64 * PAD];
   __shared__ float sX[64 * 3], sD3[64 * 4];
   const int lane = threadIdx.x;
   const int64_t n = B * S;
@@ -87,52 +92,53 @@ __global__ __launch_bounds__(64) void ndm_backward_kernel(const float* __restric
     for (int i = 0; i < H; ++i) {
       const float a = P[OW1 + 3 * i] * x0 + P[OW1 + 3 * i + 1] * x1 + P[OW1 + 3 * i + 2] * x2 +
                       P[OB1 + i];
-      h1[i] = fmaxf(a, 0.f);
-      sH1[lane * PAD + i] = on ? h1[i] : 0.f;
+      h1[i] = on ? fmaxf(a, 0.f) : 0.f;
+      sA[lane * PAD + i] = h1[i];
     }
-    // layer 2 forward + delta2, row by row
-    for (int o = 0; o < H; ++o) {
-      float a = P[OB2 + o];
-#pragma unroll
-      for (int i = 0; i < H; ++i) a += P[OW2 + o * H + i] * h1[i];
-      const float h = fmaxf(a, 0.f);
-      const float g = P[OW3 + o] * d3[0] + P[OW3 + H + o] * d3[1] + P[OW3 + 2 * H + o] * d3[2] +
-                      P[OW3 + 3 * H + o] * d3[3];
-      sH2[lane * PAD + o] = on ? h : 0.f;
-      sD2[lane * PAD + o] = (on && a > 0.f) ? g : 0.f;
-    }
-    // delta1 = (W2^T delta2) * [a1 > 0]
+    // layer 2 forward, delta2 row by row, delta1 accumulated on the way
     float d1[H];
 #pragma unroll
     for (int i = 0; i < H; ++i) d1[i] = 0.f;
     for (int o = 0; o < H; ++o) {
-      const float g = sD2[lane * PAD + o];
+      float a = P[OB2 + o];
 #pragma unroll
-      for (int i = 0; i < H; ++i) d1[i] += P[OW2 + o * H + i] * g;
+      for (int i = 0; i < H; ++i) a += P[OW2 + o * H + i] * h1[i];
+      const float g = P[OW3 + o] * d3[0] + P[OW3 + H + o] * d3[1] + P[OW3 + 2 * H + o] * d3[2] +
+                      P[OW3 + 3 * H + o] * d3[3];
+      const float d2 = (on && a > 0.f) ? g : 0.f;
+      sC[lane * PAD + o] = on ? fmaxf(a, 0.f) : 0.f;
+      sB[lane * PAD + o] = d2;
+#pragma unroll
+      for (int i = 0; i < H; ++i) d1[i] += P[OW2 + o * H + i] * d2;
     }
-#pragma unroll
-    for (int i = 0; i < H; ++i) sD1[lane * PAD + i] = h1[i] > 0.f ? d1[i] : 0.f;
     sX[lane * 3 + 0] = on ? x0 : 0.f;
     sX[lane * 3 + 1] = on ? x1 : 0.f;
     sX[lane * 3 + 2] = on ? x2 : 0.f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) sD3[lane * 4 + j] = on ? d3[j] : 0.f;
     __syncthreads();
-    // reductions over the 64 symbols of the chunk; this lane owns row `lane`
+    // phase 1: row `lane` of dW2 and db2, column `lane` of dW3, db3
     for (int s = 0; s < 64; ++s) {
-      const float d2 = sD2[s * PAD + lane];
+      const float d2 = sB[s * PAD + lane];
 #pragma unroll
-      for (int i = 0; i < H; ++i) gW2[i] += d2 * sH1[s * PAD + i];
+      for (int i = 0; i < H; ++i) gW2[i] += d2 * sA[s * PAD + i];
       gb2 += d2;
-      const float d1l = sD1[s * PAD + lane];
+      const float hh = sC[s * PAD + lane];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) gW3[j] += sD3[s * 4 + j] * hh;
+      if (lane < 4) gb3 += sD3[s * 4 + lane];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < H; ++i) sA[lane * PAD + i] = h1[i] > 0.f ? d1[i] : 0.f;
+    __syncthreads();
+    // phase 2: row `lane` of dW1 and db1
+    for (int s = 0; s < 64; ++s) {
+      const float d1l = sA[s * PAD + lane];
       gW1[0] += d1l * sX[s * 3 + 0];
       gW1[1] += d1l * sX[s * 3 + 1];
       gW1[2] += d1l * sX[s * 3 + 2];
       gb1 += d1l;
-      const float h2 = sH2[s * PAD + lane];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) gW3[j] += sD3[s * 4 + j] * h2;
-      if (lane < 4) gb3 += sD3[s * 4 + lane];
     }
     __syncthreads();
   }
