@@ -6,7 +6,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
+#include <unordered_map>
 #include <string>
 #include <vector>
 
@@ -17,6 +19,18 @@ namespace lsim {
 static thread_local std::string g_err;
 
 void set_error(const std::string& msg) { g_err = msg; }
+
+hipError_t ensure_dyn_lds(const void* kernel, size_t bytes) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, size_t> done;
+  if (bytes <= 64 * 1024) return hipSuccess;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = done.find(kernel);
+  if (it != done.end() && it->second >= bytes) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) done[kernel] = bytes;
+  return e;
+}
 
 }  // namespace lsim
 

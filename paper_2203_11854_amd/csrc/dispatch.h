@@ -26,4 +26,12 @@ __device__ __forceinline__ void with_degree(int d, F&& f) {
   }
 }
 
+// Workgroup barrier that orders LDS only: global loads and stores in flight
+// stay in flight across it (a plain __syncthreads() would wait for them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 }  // namespace lsim

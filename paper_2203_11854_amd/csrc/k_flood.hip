@@ -248,13 +248,8 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
 
 template <int NT, int DMAX, int ALG>
 hipError_t launch_t(const DevCode& c, const FloodArgs& a, size_t lds, hipStream_t s) {
-  static bool attr_done = false;
-  if (!attr_done) {
-    hipError_t e = hipFuncSetAttribute((const void*)flood_kernel<NT, DMAX, ALG>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    attr_done = true;
-  }
+  hipError_t e = ensure_dyn_lds((const void*)flood_kernel<NT, DMAX, ALG>, lds);
+  if (e != hipSuccess) return e;
   flood_kernel<NT, DMAX, ALG><<<(unsigned)a.B, NT, lds, s>>>(c, a);
   return hipGetLastError();
 }

@@ -153,7 +153,7 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
           sti[2 * Z] = npk;
         });
       }
-      __syncthreads();
+      lds_barrier();
     }
   }
 
@@ -320,7 +320,7 @@ __device__ __forceinline__ void decode_tile_pair(const DevCode& c, int64_t cw, c
           }
         });
       }
-      __syncthreads();
+      lds_barrier();
     }
   }
 
@@ -399,14 +399,6 @@ __global__ __launch_bounds__(NT) void mixed_kernel(const LayerShape* __restrict_
 
 __global__ void reset_counter_kernel(int* counter) { *counter = 0; }
 
-template <int NT, int DMAX>
-hipError_t set_attr_once(const void* fn) {
-  static bool done = false;
-  if (done) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  if (e == hipSuccess) done = true;
-  return e;
-}
 
 }  // namespace
 
@@ -427,7 +419,7 @@ hipError_t launch_layered(const DevCode& c, const lsim_decode_params& p, const f
     const int dmax = c.max_row_deg;
 #define LSIM_PAIR_CASE(NT_, D_)                                                      \
     if (ntp == NT_ && dmax <= D_) {                                                  \
-      hipError_t e = set_attr_once<NT_, D_ + 100>((const void*)layered_pair_kernel<NT_, D_>); \
+      hipError_t e = ensure_dyn_lds((const void*)layered_pair_kernel<NT_, D_>, lds); \
       if (e != hipSuccess) return e;                                                 \
       layered_pair_kernel<NT_, D_><<<(unsigned)B, NT_, lds, s>>>(c, io, p.iters, p.alpha); \
       return hipGetLastError();                                                      \
@@ -467,7 +459,7 @@ hipError_t launch_layered(const DevCode& c, const lsim_decode_params& p, const f
   const int dmax = c.max_row_deg;
 #define LSIM_LAYER_CASE(NT_, D_)                                                   \
   if (nt == NT_ && dmax <= D_) {                                                   \
-    hipError_t e = set_attr_once<NT_, D_>((const void*)layered_kernel<NT_, D_>);   \
+    hipError_t e = ensure_dyn_lds((const void*)layered_kernel<NT_, D_>, lds);   \
     if (e != hipSuccess) return e;                                                 \
     layered_kernel<NT_, D_><<<grid, NT_, lds, s>>>(c, G, io, p.iters, p.alpha);    \
     return hipGetLastError();                                                      \
@@ -507,7 +499,7 @@ hipError_t launch_mixed(const LayerShape* d_shapes, int nshapes, const int* d_ti
   const unsigned g = persistent ? (unsigned)grid : (unsigned)ntiles;
 #define LSIM_MIXED_CASE(NT_, D_)                                                           \
   if (threads == NT_ && dmax <= D_) {                                                      \
-    hipError_t e = set_attr_once<NT_, D_>((const void*)mixed_kernel<NT_, D_>);             \
+    hipError_t e = ensure_dyn_lds((const void*)mixed_kernel<NT_, D_>, lds_bytes);             \
     if (e != hipSuccess) return e;                                                         \
     mixed_kernel<NT_, D_><<<g, NT_, lds_bytes, s>>>(d_shapes, d_tile_shape, d_tile_local,  \
                                                     ntiles, (const float*)llr, bits, lpost, \

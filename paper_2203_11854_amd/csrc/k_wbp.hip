@@ -140,6 +140,7 @@ __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
       } else {
         for (int e = tid; e < c.E; e += NT) ck[e] = msg[e];
       }
+      lds_barrier();  // every wavefront has read q before the checks overwrite it
     }
     for (int ti = wave; ti < c.n_cn_tasks; ti += NW) {
       const int task = uni(ld_const(c.cn_tasks, ti));
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
         });
       }
     }
-    __syncthreads();
+    lds_barrier();
     const float* wt = w + (int64_t)it * c.E;
     for (int ti = wave; ti < c.n_vn_tasks; ti += NW) {
       const int task = uni(ld_const(c.vn_tasks, ti));
@@ -184,7 +185,7 @@ __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
         });
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -222,7 +223,7 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
         });
       }
     }
-    __syncthreads();
+    lds_barrier();
     // B: variable-side adjoint
     const float* wt = w + (int64_t)it * c.E;
     float* gwb = gw_part + (b * (int64_t)T + it) * c.E;
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
         });
       }
     }
-    __syncthreads();
+    lds_barrier();
     // C: check-side adjoint from the checkpointed inputs
     for (int ti = wave; ti < c.n_cn_tasks; ti += NW) {
       const int task = uni(ld_const(c.cn_tasks, ti));
@@ -327,7 +328,7 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
         });
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
   // D: q^(1) = lam, then the channel clamp
   for (int ti = wave; ti < c.n_vn_tasks; ti += NW) {
@@ -387,9 +388,6 @@ size_t bwd_lds(const DevCode& c) {
 constexpr int kFwdNT = 512;
 constexpr int kBwdNT = 1024;
 
-hipError_t set_attr(const void* fn) {
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-}
 
 }  // namespace
 
@@ -410,11 +408,9 @@ hipError_t launch_wbp_forward(const DevCode& c, int T, const float* w, const flo
     *why = "weighted BP state exceeds the 160 KiB LDS";
     return hipSuccess;
   }
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = set_attr((const void*)wbp_forward_kernel<kFwdNT>);
+  {
+    hipError_t e = ensure_dyn_lds((const void*)wbp_forward_kernel<kFwdNT>, lds);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   wbp_forward_kernel<kFwdNT><<<(unsigned)B, kFwdNT, lds, s>>>(c, T, w, llr, llr_max, ckpt, lpost, B);
   return hipGetLastError();
@@ -434,11 +430,9 @@ hipError_t launch_wbp_backward(const DevCode& c, int T, const float* w, const fl
     *why = "weighted BP adjoint state exceeds the 160 KiB LDS";
     return hipSuccess;
   }
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = set_attr((const void*)wbp_backward_kernel<kBwdNT>);
+  {
+    hipError_t e = ensure_dyn_lds((const void*)wbp_backward_kernel<kBwdNT>, lds);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   float* part = reinterpret_cast<float*>(work);
   wbp_backward_kernel<kBwdNT><<<(unsigned)B, kBwdNT, lds, s>>>(c, T, w, llr, ckpt, llr_max, gpost,

@@ -55,6 +55,10 @@ namespace lsim {
 
 void set_error(const std::string& msg);
 
+// Raises a kernel's dynamic-LDS limit to at least `bytes` (once per kernel
+// and size; thread-safe).
+hipError_t ensure_dyn_lds(const void* kernel, size_t bytes);
+
 // Flooding decoders (k_flood.hip)
 hipError_t launch_flood(const DevCode& c, const lsim_decode_params& p, const void* llr, int64_t B,
                         uint8_t* bits, float* lpost, const void* q_in, void* r_out, void* q_out,
