@@ -180,178 +180,6 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
   }
 }
 
-// Partner value of lane ^ 1 (DPP quad permutation 1,0,3,2).
-__device__ __forceinline__ uint32_t pair_swap(uint32_t x) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);
-}
-__device__ __forceinline__ float pair_swap(float x) {
-  return __uint_as_float(pair_swap(__float_as_uint(x)));
-}
-
-// One codeword per workgroup, two lanes per check: lane 2r handles the first
-// ceil(d/2) edges of check r, lane 2r+1 the rest; the halves exchange
-// (m1, i1, m2, sign parity, sign bits) through DPP.  Twice the wavefronts of
-// decode_tile for the same codeword hide more LDS and memory latency, and
-// each lane's serial chain is half as long.  Results are identical: the
-// first half wins ties, which keeps the first argmin.
-template <int NT, int DMAX>
-__device__ __forceinline__ void decode_tile_pair(const DevCode& c, int64_t cw, const TileIO& io,
-                                                 int iters, float alpha, unsigned char* smem) {
-  float* app = reinterpret_cast<float*>(smem);
-  const int Z = c.Z;
-  const int tid = threadIdx.x;
-  for (int v = tid; v < c.n_dec; v += NT) {
-    const int x = v - c.tx_lo;
-    app[v] = (x >= 0 && x < c.e_tx) ? -io.llr[cw * c.e_tx + x] : 0.f;
-  }
-  __syncthreads();
-
-  const int r = tid >> 1;
-  const int half = tid & 1;
-  const bool active = r < Z;
-  unsigned char* myapp = reinterpret_cast<unsigned char*>(app);
-  const int zm4 = (Z - 1) * 4, r4 = r * 4;
-  const bool zpow2 = (Z & (Z - 1)) == 0;
-  uint32_t* st = io.state + (size_t)cw * c.rows * 3 * Z + (active ? r : 0);
-
-  const int rows = c.rows;
-  float n1 = 0.f, n2 = 0.f;
-  uint32_t npk_in = 0;
-  for (int it = 0; it < iters; ++it) {
-    for (int i = 0; i < rows; ++i) {
-      const int e0 = uni(ld_const(c.row_ptr, i));
-      const int d = uni(ld_const(c.row_ptr, i + 1)) - e0;
-      const float a1 = n1, a2 = n2;
-      const uint32_t pk = npk_in;
-      {
-        int ni = i + 1, nit = it;
-        if (ni == rows) {
-          ni = 0;
-          ++nit;
-        }
-        if (active && nit >= 1 && nit < iters) {
-          const uint32_t* s2 = st + (size_t)ni * 3 * Z;
-          n1 = __uint_as_float(s2[0]);
-          n2 = __uint_as_float(s2[Z]);
-          npk_in = s2[2 * Z];
-        } else {
-          n1 = 0.f;
-          n2 = 0.f;
-          npk_in = 0;
-        }
-      }
-      if (active) {
-        uint32_t* sti = st + (size_t)i * 3 * Z;
-        with_degree<DMAX>(d, [&](auto deg) {
-          constexpr int D = decltype(deg)::value;
-          constexpr int H = (D + 1) / 2;
-          // everything lane-dependent is reduced to a few per-layer values so
-          // the edge loops below work with compile-time edge positions qq
-          const bool last_pad = half && (D & 1);            // lane 2r+1 has H-1 edges
-          const uint32_t pkh = half ? (pk >> H) : pk;       // this half's old sign bits
-          const int i1_rel = (int)(pk >> 27) - (half ? H : 0);
-          int addr[H];
-          float tv[H];
-#pragma unroll
-          for (int qq = 0; qq < H; ++qq) {
-            const int2 ea = ld_const(c.ent_cz, e0 + qq);
-            const int2 eb = ld_const(c.ent_cz, e0 + (H + qq < D ? H + qq : qq));
-            const int ex = half ? eb.x : ea.x, ey = half ? eb.y : ea.y;
-            if (zpow2) {
-              addr[qq] = ((r4 + ey * 4) & zm4) | (ex * 4);
-            } else {
-              int x = r + ey;
-              x -= x >= Z ? Z : 0;
-              addr[qq] = (ex + x) * 4;
-            }
-          }
-#pragma unroll
-          for (int qq = 0; qq < H; ++qq) tv[qq] = *reinterpret_cast<const float*>(myapp + addr[qq]);
-          uint32_t sx = 0;
-          float m1 = INFINITY, m2 = INFINITY;
-          int i1 = 0;
-#pragma unroll
-          for (int qq = 0; qq < H; ++qq) {
-            const bool ok = qq + 1 < H || !last_pad;
-            const float mag = qq == i1_rel ? a2 : a1;
-            const float rold =
-                __uint_as_float(__float_as_uint(mag) | ((pkh << (31 - qq)) & 0x80000000u));
-            const float t = __fsub_rn(tv[qq], rold);
-            tv[qq] = t;
-            if (ok) {
-              sx ^= __float_as_uint(t);
-              const float at = fabsf(t);
-              m2 = __builtin_amdgcn_fmed3f(m1, at, m2);
-              i1 = at < m1 ? qq : i1;
-              m1 = fminf(m1, at);
-            }
-          }
-          i1 += half ? H : 0;
-          // combine the halves: the first half (A) wins ties
-          const float om1 = pair_swap(m1), om2 = pair_swap(m2);
-          const uint32_t oi1 = pair_swap((uint32_t)i1), osx = pair_swap(sx);
-          const float m1A = half ? om1 : m1, m1B = half ? m1 : om1;
-          const int i1A = half ? (int)oi1 : i1, i1B = half ? i1 : (int)oi1;
-          const float gm1 = fminf(m1A, m1B);
-          const int gi1 = m1A <= m1B ? i1A : i1B;
-          const float gm2 = fminf(fminf(m2, om2), fmaxf(m1A, m1B));
-          sx ^= osx;
-          const float b1 = __fmul_rn(alpha, gm1);
-          const float b2 = __fmul_rn(alpha, gm2);
-          const int gi1_rel = gi1 - (half ? H : 0);
-          uint32_t npk = 0;
-#pragma unroll
-          for (int qq = 0; qq < H; ++qq) {
-            const bool ok = qq + 1 < H || !last_pad;
-            const float mag = qq == gi1_rel ? b2 : b1;
-            const uint32_t sg = (sx ^ __float_as_uint(tv[qq])) & 0x80000000u;
-            if (ok) {
-              *reinterpret_cast<float*>(myapp + addr[qq]) =
-                  __fadd_rn(tv[qq], __uint_as_float(__float_as_uint(mag) | sg));
-              npk |= sg >> (31 - qq);
-            }
-          }
-          npk = half ? (npk << H) : npk;
-          npk |= pair_swap(npk);
-          if (half == 0) {
-            sti[0] = __float_as_uint(b1);
-            sti[Z] = __float_as_uint(b2);
-            sti[2 * Z] = npk | ((uint32_t)gi1 << 27);
-          }
-        });
-      }
-      lds_barrier();
-    }
-  }
-
-  for (int v = tid; v < c.n_dec; v += NT) {
-    const float x = app[v];
-    if (io.bits && v < c.k) io.bits[cw * c.k + v] = x < 0.f;
-    if (io.lpost) io.lpost[cw * c.n_dec + v] = -x;
-  }
-  if (io.r_out && active && half == 0) {
-    for (int i = 0; i < c.rows; ++i) {
-      const uint32_t* sti = st + (size_t)i * 3 * Z;
-      const float a1 = __uint_as_float(sti[0]), a2 = __uint_as_float(sti[Z]);
-      const uint32_t pk = sti[2 * Z];
-      const int i1 = (int)(pk >> 27);
-      const int rb = c.row_ptr[i];
-      for (int e = rb; e < c.row_ptr[i + 1]; ++e) {
-        const int q = e - rb;
-        const float mag = q == i1 ? a2 : a1;
-        io.r_out[cw * (int64_t)c.E + (int64_t)e * Z + r] = ((pk >> q) & 1u) ? -mag : mag;
-      }
-    }
-  }
-}
-
-template <int NT, int DMAX>
-__global__ __launch_bounds__(NT) void layered_pair_kernel(DevCode c, TileIO io, int iters,
-                                                          float alpha) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  decode_tile_pair<NT, DMAX>(c, blockIdx.x, io, iters, alpha, smem);
-}
-
 template <int NT, int DMAX>
 __global__ __launch_bounds__(NT) void layered_kernel(DevCode c, int G, TileIO io, int iters,
                                                      float alpha) {
@@ -407,32 +235,6 @@ size_t layered_state_words(const DevCode& c, int64_t B) { return (size_t)B * c.r
 hipError_t launch_layered(const DevCode& c, const lsim_decode_params& p, const float* llr,
                           int64_t B, uint8_t* bits, float* lpost, float* r_out, uint32_t* state,
                           hipStream_t s, std::string* why) {
-  // large lifts: one codeword per workgroup, two lanes per check
-  if (!p.threads && c.Z >= 256 && 2 * c.Z <= 1024) {
-    const int ntp = 2 * c.Z <= 512 ? 512 : (2 * c.Z <= 768 ? 768 : 1024);
-    const size_t lds = tile_lds_bytes(c, 1);
-    if (lds > 160 * 1024) {
-      *why = "layered decoder posteriors exceed the 160 KiB LDS";
-      return hipSuccess;
-    }
-    TileIO io{llr, bits, lpost, r_out, state, B};
-    const int dmax = c.max_row_deg;
-#define LSIM_PAIR_CASE(NT_, D_)                                                      \
-    if (ntp == NT_ && dmax <= D_) {                                                  \
-      hipError_t e = ensure_dyn_lds((const void*)layered_pair_kernel<NT_, D_>, lds); \
-      if (e != hipSuccess) return e;                                                 \
-      layered_pair_kernel<NT_, D_><<<(unsigned)B, NT_, lds, s>>>(c, io, p.iters, p.alpha); \
-      return hipGetLastError();                                                      \
-    }
-    LSIM_PAIR_CASE(512, 24)
-    LSIM_PAIR_CASE(512, 27)
-    LSIM_PAIR_CASE(768, 24)
-    LSIM_PAIR_CASE(768, 27)
-    LSIM_PAIR_CASE(1024, 24)
-    LSIM_PAIR_CASE(1024, 27)
-#undef LSIM_PAIR_CASE
-    return hipErrorInvalidValue;
-  }
   int nt = p.threads;
   if (!nt) {
     const int cand[5] = {256, 384, 512, 768, 1024};

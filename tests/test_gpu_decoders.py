@@ -141,12 +141,13 @@ def test_workgroup_size_invariance():
         assert torch.equal(outs[0], o)
 
 
-def test_layered_pair_lanes_equal_single_lanes():
-    """BG1 Z=384 decodes with two lanes per check by default; forcing one
-    lane per check (threads=384) must give the same bits and posteriors."""
+def test_layered_large_lift_tile_invariance():
+    """BG1 (Z=384): one codeword per workgroup (384 threads) and two per
+    workgroup (768 and 1024 threads) give the same bits and posteriors."""
     qb, g, code = gcode("bg1")
     tx = oracle_llrs("bg1", 3, 2.5, 67)
-    llr = torch.from_numpy(np.ascontiguousarray(tx["L"].astype(np.float32))).to(dev)
-    a = lsim.decode(code, llr, lsim.params(lsim.NMS_F32), want_app=True)
-    b = lsim.decode(code, llr, lsim.params(lsim.NMS_F32, threads=384), want_app=True)
-    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    llr = T(tx["L"].astype(np.float32)).to(dev)
+    outs = [lsim.decode(code, llr, lsim.params(lsim.NMS_F32, threads=t), want_app=True)
+            for t in (0, 384, 768, 1024)]
+    for o in outs[1:]:
+        assert torch.equal(outs[0][0], o[0]) and torch.equal(outs[0][1], o[1])
