@@ -35,6 +35,18 @@ CLOCK_GHZ = 2.4
 VALU_LANES_PER_CU_CLK = 64          # 4 SIMDs x 16 lanes
 VALU_PEAK_TOPS = N_CU * VALU_LANES_PER_CU_CLK * CLOCK_GHZ / 1e3   # 39.32 T lane-ops/s
 
+# LDS: 128 bytes per clock per CU
+LDS_PEAK_GBS = N_CU * 128 * CLOCK_GHZ
+
+# HBM bytes per launch of the sum-product flooding kernel on the BG2
+# workload (B = 4096) from rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by what
+# the same counters read for a 256 MiB device copy (FETCH x2, WRITE x1).
+# Valid only for the kernel sources they were taken on (hash below); any
+# change there reports null until the counters are taken again.
+FLOOD_SPA_TRAFFIC = {"bytes": (30967 * 2 + 5120) * 1024,
+                     "sources": ("k_flood.hip", "spa_math.h", "dispatch.h", "lsim_internal.h"),
+                     "sha256_16": "89acd6f0c3923ab0"}
+
 # Algorithmic VALU work per edge and round ("Roofline"):
 # sum-product: check side 12 simple ops + 4 transcendentals (quarter rate,
 # 4 issue slots each), variable side 3 ops -> 31 issue slots.
@@ -54,21 +66,33 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=256,
+    ap.add_argument("--cpu-sample", type=int, default=512,
                     help="codewords of the oracle CPU baseline sample (0 = skip)")
+    ap.add_argument("--cpu-pool", type=int, default=1,
+                    help="also time the oracle in a process pool over the host's cores")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB of a plain device copy run first (reference for HBM counters)")
-    ap.add_argument("--legs", default="oms,nms,mixed,wbp",
-                    help="secondary legs to time: oms,nms,mixed,wbp (empty = none)")
+    ap.add_argument("--legs", default="bler,oms,nms,mixed,wbp",
+                    help="secondary legs: bler,oms,nms,mixed,wbp (empty = none)")
     return ap.parse_args()
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); "
-              "this build has no multi-GPU path", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the library "
+              "decodes on one device per process", file=sys.stderr)
         sys.exit(2)
+
+    # the oracle's CPU baseline runs first, before anything touches the GPU,
+    # so its worker processes start from a process without a GPU context
+    cpu = cpu_pool = None
+    if args.cpu_sample > 0:
+        from inputs.workloads import BG2 as _bg2
+        cpu = cpu_baseline(_bg2.load(), args.cpu_sample)
+        if args.cpu_pool:
+            cpu_pool = cpu_baseline_pool(_bg2.load(), args.cpu_sample)
+
     import torch
 
     import paper_2203_11854_amd as lsim
@@ -126,12 +150,16 @@ def main():
     slots = B * 20 * E * SPA_SLOTS_PER_EDGE
     achieved = slots / (dec_ms * 1e-3) / 1e12
     hbm_bytes = B * (code.e_tx * 4 + k)            # LLRs in, bits out
+    lds_bytes = B * 20 * (16 * E + 8 * code.n_dec)  # per round: APP by edge, r read/write/read, L + APP
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
+                "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "traffic": _flood_traffic(),
                 "kernel": "flood_kernel<512,16,SPA>", "kernel_ms": round(dec_ms, 4),
                 "algorithmic_slots_per_edge_round": SPA_SLOTS_PER_EDGE,
                 "hbm_algorithmic_bytes": hbm_bytes,
-                "hbm_frac": round(hbm_bytes / (dec_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}
+                "hbm_frac": round(hbm_bytes / (dec_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
+                "lds_algorithmic_bytes": lds_bytes,
+                "lds_frac": round(lds_bytes / (dec_ms * 1e-3) / 1e9 / LDS_PEAK_GBS, 4)}
     log(f"[bench] step {ms_step:.3f} ms, decoder {dec_ms:.3f} ms, {value:.3f} Gbit/s")
 
     extra = {"bler_by_ebn0": {f"{pts[j]:.1f}": [int(cnt[j, 1]), int(cnt[j, 2])] for j in range(9)},
@@ -139,6 +167,23 @@ def main():
              "decoder_only_gbps": round(B * k / (dec_ms * 1e-3) / 1e9, 3)}
 
     legs = [x for x in args.legs.split(",") if x]
+    if "bler" in legs:
+        # the same link and seeds through the other decoders: BLER curves
+        # and the Eb/N0 each needs for BLER 1e-2 (20 iterations each)
+        spa_bler = [cnt[j, 1] / max(1, cnt[j, 2]) for j in range(9)]
+        curves = {"spa_f32_flooding": spa_bler}
+        for name, pp in (("oms_i8_flooding", lsim.params(lsim.OMS_I8, iters=20, offset=1, sat=31)),
+                         ("nms_f32_layered", lsim.params(lsim.NMS_F32, iters=20, alpha=0.75))):
+            lk = lsim.Link(code, m, lsim.DEMAP_MAXLOG, pp, B, no, bins=tbins, nbins=9, device=dev)
+            for i in range(args.steps):
+                lk.run(data_seed(2, 1000 + i), 0)
+            cc = lk.counts.cpu().numpy()
+            curves[name] = [cc[j, 1] / max(1, cc[j, 2]) for j in range(9)]
+        extra["ebn0_db_at_bler_1e-2"] = {n: (None if ebn0_at_bler(pts, c) is None
+                                             else round(ebn0_at_bler(pts, c), 3))
+                                         for n, c in curves.items()}
+        extra["bler_curves"] = {n: [round(float(x), 5) for x in c] for n, c in curves.items()}
+        log(f"[bench] Eb/N0 at BLER 1e-2: {extra['ebn0_db_at_bler_1e-2']}")
     if "oms" in legs:
         q8 = torch.empty((B, code.e_tx), dtype=torch.int8, device=dev)
         lsim.demap_q8(m, lsim.DEMAP_MAXLOG, link.y, no, out=q8)
@@ -176,12 +221,19 @@ def main():
         extra["mixed_persistent"] = mixed_leg(torch, lsim, dev)
         log(f"[bench] mixed: {extra['mixed_persistent']}")
     if "wbp" in legs:
-        extra["wbp_ndm_bg2"] = wbp_leg(torch, lsim, dev, code, qb)
+        extra["wbp_ndm_bg2"] = {f"T{t}": wbp_leg(torch, lsim, dev, code, qb, t) for t in (10, 20)}
         log(f"[bench] wbp: {extra['wbp_ndm_bg2']}")
 
-    cpu = None
-    if args.cpu_sample > 0:
-        cpu = cpu_baseline(qb, args.cpu_sample)
+    if cpu is not None:
+        j = int(np.where(np.isclose(pts, CPU_EBN0))[0][0])
+        lo, hi = cpu.pop("bler_ci95")
+        gb = cnt[j, 1] / max(1, cnt[j, 2])
+        extra["matched_bler"] = {
+            "ebn0_db": CPU_EBN0, "gpu_bler": round(float(gb), 5), "gpu_codewords": int(cnt[j, 2]),
+            "oracle_bler_ci95": [round(lo, 5), round(hi, 5)],
+            "oracle_codewords": args.cpu_sample, "within": bool(lo <= gb <= hi)}
+    if cpu_pool is not None:
+        extra["cpu_baseline_pool"] = cpu_pool
 
     out = {
         "metric": "decoded info Gbit/s @20 BP iters (fwd; fwd+bwd) at matched BLER",
@@ -196,6 +248,28 @@ def main():
         "extra": extra,
     }
     print(json.dumps(out), flush=True)
+
+
+def _flood_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for f in FLOOD_SPA_TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, "paper_2203_11854_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return FLOOD_SPA_TRAFFIC["bytes"] if h.hexdigest()[:16] == FLOOD_SPA_TRAFFIC["sha256_16"] else None
+
+
+def ebn0_at_bler(pts, blers, target=1e-2):
+    """Eb/N0 where the BLER curve crosses ``target`` (linear in log10 BLER
+    between the two bracketing points), or None if it does not cross."""
+    for j in range(1, len(pts)):
+        a, b = blers[j - 1], blers[j]
+        if a >= target > b:
+            if b <= 0:
+                return float(pts[j])
+            la, lb, lt = math.log10(a), math.log10(b), math.log10(target)
+            return float(pts[j - 1] + (pts[j] - pts[j - 1]) * (la - lt) / (la - lb))
+    return None
 
 
 def _elapsed(torch, fn, reps):
@@ -276,15 +350,14 @@ def mixed_leg(torch, lsim, dev):
             "bit_identical_to_per_shape": bool(same)}
 
 
-def wbp_leg(torch, lsim, dev, code, qb):
-    """Weighted BP (10 rounds, per-edge per-round weights) fed by the neural
+def wbp_leg(torch, lsim, dev, code, qb, T=10):
+    """Weighted BP (T rounds, per-edge per-round weights) fed by the neural
     demapper on 16-QAM, batch 2048, Eb/N0 ~ U[1, 4] dB: one training step
     (forward; forward + backward + Adam) vs the plain sum-product decoder."""
     from inputs import rand
     from inputs.workloads import data_seed
 
-    B, T, m = 2048, 10, 4
-    S = code.e_tx // m
+    B, m = 2048, 4
     r = rand.rng(5005)
     ebn0 = r.uniform(1.0, 4.0, B)
     no = torch.tensor(lsim.ebn0_to_n0(ebn0, code.k / code.e_tx, m), dtype=torch.float32, device=dev)
@@ -326,8 +399,8 @@ def wbp_leg(torch, lsim, dev, code, qb):
     return {"batch": B, "iters": T, "fwd_ms": round(ms_f, 4), "fwd_bwd_ms": round(ms_fb, 4),
             "fwd_gbps": round(info / (ms_f * 1e-3) / 1e9, 3),
             "fwd_bwd_gbps": round(info / (ms_fb * 1e-3) / 1e9, 3),
-            "plain_spa_T10_ms": round(ms_plain, 4),
-            "plain_spa_T10_gbps": round(info / (ms_plain * 1e-3) / 1e9, 3),
+            "plain_spa_ms": round(ms_plain, 4),
+            "plain_spa_gbps": round(info / (ms_plain * 1e-3) / 1e9, 3),
             "loss_after_timing_steps": round(l0, 6)}
 
 
@@ -343,23 +416,89 @@ def glorot_params(seed):
     return np.concatenate(out)
 
 
+CPU_EBN0 = 3.0
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_chunk(job):
+    """One worker's share of the oracle link: codewords cw0 .. cw0+nb-1."""
+    from inputs.workloads import BG2, data_seed
+    from oracle import decoders, pipeline, qc, stats
+    cw0, nb = job
+    qb = BG2.load()
+    g = qc.graph_from_qcbase(qb, 3840)
+    n0 = float(pipeline.n0_for(g, CPU_EBN0, 4))
+    tx = pipeline.transmit(g, qb.family, data_seed(2, 0), cw0, nb, np.full(nb, n0), 4, "maxlog")
+    bits, _ = pipeline.decode(g, tx["L"], "spa", 20)
+    return stats.count_errors(tx["u"], bits)[0]
+
+
 def cpu_baseline(qb, ncw):
     """The FP64 oracle's link (bits .. SPA decode .. count) on a bounded
-    sample of the same workload, on the host cores."""
+    sample of the same workload, in this process."""
     from inputs.workloads import data_seed
-    from oracle import pipeline, qc
+    from oracle import pipeline, qc, stats
 
     g = qc.graph_from_qcbase(qb, 3840)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "1") or 1)
     log(f"[bench] cpu baseline: oracle on {ncw} codewords")
+    c0 = os.times()
     t0 = time.perf_counter()
-    cnt, _ = pipeline.run_point(g, qb.family, data_seed(2, 0), ncw, 2.0, 4, "maxlog", "spa", 20,
+    cnt, _ = pipeline.run_point(g, qb.family, data_seed(2, 0), ncw, CPU_EBN0, 4, "maxlog", "spa", 20,
                                 chunk=128)
     dt = time.perf_counter() - t0
-    return {"value": round(ncw * g.k / dt / 1e9, 6), "unit": "Gbit/s", "cores": 1,
-            "kind": "oracle", "threads_env": threads,
-            "sample": f"{ncw} codewords of the bg2 workload at Eb/N0 2 dB, full link with "
-                      f"FP64 flooding sum-product (20 iters), {dt:.1f} s"}
+    c1 = os.times()
+    cpu_s = (c1.user - c0.user) + (c1.system - c0.system)
+    lo, hi = stats.wilson(int(cnt[1]), int(cnt[2]))
+    return {"value": round(ncw * g.k / dt / 1e9, 7), "unit": "Gbit/s",
+            "cores": max(1, int(round(cpu_s / dt))), "kind": "oracle",
+            "cpu_model": _cpu_model(), "cpu_seconds": round(cpu_s, 1),
+            "sample": f"{ncw} codewords of the bg2 workload at Eb/N0 {CPU_EBN0} dB, full link "
+                      f"(bits, encode, 16-QAM, AWGN, max-log, FP64 flooding sum-product 20 iters, "
+                      f"count) in one process, {dt:.1f} s wall",
+            "bler_ci95": [float(lo), float(hi)]}
+
+
+def cpu_baseline_pool(qb, ncw):
+    """The same oracle link over a process pool, one chunk per worker."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    workers = max(1, min(16, ncpu))
+    per = max(1, ncw // 4)
+    jobs = [(w * per, per) for w in range(workers)]
+    log(f"[bench] cpu baseline: oracle pool of {workers} workers x {per} codewords")
+    old = os.environ.get("OMP_NUM_THREADS")
+    os.environ["OMP_NUM_THREADS"] = "1"
+    try:
+        with ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+            list(ex.map(_oracle_chunk, [(0, 1)] * workers))      # start-up outside the clock
+            t0 = time.perf_counter()
+            tot = sum(ex.map(_oracle_chunk, jobs))
+            dt = time.perf_counter() - t0
+    finally:
+        if old is None:
+            os.environ.pop("OMP_NUM_THREADS", None)
+        else:
+            os.environ["OMP_NUM_THREADS"] = old
+    n = workers * per
+    return {"value": round(n * 1280 / dt / 1e9, 7), "unit": "Gbit/s", "cores": workers,
+            "kind": "oracle", "cpu_model": _cpu_model(),
+            "sample": f"{n} codewords ({workers} processes x {per}), same link as cpu_baseline, "
+                      f"{dt:.1f} s wall", "block_errors": int(tot[1])}
 
 
 if __name__ == "__main__":

@@ -151,3 +151,35 @@ def test_layered_large_lift_tile_invariance():
             for t in (0, 384, 768, 1024)]
     for o in outs[1:]:
         assert torch.equal(outs[0][0], o[0]) and torch.equal(outs[0][1], o[1])
+
+
+@pytest.mark.parametrize("case", ["11n_three_layers", "bg2_core_layers_only"])
+def test_nms_layered_few_layers(case):
+    """Codes with as few layers as the check-state prefetch distance (four
+    core rows of a BG-shaped code sent at its highest rate) and fewer (an
+    11n-shaped code with three rows) against the oracle, every round."""
+    from inputs.qc_base import draw_base
+    from inputs.workloads import BG2
+    from oracle import pipeline
+    if case == "11n_three_layers":
+        qb = draw_base("11n", 3, 12, 27, seed=11)
+        e_tx, want_rows = 12 * 27, 3
+    else:
+        qb = BG2.load()
+        e_tx, want_rows = (qb.kb + 4) * qb.Z - 2 * qb.Z, 4
+    g = qc.graph_from_qcbase(qb, e_tx)
+    assert g.rows == want_rows
+    code = lsim.Code.from_qcbase(qb, e_tx)
+    B = 9
+    n0 = np.full(B, float(pipeline.n0_for(g, 4.5, 1)))
+    tx = pipeline.transmit(g, qb.family, 71, 0, B, n0, 1)
+    L32 = tx["L"].astype(np.float32)
+    lam = D.channel_lam(g, L32, dtype=np.float32)
+    app, hist = D.nms_layered(g, lam, 20, alpha=0.75, mode="fp32", trace=True)
+    tl = T(L32).to(dev)
+    for t in (1, 2, 3, 5, 20):
+        r, _, lp = lsim.decode_state(code, tl, lsim.params(lsim.NMS_F32, iters=t, alpha=0.75))
+        assert np.array_equal(r.cpu().numpy(), hist[t - 1][0]), t
+        assert np.array_equal(lp.cpu().numpy(), -hist[t - 1][1]), t
+    bits, _ = lsim.decode(code, tl, lsim.params(lsim.NMS_F32, iters=20, alpha=0.75))
+    assert np.array_equal(bits.cpu().numpy(), D.hard_bits(app, g.k))
