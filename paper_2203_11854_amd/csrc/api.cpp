@@ -230,11 +230,25 @@ lsim_status lsim_code_create(const int16_t* base, int mb, int nb, int Z, int fam
     ecz[2 * e + 1] = c->ent_shift[e];
   }
   if (blob.size() & 1) blob.push_back(0);  // 8-byte alignment of the int2 tables
+  // encoder lists: the dual-diagonal rows (all rows of the 11n family, the
+  // four core rows of the BG shape) XOR information columns; extension rows
+  // XOR information and core parity columns
+  const int m_core = family == LSIM_FAMILY_11N ? mb : 4;
+  std::vector<int> enc_ptr(mb + 1, 0), enc_cz;
+  for (int i = 0; i < mb; ++i) {
+    const int lim = i < m_core ? kb : kb + 4;
+    for (int j = 0; j < lim; ++j) {
+      const int sh = H[(size_t)i * nb + j];
+      if (sh < 0) continue;
+      enc_cz.push_back(j * Z);
+      enc_cz.push_back(sh);
+    }
+    enc_ptr[i + 1] = (int)(enc_cz.size() / 2);
+  }
   size_t o_ce2 = push(ce2);
   size_t o_ecz = push(ecz);
-  size_t o_base = blob.size();
-  blob.resize(blob.size() + ((size_t)mb * nb + 1) / 2, 0);
-  std::memcpy(blob.data() + o_base, H.data(), H.size() * sizeof(int16_t));
+  size_t o_encz = push(enc_cz);
+  size_t o_encp = push(enc_ptr);
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) e = hipMalloc(&c->dmem, blob.size() * sizeof(int));
   if (e == hipSuccess)
@@ -272,7 +286,8 @@ lsim_status lsim_code_create(const int16_t* base, int mb, int nb, int Z, int fam
   dc.col_ent = d + o_ce;
   dc.cn_tasks = d + o_cn;
   dc.vn_tasks = d + o_vn;
-  dc.base = reinterpret_cast<const int16_t*>(d + o_base);
+  dc.enc_ptr = d + o_encp;
+  dc.enc_cz = reinterpret_cast<const int2*>(d + o_encz);
   dc.col_edge = reinterpret_cast<const int2*>(d + o_ce2);
   dc.ent_cz = reinterpret_cast<const int2*>(d + o_ecz);
   lsim_code_info& in = c->info;

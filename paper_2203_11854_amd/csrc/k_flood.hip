@@ -175,30 +175,29 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
 #pragma unroll
           for (int q = 0; q < D; ++q) x[q] = row[q * Z];
           if constexpr (ALG == LSIM_SPA_F32) {
-            // sum-product in the "1 - prod tanh" domain (spa_math.h); the
+            // sum-product in the sum / difference form (spa_math.h); the
             // output sign is the XOR of the other inputs' sign bits (a zero
             // input only ever receives or sends zero magnitudes, so the sign
             // of a zero is immaterial)
             uint32_t sx = 0;
 #pragma unroll
             for (int q = 0; q < D; ++q) sx ^= __float_as_uint(x[q]);
-            float mm[D], pD[D], pC[D];
-            SpaAcc pre;
+            float ee[D], pS[D], pA[D];
+            SpaSA pre;
 #pragma unroll
             for (int q = 0; q < D; ++q) {
-              mm[q] = spa_m(x[q]);
-              pD[q] = pre.D;
-              pC[q] = pre.C;
-              pre.add(mm[q]);
+              ee[q] = spa_e(x[q]);
+              pS[q] = pre.S;
+              pA[q] = pre.A;
+              pre.add(ee[q]);
             }
-            SpaAcc suf;
+            SpaSA suf;
 #pragma unroll
             for (int q = D - 1; q >= 0; --q) {
-              const float Dx = fmaf(suf.D, pC[q], pD[q]);
-              const float rv = fminf(spa_mag(Dx), a.llr_max);
+              const float rv = spa_mag_sa(pS[q], pA[q], suf.S, suf.A, a.llr_max);
               const uint32_t sg = (sx ^ __float_as_uint(x[q])) & 0x80000000u;
               row[q * Z] = __uint_as_float(__float_as_uint(rv) | sg);
-              suf.add(mm[q]);
+              suf.add(ee[q]);
             }
           } else {
             uint32_t neg = 0;

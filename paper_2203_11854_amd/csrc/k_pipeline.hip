@@ -2,6 +2,7 @@
 // mapper + AWGN, demappers, quantizer, error counting and syndrome.
 #include <hip/hip_runtime.h>
 
+#include "dispatch.h"
 #include "lsim_internal.h"
 #include "philox.h"
 
@@ -39,43 +40,70 @@ __global__ void source_bits_kernel(uint64_t seed, int64_t cw0, int64_t B, int64_
 
 // ---------------------------------------------------------------- encoder
 
-// One workgroup per codeword; the whole mother codeword sits in LDS.
-// lambda_i (core rows) = XOR over information blocks of rotated u_j;
-// p_0 = XOR of all lambda_i; p_1 = lambda_0 ^ P^1 p_0;
-// p_{i+1} = lambda_i ^ p_i (^ p_0 at the middle row); extension rows (BG
-// shape) then set their own block from columns < kb + 4.
-__global__ __launch_bounds__(256) void encode_kernel(DevCode c, const uint8_t* __restrict__ u,
-                                                     uint8_t* __restrict__ cw) {
-  extern __shared__ uint8_t sm[];
-  const int Z = c.Z, kb = c.kb, nb = c.nb, mb = c.mb;
+// One workgroup per codeword; the whole mother codeword sits in LDS, one
+// byte per bit.  lambda_i (dual-diagonal rows) = XOR over the row's
+// information blocks of rotated u_j; p_0 = XOR of all lambda_i;
+// p_1 = lambda_0 ^ P^1 p_0; p_{i+1} = lambda_i ^ p_i (^ p_0 at the middle
+// row); extension rows (BG shape) then set their own block from columns
+// < kb + 4.  XOR rows are dealt to wavefronts as (row, 64-lift chunk) items
+// so the row's entry list is read with scalar loads; bits move in and out
+// with 16-byte accesses when the rows are aligned.
+constexpr int kEncThreads = 256;
+
+__device__ __forceinline__ void enc_xor_rows(const DevCode& c, uint8_t* cb, int row0, int nrows,
+                                             uint8_t* dst, int dst_stride) {
+  const int Z = c.Z;
+  const int cpr = (Z + 63) >> 6;
+  const int lane = threadIdx.x & 63;
+  for (int q = uni(threadIdx.x >> 6); q < nrows * cpr; q += kEncThreads / 64) {
+    const int i = q / cpr;
+    const int r = (q - i * cpr) * 64 + lane;
+    const int e0 = ld_const(c.enc_ptr, row0 + i), e1 = ld_const(c.enc_ptr, row0 + i + 1);
+    if (r < Z) {
+      uint8_t acc = 0;
+      for (int e = e0; e < e1; ++e) {
+        const int2 cs = ld_const(c.enc_cz, e);
+        int x = r + cs.y;
+        x -= x >= Z ? Z : 0;
+        acc ^= cb[cs.x + x];
+      }
+      dst[i * dst_stride + r] = acc;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kEncThreads) void encode_kernel(DevCode c, const uint8_t* __restrict__ u,
+                                                             uint8_t* __restrict__ cw) {
+  extern __shared__ __align__(16) uint8_t sm[];
+  const int Z = c.Z, kb = c.kb, mb = c.mb;
   const int m = c.family == LSIM_FAMILY_11N ? mb : 4;
   const int mid = m / 2;
-  uint8_t* cb = sm;                        // n_mother bits
-  uint8_t* lam = sm + c.n_mother;          // m * Z
+  uint8_t* cb = sm;                                        // n_mother bits
+  uint8_t* lam = sm + ((c.n_mother + 15) & ~15);           // m * Z
   const int64_t b = blockIdx.x;
   const uint8_t* ub = u + b * (int64_t)c.k;
-  for (int i = threadIdx.x; i < c.k; i += blockDim.x) cb[i] = ub[i] & 1;
-  __syncthreads();
-  for (int t = threadIdx.x; t < m * Z; t += blockDim.x) {
-    const int i = t / Z, r = t - i * Z;
-    uint8_t acc = 0;
-    for (int j = 0; j < kb; ++j) {
-      const int s = c.base[i * nb + j];
-      if (s < 0) continue;
-      int x = r + s;
-      x -= x >= Z ? Z : 0;
-      acc ^= cb[j * Z + x];
+  if (((c.k & 15) | ((uintptr_t)ub & 15)) == 0) {
+    for (int i = threadIdx.x; i < (c.k >> 4); i += kEncThreads) {
+      uint4 v = reinterpret_cast<const uint4*>(ub)[i];
+      v.x &= 0x01010101u;
+      v.y &= 0x01010101u;
+      v.z &= 0x01010101u;
+      v.w &= 0x01010101u;
+      reinterpret_cast<uint4*>(cb)[i] = v;
     }
-    lam[t] = acc;
+  } else {
+    for (int i = threadIdx.x; i < c.k; i += kEncThreads) cb[i] = ub[i] & 1;
   }
   __syncthreads();
-  for (int r = threadIdx.x; r < Z; r += blockDim.x) {
+  enc_xor_rows(c, cb, 0, m, lam, Z);
+  __syncthreads();
+  for (int r = threadIdx.x; r < Z; r += kEncThreads) {
     uint8_t p0 = 0;
     for (int i = 0; i < m; ++i) p0 ^= lam[i * Z + r];
     cb[kb * Z + r] = p0;
   }
   __syncthreads();
-  for (int r = threadIdx.x; r < Z; r += blockDim.x) {
+  for (int r = threadIdx.x; r < Z; r += kEncThreads) {
     const int r1 = r + 1 == Z ? 0 : r + 1;
     const uint8_t p0r = cb[kb * Z + r];
     uint8_t p = lam[r] ^ cb[kb * Z + r1];
@@ -86,24 +114,17 @@ __global__ __launch_bounds__(256) void encode_kernel(DevCode c, const uint8_t* _
     }
   }
   __syncthreads();
-  if (c.family == LSIM_FAMILY_BG) {
-    const int ext = mb - 4;
-    for (int t = threadIdx.x; t < ext * Z; t += blockDim.x) {
-      const int row = 4 + t / Z, r = t % Z;
-      uint8_t acc = 0;
-      for (int j = 0; j < kb + 4; ++j) {
-        const int s = c.base[row * nb + j];
-        if (s < 0) continue;
-        int x = r + s;
-        x -= x >= Z ? Z : 0;
-        acc ^= cb[j * Z + x];
-      }
-      cb[(kb + row) * Z + r] = acc;
-    }
+  if (c.family == LSIM_FAMILY_BG && mb > 4) {
+    enc_xor_rows(c, cb, 4, mb - 4, cb + (kb + 4) * Z, Z);
     __syncthreads();
   }
   uint8_t* out = cw + b * (int64_t)c.n_mother;
-  for (int i = threadIdx.x; i < c.n_mother; i += blockDim.x) out[i] = cb[i];
+  if (((c.n_mother & 15) | ((uintptr_t)out & 15)) == 0) {
+    for (int i = threadIdx.x; i < (c.n_mother >> 4); i += kEncThreads)
+      reinterpret_cast<uint4*>(out)[i] = reinterpret_cast<const uint4*>(cb)[i];
+  } else {
+    for (int i = threadIdx.x; i < c.n_mother; i += kEncThreads) out[i] = cb[i];
+  }
 }
 
 // ------------------------------------------------------- mapper + channel
@@ -269,39 +290,78 @@ __global__ void quantize_kernel(const float* __restrict__ L, int64_t n, float sc
 
 // ------------------------------------------------------------ error count
 
-// One wavefront per codeword.  Bits are bytes holding 0/1, so the
-// population count of the XOR of two 32-bit words counts 4 bit errors at
-// a time; rows that are not 4-byte aligned fall back to bytes.
-__global__ __launch_bounds__(256) void count_errors_kernel(const uint8_t* __restrict__ ref,
-                                                           int64_t ref_stride,
-                                                           const uint8_t* __restrict__ hat,
-                                                           int64_t k, int64_t B,
-                                                           const int32_t* __restrict__ bin,
-                                                           int nbins, int64_t* __restrict__ counts) {
+// One wavefront per codeword, four codewords per wavefront and sixteen per
+// workgroup.  Bits are bytes holding 0/1, so the population count of the
+// XOR of two words counts 4 bit errors at a time (16-byte loads when both
+// rows are 16-byte aligned, 4-byte when 4-byte aligned, else bytes).  Up to
+// kLdsBins bins are summed in LDS and added to the device counters once per
+// workgroup; with more bins each codeword adds its own counts.
+constexpr int kCountThreads = 256;
+constexpr int kCwPerWave = 4;
+constexpr int kCwPerBlock = kCountThreads / 64 * kCwPerWave;
+constexpr int kLdsBins = 64;
+
+__device__ __forceinline__ int popc_err(uint32_t a, uint32_t b) {
+  return __popc((a ^ b) & 0x01010101u);
+}
+
+__global__ __launch_bounds__(kCountThreads) void count_errors_kernel(
+    const uint8_t* __restrict__ ref, int64_t ref_stride, const uint8_t* __restrict__ hat,
+    int64_t k, int64_t B, const int32_t* __restrict__ bin, int nbins,
+    int64_t* __restrict__ counts) {
+  __shared__ unsigned long long acc[3 * kLdsBins];
+  const bool in_lds = nbins <= kLdsBins;
+  for (int t = threadIdx.x; t < 3 * kLdsBins; t += kCountThreads) acc[t] = 0;
+  __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (b >= B) return;
-  const uint8_t* rr = ref + b * ref_stride;
-  const uint8_t* hh = hat + b * k;
-  int err = 0;
-  if (((((uintptr_t)rr) | ((uintptr_t)hh)) & 3) == 0) {
-    const int64_t nw = k >> 2;
-    const uint32_t* r4 = reinterpret_cast<const uint32_t*>(rr);
-    const uint32_t* h4 = reinterpret_cast<const uint32_t*>(hh);
-    for (int64_t i = lane; i < nw; i += 64) err += __popc((r4[i] ^ h4[i]) & 0x01010101u);
-    for (int64_t i = nw * 4 + lane; i < k; i += 64) err += (rr[i] & 1) != (hh[i] & 1);
-  } else {
-    for (int64_t i = lane; i < k; i += 64) err += (rr[i] & 1) != (hh[i] & 1);
+  const int64_t first = (int64_t)blockIdx.x * kCwPerBlock + uni(threadIdx.x >> 6) * kCwPerWave;
+  for (int j = 0; j < kCwPerWave; ++j) {
+    const int64_t b = first + j;
+    if (b >= B) break;
+    const uint8_t* rr = ref + b * ref_stride;
+    const uint8_t* hh = hat + b * k;
+    const uintptr_t al = (uintptr_t)rr | (uintptr_t)hh;
+    int err = 0;
+    int64_t done = 0;
+    if ((al & 15) == 0) {
+      const int64_t nv = k >> 4;
+      const uint4* r4 = reinterpret_cast<const uint4*>(rr);
+      const uint4* h4 = reinterpret_cast<const uint4*>(hh);
+      for (int64_t i = lane; i < nv; i += 64) {
+        const uint4 x = r4[i], y = h4[i];
+        err += popc_err(x.x, y.x) + popc_err(x.y, y.y) + popc_err(x.z, y.z) + popc_err(x.w, y.w);
+      }
+      done = nv << 4;
+    } else if ((al & 3) == 0) {
+      const int64_t nw = k >> 2;
+      const uint32_t* r1 = reinterpret_cast<const uint32_t*>(rr);
+      const uint32_t* h1 = reinterpret_cast<const uint32_t*>(hh);
+      for (int64_t i = lane; i < nw; i += 64) err += popc_err(r1[i], h1[i]);
+      done = nw << 2;
+    }
+    for (int64_t i = done + lane; i < k; i += 64) err += (rr[i] & 1) != (hh[i] & 1);
+    for (int off = 32; off > 0; off >>= 1) err += __shfl_down(err, off, 64);
+    if (lane == 0) {
+      const int bb = bin ? bin[b] : 0;
+      if (bb >= 0 && bb < nbins) {  // codewords outside every bin are not counted
+        if (in_lds) {
+          atomicAdd(&acc[3 * bb + 0], (unsigned long long)err);
+          atomicAdd(&acc[3 * bb + 1], (unsigned long long)(err > 0));
+          atomicAdd(&acc[3 * bb + 2], 1ull);
+        } else {
+          unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counts) + 3 * (int64_t)bb;
+          atomicAdd(cnt + 0, (unsigned long long)err);
+          atomicAdd(cnt + 1, (unsigned long long)(err > 0));
+          atomicAdd(cnt + 2, 1ull);
+        }
+      }
+    }
   }
-  for (int off = 32; off > 0; off >>= 1) err += __shfl_down(err, off, 64);
-  if (lane == 0) {
-    const int bb = bin ? bin[b] : 0;
-    if (bb < 0 || bb >= nbins) return;  // codewords outside every bin are not counted
-    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counts) + 3 * (int64_t)bb;
-    atomicAdd(cnt + 0, (unsigned long long)err);
-    atomicAdd(cnt + 1, (unsigned long long)(err > 0));
-    atomicAdd(cnt + 2, 1ull);
-  }
+  if (!in_lds) return;
+  __syncthreads();
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(counts);
+  for (int t = threadIdx.x; t < 3 * nbins; t += kCountThreads)
+    if (acc[t]) atomicAdd(cnt + t, acc[t]);
 }
 
 __global__ __launch_bounds__(256) void syndrome_kernel(DevCode c, const uint8_t* __restrict__ cw,
@@ -341,8 +401,8 @@ hipError_t launch_source_bits(uint64_t seed, int64_t cw0, int64_t B, int64_t k, 
 hipError_t launch_encode(const DevCode& c, const uint8_t* u, int64_t B, uint8_t* cw,
                          hipStream_t s) {
   const int m = c.family == LSIM_FAMILY_11N ? c.mb : 4;
-  const size_t lds = (size_t)c.n_mother + (size_t)m * c.Z;
-  encode_kernel<<<(unsigned)B, 256, lds, s>>>(c, u, cw);
+  const size_t lds = (((size_t)c.n_mother + 15) & ~(size_t)15) + (size_t)m * c.Z;
+  encode_kernel<<<(unsigned)B, kEncThreads, lds, s>>>(c, u, cw);
   return hipGetLastError();
 }
 
@@ -375,8 +435,8 @@ hipError_t launch_quantize(const float* llr, int64_t n, float scale, int sat, in
 hipError_t launch_count_errors(const uint8_t* ref, int64_t ref_stride, const uint8_t* hat,
                                int64_t B, int64_t k, const int32_t* bin, int nbins,
                                int64_t* counts, hipStream_t s) {
-  count_errors_kernel<<<(unsigned)((B + 3) / 4), 256, 0, s>>>(ref, ref_stride, hat, k, B, bin,
-                                                               nbins, counts);
+  count_errors_kernel<<<grid_for(B, kCwPerBlock), kCountThreads, 0, s>>>(ref, ref_stride, hat, k,
+                                                                         B, bin, nbins, counts);
   return hipGetLastError();
 }
 

@@ -24,7 +24,9 @@ struct DevCode {
   const int* col_ent;    // entry ids of each column, rows ascending
   const int* cn_tasks;   // (row << 16) | lift0, heaviest first
   const int* vn_tasks;   // (col << 16) | lift0, heaviest first
-  const int16_t* base;   // full mb x nb base matrix (encoder)
+  const int* enc_ptr;    // mb+1; encoder entries of base row i: enc_ptr[i]..enc_ptr[i+1]-1
+  const int2* enc_cz;    // (col * Z, shift) of the row's entries the encoder XORs: information
+                         // columns for the dual-diagonal rows, columns < kb+4 for extension rows
   const int2* col_edge;  // per column entry (col_ptr order): (e * Z, shift of e)
   const int2* ent_cz;    // per entry (row-major): (col * Z, shift)
 };

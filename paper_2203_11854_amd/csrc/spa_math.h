@@ -43,4 +43,36 @@ __device__ __forceinline__ float spa_mag(float D) {
   return kLn2 * __builtin_amdgcn_logf((2.f - D) * __builtin_amdgcn_rcpf(D));
 }
 
+// Sum / difference form (flooding decoder).  With e = exp(-|q|) per input,
+// tanh(|q|/2) = (1 - e) / (1 + e), so the product over a set of inputs is
+// N / Dn with N = prod (1 - e_j) and Dn = prod (1 + e_j).  The decoder keeps
+// S = Dn + N and A = Dn - N, which grow from (2, 0) through
+//   S' = S + e A,   A' = A + e S
+// (positive terms only: no cancellation when every e is tiny).  For the
+// inputs other than v, split into a prefix p and a suffix s,
+//   S_v ~ Sp Ss + Ap As,   A_v ~ Sp As + Ap Ss   (common factor 1/2),
+// and the extrinsic magnitude is 2 atanh(N_v / Dn_v) = ln(S_v / A_v).  One
+// exp per input (no reciprocal) and one reciprocal + one log per output.
+struct SpaSA {
+  float S = 2.f, A = 0.f;
+  __device__ __forceinline__ void add(float e) {
+    const float s = fmaf(e, A, S);
+    A = fmaf(e, S, A);
+    S = s;
+  }
+};
+
+__device__ __forceinline__ float spa_e(float q) {
+  return __builtin_amdgcn_exp2f(fabsf(q) * -kLog2e);
+}
+
+// ln(S_v / A_v) of a prefix (sp, ap) and a suffix (ss, as), clamped to
+// [0, lmax] (the ratio is >= 1 up to rounding).
+__device__ __forceinline__ float spa_mag_sa(float sp, float ap, float ss, float as, float lmax) {
+  const float num = fmaf(sp, ss, ap * as);
+  const float den = fmaf(sp, as, ap * ss);
+  const float l = kLn2 * __builtin_amdgcn_logf(num * __builtin_amdgcn_rcpf(den));
+  return __builtin_amdgcn_fmed3f(l, 0.f, lmax);
+}
+
 }  // namespace lsim

@@ -125,6 +125,28 @@ def test_count_errors_exact():
     assert np.array_equal(cnt, stats.count_errors(u, h, bins, 5))
 
 
+@pytest.mark.parametrize("B,k,nbins,stride_pad", [(1000, 1280, 9, 0), (777, 1284, 100, 0),
+                                                  (257, 1280, 7, 5376), (64, 16, 1, 0)])
+def test_count_errors_shapes(B, k, nbins, stride_pad):
+    """16-byte, 4-byte and byte paths (rows of 1284 bytes alternate between
+    them), LDS-summed bins and per-codeword device atomics (100 bins), a
+    reference with a row stride larger than k (the encoder's codewords),
+    and bin indices outside [0, nbins) that must not be counted."""
+    r = rand.rng(3)
+    full = rand.bits(4, (B, k + stride_pad))
+    u = full[:, :k]
+    h = u.copy()
+    h[r.random((B, k)) < 0.003] ^= 1
+    bins = r.integers(-1, nbins + 1, B).astype(np.int32)
+    tref = T(full).to(dev)[:, :k]
+    cnt = lsim.count_errors(tref, T(h).to(dev), T(bins).to(dev), nbins).cpu().numpy()
+    assert np.array_equal(cnt, stats.count_errors(u, h, bins, nbins))
+    # accumulation into existing counters
+    cnt2 = lsim.count_errors(tref, T(h).to(dev), T(bins).to(dev), nbins,
+                             counts=torch.tensor(cnt).to(dev)).cpu().numpy()
+    assert np.array_equal(cnt2, 2 * cnt)
+
+
 def test_syndrome_exact():
     qb, code, _ = code_for("bg2")
     g = qc.graph_from_qcbase(qb, code.e_tx)
