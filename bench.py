@@ -47,10 +47,12 @@ FLOOD_SPA_TRAFFIC = {"bytes": (30967 * 2 + 5120) * 1024,
                      "sources": ("k_flood.hip", "spa_math.h", "dispatch.h", "lsim_internal.h"),
                      "sha256_16": "89acd6f0c3923ab0"}
 
-# Algorithmic VALU work per edge and round ("Roofline"):
-# sum-product: check side 12 simple ops + 4 transcendentals (quarter rate,
-# 4 issue slots each), variable side 3 ops -> 31 issue slots.
-SPA_SLOTS_PER_EDGE = 12 + 4 * 4 + 3
+# Algorithmic VALU work per edge and round:
+# sum-product in the sum / difference form: check side 13 simple ops
+# (sign xor, prefix and suffix updates 2 + 2, combination 4, ratio product,
+# clamp, sign insert 2) + 3 transcendentals (exp, rcp, log; quarter rate,
+# 4 issue slots each), variable side 3 ops -> 28 issue slots.
+SPA_SLOTS_PER_EDGE = 13 + 3 * 4 + 3
 # offset min-sum: check side 9 ops, variable side 3 ops.
 OMS_SLOTS_PER_EDGE = 9 + 3
 # layered normalized min-sum: 12 ops per edge and layer visit.

@@ -82,13 +82,15 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
   // loads from the code's device tables)
   const int zm = Z - 1;
   const bool zpow2 = (Z & zm) == 0;
+  // sum-product messages live in log2 units (x log2 e) inside the kernel
+  const float lmax2 = a.llr_max * kLog2e;
   const In* llr = reinterpret_cast<const In*>(a.llr) + b * (int64_t)c.e_tx;
   for (int v = tid; v < c.n_dec; v += NT) {
     const int x = v - c.tx_lo;
     M l = 0;
     if (x >= 0 && x < c.e_tx) {
       if constexpr (ALG == LSIM_SPA_F32) {
-        l = fminf(fmaxf(-llr[x], -a.llr_max), a.llr_max);
+        l = fminf(fmaxf(-llr[x], -a.llr_max), a.llr_max) * kLog2e;
       } else {
         l = (M)min(max(-(int)llr[x], -a.sat), a.sat);
       }
@@ -97,7 +99,12 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
   }
   if (a.q_in) {
     const M* qi = reinterpret_cast<const M*>(a.q_in) + b * (int64_t)c.E;
-    for (int e = tid; e < c.E; e += NT) msg[e] = qi[e];
+    for (int e = tid; e < c.E; e += NT) {
+      if constexpr (ALG == LSIM_SPA_F32)
+        msg[e] = qi[e] * kLog2e;
+      else
+        msg[e] = qi[e];
+    }
   } else {
     for (int e = tid; e < c.E; e += NT) msg[e] = 0;
   }
@@ -146,14 +153,19 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
             for (int q = 0; q < DC; ++q) {
               if constexpr (ALG == LSIM_SPA_F32)
                 *reinterpret_cast<M*>(mb + idx[q]) =
-                    __builtin_amdgcn_fmed3f(acc - rv[q], -a.llr_max, a.llr_max);
+                    __builtin_amdgcn_fmed3f(acc - rv[q], -lmax2, lmax2);
               else
                 *reinterpret_cast<M*>(mb + idx[q]) = (M)min(max(acc - rv[q], -a.sat), a.sat);
             }
           }
           if (final_round) {
             if (a.bits && v < c.k) a.bits[b * (int64_t)c.k + v] = acc < 0;
-            if (a.lpost) a.lpost[b * (int64_t)c.n_dec + v] = (float)(-acc);
+            if (a.lpost) {
+              if constexpr (ALG == LSIM_SPA_F32)
+                a.lpost[b * (int64_t)c.n_dec + v] = -acc * kLn2;
+              else
+                a.lpost[b * (int64_t)c.n_dec + v] = (float)(-acc);
+            }
           }
         });
       }
@@ -175,29 +187,41 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
 #pragma unroll
           for (int q = 0; q < D; ++q) x[q] = row[q * Z];
           if constexpr (ALG == LSIM_SPA_F32) {
-            // sum-product in the sum / difference form (spa_math.h); the
-            // output sign is the XOR of the other inputs' sign bits (a zero
-            // input only ever receives or sends zero magnitudes, so the sign
-            // of a zero is immaterial)
+            // sum-product in the sum / difference form, log2 units
+            // (spa_math.h); the output sign is the XOR of the other inputs'
+            // sign bits (a zero input only ever receives or sends zero
+            // magnitudes, so the sign of a zero is immaterial)
             uint32_t sx = 0;
 #pragma unroll
             for (int q = 0; q < D; ++q) sx ^= __float_as_uint(x[q]);
             float ee[D], pS[D], pA[D];
-            SpaSA pre;
 #pragma unroll
-            for (int q = 0; q < D; ++q) {
-              ee[q] = spa_e(x[q]);
+            for (int q = 0; q < D; ++q) ee[q] = spa_e2(x[q]);
+            SpaSA pre{1.f, ee[0]};
+#pragma unroll
+            for (int q = 1; q < D; ++q) {
               pS[q] = pre.S;
               pA[q] = pre.A;
-              pre.add(ee[q]);
+              if (q + 1 < D) pre.add(ee[q]);
             }
-            SpaSA suf;
+            SpaSA suf{1.f, ee[D - 1]};
 #pragma unroll
             for (int q = D - 1; q >= 0; --q) {
-              const float rv = spa_mag_sa(pS[q], pA[q], suf.S, suf.A, a.llr_max);
+              float num, den;
+              if (q == D - 1) {
+                num = pS[q];
+                den = pA[q];
+              } else if (q == 0) {
+                num = suf.S;
+                den = suf.A;
+              } else {
+                num = fmaf(pS[q], suf.S, pA[q] * suf.A);
+                den = fmaf(pS[q], suf.A, pA[q] * suf.S);
+              }
+              const float rv = spa_log2_ratio(num, den, lmax2);
               const uint32_t sg = (sx ^ __float_as_uint(x[q])) & 0x80000000u;
               row[q * Z] = __uint_as_float(__float_as_uint(rv) | sg);
-              suf.add(ee[q]);
+              if (q < D - 1 && q > 0) suf.add(ee[q]);
             }
           } else {
             uint32_t neg = 0;
@@ -233,7 +257,12 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
     __syncthreads();
     if (last && a.r_out) {
       M* ro = reinterpret_cast<M*>(a.r_out) + b * (int64_t)c.E;
-      for (int e = tid; e < c.E; e += NT) ro[e] = msg[e];
+      for (int e = tid; e < c.E; e += NT) {
+        if constexpr (ALG == LSIM_SPA_F32)
+          ro[e] = msg[e] * kLn2;
+        else
+          ro[e] = msg[e];
+      }
       __syncthreads();
     }
     var_phase(!last || a.q_out != nullptr, last);
@@ -241,7 +270,12 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
   }
   if (a.q_out) {
     M* qo = reinterpret_cast<M*>(a.q_out) + b * (int64_t)c.E;
-    for (int e = tid; e < c.E; e += NT) qo[e] = msg[e];
+    for (int e = tid; e < c.E; e += NT) {
+      if constexpr (ALG == LSIM_SPA_F32)
+        qo[e] = msg[e] * kLn2;
+      else
+        qo[e] = msg[e];
+    }
   }
 }
 

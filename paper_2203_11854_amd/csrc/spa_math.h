@@ -46,15 +46,18 @@ __device__ __forceinline__ float spa_mag(float D) {
 // Sum / difference form (flooding decoder).  With e = exp(-|q|) per input,
 // tanh(|q|/2) = (1 - e) / (1 + e), so the product over a set of inputs is
 // N / Dn with N = prod (1 - e_j) and Dn = prod (1 + e_j).  The decoder keeps
-// S = Dn + N and A = Dn - N, which grow from (2, 0) through
+// S and A proportional to Dn + N and Dn - N: one input gives (1, e), and
+// each further input maps
 //   S' = S + e A,   A' = A + e S
 // (positive terms only: no cancellation when every e is tiny).  For the
 // inputs other than v, split into a prefix p and a suffix s,
-//   S_v ~ Sp Ss + Ap As,   A_v ~ Sp As + Ap Ss   (common factor 1/2),
-// and the extrinsic magnitude is 2 atanh(N_v / Dn_v) = ln(S_v / A_v).  One
-// exp per input (no reciprocal) and one reciprocal + one log per output.
+//   S_v ~ Sp Ss + Ap As,   A_v ~ Sp As + Ap Ss,
+// and the extrinsic magnitude is 2 atanh(N_v / Dn_v) = ln(S_v / A_v); at
+// the ends of a check one side is empty and the ratio is that of the other.
+// The flooding kernel keeps messages in log2 units (x log2 e), so e is one
+// exp2 of the stored value and the magnitude one log2 of the ratio.
 struct SpaSA {
-  float S = 2.f, A = 0.f;
+  float S, A;
   __device__ __forceinline__ void add(float e) {
     const float s = fmaf(e, A, S);
     A = fmaf(e, S, A);
@@ -62,17 +65,13 @@ struct SpaSA {
   }
 };
 
-__device__ __forceinline__ float spa_e(float q) {
-  return __builtin_amdgcn_exp2f(fabsf(q) * -kLog2e);
-}
+// e = exp(-|q|) of a message stored in log2 units
+__device__ __forceinline__ float spa_e2(float q2) { return __builtin_amdgcn_exp2f(-fabsf(q2)); }
 
-// ln(S_v / A_v) of a prefix (sp, ap) and a suffix (ss, as), clamped to
-// [0, lmax] (the ratio is >= 1 up to rounding).
-__device__ __forceinline__ float spa_mag_sa(float sp, float ap, float ss, float as, float lmax) {
-  const float num = fmaf(sp, ss, ap * as);
-  const float den = fmaf(sp, as, ap * ss);
-  const float l = kLn2 * __builtin_amdgcn_logf(num * __builtin_amdgcn_rcpf(den));
-  return __builtin_amdgcn_fmed3f(l, 0.f, lmax);
+// log2 of num / den clamped to [0, lmax2] (the ratio is >= 1 up to rounding)
+__device__ __forceinline__ float spa_log2_ratio(float num, float den, float lmax2) {
+  const float l = __builtin_amdgcn_logf(num * __builtin_amdgcn_rcpf(den));
+  return __builtin_amdgcn_fmed3f(l, 0.f, lmax2);
 }
 
 }  // namespace lsim
