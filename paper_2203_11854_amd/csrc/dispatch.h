@@ -7,6 +7,16 @@ namespace lsim {
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Returns x unchanged in a vector register the optimizer cannot look
+// through.  Rotated LDS addresses ((lane_bytes - shift_bytes) & mask) | base
+// then stay one subtract and one v_and_or_b32 per edge: with the mask in a
+// VGPR the and-or reads a single scalar (the base), and the lane's byte
+// offset is not refactored into (lane - shift) & mask followed by a shift.
+__device__ __forceinline__ int vreg(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 template <int N>
 struct Deg {
   static constexpr int value = N;

@@ -66,6 +66,12 @@ hipError_t launch_flood(const DevCode& c, const lsim_decode_params& p, const voi
                         uint8_t* bits, float* lpost, const void* q_in, void* r_out, void* q_out,
                         hipStream_t s, std::string* why);
 size_t flood_lds_bytes(const DevCode& c, int algo);
+// Packed two-codeword int8 offset min-sum (k_oms2.hip); launch_flood routes
+// LSIM_OMS_I8 here.
+hipError_t launch_oms2(const DevCode& c, const lsim_decode_params& p, const int8_t* llr, int64_t B,
+                       uint8_t* bits, float* lpost, const int8_t* q_in, int8_t* r_out,
+                       int8_t* q_out, hipStream_t s, std::string* why);
+size_t oms2_lds_bytes(const DevCode& c);
 
 // Layered decoder and mixed batches (k_layered.hip)
 struct LayerShape {
