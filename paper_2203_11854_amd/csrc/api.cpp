@@ -20,6 +20,20 @@ static thread_local std::string g_err;
 
 void set_error(const std::string& msg) { g_err = msg; }
 
+hipError_t require_lds_at_zero(const void* kernel) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, bool> ok;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = ok.find(kernel);
+  if (it == ok.end()) {
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, kernel);
+    if (e != hipSuccess) return e;
+    it = ok.emplace(kernel, attr.sharedSizeBytes == 0).first;
+  }
+  return it->second ? hipSuccess : hipErrorInvalidDeviceFunction;
+}
+
 hipError_t ensure_dyn_lds(const void* kernel, size_t bytes) {
   static std::mutex mu;
   static std::unordered_map<const void*, size_t> done;

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dispatch.h"
+#include "lds.h"
 #include "lsim_internal.h"
 #include "spa_math.h"
 
@@ -44,17 +45,21 @@ __host__ __device__ inline size_t spa_lds(const DevCode& c) {
   return align16((size_t)c.E * 4) + align16((size_t)c.n_dec * 4);
 }
 
-template <int NT, int DMAX>
+// ZC: the lift size when it is a compile-time constant (0: read from the
+// code), which turns the check phase's row strides into immediate offsets.
+// LDS: messages at byte 0, channel LLRs at lam_b (kernel has no static LDS).
+template <int NT, int DMAX, int ZC>
 __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
   using M = float;
   constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   M* msg = reinterpret_cast<M*>(smem);
   M* lam = reinterpret_cast<M*>(smem + align16((size_t)c.E * sizeof(M)));
+  const int lam_b = (int)align16((size_t)c.E * sizeof(M));
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = uni(tid >> 6);
-  const int Z = c.Z;
+  const int Z = ZC ? ZC : c.Z;
   const int64_t b = blockIdx.x;
 
   // ---- channel LLRs, zero messages (graph tables are read with scalar
@@ -110,16 +115,15 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
               idx[q] = (ce.x + x) * SZ;
             }
           }
-          unsigned char* mb = reinterpret_cast<unsigned char*>(msg);
 #pragma unroll
-          for (int q = 0; q < DC; ++q) rv[q] = *reinterpret_cast<M*>(mb + idx[q]);
-          float acc = lam[v];
+          for (int q = 0; q < DC; ++q) rv[q] = lds_ld<float>(idx[q]);
+          float acc = lds_ld<float>(lam_b + v * 4);
 #pragma unroll
           for (int q = 0; q < DC; ++q) acc += rv[q];
           if (write_q) {
 #pragma unroll
             for (int q = 0; q < DC; ++q)
-              *reinterpret_cast<M*>(mb + idx[q]) = __builtin_amdgcn_fmed3f(acc - rv[q], -lmax2, lmax2);
+              lds_st<float>(idx[q], __builtin_amdgcn_fmed3f(acc - rv[q], -lmax2, lmax2));
           }
           if (final_round) {
             if (a.bits && v < c.k) a.bits[b * (int64_t)c.k + v] = acc < 0;
@@ -138,13 +142,13 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
       const int e0 = uni(ld_const(c.row_ptr, i));
       const int d = uni(ld_const(c.row_ptr, i + 1)) - e0;
       if (r < Z) {
-        M* row = msg + (size_t)e0 * Z + r;
+        const int row_b = (e0 * Z + r) * 4;
         with_degree<DMAX>(d, [&](auto deg) {
           constexpr int D = decltype(deg)::value;
           if constexpr (D >= 2) {  // decoded checks have degree >= 2
           M x[D];
 #pragma unroll
-          for (int q = 0; q < D; ++q) x[q] = row[q * Z];
+          for (int q = 0; q < D; ++q) x[q] = lds_ld<float>(row_b + q * Z * 4);
           // sum-product in the sum / difference form, log2 units
           // (spa_math.h); the output sign is the XOR of the other inputs'
           // sign bits (a zero input only ever receives or sends zero
@@ -178,7 +182,7 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
             }
             const float rv = spa_log2_ratio(num, den, lmax2);
             const uint32_t sg = (sx ^ __float_as_uint(x[q])) & 0x80000000u;
-            row[q * Z] = __uint_as_float(__float_as_uint(rv) | sg);
+            lds_st<float>(row_b + q * Z * 4, __uint_as_float(__float_as_uint(rv) | sg));
             if (q < D - 1 && q > 0) suf.add(ee[q]);
           }
           }
@@ -209,18 +213,23 @@ __global__ __launch_bounds__(NT) void flood_kernel(DevCode c, FloodArgs a) {
   }
 }
 
-template <int NT, int DMAX>
+template <int NT, int DMAX, int ZC>
 hipError_t launch_t(const DevCode& c, const FloodArgs& a, size_t lds, hipStream_t s) {
-  hipError_t e = ensure_dyn_lds((const void*)flood_kernel<NT, DMAX>, lds);
+  const void* k = (const void*)flood_kernel<NT, DMAX, ZC>;
+  hipError_t e = require_lds_at_zero(k);
+  if (e == hipSuccess) e = ensure_dyn_lds(k, lds);
   if (e != hipSuccess) return e;
-  flood_kernel<NT, DMAX><<<(unsigned)a.B, NT, lds, s>>>(c, a);
+  flood_kernel<NT, DMAX, ZC><<<(unsigned)a.B, NT, lds, s>>>(c, a);
   return hipGetLastError();
 }
 
 hipError_t dispatch(const DevCode& c, int nt, const FloodArgs& a, size_t lds, hipStream_t s) {
   const int dmax = c.max_row_deg > c.max_col_deg ? c.max_row_deg : c.max_col_deg;
+  // the lift of the BG2-shaped workloads with its own code
+  if (c.Z == 128 && nt == 512 && dmax <= 16) return launch_t<512, 16, 128>(c, a, lds, s);
+  if (c.Z == 128 && nt == 512 && dmax <= 24) return launch_t<512, 24, 128>(c, a, lds, s);
 #define LSIM_FLOOD_CASE(NT_, D_) \
-  if (nt == NT_ && dmax <= D_) return launch_t<NT_, D_>(c, a, lds, s);
+  if (nt == NT_ && dmax <= D_) return launch_t<NT_, D_, 0>(c, a, lds, s);
   LSIM_FLOOD_CASE(256, 16)
   LSIM_FLOOD_CASE(256, 24)
   LSIM_FLOOD_CASE(256, 32)

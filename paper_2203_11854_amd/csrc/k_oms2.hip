@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dispatch.h"
+#include "lds.h"
 #include "lsim_internal.h"
 
 namespace lsim {
@@ -61,16 +62,19 @@ __host__ __device__ inline size_t oms2_lds(const DevCode& c) {
   return align16((size_t)c.E * 4) + align16((size_t)c.n_dec * 4);
 }
 
-template <int NT, int DMAX>
+// ZC: compile-time lift size or 0 (read from the code).  LDS: messages at
+// byte 0, channel values at lam_b (kernel has no static LDS).
+template <int NT, int DMAX, int ZC>
 __global__ __launch_bounds__(NT) void oms2_kernel(DevCode c, Oms2Args a) {
   constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   s16x2* msg = reinterpret_cast<s16x2*>(smem);
   s16x2* lam = reinterpret_cast<s16x2*>(smem + align16((size_t)c.E * 4));
+  const int lam_b = (int)align16((size_t)c.E * 4);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = uni(tid >> 6);
-  const int Z = c.Z;
+  const int Z = ZC ? ZC : c.Z;
   const int zm = Z - 1;
   const bool zpow2 = (Z & zm) == 0;
   const int64_t b0 = 2 * (int64_t)blockIdx.x;
@@ -130,10 +134,9 @@ __global__ __launch_bounds__(NT) void oms2_kernel(DevCode c, Oms2Args a) {
               idx[q] = (ce.x + x) * 4;
             }
           }
-          unsigned char* mb = reinterpret_cast<unsigned char*>(msg);
 #pragma unroll
-          for (int q = 0; q < DC; ++q) rv[q] = *reinterpret_cast<const s16x2*>(mb + idx[q]);
-          s16x2 acc = lam[v];
+          for (int q = 0; q < DC; ++q) rv[q] = lds_ld<s16x2>(idx[q]);
+          s16x2 acc = lds_ld<s16x2>(lam_b + v * 4);
 #pragma unroll
           for (int q = 0; q < DC; ++q) acc += rv[q];
           if (write_q) {
@@ -145,7 +148,7 @@ __global__ __launch_bounds__(NT) void oms2_kernel(DevCode c, Oms2Args a) {
 #pragma unroll
             for (int q = 0; q < DC; ++q) rv[q] = vmax(rv[q], nsat);
 #pragma unroll
-            for (int q = 0; q < DC; ++q) *reinterpret_cast<s16x2*>(mb + idx[q]) = rv[q];
+            for (int q = 0; q < DC; ++q) lds_st<s16x2>(idx[q], rv[q]);
           }
           if (final_round) {
             if (a.bits && v < c.k) {
@@ -170,12 +173,12 @@ __global__ __launch_bounds__(NT) void oms2_kernel(DevCode c, Oms2Args a) {
       const int e0 = uni(ld_const(c.row_ptr, i));
       const int d = uni(ld_const(c.row_ptr, i + 1)) - e0;
       if (r < Z) {
-        s16x2* row = msg + (size_t)e0 * Z + r;
+        const int row_b = (e0 * Z + r) * 4;
         with_degree<DMAX>(d, [&](auto deg) {
           constexpr int D = decltype(deg)::value;
           s16x2 x[D], ax[D];
 #pragma unroll
-          for (int q = 0; q < D; ++q) x[q] = row[q * Z];
+          for (int q = 0; q < D; ++q) x[q] = lds_ld<s16x2>(row_b + q * Z * 4);
           // sign parity in bits 15 and 31, the two smallest magnitudes
           uint32_t sx = 0;
           s16x2 m1 = pk(0x7fff, 0x7fff), m2 = m1;
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(NT) void oms2_kernel(DevCode c, Oms2Args a) {
 #pragma unroll
           for (int q = 0; q < D; ++q) mag[q] = mag[q] ^ neg[q];
 #pragma unroll
-          for (int q = 0; q < D; ++q) row[q * Z] = mag[q] - neg[q];
+          for (int q = 0; q < D; ++q) lds_st<s16x2>(row_b + q * Z * 4, mag[q] - neg[q]);
         });
       }
     }
@@ -237,11 +240,13 @@ __global__ __launch_bounds__(NT) void oms2_kernel(DevCode c, Oms2Args a) {
   }
 }
 
-template <int NT, int DMAX>
+template <int NT, int DMAX, int ZC>
 hipError_t launch_t(const DevCode& c, const Oms2Args& a, size_t lds, hipStream_t s) {
-  hipError_t e = ensure_dyn_lds((const void*)oms2_kernel<NT, DMAX>, lds);
+  const void* k = (const void*)oms2_kernel<NT, DMAX, ZC>;
+  hipError_t e = require_lds_at_zero(k);
+  if (e == hipSuccess) e = ensure_dyn_lds(k, lds);
   if (e != hipSuccess) return e;
-  oms2_kernel<NT, DMAX><<<(unsigned)((a.B + 1) / 2), NT, lds, s>>>(c, a);
+  oms2_kernel<NT, DMAX, ZC><<<(unsigned)((a.B + 1) / 2), NT, lds, s>>>(c, a);
   return hipGetLastError();
 }
 
@@ -260,8 +265,10 @@ hipError_t launch_oms2(const DevCode& c, const lsim_decode_params& p, const int8
   Oms2Args a{llr, B, bits, lpost, q_in, r_out, q_out, p.iters, (int)p.offset, p.sat};
   const int nt = p.threads ? p.threads : 512;
   const int dmax = c.max_row_deg > c.max_col_deg ? c.max_row_deg : c.max_col_deg;
+  if (c.Z == 128 && nt == 512 && dmax <= 16) return launch_t<512, 16, 128>(c, a, lds, s);
+  if (c.Z == 128 && nt == 512 && dmax <= 24) return launch_t<512, 24, 128>(c, a, lds, s);
 #define LSIM_OMS2_CASE(NT_, D_) \
-  if (nt == NT_ && dmax <= D_) return launch_t<NT_, D_>(c, a, lds, s);
+  if (nt == NT_ && dmax <= D_) return launch_t<NT_, D_, 0>(c, a, lds, s);
   LSIM_OMS2_CASE(256, 16)
   LSIM_OMS2_CASE(256, 24)
   LSIM_OMS2_CASE(256, 32)

@@ -61,6 +61,11 @@ void set_error(const std::string& msg);
 // and size; thread-safe).
 hipError_t ensure_dyn_lds(const void* kernel, size_t bytes);
 
+// Kernels that address their dynamic LDS by byte offset from 0 (lds.h) are
+// valid only without static LDS, which would come first; checked once per
+// kernel from its attributes.
+hipError_t require_lds_at_zero(const void* kernel);
+
 // Flooding decoders (k_flood.hip)
 hipError_t launch_flood(const DevCode& c, const lsim_decode_params& p, const void* llr, int64_t B,
                         uint8_t* bits, float* lpost, const void* q_in, void* r_out, void* q_out,
