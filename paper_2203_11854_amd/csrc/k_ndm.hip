@@ -1,14 +1,25 @@
 // Neural demapper (3 -> 64 -> 64 -> 4 MLP per symbol, ReLU), its parameter
 // gradient, the binary cross-entropy on logits and an Adam step.
 //
-// Forward: one thread per symbol; the parameters are read with
-// wave-uniform addresses (scalar loads), h1 stays in registers and the
-// second layer is consumed row by row straight into the 4 outputs.
-// Backward: one wavefront handles 64 symbols at a time; each lane recomputes
-// its symbol's activations, forms the deltas, and the wavefront reduces the
-// outer products through LDS tiles in two phases with every lane owning one
-// row of W2 (and of W1, b1, b2, one column of W3).  Per-workgroup partial gradients are then
-// summed over workgroups in a fixed order, so the result is deterministic.
+// Both passes run the layers as 16x16x4 FP32 matrix-core products
+// (v_mfma_f32_16x16x4f32) over tiles of 16 symbols.  Lane l = 16 g + c
+// supplies A[c][g] and B[g][c] and receives D[4 g + v][c], v = 0..3.
+// Activations are kept in that output layout with hidden units on the rows
+// (unit 16 m + 4 g + v of row tile m) and symbols on the columns, and a
+// product over hidden units takes its K-steps as (tile, v): step (u, v)
+// covers units 16 u + 4 g + v, so the previous layer's output register v is
+// the next product's B operand as is and only the weight operand is
+// gathered in that order.  The input layer is one K = 4 product of
+// [W1 | b1] with [Re y, Im y, ln N0, 1].
+//
+// Backward (per wavefront, 32 symbols per step): H1, A2 = W2 H1 + b2,
+// D2 = (W3^T D3) * [A2 > 0], D1 = (W2^T D2) * [H1 > 0] as above; the
+// weight gradient dW2 = D2 H1^T contracts over symbols, so D2 and H1 go
+// through an LDS transpose (per-wave tiles) and come back with symbols on
+// the K axis.  db2, db1, dW1, dW3, db3 are summed per lane over its symbols
+// and across the 16 lanes of a row group at the end.  Every wavefront writes
+// one partial-gradient row; rows are then summed in a fixed order, so the
+// result is deterministic.
 #include <hip/hip_runtime.h>
 
 #include "lsim_internal.h"
@@ -20,139 +31,295 @@ namespace {
 constexpr int H = 64;
 constexpr int OW1 = 0, OB1 = 192, OW2 = 256, OB2 = 4352, OW3 = 4416, OB3 = 4672, NP = 4676;
 
-__global__ __launch_bounds__(256) void ndm_forward_kernel(const float* __restrict__ P,
-                                                          const float* __restrict__ y,
-                                                          const float* __restrict__ no,
-                                                          int64_t B, int64_t S,
-                                                          float* __restrict__ llr) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= B * S) return;
-  const int64_t b = t / S;
-  const float x0 = y[2 * t], x1 = y[2 * t + 1], x2 = logf(no[b]);
-  float h1[H];
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 mfma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 relu4(f4 x) {
+  f4 r;
 #pragma unroll
-  for (int i = 0; i < H; ++i) {
-    const float a = P[OW1 + 3 * i] * x0 + P[OW1 + 3 * i + 1] * x1 + P[OW1 + 3 * i + 2] * x2 +
-                    P[OB1 + i];
-    h1[i] = fmaxf(a, 0.f);
-  }
-  float o0 = P[OB3], o1 = P[OB3 + 1], o2 = P[OB3 + 2], o3 = P[OB3 + 3];
-  for (int o = 0; o < H; ++o) {
-    float a = P[OB2 + o];
-#pragma unroll
-    for (int i = 0; i < H; ++i) a += P[OW2 + o * H + i] * h1[i];
-    const float h = fmaxf(a, 0.f);
-    o0 += P[OW3 + o] * h;
-    o1 += P[OW3 + H + o] * h;
-    o2 += P[OW3 + 2 * H + o] * h;
-    o3 += P[OW3 + 3 * H + o] * h;
-  }
-  float4 out = make_float4(o0, o1, o2, o3);
-  reinterpret_cast<float4*>(llr)[t] = out;
+  for (int v = 0; v < 4; ++v) r[v] = fmaxf(x[v], 0.f);
+  return r;
 }
 
-constexpr int PAD = H + 1;
+constexpr int kNdmFwdThreads = 256;
 
-// LDS per wavefront: three 64 x 65 float tiles (50 KB), so three
-// wavefronts fit on a CU.  delta1 = W2^T delta2 is accumulated while the
-// rows of delta2 are produced, so delta2 and h2 never sit in registers.
-// Phase 1 reduces dW2 = D2^T H1, db2, dW3 = D3^T H2, db3; phase 2 reuses
-// the H1 tile for dW1 = D1^T X and db1.
-__global__ __launch_bounds__(64) void ndm_backward_kernel(const float* __restrict__ P,
-                                                          const float* __restrict__ y,
-                                                          const float* __restrict__ no,
-                                                          const float* __restrict__ gllr,
-                                                          int64_t B, int64_t S,
-                                                          float* __restrict__ part) {
-  __shared__ float sA[64 * PAD], sB[64 * PAD], sC[64 * PAD];
-  __shared__ float sX[64 * 3], sD3[64 * 4];
-  const int lane = threadIdx.x;
-  const int64_t n = B * S;
-  const int64_t nchunk = (n + 63) / 64;
-  // accumulators owned by this lane (row/col `lane`)
-  float gW2[H];
+// Forward: each wavefront takes 16-symbol tiles; the layer-2 weights are
+// held in registers in the gathered order (64 values per lane).
+__global__ __launch_bounds__(kNdmFwdThreads) void ndm_forward_kernel(
+    const float* __restrict__ P, const float* __restrict__ y, const float* __restrict__ no,
+    int64_t B, int64_t S, float* __restrict__ llr) {
+  const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+  const int64_t n = B * S, ntile = (n + 15) / 16;
+  const int64_t w0 = (int64_t)blockIdx.x * (kNdmFwdThreads / 64) + (threadIdx.x >> 6);
+  const int64_t nw = (int64_t)gridDim.x * (kNdmFwdThreads / 64);
+  float w1a[4], w2a[4][4][4], w3a[4][4];
+  f4 b2i[4];
 #pragma unroll
-  for (int i = 0; i < H; ++i) gW2[i] = 0.f;
-  float gW1[3] = {0.f, 0.f, 0.f}, gb1 = 0.f, gb2 = 0.f, gW3[4] = {0.f, 0.f, 0.f, 0.f}, gb3 = 0.f;
+  for (int u = 0; u < 4; ++u) w1a[u] = g < 3 ? P[OW1 + 3 * (16 * u + c) + g] : P[OB1 + 16 * u + c];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) w2a[m][u][v] = P[OW2 + (16 * m + c) * H + 16 * u + 4 * g + v];
+  // output layer as a 16-row tile whose rows 0..3 are the four LLRs
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) w3a[m][v] = c < 4 ? P[OW3 + c * H + 16 * m + 4 * g + v] : 0.f;
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) b2i[m][v] = P[OB2 + 16 * m + 4 * g + v];
+  f4 b3i = {0.f, 0.f, 0.f, 0.f};
+  if (g == 0) b3i = f4{P[OB3], P[OB3 + 1], P[OB3 + 2], P[OB3 + 3]};
+  const f4 zero = {0.f, 0.f, 0.f, 0.f};
 
-  for (int64_t ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
-    const int64_t t = ch * 64 + lane;
-    const bool on = t < n;
-    float x0 = 0.f, x1 = 0.f, x2 = 0.f, d3[4] = {0.f, 0.f, 0.f, 0.f};
-    if (on) {
-      const int64_t b = t / S;
-      x0 = y[2 * t];
-      x1 = y[2 * t + 1];
-      x2 = logf(no[b]);
+  for (int64_t tile = w0; tile < ntile; tile += nw) {
+    const int64_t sym = tile * 16 + c;
+    const bool on = sym < n;
+    float xb = 1.f;
+    if (on) xb = g == 0 ? y[2 * sym] : g == 1 ? y[2 * sym + 1] : g == 2 ? logf(no[sym / S]) : 1.f;
+    f4 h1[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) d3[j] = gllr[4 * t + j];
+    for (int u = 0; u < 4; ++u) h1[u] = relu4(mfma(w1a[u], xb, zero));
+    f4 a2[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) a2[m] = b2i[m];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) a2[m] = mfma(w2a[m][u][v], h1[u][v], a2[m]);
+    f4 o = b3i;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const f4 h2 = relu4(a2[m]);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o = mfma(w3a[m][v], h2[v], o);
     }
-    float h1[H];
-#pragma unroll
-    for (int i = 0; i < H; ++i) {
-      const float a = P[OW1 + 3 * i] * x0 + P[OW1 + 3 * i + 1] * x1 + P[OW1 + 3 * i + 2] * x2 +
-                      P[OB1 + i];
-      h1[i] = on ? fmaxf(a, 0.f) : 0.f;
-      sA[lane * PAD + i] = h1[i];
-    }
-    // layer 2 forward, delta2 row by row, delta1 accumulated on the way
-    float d1[H];
-#pragma unroll
-    for (int i = 0; i < H; ++i) d1[i] = 0.f;
-    for (int o = 0; o < H; ++o) {
-      float a = P[OB2 + o];
-#pragma unroll
-      for (int i = 0; i < H; ++i) a += P[OW2 + o * H + i] * h1[i];
-      const float g = P[OW3 + o] * d3[0] + P[OW3 + H + o] * d3[1] + P[OW3 + 2 * H + o] * d3[2] +
-                      P[OW3 + 3 * H + o] * d3[3];
-      const float d2 = (on && a > 0.f) ? g : 0.f;
-      sC[lane * PAD + o] = on ? fmaxf(a, 0.f) : 0.f;
-      sB[lane * PAD + o] = d2;
-#pragma unroll
-      for (int i = 0; i < H; ++i) d1[i] += P[OW2 + o * H + i] * d2;
-    }
-    sX[lane * 3 + 0] = on ? x0 : 0.f;
-    sX[lane * 3 + 1] = on ? x1 : 0.f;
-    sX[lane * 3 + 2] = on ? x2 : 0.f;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) sD3[lane * 4 + j] = on ? d3[j] : 0.f;
-    __syncthreads();
-    // phase 1: row `lane` of dW2 and db2, column `lane` of dW3, db3
-    for (int s = 0; s < 64; ++s) {
-      const float d2 = sB[s * PAD + lane];
-#pragma unroll
-      for (int i = 0; i < H; ++i) gW2[i] += d2 * sA[s * PAD + i];
-      gb2 += d2;
-      const float hh = sC[s * PAD + lane];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) gW3[j] += sD3[s * 4 + j] * hh;
-      if (lane < 4) gb3 += sD3[s * 4 + lane];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < H; ++i) sA[lane * PAD + i] = h1[i] > 0.f ? d1[i] : 0.f;
-    __syncthreads();
-    // phase 2: row `lane` of dW1 and db1
-    for (int s = 0; s < 64; ++s) {
-      const float d1l = sA[s * PAD + lane];
-      gW1[0] += d1l * sX[s * 3 + 0];
-      gW1[1] += d1l * sX[s * 3 + 1];
-      gW1[2] += d1l * sX[s * 3 + 2];
-      gb1 += d1l;
-    }
-    __syncthreads();
+    // rows 0..3 (lanes 0..15) hold the four LLRs of symbol 16 tile + c
+    if (g == 0 && on) reinterpret_cast<float4*>(llr)[sym] = make_float4(o[0], o[1], o[2], o[3]);
   }
-  float* out = part + (int64_t)blockIdx.x * NP;
+}
+
+constexpr int kBwdWaves = 4;             // wavefronts per workgroup
+constexpr int kBwdThreads = 64 * kBwdWaves;
+constexpr int kTS = 32;                  // symbols per wavefront step
+constexpr int kPW = H + 4;               // LDS pitch of W2 and W2^T
+constexpr int kPS = kTS + 4;             // LDS pitch of the per-wave transposes
+
+__host__ __device__ constexpr size_t ndm_bwd_lds() {
+  return (size_t)(2 * H * kPW + kBwdWaves * 2 * H * kPS) * 4;
+}
+
+__global__ __launch_bounds__(kBwdThreads) void ndm_backward_kernel(
+    const float* __restrict__ P, const float* __restrict__ y, const float* __restrict__ no,
+    const float* __restrict__ gllr, int64_t B, int64_t S, float* __restrict__ part) {
+  extern __shared__ __align__(16) float sm[];
+  float* w2s = sm;               // W2[out][in], pitch kPW
+  float* w2t = sm + H * kPW;     // W2^T[in][out]
+  const int wave = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+  float* h1u = sm + 2 * H * kPW + wave * 2 * H * kPS;  // H1[in][symbol]
+  float* d2u = h1u + H * kPS;                          // D2[out][symbol]
+  for (int t = threadIdx.x; t < H * H; t += kBwdThreads) {
+    const int o = t >> 6, i = t & 63;
+    const float w = P[OW2 + t];
+    w2s[o * kPW + i] = w;
+    w2t[i * kPW + o] = w;
+  }
+  __syncthreads();
+
+  float w1a[4], w3a[4];
+  f4 b2i[4];
 #pragma unroll
-  for (int i = 0; i < H; ++i) out[OW2 + lane * H + i] = gW2[i];
-  out[OW1 + 3 * lane + 0] = gW1[0];
-  out[OW1 + 3 * lane + 1] = gW1[1];
-  out[OW1 + 3 * lane + 2] = gW1[2];
-  out[OB1 + lane] = gb1;
-  out[OB2 + lane] = gb2;
+  for (int u = 0; u < 4; ++u) w1a[u] = g < 3 ? P[OW1 + 3 * (16 * u + c) + g] : P[OB1 + 16 * u + c];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) out[OW3 + j * H + lane] = gW3[j];
-  if (lane < 4) out[OB3 + lane] = gb3;
+  for (int m = 0; m < 4; ++m) w3a[m] = P[OW3 + g * H + 16 * m + c];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) b2i[m][v] = P[OB2 + 16 * m + 4 * g + v];
+  const f4 zero = {0.f, 0.f, 0.f, 0.f};
+
+  f4 gw2[4][4];                   // tile (m, u): dW2[16m + 4g + v][16u + c]
+  f4 pb2[4], pb1[4], pw1[4][3], pw3[4][4];
+  float pb3[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    pb2[m] = zero;
+    pb1[m] = zero;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) gw2[m][u] = zero;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) pw1[m][k] = zero;
+#pragma unroll
+    for (int o = 0; o < 4; ++o) pw3[o][m] = zero;
+  }
+
+  const int64_t n = B * S, nstep = (n + kTS - 1) / kTS;
+  const int64_t gwv = (int64_t)blockIdx.x * kBwdWaves + wave;
+  const int64_t nwv = (int64_t)gridDim.x * kBwdWaves;
+  for (int64_t st = gwv; st < nstep; st += nwv) {
+    float xk[2][3], d3[2][4], xb[2], d3b[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int64_t sym = st * kTS + 16 * t + c;
+      const bool on = sym < n;
+      xk[t][0] = on ? y[2 * sym] : 0.f;
+      xk[t][1] = on ? y[2 * sym + 1] : 0.f;
+      xk[t][2] = on ? logf(no[sym / S]) : 0.f;
+      // a padded symbol has zero output gradient, so it adds nothing
+#pragma unroll
+      for (int o = 0; o < 4; ++o) d3[t][o] = on ? gllr[4 * sym + o] : 0.f;
+      xb[t] = g == 0 ? xk[t][0] : g == 1 ? xk[t][1] : g == 2 ? xk[t][2] : 1.f;
+      d3b[t] = g == 0 ? d3[t][0] : g == 1 ? d3[t][1] : g == 2 ? d3[t][2] : d3[t][3];
+    }
+    f4 h1[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) h1[u][t] = relu4(mfma(w1a[u], xb[t], zero));
+    f4 a2[4][2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) a2[m][0] = a2[m][1] = b2i[m];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const f4 w = *reinterpret_cast<const f4*>(w2s + (16 * m + c) * kPW + 16 * u + 4 * g);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int t = 0; t < 2; ++t) a2[m][t] = mfma(w[v], h1[u][t][v], a2[m][t]);
+      }
+    f4 d2[4][2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        d2[m][t] = mfma(w3a[m], d3b[t], zero);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float a = a2[m][t][v];
+          d2[m][t][v] = a > 0.f ? d2[m][t][v] : 0.f;
+          pb2[m][v] += d2[m][t][v];
+          const float h2 = fmaxf(a, 0.f);
+#pragma unroll
+          for (int o = 0; o < 4; ++o) pw3[o][m][v] += d3[t][o] * h2;
+        }
+      }
+    if (g == 0) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int o = 0; o < 4; ++o) pb3[o] += d3[t][o];
+    }
+    f4 d1[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) d1[u][0] = d1[u][1] = zero;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const f4 w = *reinterpret_cast<const f4*>(w2t + (16 * u + c) * kPW + 16 * m + 4 * g);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int t = 0; t < 2; ++t) d1[u][t] = mfma(w[v], d2[m][t][v], d1[u][t]);
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float d = h1[u][t][v] > 0.f ? d1[u][t][v] : 0.f;
+          pb1[u][v] += d;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) pw1[u][k][v] += d * xk[t][k];
+        }
+    // transpose H1 and D2 through this wavefront's LDS tiles
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          h1u[(16 * u + 4 * g + v) * kPS + 16 * t + c] = h1[u][t][v];
+          d2u[(16 * u + 4 * g + v) * kPS + 16 * t + c] = d2[u][t][v];
+        }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+    // dW2 += D2 H1^T over the step's 32 symbols: K-step k covers symbols
+    // 8 g + k of lane group g
+    f4 hb[4][2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      hb[u][0] = *reinterpret_cast<const f4*>(h1u + (16 * u + c) * kPS + 8 * g);
+      hb[u][1] = *reinterpret_cast<const f4*>(h1u + (16 * u + c) * kPS + 8 * g + 4);
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const f4 da0 = *reinterpret_cast<const f4*>(d2u + (16 * m + c) * kPS + 8 * g);
+      const f4 da1 = *reinterpret_cast<const f4*>(d2u + (16 * m + c) * kPS + 8 * g + 4);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) gw2[m][u] = mfma(da0[k], hb[u][0][k], gw2[m][u]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) gw2[m][u] = mfma(da1[k], hb[u][1][k], gw2[m][u]);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+  }
+
+  // per-lane sums -> sums over the 16 lanes of each row group (fixed order)
+  auto red16 = [](float x) {
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) x += __shfl_xor(x, off, 16);
+    return x;
+  };
+  float* out = part + gwv * NP;
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[OW2 + (16 * m + 4 * g + v) * H + 16 * u + c] = gw2[m][u][v];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int unit = 16 * m + 4 * g + v;
+      const float sb2 = red16(pb2[m][v]), sb1 = red16(pb1[m][v]);
+      const float s0 = red16(pw1[m][0][v]), s1 = red16(pw1[m][1][v]), s2 = red16(pw1[m][2][v]);
+      float s3[4];
+#pragma unroll
+      for (int o = 0; o < 4; ++o) s3[o] = red16(pw3[o][m][v]);
+      if (c == 0) {
+        out[OB2 + unit] = sb2;
+        out[OB1 + unit] = sb1;
+        out[OW1 + 3 * unit + 0] = s0;
+        out[OW1 + 3 * unit + 1] = s1;
+        out[OW1 + 3 * unit + 2] = s2;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) out[OW3 + o * H + unit] = s3[o];
+      }
+    }
+#pragma unroll
+  for (int o = 0; o < 4; ++o) {
+    const float sb3 = red16(pb3[o]);
+    if (l == 0) out[OB3 + o] = sb3;
+  }
 }
 
 // out[i] = sum over rows of part[r][i] in a fixed order: pass 1 sums
@@ -226,21 +393,25 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// workgroups of the backward pass: one per CU worth of steps at most
 inline int ndm_bwd_blocks(int64_t n) {
-  const int64_t nchunk = (n + 63) / 64;
-  return (int)(nchunk < 2048 ? nchunk : 2048);
+  const int64_t nstep = (n + kTS - 1) / kTS;
+  const int64_t want = (nstep + kBwdWaves - 1) / kBwdWaves;
+  return (int)(want < 256 ? want : 256);
 }
 
 }  // namespace
 
 size_t ndm_work_bytes(int64_t B, int64_t S) {
-  return ((size_t)ndm_bwd_blocks(B * S) + kSlices) * NP * 4;
+  return ((size_t)ndm_bwd_blocks(B * S) * kBwdWaves + kSlices) * NP * 4;
 }
 
 hipError_t launch_ndm_forward(const float* params, const float* y, const float* no, int64_t B,
                               int64_t S, float* llr, hipStream_t s) {
-  const int64_t n = B * S;
-  ndm_forward_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(params, y, no, B, S, llr);
+  const int64_t ntile = (B * S + 15) / 16;
+  const int64_t waves = ntile < 8192 ? ntile : 8192;
+  const unsigned grid = (unsigned)((waves + kNdmFwdThreads / 64 - 1) / (kNdmFwdThreads / 64));
+  ndm_forward_kernel<<<grid, kNdmFwdThreads, 0, s>>>(params, y, no, B, S, llr);
   return hipGetLastError();
 }
 
@@ -248,13 +419,16 @@ hipError_t launch_ndm_backward(const float* params, const float* y, const float*
                                const float* gllr, int64_t B, int64_t S, float* gparams,
                                void* work, hipStream_t s) {
   const int nb = ndm_bwd_blocks(B * S);
+  const int rows = nb * kBwdWaves;
   float* part = reinterpret_cast<float*>(work);
-  ndm_backward_kernel<<<nb, 64, 0, s>>>(params, y, no, gllr, B, S, part);
-  hipError_t e = hipGetLastError();
+  hipError_t e = ensure_dyn_lds((const void*)ndm_backward_kernel, ndm_bwd_lds());
   if (e != hipSuccess) return e;
-  float* slices = part + (size_t)nb * NP;
+  ndm_backward_kernel<<<nb, kBwdThreads, ndm_bwd_lds(), s>>>(params, y, no, gllr, B, S, part);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  float* slices = part + (size_t)rows * NP;
   dim3 grid((NP + 255) / 256, kSlices);
-  sum_slices_kernel<<<grid, 256, 0, s>>>(part, nb, NP, slices);
+  sum_slices_kernel<<<grid, 256, 0, s>>>(part, rows, NP, slices);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   sum_final_kernel<<<(NP + 255) / 256, 256, 0, s>>>(slices, NP, gparams);

@@ -181,6 +181,56 @@ def test_ndm_forward_backward_vs_oracle():
                             gl.astype(np.float64))
     rel = np.linalg.norm(gp - gref) / np.linalg.norm(gref)
     assert rel <= 1e-5, rel
+    _check_groups(gp, gref, 1e-5)
+
+
+def _check_groups(gp, gref, tol):
+    """Relative error per parameter group (W1, b1, W2, b2, W3, b3)."""
+    o, errs = 0, []
+    for shape in ondm.SIZES:
+        n = int(np.prod(shape))
+        a, b = gp[o:o + n], gref[o:o + n]
+        errs.append((shape, float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))))
+        o += n
+    print("relative error per group", errs)
+    for shape, rel in errs:
+        assert rel <= tol, (shape, rel, errs)
+
+
+def test_ndm_full_size():
+    """The training step's demapper shape (2048 codewords x 960 16-QAM
+    symbols, the launch bench.py times): sampled forward outputs and the
+    full parameter gradient, per group, against the oracle."""
+    params = glorot(21).astype(np.float32)
+    B, S = 2048, 960
+    y = (rand.gaussian(22, (B, S)) + 1j * rand.gaussian(23, (B, S))).astype(np.complex64)
+    n0 = rand.uniform(24, B, 0.05, 1.0).astype(np.float32)
+    yy = np.stack([y.real, y.imag], -1).astype(np.float32)
+    tp, ty, tn = T(params).to(dev), T(yy).to(dev), T(n0).to(dev)
+    out = lsim.ndm_forward(tp, ty, tn).cpu().numpy()
+    rows = np.array([0, 1, 777, 1500, 2047])
+    ref = ondm.forward_numpy(params.astype(np.float64), y[rows].astype(np.complex128),
+                             n0[rows].astype(np.float64))
+    assert np.abs(out[rows] - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+    gl = (rand.gaussian(25, (B, S * 4)) * 1e-3).astype(np.float32)
+    # A ReLU has no derivative at its kink, and a pre-activation within
+    # rounding of zero may fall on either side in float32 and float64 (one
+    # such symbol moves a bias gradient by ~1e-4 here).  Symbols with a
+    # hidden pre-activation within 1e-6 of zero get no output gradient, so
+    # both sides agree on every mask that matters.
+    W1, b1, W2, b2 = [a.astype(np.float64) for a in ondm.unpack(params)[:4]]
+    x = np.stack([y.real, y.imag, np.broadcast_to(np.log(n0.astype(np.float64))[:, None], y.shape)],
+                 -1).reshape(-1, 3).astype(np.float64)
+    a1 = x @ W1.T + b1
+    a2 = np.maximum(a1, 0) @ W2.T + b2
+    near = ((np.abs(a1) < 1e-6).any(1) | (np.abs(a2) < 1e-6).any(1)).reshape(B, S)
+    del x, a1, a2
+    gl.reshape(B, S, 4)[near] = 0.0
+    gp = lsim.ndm_backward(tp, ty, tn, T(gl).to(dev)).cpu().numpy()
+    gref = ondm.grad_params(params.astype(np.float64), y.astype(np.complex128),
+                            n0.astype(np.float64), gl.astype(np.float64))
+    print("symbols next to a kink:", int(near.sum()))
+    _check_groups(gp, gref, 1e-5)
 
 
 def test_bce_and_adam():
