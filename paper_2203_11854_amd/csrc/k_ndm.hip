@@ -372,12 +372,20 @@ __global__ __launch_bounds__(256) void bce_kernel(const float* __restrict__ L,
   if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-__global__ void bce_final_kernel(const float* __restrict__ part, int n, float scale,
-                                 float* __restrict__ loss) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  float acc = 0.f;
-  for (int i = 0; i < n; ++i) acc += part[i];
-  *loss = scale * acc;
+// Loss total: a fixed-shape tree over the per-workgroup partials.
+__global__ __launch_bounds__(1024) void bce_final_kernel(const float* __restrict__ part, int n,
+                                                         float scale, float* __restrict__ loss) {
+  __shared__ float red[1024];
+  const int tid = threadIdx.x;
+  float a = 0.f;
+  for (int i = tid; i < n; i += 1024) a += part[i];
+  red[tid] = a;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) *loss = scale * red[0];
 }
 
 __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
@@ -444,7 +452,7 @@ hipError_t launch_bce_grad(const float* lpost, const uint8_t* c, int64_t c_strid
   bce_kernel<<<kBceBlocks, 256, 0, s>>>(lpost, c, c_stride, B, n, scale, g, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !loss) return e;
-  bce_final_kernel<<<1, 64, 0, s>>>(part, kBceBlocks, scale, loss);
+  bce_final_kernel<<<1, 1024, 0, s>>>(part, kBceBlocks, scale, loss);
   return hipGetLastError();
 }
 

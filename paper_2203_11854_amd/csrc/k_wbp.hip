@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dispatch.h"
+#include "lds.h"
 #include "lsim_internal.h"
 #include "spa_math.h"
 
@@ -96,7 +97,12 @@ __device__ __forceinline__ void cn_forward(const float* in, float* out, int Z, f
   }
 }
 
-template <int NT>
+// Forward.  Same schedule and arithmetic as the flooding sum-product
+// decoder (sum / difference check update, messages in log2 units inside
+// the kernel, LDS addressed by byte offset from 0); the weights multiply
+// the check outputs and the checkpoints are stored in natural units.  ZC:
+// compile-time lift size or 0.
+template <int NT, int ZC>
 __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
                                                          const float* __restrict__ w,
                                                          const float* __restrict__ llr,
@@ -105,27 +111,51 @@ __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
   constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   float* msg = reinterpret_cast<float*>(smem);
-  float* lam = reinterpret_cast<float*>(smem + align16((size_t)c.E * 4));
+  const int lam_b = (int)align16((size_t)c.E * 4);
   const int tid = threadIdx.x, lane = tid & 63, wave = uni(tid >> 6);
-  const int Z = c.Z;
-  const bool zpow2 = (Z & (Z - 1)) == 0;
+  const int Z = ZC ? ZC : c.Z;
+  const int zm = Z - 1;
+  const bool zpow2 = (Z & zm) == 0;
+  const float lmax2 = lmax * kLog2e;
   const int64_t b = blockIdx.x;
   const float* llr_b = llr + b * (int64_t)c.e_tx;
-  for (int v = tid; v < c.n_dec; v += NT) lam[v] = chan_lam(c, llr_b, v, lmax);
+  for (int v = tid; v < c.n_dec; v += NT) lds_st<float>(lam_b + 4 * v, chan_lam(c, llr_b, v, lmax) * kLog2e);
   __syncthreads();
+
+  // byte offsets of the DC edges of variable node (j, cc)
+  auto col_b = [&](auto deg, int cb, int cc, int* off) {
+    constexpr int DC = decltype(deg)::value;
+    if (zpow2) {
+      const int cc_b = vreg(cc * 4), zm_b = vreg(zm * 4);
+#pragma unroll
+      for (int q = 0; q < DC; ++q) {
+        const int2 ce = ld_const(c.col_edge, cb + q);
+        off[q] = ((cc_b - ce.y * 4) & zm_b) | (ce.x * 4);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < DC; ++q) {
+        const int2 ce = ld_const(c.col_edge, cb + q);
+        int x = cc - ce.y;
+        x += x < 0 ? Z : 0;
+        off[q] = (ce.x + x) * 4;
+      }
+    }
+  };
+
   // q^(1) = lam on every edge
   for (int ti = wave; ti < c.n_vn_tasks; ti += NW) {
     const int task = uni(ld_const(c.vn_tasks, ti));
     const int j = task >> 16, cc = (task & 0xffff) + lane;
     const int cb = uni(ld_const(c.col_ptr, j)), dc = uni(ld_const(c.col_ptr, j + 1)) - cb;
     if (cc < Z) {
-      const float l = lam[j * Z + cc];
+      const float l = lds_ld<float>(lam_b + 4 * (j * Z + cc));
       with_degree<kDMAX>(dc, [&](auto deg) {
         constexpr int DC = decltype(deg)::value;
         int off[DC];
-        col_offsets<DC>(c, cb, cc, zpow2, off);
+        col_b(deg, cb, cc, off);
 #pragma unroll
-        for (int q = 0; q < DC; ++q) at(msg, off[q]) = l;
+        for (int q = 0; q < DC; ++q) lds_st<float>(off[q], l);
       });
     }
   }
@@ -136,9 +166,16 @@ __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
       float* ck = ckpt + ((int64_t)it * B + b) * c.E;
       if ((c.E & 3) == 0) {
         const float4* m4 = reinterpret_cast<const float4*>(msg);
-        for (int e = tid; e < c.E / 4; e += NT) reinterpret_cast<float4*>(ck)[e] = m4[e];
+        for (int e = tid; e < c.E / 4; e += NT) {
+          float4 x = m4[e];
+          x.x *= kLn2;
+          x.y *= kLn2;
+          x.z *= kLn2;
+          x.w *= kLn2;
+          reinterpret_cast<float4*>(ck)[e] = x;
+        }
       } else {
-        for (int e = tid; e < c.E; e += NT) ck[e] = msg[e];
+        for (int e = tid; e < c.E; e += NT) ck[e] = msg[e] * kLn2;
       }
       lds_barrier();  // every wavefront has read q before the checks overwrite it
     }
@@ -147,14 +184,50 @@ __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
       const int i = task >> 16, r = (task & 0xffff) + lane;
       const int e0 = uni(ld_const(c.row_ptr, i)), d = uni(ld_const(c.row_ptr, i + 1)) - e0;
       if (r < Z) {
-        float* row = msg + (size_t)e0 * Z + r;
+        const int row_b = (e0 * Z + r) * 4;
         with_degree<kDMAX>(d, [&](auto deg) {
-          cn_forward<decltype(deg)::value>(row, row, Z, lmax);
+          constexpr int D = decltype(deg)::value;
+          if constexpr (D >= 2) {  // decoded checks have degree >= 2
+            float x[D], ee[D], pS[D], pA[D];
+#pragma unroll
+            for (int q = 0; q < D; ++q) x[q] = lds_ld<float>(row_b + q * Z * 4);
+            uint32_t sx = 0;
+#pragma unroll
+            for (int q = 0; q < D; ++q) sx ^= __float_as_uint(x[q]);
+#pragma unroll
+            for (int q = 0; q < D; ++q) ee[q] = spa_e2(x[q]);
+            SpaSA pre{1.f, ee[0]};
+#pragma unroll
+            for (int q = 1; q < D; ++q) {
+              pS[q] = pre.S;
+              pA[q] = pre.A;
+              if (q + 1 < D) pre.add(ee[q]);
+            }
+            SpaSA suf{1.f, ee[D - 1]};
+#pragma unroll
+            for (int q = D - 1; q >= 0; --q) {
+              float num, den;
+              if (q == D - 1) {
+                num = pS[q];
+                den = pA[q];
+              } else if (q == 0) {
+                num = suf.S;
+                den = suf.A;
+              } else {
+                num = fmaf(pS[q], suf.S, pA[q] * suf.A);
+                den = fmaf(pS[q], suf.A, pA[q] * suf.S);
+              }
+              const float rv = spa_log2_ratio(num, den, lmax2);
+              const uint32_t sg = (sx ^ __float_as_uint(x[q])) & 0x80000000u;
+              lds_st<float>(row_b + q * Z * 4, __uint_as_float(__float_as_uint(rv) | sg));
+              if (q < D - 1 && q > 0) suf.add(ee[q]);
+            }
+          }
         });
       }
     }
     lds_barrier();
-    const float* wt = w + (int64_t)it * c.E;
+    const unsigned char* wt = reinterpret_cast<const unsigned char*>(w + (int64_t)it * c.E);
     for (int ti = wave; ti < c.n_vn_tasks; ti += NW) {
       const int task = uni(ld_const(c.vn_tasks, ti));
       const int j = task >> 16, cc = (task & 0xffff) + lane;
@@ -164,13 +237,13 @@ __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
         with_degree<kDMAX>(dc, [&](auto deg) {
           constexpr int DC = decltype(deg)::value;
           int off[DC];
-          col_offsets<DC>(c, cb, cc, zpow2, off);
+          col_b(deg, cb, cc, off);
           float s[DC], wv[DC];
 #pragma unroll
-          for (int q = 0; q < DC; ++q) wv[q] = at(const_cast<float*>(wt), off[q]);
+          for (int q = 0; q < DC; ++q) wv[q] = *reinterpret_cast<const float*>(wt + off[q]);
 #pragma unroll
-          for (int q = 0; q < DC; ++q) s[q] = at(msg, off[q]);
-          float acc = lam[v];
+          for (int q = 0; q < DC; ++q) s[q] = lds_ld<float>(off[q]);
+          float acc = lds_ld<float>(lam_b + 4 * v);
 #pragma unroll
           for (int q = 0; q < DC; ++q) {
             s[q] *= wv[q];
@@ -178,9 +251,10 @@ __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
           }
           if (!last) {
 #pragma unroll
-            for (int q = 0; q < DC; ++q) at(msg, off[q]) = __builtin_amdgcn_fmed3f(acc - s[q], -lmax, lmax);
+            for (int q = 0; q < DC; ++q)
+              lds_st<float>(off[q], __builtin_amdgcn_fmed3f(acc - s[q], -lmax2, lmax2));
           } else {
-            lpost[b * (int64_t)c.n_dec + v] = -acc;
+            lpost[b * (int64_t)c.n_dec + v] = -acc * kLn2;
           }
         });
       }
@@ -355,20 +429,43 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
 }
 
 // gw[t][e] = sum over b of part[b][t][e], in a fixed order: pass 1 sums
-// kSlices contiguous batch slices into slice partials (every block reads
-// coalesced rows), pass 2 adds the slices in order.
+// kSlices contiguous batch slices into slice partials, pass 2 adds the
+// slices in order.  When rows are a multiple of four floats every thread
+// reads four adjacent columns with 16-byte loads.
 constexpr int kSlices = 32;
 
-__global__ void sum_slices_kernel(const float* __restrict__ part, int64_t B, int64_t n,
-                                  float* __restrict__ slices) {
+__global__ __launch_bounds__(256) void sum_slices_kernel(const float* __restrict__ part, int64_t B,
+                                                         int64_t n, float* __restrict__ slices) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t per = (B + kSlices - 1) / kSlices;
-  const int64_t b0 = (int64_t)blockIdx.y * per;
-  const int64_t b1 = min(B, b0 + per);
+  const int64_t b0 = blockIdx.y * per;
+  const int64_t b1 = b0 + per < B ? b0 + per : B;
   float acc = 0.f;
+#pragma unroll 8
   for (int64_t b = b0; b < b1; ++b) acc += part[b * n + i];
   slices[(int64_t)blockIdx.y * n + i] = acc;
+}
+
+__global__ __launch_bounds__(256) void sum_slices4_kernel(const float* __restrict__ part, int64_t B,
+                                                         int64_t n, float* __restrict__ slices) {
+  const int64_t i4 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // column quad
+  if (4 * i4 >= n) return;
+  const int64_t per = (B + kSlices - 1) / kSlices;
+  const int64_t b0 = blockIdx.y * per;
+  const int64_t b1 = b0 + per < B ? b0 + per : B;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4* p = reinterpret_cast<const float4*>(part) + i4;
+  const int64_t stride = n / 4;
+#pragma unroll 8
+  for (int64_t b = b0; b < b1; ++b) {
+    const float4 x = p[b * stride];
+    acc.x += x.x;
+    acc.y += x.y;
+    acc.z += x.z;
+    acc.w += x.w;
+  }
+  reinterpret_cast<float4*>(slices)[(int64_t)blockIdx.y * stride + i4] = acc;
 }
 
 __global__ void sum_final_kernel(const float* __restrict__ slices, int64_t n,
@@ -408,11 +505,17 @@ hipError_t launch_wbp_forward(const DevCode& c, int T, const float* w, const flo
     *why = "weighted BP state exceeds the 160 KiB LDS";
     return hipSuccess;
   }
-  {
-    hipError_t e = ensure_dyn_lds((const void*)wbp_forward_kernel<kFwdNT>, lds);
-    if (e != hipSuccess) return e;
-  }
-  wbp_forward_kernel<kFwdNT><<<(unsigned)B, kFwdNT, lds, s>>>(c, T, w, llr, llr_max, ckpt, lpost, B);
+  const void* k = c.Z == 128 ? (const void*)wbp_forward_kernel<kFwdNT, 128>
+                             : (const void*)wbp_forward_kernel<kFwdNT, 0>;
+  hipError_t e = require_lds_at_zero(k);
+  if (e == hipSuccess) e = ensure_dyn_lds(k, lds);
+  if (e != hipSuccess) return e;
+  if (c.Z == 128)
+    wbp_forward_kernel<kFwdNT, 128><<<(unsigned)B, kFwdNT, lds, s>>>(c, T, w, llr, llr_max, ckpt,
+                                                                    lpost, B);
+  else
+    wbp_forward_kernel<kFwdNT, 0><<<(unsigned)B, kFwdNT, lds, s>>>(c, T, w, llr, llr_max, ckpt,
+                                                                  lpost, B);
   return hipGetLastError();
 }
 
@@ -441,8 +544,13 @@ hipError_t launch_wbp_backward(const DevCode& c, int T, const float* w, const fl
   if (e != hipSuccess) return e;
   const int64_t n = (int64_t)T * c.E;
   float* slices = part + (size_t)B * n;
-  dim3 grid((unsigned)((n + 255) / 256), kSlices);
-  sum_slices_kernel<<<grid, 256, 0, s>>>(part, B, n, slices);
+  if ((n & 3) == 0) {
+    dim3 grid((unsigned)((n / 4 + 255) / 256), kSlices);
+    sum_slices4_kernel<<<grid, 256, 0, s>>>(part, B, n, slices);
+  } else {
+    dim3 grid((unsigned)((n + 255) / 256), kSlices);
+    sum_slices_kernel<<<grid, 256, 0, s>>>(part, B, n, slices);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   sum_final_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(slices, n, gw);
