@@ -23,6 +23,8 @@
 // codeword writes its own contribution, a second kernel adds them up.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "dispatch.h"
 #include "lds.h"
 #include "lsim_internal.h"
@@ -42,58 +44,46 @@ __device__ __forceinline__ float chan_lam(const DevCode& c, const float* llr_b, 
   return (x >= 0 && x < c.e_tx) ? fminf(fmaxf(-llr_b[x], -lmax), lmax) : 0.f;
 }
 
-// Byte offsets of the D edges of variable node (column j, lift cc), in the
-// column's entry order: (e*Z + (cc - shift) mod Z) * 4.
+// Clamped check outputs (natural units) of one check of degree D >= 2 from
+// its inputs at byte offsets q*zs from in (device memory), written to LDS at
+// out_b + q*zs:
+// the sum / difference form of spa_math.h.
 template <int D>
-__device__ __forceinline__ void col_offsets(const DevCode& c, int cb, int cc, bool zpow2,
-                                            int* off) {
-  const int Z = c.Z;
-  if (zpow2) {
+__device__ __forceinline__ void cn_forward(const float* in, int zs, int out_b, float lmax2) {
+  float x[D], ee[D], pS[D], pA[D];
 #pragma unroll
-    for (int q = 0; q < D; ++q) {
-      const int2 ce = ld_const(c.col_edge, cb + q);
-      off[q] = ((cc * 4 - ce.y * 4) & ((Z - 1) * 4)) | (ce.x * 4);
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < D; ++q) {
-      const int2 ce = ld_const(c.col_edge, cb + q);
-      int x = cc - ce.y;
-      x += x < 0 ? Z : 0;
-      off[q] = (ce.x + x) * 4;
-    }
-  }
-}
-
-__device__ __forceinline__ float& at(float* base, int off) {
-  return *reinterpret_cast<float*>(reinterpret_cast<unsigned char*>(base) + off);
-}
-
-// Check update of one check of degree D from inputs in[q*Z], clamped outputs
-// to out[q*Z] (spa_math.h).
-template <int D>
-__device__ __forceinline__ void cn_forward(const float* in, float* out, int Z, float lmax) {
-  float x[D];
-#pragma unroll
-  for (int q = 0; q < D; ++q) x[q] = in[q * Z];
+  for (int q = 0; q < D; ++q) x[q] = *reinterpret_cast<const float*>(
+      reinterpret_cast<const unsigned char*>(in) + q * zs);
   uint32_t sx = 0;
 #pragma unroll
   for (int q = 0; q < D; ++q) sx ^= __float_as_uint(x[q]);
-  float mm[D], pD[D], pC[D];
-  SpaAcc pre;
 #pragma unroll
-  for (int q = 0; q < D; ++q) {
-    mm[q] = spa_m(x[q]);
-    pD[q] = pre.D;
-    pC[q] = pre.C;
-    pre.add(mm[q]);
+  for (int q = 0; q < D; ++q) ee[q] = spa_e2(x[q] * kLog2e);
+  SpaSA pre{1.f, ee[0]};
+#pragma unroll
+  for (int q = 1; q < D; ++q) {
+    pS[q] = pre.S;
+    pA[q] = pre.A;
+    if (q + 1 < D) pre.add(ee[q]);
   }
-  SpaAcc suf;
+  SpaSA suf{1.f, ee[D - 1]};
 #pragma unroll
   for (int q = D - 1; q >= 0; --q) {
-    const float rv = fminf(spa_mag(fmaf(suf.D, pC[q], pD[q])), lmax);
-    out[q * Z] = __uint_as_float(__float_as_uint(rv) | ((sx ^ __float_as_uint(x[q])) & 0x80000000u));
-    suf.add(mm[q]);
+    float num, den;
+    if (q == D - 1) {
+      num = pS[q];
+      den = pA[q];
+    } else if (q == 0) {
+      num = suf.S;
+      den = suf.A;
+    } else {
+      num = fmaf(pS[q], suf.S, pA[q] * suf.A);
+      den = fmaf(pS[q], suf.A, pA[q] * suf.S);
+    }
+    const float rv = spa_log2_ratio(num, den, lmax2) * kLn2;
+    lds_st<float>(out_b + q * zs,
+                  __uint_as_float(__float_as_uint(rv) | ((sx ^ __float_as_uint(x[q])) & 0x80000000u)));
+    if (q < D - 1 && q > 0) suf.add(ee[q]);
   }
 }
 
@@ -263,26 +253,49 @@ __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
   }
 }
 
-// LDS: R[E] (recomputed clamped check outputs), QB[E] (adjoints of the
-// variable-to-check messages, then of the check outputs), LB[n_dec].
-template <int NT>
+// LDS (byte offsets from 0; no static LDS): R[E] (recomputed clamped check
+// outputs) at 0, QB[E] (adjoints of the variable-to-check messages, then of
+// the check outputs) at qb_b, LB[n_dec] at lb_b.  ZC: compile-time lift size
+// or 0.  A check output is unclamped, ln((2 - D)/D) <= L, exactly when
+// D >= dth = 2 / (1 + e^L), so the clamp mask needs no logarithm.
+template <int NT, int ZC>
 __global__ __launch_bounds__(NT) void wbp_backward_kernel(
     DevCode c, int T, const float* __restrict__ w, const float* __restrict__ llr,
-    const float* __restrict__ ckpt, float lmax, const float* __restrict__ gpost,
+    const float* __restrict__ ckpt, float lmax, float dth, const float* __restrict__ gpost,
     float* __restrict__ gllr, float* __restrict__ gw_part, int64_t B) {
   constexpr int NW = NT / 64;
-  extern __shared__ __align__(16) unsigned char smem[];
-  float* R = reinterpret_cast<float*>(smem);
-  float* QB = R + c.E;
-  float* LB = reinterpret_cast<float*>(smem + align16((size_t)2 * c.E * 4));
+  const int qb_b = c.E * 4;
+  const int lb_b = (int)align16((size_t)2 * c.E * 4);
   const int tid = threadIdx.x, lane = tid & 63, wave = uni(tid >> 6);
-  const int Z = c.Z;
-  const bool zpow2 = (Z & (Z - 1)) == 0;
+  const int Z = ZC ? ZC : c.Z;
+  const int zm = Z - 1;
+  const bool zpow2 = (Z & zm) == 0;
+  const float lmax2 = lmax * kLog2e;
   const int64_t b = blockIdx.x;
   const float* llr_b = llr + b * (int64_t)c.e_tx;
-  for (int v = tid; v < c.n_dec; v += NT) LB[v] = 0.f;
-  for (int e = tid; e < c.E; e += NT) QB[e] = 0.f;
+  for (int v = tid; v < c.n_dec; v += NT) lds_st<float>(lb_b + 4 * v, 0.f);
+  for (int e = tid; e < c.E; e += NT) lds_st<float>(qb_b + 4 * e, 0.f);
   __syncthreads();
+
+  auto col_b = [&](auto deg, int cb, int cc, int* off) {
+    constexpr int DC = decltype(deg)::value;
+    if (zpow2) {
+      const int cc_b = vreg(cc * 4), zm_b = vreg(zm * 4);
+#pragma unroll
+      for (int q = 0; q < DC; ++q) {
+        const int2 ce = ld_const(c.col_edge, cb + q);
+        off[q] = ((cc_b - ce.y * 4) & zm_b) | (ce.x * 4);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < DC; ++q) {
+        const int2 ce = ld_const(c.col_edge, cb + q);
+        int x = cc - ce.y;
+        x += x < 0 ? Z : 0;
+        off[q] = (ce.x + x) * 4;
+      }
+    }
+  };
 
   for (int it = T - 1; it >= 0; --it) {
     const float* ck = ckpt + ((int64_t)it * B + b) * c.E;
@@ -293,14 +306,16 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
       const int e0 = uni(ld_const(c.row_ptr, i)), d = uni(ld_const(c.row_ptr, i + 1)) - e0;
       if (r < Z) {
         with_degree<kDMAX>(d, [&](auto deg) {
-          cn_forward<decltype(deg)::value>(ck + (size_t)e0 * Z + r, R + (size_t)e0 * Z + r, Z, lmax);
+          constexpr int D = decltype(deg)::value;
+          if constexpr (D >= 2)
+            cn_forward<D>(ck + (size_t)e0 * Z + r, Z * 4, (e0 * Z + r) * 4, lmax2);
         });
       }
     }
     lds_barrier();
     // B: variable-side adjoint
-    const float* wt = w + (int64_t)it * c.E;
-    float* gwb = gw_part + (b * (int64_t)T + it) * c.E;
+    const unsigned char* wt = reinterpret_cast<const unsigned char*>(w + (int64_t)it * c.E);
+    unsigned char* gwb = reinterpret_cast<unsigned char*>(gw_part + (b * (int64_t)T + it) * c.E);
     const bool last = it + 1 == T;
     for (int ti = wave; ti < c.n_vn_tasks; ti += NW) {
       const int task = uni(ld_const(c.vn_tasks, ti));
@@ -311,12 +326,12 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
         with_degree<kDMAX>(dc, [&](auto deg) {
           constexpr int DC = decltype(deg)::value;
           int off[DC];
-          col_offsets<DC>(c, cb, cc, zpow2, off);
+          col_b(deg, cb, cc, off);
           float rr[DC], ww[DC], s[DC], g[DC];
 #pragma unroll
-          for (int q = 0; q < DC; ++q) ww[q] = at(const_cast<float*>(wt), off[q]);
+          for (int q = 0; q < DC; ++q) ww[q] = *reinterpret_cast<const float*>(wt + off[q]);
 #pragma unroll
-          for (int q = 0; q < DC; ++q) rr[q] = at(R, off[q]);
+          for (int q = 0; q < DC; ++q) rr[q] = lds_ld<float>(off[q]);
           float acc = chan_lam(c, llr_b, v, lmax);
 #pragma unroll
           for (int q = 0; q < DC; ++q) {
@@ -328,19 +343,19 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
 #pragma unroll
             for (int q = 0; q < DC; ++q) {
               const float qv = acc - s[q];
-              g[q] = fabsf(qv) <= lmax ? at(QB, off[q]) : 0.f;
+              g[q] = fabsf(qv) <= lmax ? lds_ld<float>(qb_b + off[q]) : 0.f;
               A += g[q];
             }
           } else {
 #pragma unroll
             for (int q = 0; q < DC; ++q) g[q] = 0.f;
           }
-          LB[v] += A;
+          lds_st<float>(lb_b + 4 * v, lds_ld<float>(lb_b + 4 * v) + A);
 #pragma unroll
           for (int q = 0; q < DC; ++q) {
             const float sb = A - g[q];
-            at(gwb, off[q]) = sb * rr[q];
-            at(QB, off[q]) = sb * ww[q];
+            *reinterpret_cast<float*>(gwb + off[q]) = sb * rr[q];
+            lds_st<float>(qb_b + off[q], sb * ww[q]);
           }
         });
       }
@@ -353,14 +368,14 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
       const int e0 = uni(ld_const(c.row_ptr, i)), d = uni(ld_const(c.row_ptr, i + 1)) - e0;
       if (r < Z) {
         const float* qin = ck + (size_t)e0 * Z + r;
-        float* qb = QB + (size_t)e0 * Z + r;
+        const int qrow_b = qb_b + (e0 * Z + r) * 4;
         with_degree<kDMAX>(d, [&](auto deg) {
           constexpr int D = decltype(deg)::value;
           float x[D], cbar[D];
 #pragma unroll
           for (int q = 0; q < D; ++q) x[q] = qin[q * Z];
 #pragma unroll
-          for (int q = 0; q < D; ++q) cbar[q] = qb[q * Z];
+          for (int q = 0; q < D; ++q) cbar[q] = lds_ld<float>(qrow_b + q * Z * 4);
           float mm[D], tt[D], pD[D], pC[D], av[D];
           SpaAcc pre;
 #pragma unroll
@@ -377,8 +392,7 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
 #pragma unroll
           for (int q = D - 1; q >= 0; --q) {
             const float Dx = fmaf(suf.D, pC[q], pD[q]);
-            const float cb = spa_mag(Dx) <= lmax ? cbar[q] : 0.f;
-            av[q] = cb == 0.f ? 0.f : cb * __builtin_amdgcn_rcpf(Dx * (2.f - Dx));
+            av[q] = Dx >= dth ? cbar[q] * __builtin_amdgcn_rcpf(Dx * (2.f - Dx)) : 0.f;
             suf.add(mm[q]);
           }
           // S_k = Apre_k Psuf_k + Ppre_k Asuf_k
@@ -395,7 +409,7 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
 #pragma unroll
           for (int q = D - 1; q >= 0; --q) {
             const float S = ap[q] * Ps + pp[q] * As;
-            qb[q * Z] = mm[q] * (2.f - mm[q]) * S;
+            lds_st<float>(qrow_b + q * Z * 4, mm[q] * (2.f - mm[q]) * S);
             As = As * tt[q] + av[q] * Ps;
             Ps *= tt[q];
           }
@@ -411,13 +425,13 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
     const int cb = uni(ld_const(c.col_ptr, j)), dc = uni(ld_const(c.col_ptr, j + 1)) - cb;
     if (cc < Z) {
       const int v = j * Z + cc;
-      float acc = LB[v];
+      float acc = lds_ld<float>(lb_b + 4 * v);
       with_degree<kDMAX>(dc, [&](auto deg) {
         constexpr int DC = decltype(deg)::value;
         int off[DC];
-        col_offsets<DC>(c, cb, cc, zpow2, off);
+        col_b(deg, cb, cc, off);
 #pragma unroll
-        for (int q = 0; q < DC; ++q) acc += at(QB, off[q]);
+        for (int q = 0; q < DC; ++q) acc += lds_ld<float>(qb_b + off[q]);
       });
       const int xx = v - c.tx_lo;
       if (xx >= 0 && xx < c.e_tx) {
@@ -533,14 +547,21 @@ hipError_t launch_wbp_backward(const DevCode& c, int T, const float* w, const fl
     *why = "weighted BP adjoint state exceeds the 160 KiB LDS";
     return hipSuccess;
   }
-  {
-    hipError_t e = ensure_dyn_lds((const void*)wbp_backward_kernel<kBwdNT>, lds);
-    if (e != hipSuccess) return e;
-  }
+  const void* k = c.Z == 128 ? (const void*)wbp_backward_kernel<kBwdNT, 128>
+                             : (const void*)wbp_backward_kernel<kBwdNT, 0>;
+  hipError_t e = require_lds_at_zero(k);
+  if (e == hipSuccess) e = ensure_dyn_lds(k, lds);
+  if (e != hipSuccess) return e;
   float* part = reinterpret_cast<float*>(work);
-  wbp_backward_kernel<kBwdNT><<<(unsigned)B, kBwdNT, lds, s>>>(c, T, w, llr, ckpt, llr_max, gpost,
-                                                               gllr, part, B);
-  hipError_t e = hipGetLastError();
+  // the clamp threshold on D: ln((2 - D) / D) <= L  <=>  D >= 2 / (1 + e^L)
+  const float dth = (float)(2.0 / (1.0 + std::exp((double)llr_max)));
+  if (c.Z == 128)
+    wbp_backward_kernel<kBwdNT, 128><<<(unsigned)B, kBwdNT, lds, s>>>(
+        c, T, w, llr, ckpt, llr_max, dth, gpost, gllr, part, B);
+  else
+    wbp_backward_kernel<kBwdNT, 0><<<(unsigned)B, kBwdNT, lds, s>>>(
+        c, T, w, llr, ckpt, llr_max, dth, gpost, gllr, part, B);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n = (int64_t)T * c.E;
   float* slices = part + (size_t)B * n;
