@@ -254,3 +254,36 @@ def test_bce_and_adam():
         v = 0.999 * v + 0.001 * gr.astype(np.float64) ** 2
         pp -= 1e-2 * (m / (1 - 0.9 ** step)) / (np.sqrt(v / (1 - 0.999 ** step)) + 1e-8)
     assert np.allclose(tp.cpu().numpy(), pp, atol=1e-5)
+
+
+def test_autotuner_mixed_and_decode(tmp_path):
+    """The autotuner times only result-invariant knobs: its choice decodes
+    to the default plan's bits, the choice is cached and read back."""
+    from paper_2203_11854_amd import autotune
+    specs = mixed_specs()[:4]
+    counts = [5, 3, 4, 2]
+    p = lsim.params(lsim.NMS_F32, iters=5)
+    codes, parts = [], []
+    for s, ((spec, e_tx), cnt) in enumerate(zip(specs, counts)):
+        code = lsim.Code.from_qcbase(spec.load(), e_tx)
+        codes.append(code)
+        parts.append(rand.gaussian(700 + s, (cnt, e_tx), scale=3.0).astype(np.float32))
+    cat = T(np.concatenate([x.reshape(-1) for x in parts])).to(dev)
+    cache = str(tmp_path / "tune.json")
+    best = autotune.tune_mixed(codes, counts, p, cat, cache_path=cache)
+    assert set(best) >= {"threads", "codewords_per_tile", "persistent", "ms"}
+    again = autotune.tune_mixed(codes, counts, p, cat, cache_path=cache)
+    assert again == best
+    ref = torch.zeros(sum(c.k * n for c, n in zip(codes, counts)), dtype=torch.uint8, device=dev)
+    lsim.MixedPlan(codes, counts, p).decode(cat, bits=ref)
+    tuned = torch.zeros_like(ref)
+    plan = lsim.MixedPlan(codes, counts, p, codewords_per_tile=best["codewords_per_tile"],
+                          threads=best["threads"])
+    plan.decode(cat, bits=tuned, persistent=best["persistent"])
+    assert torch.equal(ref, tuned)
+    qb = BG2.load()
+    code = lsim.Code.from_qcbase(qb, 3840)
+    llr = T(rand.gaussian(710, (16, 3840), scale=3.0).astype(np.float32)).to(dev)
+    for algo in (lsim.SPA_F32, lsim.NMS_F32):
+        bd = autotune.tune_decode(code, llr, lsim.params(algo), cache_path=cache)
+        assert bd["threads"] in (256, 384, 512, 768, 1024)
