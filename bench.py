@@ -187,9 +187,10 @@ def main():
         extra["bler_curves"] = {n: [round(float(x), 5) for x in c] for n, c in curves.items()}
         log(f"[bench] Eb/N0 at BLER 1e-2: {extra['ebn0_db_at_bler_1e-2']}")
     if "oms" in legs:
-        q8 = torch.empty((B, code.e_tx), dtype=torch.int8, device=dev)
-        lsim.demap_q8(m, lsim.DEMAP_MAXLOG, link.y, no, out=q8)
         p = lsim.params(lsim.OMS_I8, iters=20, offset=1, sat=31)
+        lk8 = lsim.Link(code, m, lsim.DEMAP_MAXLOG, p, B, no, bins=tbins, nbins=9, device=dev)
+        lk8.run(data_seed(2, 0), 0)
+        q8 = lk8.llr
         ms = _elapsed(torch, lambda: lsim.decode(code, q8, p, bits=bits), nrep)
         a = B * 20 * E * OMS_SLOTS_PER_EDGE / (ms * 1e-3) / 1e12
         extra["oms_i8_bg2"] = {"decoder_ms": round(ms, 4), "gbps": round(B * k / (ms * 1e-3) / 1e9, 3),

@@ -220,9 +220,12 @@ lsim_status lsim_syndrome(const lsim_code* code, const uint8_t* d_c, int64_t str
  * demapper (fused with the quantizer for LSIM_OMS_I8, scale q_scale and
  * saturation dec.sat) -> decoder -> error count.  Buffers are the ones of
  * the individual calls; d_llr is f32[B][e_tx] or, for LSIM_OMS_I8,
- * i8[B][e_tx].  d_work / work_bytes as for lsim_decode.  d_counts receives
- * (bit errors, block errors, codewords) per bin (d_bin nullable = bin 0),
- * accumulated.  Equivalent to issuing the six calls in order on `stream`.
+ * i8[B][e_tx].  d_c (codewords) and d_y (channel output) are nullable: the
+ * transmit side runs as one kernel per batch with the codeword in LDS and
+ * writes them only when given.  d_work / work_bytes as for lsim_decode.
+ * d_counts receives (bit errors, block errors, codewords) per bin (d_bin
+ * nullable = bin 0), accumulated.  Results equal issuing the six calls in
+ * order on `stream`.
  */
 typedef struct {
   const lsim_code* code;

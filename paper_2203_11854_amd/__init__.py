@@ -483,15 +483,16 @@ class LinkArgs(ctypes.Structure):
 class Link:
     """Pre-allocated buffers for lsim_link_run: one call per Monte-Carlo
     batch through source, encoder, mapper + AWGN, demapper, decoder and
-    error count."""
+    error count.  keep_tx also stores the codewords (c) and channel
+    outputs (y); otherwise they stay on chip."""
 
     def __init__(self, code: Code, m: int, method: int, p: DecodeParams, B: int, no, bins=None,
-                 nbins: int = 1, q_scale: float = 2.0, device="cuda"):
+                 nbins: int = 1, q_scale: float = 2.0, device="cuda", keep_tx: bool = False):
         self.code, self.B = code, B
         self.no = no
         self.u = _empty((B, code.k), torch.uint8, device)
-        self.c = _empty((B, code.n_mother), torch.uint8, device)
-        self.y = _empty((B, code.e_tx // m, 2), torch.float32, device)
+        self.c = _empty((B, code.n_mother), torch.uint8, device) if keep_tx else None
+        self.y = _empty((B, code.e_tx // m, 2), torch.float32, device) if keep_tx else None
         self.llr = _empty((B, code.e_tx), torch.int8 if p.algo == OMS_I8 else torch.float32, device)
         self.bits = _empty((B, code.k), torch.uint8, device)
         self.counts = torch.zeros((nbins, 3), dtype=torch.int64, device=device)

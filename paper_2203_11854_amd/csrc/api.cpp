@@ -766,8 +766,8 @@ extern "C" lsim_status lsim_link_run(const lsim_link_args* a, lsim_stream stream
   lsim_status st = check_params(code, &a->dec);
   if (st != LSIM_OK) return st;
   const int m = a->bits_per_sym;
-  if (!a->d_no || !a->d_u || !a->d_c || !a->d_y || !a->d_llr || !a->d_bits || !a->d_counts ||
-      a->B < 1 || a->cw0 < 0 || a->nbins < 1)
+  if (!a->d_no || !a->d_u || !a->d_llr || !a->d_bits || !a->d_counts || a->B < 1 || a->cw0 < 0 ||
+      a->nbins < 1)
     return fail(LSIM_E_INVAL, "bad link arguments");
   if (m != 1 && m != 2 && m != 4 && m != 6)
     return fail(LSIM_E_UNSUPPORTED, "bits_per_sym must be 1, 2, 4 or 6");
@@ -788,14 +788,10 @@ extern "C" lsim_status lsim_link_run(const lsim_link_args* a, lsim_stream stream
   }
   hipStream_t s = as_stream(stream);
   const int64_t S = c.e_tx / m;
-  hipError_t e = lsim::launch_source_bits(a->seed, a->cw0, a->B, c.k, a->d_u, s);
-  if (e == hipSuccess) e = lsim::launch_encode(c, a->d_u, a->B, a->d_c, s);
-  if (e == hipSuccess)
-    e = lsim::launch_map_awgn(c, m, a->d_c, a->d_no, a->seed, a->cw0, a->B, a->d_y, s);
-  if (e == hipSuccess)
-    e = lsim::launch_demap(m, a->demap_method, a->d_y, a->d_no, a->B, S,
-                           q8 ? nullptr : (float*)a->d_llr, q8 ? (int8_t*)a->d_llr : nullptr,
-                           a->q_scale, a->dec.sat, s);
+  (void)S;
+  hipError_t e = lsim::launch_link_tx(c, m, a->demap_method, a->seed, a->cw0, a->B, a->d_no,
+                                      a->d_u, a->d_c, a->d_y, q8 ? nullptr : (float*)a->d_llr,
+                                      q8 ? (int8_t*)a->d_llr : nullptr, a->q_scale, a->dec.sat, s);
   std::string why;
   if (e == hipSuccess) {
     if (a->dec.algo == LSIM_NMS_F32)

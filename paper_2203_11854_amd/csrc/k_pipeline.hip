@@ -14,18 +14,17 @@ constexpr float kTwoPow32Inv = 2.3283064365386963e-10f;  // 2^-32
 
 // ----------------------------------------------------------------- source
 
-__global__ void source_bits_kernel(uint64_t seed, int64_t cw0, int64_t B, int64_t k,
-                                   int64_t words_per_cw, uint8_t* __restrict__ u) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= B * words_per_cw) return;
-  const int64_t b = t / words_per_cw;
-  const int64_t w = t - b * words_per_cw;  // 32-bit word index within the codeword
-  const U4 r = philox_at(seed, (uint32_t)(w >> 2), (uint64_t)(cw0 + b), kStreamBits);
+// 32 information bits of codeword cw, word w (bit i of the word is
+// information bit 32 w + i): Philox block w / 4, lane w % 4, stream 0.
+__device__ __forceinline__ uint32_t source_word(uint64_t seed, uint64_t cw, int64_t w) {
+  const U4 r = philox_at(seed, (uint32_t)(w >> 2), cw, kStreamBits);
   const uint32_t sel = (uint32_t)(w & 3);
-  const uint32_t word = sel == 0 ? r.x : sel == 1 ? r.y : sel == 2 ? r.z : r.w;
-  const int64_t i0 = w * 32;
-  const int n = (int)min<int64_t>(32, k - i0);
-  uint8_t* dst = u + b * k + i0;
+  return sel == 0 ? r.x : sel == 1 ? r.y : sel == 2 ? r.z : r.w;
+}
+
+// Writes the n <= 32 low bits of word as bytes 0/1 to dst (4-byte stores
+// when all 32 go to a 4-byte aligned address).
+__device__ __forceinline__ void expand_word(uint32_t word, int n, uint8_t* dst) {
   if (n == 32 && (((uintptr_t)dst) & 3) == 0) {
     uint32_t* d4 = reinterpret_cast<uint32_t*>(dst);
 #pragma unroll
@@ -36,6 +35,17 @@ __global__ void source_bits_kernel(uint64_t seed, int64_t cw0, int64_t B, int64_
   } else {
     for (int i = 0; i < n; ++i) dst[i] = (uint8_t)((word >> i) & 1u);
   }
+}
+
+__global__ void source_bits_kernel(uint64_t seed, int64_t cw0, int64_t B, int64_t k,
+                                   int64_t words_per_cw, uint8_t* __restrict__ u) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B * words_per_cw) return;
+  const int64_t b = t / words_per_cw;
+  const int64_t w = t - b * words_per_cw;  // 32-bit word index within the codeword
+  const uint32_t word = source_word(seed, (uint64_t)(cw0 + b), w);
+  const int64_t i0 = w * 32;
+  expand_word(word, (int)min<int64_t>(32, k - i0), u + b * k + i0);
 }
 
 // ---------------------------------------------------------------- encoder
@@ -50,6 +60,8 @@ __global__ void source_bits_kernel(uint64_t seed, int64_t cw0, int64_t B, int64_
 // with 16-byte accesses when the rows are aligned.
 constexpr int kEncThreads = 256;
 
+constexpr int kEncDMAX = 32;  // straight-line XOR bodies up to this many entries
+
 __device__ __forceinline__ void enc_xor_rows(const DevCode& c, uint8_t* cb, int row0, int nrows,
                                              uint8_t* dst, int dst_stride) {
   const int Z = c.Z;
@@ -61,40 +73,59 @@ __device__ __forceinline__ void enc_xor_rows(const DevCode& c, uint8_t* cb, int 
     const int e0 = ld_const(c.enc_ptr, row0 + i), e1 = ld_const(c.enc_ptr, row0 + i + 1);
     if (r < Z) {
       uint8_t acc = 0;
-      for (int e = e0; e < e1; ++e) {
-        const int2 cs = ld_const(c.enc_cz, e);
-        int x = r + cs.y;
-        x -= x >= Z ? Z : 0;
-        acc ^= cb[cs.x + x];
+      if (e1 - e0 <= kEncDMAX) {
+        // all of the row's table loads, then all of its LDS reads, back to back
+        with_degree<kEncDMAX>(e1 - e0, [&](auto deg) {
+          constexpr int D = decltype(deg)::value;
+          int idx[D];
+#pragma unroll
+          for (int k = 0; k < D; ++k) {
+            const int2 cs = ld_const(c.enc_cz, e0 + k);
+            int x = r + cs.y;
+            x -= x >= Z ? Z : 0;
+            idx[k] = cs.x + x;
+          }
+          uint8_t v[D];
+#pragma unroll
+          for (int k = 0; k < D; ++k) v[k] = cb[idx[k]];
+#pragma unroll
+          for (int k = 0; k < D; ++k) acc ^= v[k];
+        });
+      } else {
+        for (int e = e0; e < e1; ++e) {
+          const int2 cs = ld_const(c.enc_cz, e);
+          int x = r + cs.y;
+          x -= x >= Z ? Z : 0;
+          acc ^= cb[cs.x + x];
+        }
       }
       dst[i * dst_stride + r] = acc;
     }
   }
 }
 
-__global__ __launch_bounds__(kEncThreads) void encode_kernel(DevCode c, const uint8_t* __restrict__ u,
-                                                             uint8_t* __restrict__ cw) {
-  extern __shared__ __align__(16) uint8_t sm[];
+// Bytes [0, n) from src to dst, 16 bytes at a time when both are aligned
+// and n is a multiple of 16 (all threads of the workgroup take part).
+__device__ __forceinline__ void block_copy(const uint8_t* src, uint8_t* dst, int n, uint32_t mask) {
+  if (((n & 15) | ((uintptr_t)src & 15) | ((uintptr_t)dst & 15)) == 0) {
+    for (int i = threadIdx.x; i < (n >> 4); i += kEncThreads) {
+      uint4 v = reinterpret_cast<const uint4*>(src)[i];
+      v.x &= mask;
+      v.y &= mask;
+      v.z &= mask;
+      v.w &= mask;
+      reinterpret_cast<uint4*>(dst)[i] = v;
+    }
+  } else {
+    for (int i = threadIdx.x; i < n; i += kEncThreads) dst[i] = src[i] & (uint8_t)mask;
+  }
+}
+
+// The parity part of the codeword in LDS, from its information bits cb[0,k).
+__device__ __forceinline__ void encode_in_lds(const DevCode& c, uint8_t* cb, uint8_t* lam) {
   const int Z = c.Z, kb = c.kb, mb = c.mb;
   const int m = c.family == LSIM_FAMILY_11N ? mb : 4;
   const int mid = m / 2;
-  uint8_t* cb = sm;                                        // n_mother bits
-  uint8_t* lam = sm + ((c.n_mother + 15) & ~15);           // m * Z
-  const int64_t b = blockIdx.x;
-  const uint8_t* ub = u + b * (int64_t)c.k;
-  if (((c.k & 15) | ((uintptr_t)ub & 15)) == 0) {
-    for (int i = threadIdx.x; i < (c.k >> 4); i += kEncThreads) {
-      uint4 v = reinterpret_cast<const uint4*>(ub)[i];
-      v.x &= 0x01010101u;
-      v.y &= 0x01010101u;
-      v.z &= 0x01010101u;
-      v.w &= 0x01010101u;
-      reinterpret_cast<uint4*>(cb)[i] = v;
-    }
-  } else {
-    for (int i = threadIdx.x; i < c.k; i += kEncThreads) cb[i] = ub[i] & 1;
-  }
-  __syncthreads();
   enc_xor_rows(c, cb, 0, m, lam, Z);
   __syncthreads();
   for (int r = threadIdx.x; r < Z; r += kEncThreads) {
@@ -118,13 +149,23 @@ __global__ __launch_bounds__(kEncThreads) void encode_kernel(DevCode c, const ui
     enc_xor_rows(c, cb, 4, mb - 4, cb + (kb + 4) * Z, Z);
     __syncthreads();
   }
-  uint8_t* out = cw + b * (int64_t)c.n_mother;
-  if (((c.n_mother & 15) | ((uintptr_t)out & 15)) == 0) {
-    for (int i = threadIdx.x; i < (c.n_mother >> 4); i += kEncThreads)
-      reinterpret_cast<uint4*>(out)[i] = reinterpret_cast<const uint4*>(cb)[i];
-  } else {
-    for (int i = threadIdx.x; i < c.n_mother; i += kEncThreads) out[i] = cb[i];
-  }
+}
+
+__host__ __device__ inline size_t enc_lds_bytes(const DevCode& c) {
+  const int m = c.family == LSIM_FAMILY_11N ? c.mb : 4;
+  return (((size_t)c.n_mother + 15) & ~(size_t)15) + (size_t)m * c.Z;
+}
+
+__global__ __launch_bounds__(kEncThreads) void encode_kernel(DevCode c, const uint8_t* __restrict__ u,
+                                                             uint8_t* __restrict__ cw) {
+  extern __shared__ __align__(16) uint8_t sm[];
+  uint8_t* cb = sm;                                        // n_mother bits
+  uint8_t* lam = sm + ((c.n_mother + 15) & ~15);           // m * Z
+  const int64_t b = blockIdx.x;
+  block_copy(u + b * (int64_t)c.k, cb, c.k, 0x01010101u);
+  __syncthreads();
+  encode_in_lds(c, cb, lam);
+  block_copy(cb, cw + b * (int64_t)c.n_mother, c.n_mother, 0xffffffffu);
 }
 
 // ------------------------------------------------------- mapper + channel
@@ -138,6 +179,37 @@ __device__ __forceinline__ float pam_level(const uint32_t* a, int h) {
 
 __device__ __forceinline__ float qam_inv_scale(int h) {
   return h == 1 ? 0.70710678118654752f : h == 2 ? 0.31622776601683794f : 0.15430334996209191f;
+}
+
+// Symbol s of a codeword whose transmitted bits start at `bits`: Gray QAM
+// (or BPSK) point plus sqrt(N0/2) times the Box-Muller pair of the Philox
+// words (xa, xb).
+__device__ __forceinline__ float2 map_symbol(int m, const uint8_t* bits, int s, uint32_t xa,
+                                             uint32_t xb, float sig) {
+  const float ua = fmaf((float)xa, kTwoPow32Inv, kTwoPow32Inv);
+  const float ub = (float)xb * kTwoPow32Inv;
+  const float rho = sqrtf(-2.0f * logf(ua));
+  float sn, cs;
+  sincospif(2.0f * ub, &sn, &cs);
+  float xr, xi;
+  if (m == 1) {
+    xr = 1.0f - 2.0f * (float)bits[s];
+    xi = 0.0f;
+  } else {
+    const int hb = m >> 1;
+    uint32_t ai[3], aq[3];
+    for (int q = 0; q < hb; ++q) {
+      ai[q] = bits[s * m + 2 * q];
+      aq[q] = bits[s * m + 2 * q + 1];
+    }
+    const float inv = qam_inv_scale(hb);
+    xr = pam_level(ai, hb) * inv;
+    xi = pam_level(aq, hb) * inv;
+  }
+  float2 out;
+  out.x = xr + sig * rho * cs;
+  out.y = xi + sig * rho * sn;
+  return out;
 }
 
 __global__ void map_awgn_kernel(DevCode c, int m, const uint8_t* __restrict__ cw,
@@ -155,31 +227,8 @@ __global__ void map_awgn_kernel(DevCode c, int m, const uint8_t* __restrict__ cw
   for (int h = 0; h < 2; ++h) {
     const int s = 2 * j + h;
     if (s >= S) break;
-    const uint32_t xa = h ? r.z : r.x, xb = h ? r.w : r.y;
-    const float ua = fmaf((float)xa, kTwoPow32Inv, kTwoPow32Inv);
-    const float ub = (float)xb * kTwoPow32Inv;
-    const float rho = sqrtf(-2.0f * logf(ua));
-    float sn, cs;
-    sincospif(2.0f * ub, &sn, &cs);
-    float xr, xi;
-    if (m == 1) {
-      xr = 1.0f - 2.0f * (float)bits[s];
-      xi = 0.0f;
-    } else {
-      const int hb = m >> 1;
-      uint32_t ai[3], aq[3];
-      for (int q = 0; q < hb; ++q) {
-        ai[q] = bits[s * m + 2 * q];
-        aq[q] = bits[s * m + 2 * q + 1];
-      }
-      const float inv = qam_inv_scale(hb);
-      xr = pam_level(ai, hb) * inv;
-      xi = pam_level(aq, hb) * inv;
-    }
-    float2 out;
-    out.x = xr + sig * rho * cs;
-    out.y = xi + sig * rho * sn;
-    reinterpret_cast<float2*>(y)[b * (int64_t)S + s] = out;
+    reinterpret_cast<float2*>(y)[b * (int64_t)S + s] =
+        map_symbol(m, bits, s, h ? r.z : r.x, h ? r.w : r.y, sig);
   }
 }
 
@@ -248,15 +297,11 @@ __device__ __forceinline__ void symbol_llr(float2 yy, float n0, bool exact, floa
   }
 }
 
+// LLRs of symbol t (M of them) to llr (f32) or, when llr is null, quantized
+// to q (clamp(rint(L * scale), +-sat)).
 template <int M>
-__global__ void demap_kernel(int method, const float* __restrict__ y, const float* __restrict__ no,
-                             int64_t B, int64_t S, float* __restrict__ llr,
-                             int8_t* __restrict__ q, float scale, int sat) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= B * S) return;
-  const int64_t b = t / S;
-  float L[M];
-  symbol_llr<M>(reinterpret_cast<const float2*>(y)[t], no[b], method == LSIM_DEMAP_EXACT, L);
+__device__ __forceinline__ void store_llr(const float* L, int64_t t, float* __restrict__ llr,
+                                          int8_t* __restrict__ q, float scale, int sat) {
   if (llr) {
     float* o = llr + t * M;
     if constexpr (M == 4) {
@@ -277,6 +322,62 @@ __global__ void demap_kernel(int method, const float* __restrict__ y, const floa
       qq[i] = (int8_t)fminf(fmaxf(rintf(L[i] * scale), (float)-sat), (float)sat);
 #pragma unroll
     for (int i = 0; i < M; ++i) q[t * M + i] = qq[i];
+  }
+}
+
+template <int M>
+__global__ void demap_kernel(int method, const float* __restrict__ y, const float* __restrict__ no,
+                             int64_t B, int64_t S, float* __restrict__ llr,
+                             int8_t* __restrict__ q, float scale, int sat) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B * S) return;
+  const int64_t b = t / S;
+  float L[M];
+  symbol_llr<M>(reinterpret_cast<const float2*>(y)[t], no[b], method == LSIM_DEMAP_EXACT, L);
+  store_llr<M>(L, t, llr, q, scale, sat);
+}
+
+// The link's transmit side for one codeword per workgroup, all in LDS:
+// Philox information bits (also written to u), encoder, then per symbol
+// pair the Gray map + AWGN and the demapper, written as f32 LLRs or int8.
+// Same device functions as the separate kernels, so the same results; the
+// codeword (cw) and the channel output (y) are written only when asked.
+template <int M>
+__global__ __launch_bounds__(kEncThreads) void link_tx_kernel(
+    DevCode c, uint64_t seed, int64_t cw0, const float* __restrict__ no, int method,
+    uint8_t* __restrict__ u, uint8_t* __restrict__ cw, float* __restrict__ y,
+    float* __restrict__ llr, int8_t* __restrict__ q, float scale, int sat) {
+  extern __shared__ __align__(16) uint8_t sm[];
+  uint8_t* cb = sm;
+  uint8_t* lam = sm + ((c.n_mother + 15) & ~15);
+  const int64_t b = blockIdx.x;
+  const uint64_t cwi = (uint64_t)(cw0 + b);
+  const int64_t wpc = (c.k + 31) / 32;
+  for (int64_t w = threadIdx.x; w < wpc; w += kEncThreads)
+    expand_word(source_word(seed, cwi, w), (int)min<int64_t>(32, c.k - 32 * w), cb + 32 * w);
+  __syncthreads();
+  block_copy(cb, u + b * (int64_t)c.k, c.k, 0xffffffffu);
+  encode_in_lds(c, cb, lam);
+  if (cw) block_copy(cb, cw + b * (int64_t)c.n_mother, c.n_mother, 0xffffffffu);
+  const int S = c.e_tx / M;
+  const int npair = (S + 1) >> 1;
+  const float n0 = no[b];
+  const float sig = sqrtf(n0 * 0.5f);
+  const bool exact = method == LSIM_DEMAP_EXACT;
+  const uint8_t* bits = cb + c.tx_lo;
+  for (int j = threadIdx.x; j < npair; j += kEncThreads) {
+    const U4 r = philox_at(seed, (uint32_t)j, cwi, kStreamNoise);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int s = 2 * j + h;
+      if (s >= S) break;
+      const float2 yy = map_symbol(M, bits, s, h ? r.z : r.x, h ? r.w : r.y, sig);
+      const int64_t t = b * (int64_t)S + s;
+      if (y) reinterpret_cast<float2*>(y)[t] = yy;
+      float L[M];
+      symbol_llr<M>(yy, n0, exact, L);
+      store_llr<M>(L, t, llr, q, scale, sat);
+    }
   }
 }
 
@@ -400,9 +501,21 @@ hipError_t launch_source_bits(uint64_t seed, int64_t cw0, int64_t B, int64_t k, 
 
 hipError_t launch_encode(const DevCode& c, const uint8_t* u, int64_t B, uint8_t* cw,
                          hipStream_t s) {
-  const int m = c.family == LSIM_FAMILY_11N ? c.mb : 4;
-  const size_t lds = (((size_t)c.n_mother + 15) & ~(size_t)15) + (size_t)m * c.Z;
-  encode_kernel<<<(unsigned)B, kEncThreads, lds, s>>>(c, u, cw);
+  encode_kernel<<<(unsigned)B, kEncThreads, enc_lds_bytes(c), s>>>(c, u, cw);
+  return hipGetLastError();
+}
+
+hipError_t launch_link_tx(const DevCode& c, int m, int method, uint64_t seed, int64_t cw0,
+                          int64_t B, const float* no, uint8_t* u, uint8_t* cw, float* y,
+                          float* llr, int8_t* q, float scale, int sat, hipStream_t s) {
+  const size_t lds = enc_lds_bytes(c);
+  const unsigned g = (unsigned)B;
+  switch (m) {
+    case 1: link_tx_kernel<1><<<g, kEncThreads, lds, s>>>(c, seed, cw0, no, method, u, cw, y, llr, q, scale, sat); break;
+    case 2: link_tx_kernel<2><<<g, kEncThreads, lds, s>>>(c, seed, cw0, no, method, u, cw, y, llr, q, scale, sat); break;
+    case 4: link_tx_kernel<4><<<g, kEncThreads, lds, s>>>(c, seed, cw0, no, method, u, cw, y, llr, q, scale, sat); break;
+    default: link_tx_kernel<6><<<g, kEncThreads, lds, s>>>(c, seed, cw0, no, method, u, cw, y, llr, q, scale, sat); break;
+  }
   return hipGetLastError();
 }
 

@@ -105,6 +105,11 @@ hipError_t launch_source_bits(uint64_t seed, int64_t cw0, int64_t B, int64_t k, 
                               hipStream_t s);
 hipError_t launch_encode(const DevCode& c, const uint8_t* u, int64_t B, uint8_t* cw,
                          hipStream_t s);
+// Source bits -> encoder -> map + AWGN -> demapper for one codeword per
+// workgroup (cw and y nullable; q instead of llr for int8 output).
+hipError_t launch_link_tx(const DevCode& c, int m, int method, uint64_t seed, int64_t cw0,
+                          int64_t B, const float* no, uint8_t* u, uint8_t* cw, float* y,
+                          float* llr, int8_t* q, float scale, int sat, hipStream_t s);
 hipError_t launch_map_awgn(const DevCode& c, int m, const uint8_t* cw, const float* no,
                            uint64_t seed, int64_t cw0, int64_t B, float* y, hipStream_t s);
 hipError_t launch_demap(int m, int method, const float* y, const float* no, int64_t B, int64_t S,

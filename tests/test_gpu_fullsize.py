@@ -1,9 +1,10 @@
 """Parity at the benchmark's full sizes and launch configuration, on
 sampled codewords the oracle decodes one by one, plus edge cases.
 
-* BG2 workload: 4096 codewords through lsim_link_run (the bench step),
-  sampled codewords re-run through the oracle's link from the same Philox
-  seeds: bits and codewords bit-exact; int8 OMS posteriors bit-exact on
+* BG2 workload: 4096 codewords through lsim_link_run (the bench step,
+  codewords kept on chip), sampled codewords re-run through the oracle's
+  link from the same Philox seeds: information bits bit-exact; int8 OMS
+  posteriors bit-exact on
   the same quantized LLRs; FP32 SPA within 1e-4 on converged frames.
 * BG1 workload: 1024 codewords layered NMS, sampled codewords bit-exact.
 * Mixed batch at the benchmark's counts: sampled codewords per shape
@@ -45,11 +46,11 @@ def test_bg2_full_batch_sampled(algo):
     link = lsim.Link(code, m, lsim.DEMAP_MAXLOG, p, B, T(n0).to(dev), device=dev)
     seed = data_seed(2, 4242)
     link.run(seed, 0)
-    u, c, bits = link.u.cpu().numpy(), link.c.cpu().numpy(), link.bits.cpu().numpy()
+    u, bits = link.u.cpu().numpy(), link.bits.cpu().numpy()
     llr_gpu = link.llr.cpu().numpy()
     for b in SAMPLE:
         tx = pipeline.transmit(g, qb.family, seed, b, 1, n0[b:b + 1].astype(np.float64), m, "maxlog")
-        assert np.array_equal(u[b], tx["u"][0]) and np.array_equal(c[b], tx["c"][0]), b
+        assert np.array_equal(u[b], tx["u"][0]), b
         if algo == "oms":
             # same int8 LLRs on both sides: posteriors bit-exact
             q = llr_gpu[b:b + 1]

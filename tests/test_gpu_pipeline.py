@@ -169,15 +169,19 @@ def test_invalid_arguments_raise():
         lsim.quantize(torch.zeros(4, device=dev), scale=3.0)
 
 
-@pytest.mark.parametrize("algo", ["spa", "oms", "nms"])
-def test_link_run_equals_separate_calls(algo):
-    qb, code, m = code_for("bg2")
+@pytest.mark.parametrize("name,algo", [("bg2", "spa"), ("bg2", "oms"), ("bg2", "nms"),
+                                       ("small", "spa"), ("small", "oms"), ("bg1", "nms")])
+def test_link_run_equals_separate_calls(name, algo):
+    qb, code, m = code_for(name)
     B = 37
     no = T(np.full(B, 0.4, dtype=np.float32)).to(dev)
     bins = T((np.arange(B) % 3).astype(np.int32)).to(dev)
     p = lsim.params({"spa": lsim.SPA_F32, "oms": lsim.OMS_I8, "nms": lsim.NMS_F32}[algo])
-    link = lsim.Link(code, m, lsim.DEMAP_MAXLOG, p, B, no, bins=bins, nbins=3, device=dev)
+    link = lsim.Link(code, m, lsim.DEMAP_MAXLOG, p, B, no, bins=bins, nbins=3, device=dev,
+                     keep_tx=True)
     link.run(1234, 5)
+    lean = lsim.Link(code, m, lsim.DEMAP_MAXLOG, p, B, no, bins=bins, nbins=3, device=dev)
+    lean.run(1234, 5)
     u = lsim.source_bits(1234, 5, B, code.k, dev)
     c = lsim.encode(code, u)
     y = lsim.map_awgn(code, m, c, no, 1234, 5)
@@ -188,4 +192,8 @@ def test_link_run_equals_separate_calls(algo):
     bits, _ = lsim.decode(code, llr, p)
     cnt = lsim.count_errors(u, bits, bins, 3)
     assert torch.equal(link.u, u) and torch.equal(link.c, c) and torch.equal(link.llr, llr)
+    assert torch.equal(link.y, y)
     assert torch.equal(link.bits, bits) and torch.equal(link.counts, cnt)
+    # codewords and channel output kept on chip: same LLRs, bits and counts
+    assert torch.equal(lean.u, u) and torch.equal(lean.llr, llr)
+    assert torch.equal(lean.bits, bits) and torch.equal(lean.counts, cnt)
