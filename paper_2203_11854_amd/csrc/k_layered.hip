@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dispatch.h"
+#include "lds.h"
 #include "lsim_internal.h"
 
 #pragma clang fp contract(off)
@@ -59,8 +60,10 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
   const int g = tid / Z;
   const int r = tid - g * Z;
   const bool active = g < gmax;
-  unsigned char* myapp = reinterpret_cast<unsigned char*>(app + (size_t)(active ? g : 0) * c.n_dec);
-  const int zm4 = (Z - 1) * 4, r4 = r * 4;
+  // LDS byte address of this lane's codeword's posteriors (the tile's LDS
+  // starts at offset 0: the kernels have no static LDS)
+  const int app_b = vreg((active ? g : 0) * c.n_dec * 4);
+  const int Z4 = Z * 4, zm4 = (Z - 1) * 4, r4 = vreg(r * 4);
   const bool zpow2 = (Z & (Z - 1)) == 0;
   uint32_t* st = io.state + (size_t)(cw0 + (active ? g : 0)) * c.rows * 3 * Z + r;
 
@@ -100,31 +103,30 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
           constexpr int D = decltype(deg)::value;
           int addr[D];
           float tv[D];
-          // byte offset of the variable node of entry e at lift r:
-          // (col*Z + (r + shift) mod Z) * 4
+          // LDS byte address of the variable node of entry e at lift r:
+          // app_b + col*Z*4 + ((r + shift) mod Z)*4; the reduction is a mask
+          // for a power-of-two lift, else min(x, x - Z*4) on unsigned x
           if (zpow2) {
 #pragma unroll
             for (int q = 0; q < D; ++q) {
               const int2 en = ld_const(c.ent_cz, e0 + q);
-              addr[q] = ((r4 + en.y * 4) & zm4) | (en.x * 4);
+              addr[q] = app_b + en.x * 4 + ((r4 + en.y * 4) & zm4);
             }
           } else {
 #pragma unroll
             for (int q = 0; q < D; ++q) {
               const int2 en = ld_const(c.ent_cz, e0 + q);
-              int x = r + en.y;
-              x -= x >= Z ? Z : 0;
-              addr[q] = (en.x + x) * 4;
+              const uint32_t x = (uint32_t)(r4 + en.y * 4);
+              addr[q] = app_b + en.x * 4 + (int)min(x, x - (uint32_t)Z4);
             }
           }
 #pragma unroll
-          for (int q = 0; q < D; ++q) tv[q] = *reinterpret_cast<const float*>(myapp + addr[q]);
+          for (int q = 0; q < D; ++q) tv[q] = lds_ld<float>(addr[q]);
           const int i1_old = (int)(pk >> 27);
           // sign of a zero never reaches a nonzero value (a zero input forces
           // every other output magnitude to zero), so sign bits are used as is
           uint32_t sx = 0;
           float m1 = INFINITY, m2 = INFINITY;
-          int i1 = 0;
 #pragma unroll
           for (int q = 0; q < D; ++q) {
             const float mag = q == i1_old ? a2 : a1;
@@ -134,20 +136,25 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
             sx ^= __float_as_uint(t);
             const float at = fabsf(t);
             m2 = __builtin_amdgcn_fmed3f(m1, at, m2);
-            i1 = at < m1 ? q : i1;
             m1 = fminf(m1, at);
           }
           const float b1 = __fmul_rn(alpha, m1);
           const float b2 = __fmul_rn(alpha, m2);
-          uint32_t npk = (uint32_t)i1 << 27;
+          // Outputs in reverse order: the input at the minimum gets alpha*m2,
+          // the others alpha*m1, and i1 ends on the first index at the minimum.
+          // A repeated minimum makes m2 == m1, so every tie gets the same value.
+          int i1 = 0;
+          uint32_t npk = 0;
 #pragma unroll
-          for (int q = 0; q < D; ++q) {
-            const float mag = q == i1 ? b2 : b1;
+          for (int q = D - 1; q >= 0; --q) {
+            const bool at_min = fabsf(tv[q]) == m1;
+            const float mag = at_min ? b2 : b1;
+            i1 = at_min ? q : i1;
             const uint32_t sg = (sx ^ __float_as_uint(tv[q])) & 0x80000000u;
-            *reinterpret_cast<float*>(myapp + addr[q]) =
-                __fadd_rn(tv[q], __uint_as_float(__float_as_uint(mag) | sg));
+            lds_st<float>(addr[q], __fadd_rn(tv[q], __uint_as_float(__float_as_uint(mag) | sg)));
             npk |= sg >> (31 - q);
           }
+          npk |= (uint32_t)i1 << 27;
           sti[0] = __float_as_uint(b1);
           sti[Z] = __float_as_uint(b2);
           sti[2 * Z] = npk;
@@ -198,15 +205,17 @@ __global__ __launch_bounds__(NT) void mixed_kernel(const LayerShape* __restrict_
                                                    int64_t ntiles, const float* llr,
                                                    uint8_t* bits, float* lpost, uint32_t* state,
                                                    int* counter, int persistent, int iters,
-                                                   float alpha) {
+                                                   float alpha, int next_off) {
+  // dynamic LDS only (tiles address it from offset 0); the work item taken
+  // by thread 0 is broadcast through the word at next_off
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int64_t next;
+  int* next = reinterpret_cast<int*>(smem + next_off);
   int64_t item = persistent ? -1 : (int64_t)blockIdx.x;
   for (;;) {
     if (persistent) {
-      if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+      if (threadIdx.x == 0) *next = atomicAdd(counter, 1);
       __syncthreads();
-      item = next;
+      item = *next;
       __syncthreads();
     }
     if (item >= ntiles) break;
@@ -261,7 +270,8 @@ hipError_t launch_layered(const DevCode& c, const lsim_decode_params& p, const f
   const int dmax = c.max_row_deg;
 #define LSIM_LAYER_CASE(NT_, D_)                                                   \
   if (nt == NT_ && dmax <= D_) {                                                   \
-    hipError_t e = ensure_dyn_lds((const void*)layered_kernel<NT_, D_>, lds);   \
+    hipError_t e = require_lds_at_zero((const void*)layered_kernel<NT_, D_>);   \
+    if (e == hipSuccess) e = ensure_dyn_lds((const void*)layered_kernel<NT_, D_>, lds); \
     if (e != hipSuccess) return e;                                                 \
     layered_kernel<NT_, D_><<<grid, NT_, lds, s>>>(c, G, io, p.iters, p.alpha);    \
     return hipGetLastError();                                                      \
@@ -299,14 +309,17 @@ hipError_t launch_mixed(const LayerShape* d_shapes, int nshapes, const int* d_ti
     if (e != hipSuccess) return e;
   }
   const unsigned g = persistent ? (unsigned)grid : (unsigned)ntiles;
+  const int next_off = (int)((lds_bytes + 15) & ~(size_t)15);
+  const size_t lds_all = (size_t)next_off + 16;
 #define LSIM_MIXED_CASE(NT_, D_)                                                           \
   if (threads == NT_ && dmax <= D_) {                                                      \
-    hipError_t e = ensure_dyn_lds((const void*)mixed_kernel<NT_, D_>, lds_bytes);             \
+    hipError_t e = require_lds_at_zero((const void*)mixed_kernel<NT_, D_>);               \
+    if (e == hipSuccess) e = ensure_dyn_lds((const void*)mixed_kernel<NT_, D_>, lds_all);  \
     if (e != hipSuccess) return e;                                                         \
-    mixed_kernel<NT_, D_><<<g, NT_, lds_bytes, s>>>(d_shapes, d_tile_shape, d_tile_local,  \
-                                                    ntiles, (const float*)llr, bits, lpost, \
-                                                    state, counter, persistent, p.iters,   \
-                                                    p.alpha);                              \
+    mixed_kernel<NT_, D_><<<g, NT_, lds_all, s>>>(d_shapes, d_tile_shape, d_tile_local,    \
+                                                  ntiles, (const float*)llr, bits, lpost,   \
+                                                  state, counter, persistent, p.iters,     \
+                                                  p.alpha, next_off);                      \
     return hipGetLastError();                                                              \
   }
   LSIM_MIXED_CASE(256, 16)
