@@ -36,6 +36,18 @@ __device__ __forceinline__ void with_degree(int d, F&& f) {
   }
 }
 
+// Global access at an unsigned 32-bit byte offset from a wave-uniform base:
+// the zero-extended offset lets the compiler use the scalar-base form of
+// global_load/global_store (no 64-bit address arithmetic per lane).
+template <class T>
+__device__ __forceinline__ T ldg_at(const T* base, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const unsigned char*>(base) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void stg_at(T* base, uint32_t byte_off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(base) + byte_off) = v;
+}
+
 // Workgroup barrier that orders LDS only: global loads and stores in flight
 // stay in flight across it (a plain __syncthreads() would wait for them).
 __device__ __forceinline__ void lds_barrier() {

@@ -45,15 +45,14 @@ __device__ __forceinline__ float chan_lam(const DevCode& c, const float* llr_b, 
 }
 
 // Clamped check outputs (natural units) of one check of degree D >= 2 from
-// its inputs at byte offsets q*zs from in (device memory), written to LDS at
-// out_b + q*zs:
-// the sum / difference form of spa_math.h.
+// its inputs at byte offsets in_b + q*zs of ck (device memory), written to
+// LDS at out_b + q*zs: the sum / difference form of spa_math.h.
 template <int D>
-__device__ __forceinline__ void cn_forward(const float* in, int zs, int out_b, float lmax2) {
+__device__ __forceinline__ void cn_forward(const float* ck, uint32_t in_b, int zs, int out_b,
+                                           float lmax2) {
   float x[D], ee[D], pS[D], pA[D];
 #pragma unroll
-  for (int q = 0; q < D; ++q) x[q] = *reinterpret_cast<const float*>(
-      reinterpret_cast<const unsigned char*>(in) + q * zs);
+  for (int q = 0; q < D; ++q) x[q] = ldg_at(ck, in_b + (uint32_t)(q * zs));
   uint32_t sx = 0;
 #pragma unroll
   for (int q = 0; q < D; ++q) sx ^= __float_as_uint(x[q]);
@@ -217,7 +216,7 @@ __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
       }
     }
     lds_barrier();
-    const unsigned char* wt = reinterpret_cast<const unsigned char*>(w + (int64_t)it * c.E);
+    const float* wt = w + (int64_t)it * c.E;
     for (int ti = wave; ti < c.n_vn_tasks; ti += NW) {
       const int task = uni(ld_const(c.vn_tasks, ti));
       const int j = task >> 16, cc = (task & 0xffff) + lane;
@@ -230,7 +229,7 @@ __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
           col_b(deg, cb, cc, off);
           float s[DC], wv[DC];
 #pragma unroll
-          for (int q = 0; q < DC; ++q) wv[q] = *reinterpret_cast<const float*>(wt + off[q]);
+          for (int q = 0; q < DC; ++q) wv[q] = ldg_at(wt, (uint32_t)off[q]);
 #pragma unroll
           for (int q = 0; q < DC; ++q) s[q] = lds_ld<float>(off[q]);
           float acc = lds_ld<float>(lam_b + 4 * v);
@@ -308,14 +307,14 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
         with_degree<kDMAX>(d, [&](auto deg) {
           constexpr int D = decltype(deg)::value;
           if constexpr (D >= 2)
-            cn_forward<D>(ck + (size_t)e0 * Z + r, Z * 4, (e0 * Z + r) * 4, lmax2);
+            cn_forward<D>(ck, (uint32_t)((e0 * Z + r) * 4), Z * 4, (e0 * Z + r) * 4, lmax2);
         });
       }
     }
     lds_barrier();
     // B: variable-side adjoint
-    const unsigned char* wt = reinterpret_cast<const unsigned char*>(w + (int64_t)it * c.E);
-    unsigned char* gwb = reinterpret_cast<unsigned char*>(gw_part + (b * (int64_t)T + it) * c.E);
+    const float* wt = w + (int64_t)it * c.E;
+    float* gwb = gw_part + (b * (int64_t)T + it) * c.E;
     const bool last = it + 1 == T;
     for (int ti = wave; ti < c.n_vn_tasks; ti += NW) {
       const int task = uni(ld_const(c.vn_tasks, ti));
@@ -329,7 +328,7 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
           col_b(deg, cb, cc, off);
           float rr[DC], ww[DC], s[DC], g[DC];
 #pragma unroll
-          for (int q = 0; q < DC; ++q) ww[q] = *reinterpret_cast<const float*>(wt + off[q]);
+          for (int q = 0; q < DC; ++q) ww[q] = ldg_at(wt, (uint32_t)off[q]);
 #pragma unroll
           for (int q = 0; q < DC; ++q) rr[q] = lds_ld<float>(off[q]);
           float acc = chan_lam(c, llr_b, v, lmax);
@@ -354,7 +353,7 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
 #pragma unroll
           for (int q = 0; q < DC; ++q) {
             const float sb = A - g[q];
-            *reinterpret_cast<float*>(gwb + off[q]) = sb * rr[q];
+            stg_at(gwb, (uint32_t)off[q], sb * rr[q]);
             lds_st<float>(qb_b + off[q], sb * ww[q]);
           }
         });
@@ -367,13 +366,13 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
       const int i = task >> 16, r = (task & 0xffff) + lane;
       const int e0 = uni(ld_const(c.row_ptr, i)), d = uni(ld_const(c.row_ptr, i + 1)) - e0;
       if (r < Z) {
-        const float* qin = ck + (size_t)e0 * Z + r;
+        const uint32_t qin_b = (uint32_t)((e0 * Z + r) * 4);
         const int qrow_b = qb_b + (e0 * Z + r) * 4;
         with_degree<kDMAX>(d, [&](auto deg) {
           constexpr int D = decltype(deg)::value;
           float x[D], cbar[D];
 #pragma unroll
-          for (int q = 0; q < D; ++q) x[q] = qin[q * Z];
+          for (int q = 0; q < D; ++q) x[q] = ldg_at(ck, qin_b + (uint32_t)(q * Z * 4));
 #pragma unroll
           for (int q = 0; q < D; ++q) cbar[q] = lds_ld<float>(qrow_b + q * Z * 4);
           float mm[D], tt[D], pD[D], pC[D], av[D];
