@@ -148,6 +148,15 @@ def main():
     llr, bits = link.llr, link.bits
     nrep = 10
     dec_ms = _elapsed(torch, lambda: lsim.decode(code, llr, p_spa, bits=bits), nrep)
+    dec_med = _median_ms(torch, lambda: lsim.decode(code, llr, p_spa, bits=bits), 20, 5)
+    # decode time does not depend on the data: spot checks at 0 dB and 4 dB
+    snr_ms = {}
+    for pt in (0.0, 4.0):
+        no_pt = torch.full((B,), float(lsim.ebn0_to_n0(pt, rate, m)), dtype=torch.float32, device=dev)
+        lk_pt = lsim.Link(code, m, lsim.DEMAP_MAXLOG, p_spa, B, no_pt, device=dev)
+        lk_pt.run(data_seed(2, 77), 0)
+        snr_ms[f"{pt:.1f}"] = round(_median_ms(torch, lambda: lsim.decode(code, lk_pt.llr, p_spa,
+                                                                          bits=bits), 20, 5), 4)
     E = code.E
     slots = B * 20 * E * SPA_SLOTS_PER_EDGE
     achieved = slots / (dec_ms * 1e-3) / 1e12
@@ -157,6 +166,7 @@ def main():
                 "unit": "TOP/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": _flood_traffic(),
                 "kernel": "flood_kernel<512,16,SPA>", "kernel_ms": round(dec_ms, 4),
+                "kernel_ms_median20": round(dec_med, 4), "kernel_ms_median20_by_ebn0": snr_ms,
                 "algorithmic_slots_per_edge_round": SPA_SLOTS_PER_EDGE,
                 "hbm_algorithmic_bytes": hbm_bytes,
                 "hbm_frac": round(hbm_bytes / (dec_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5),
@@ -164,7 +174,8 @@ def main():
                 "lds_frac": round(lds_bytes / (dec_ms * 1e-3) / 1e9 / LDS_PEAK_GBS, 4)}
     log(f"[bench] step {ms_step:.3f} ms, decoder {dec_ms:.3f} ms, {value:.3f} Gbit/s")
 
-    extra = {"bler_by_ebn0": {f"{pts[j]:.1f}": [int(cnt[j, 1]), int(cnt[j, 2])] for j in range(9)},
+    extra = {"hbm_copy_gbs_measured": round(_copy_gbs(torch, dev), 1),
+             "bler_by_ebn0": {f"{pts[j]:.1f}": [int(cnt[j, 1]), int(cnt[j, 2])] for j in range(9)},
              "ber_by_ebn0": {f"{pts[j]:.1f}": float(cnt[j, 0]) / max(1, cnt[j, 2] * k) for j in range(9)},
              "decoder_only_gbps": round(B * k / (dec_ms * 1e-3) / 1e9, 3)}
 
@@ -273,6 +284,31 @@ def ebn0_at_bler(pts, blers, target=1e-2):
             la, lb, lt = math.log10(a), math.log10(b), math.log10(target)
             return float(pts[j - 1] + (pts[j] - pts[j - 1]) * (la - lt) / (la - lb))
     return None
+
+
+def _median_ms(torch, fn, reps, warm):
+    """Median of `reps` launches, each between its own pair of HIP events on
+    the current stream, after `warm` untimed ones."""
+    for _ in range(warm):
+        fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def _copy_gbs(torch, dev, mib=1024):
+    """Device-to-device copy bandwidth (read + write bytes per second)."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    ms = _median_ms(torch, lambda: dst.copy_(src), 10, 2)
+    del src, dst
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
 
 
 def _elapsed(torch, fn, reps):
@@ -475,6 +511,7 @@ def cpu_baseline(qb, ncw):
     cpu_s = (c1.user - c0.user) + (c1.system - c0.system)
     lo, hi = stats.wilson(int(cnt[1]), int(cnt[2]))
     return {"value": round(ncw * g.k / dt / 1e9, 7), "unit": "Gbit/s",
+            "codewords_per_s": round(ncw / dt, 2),
             "cores": max(1, int(round(cpu_s / dt))), "kind": "oracle",
             "cpu_model": _cpu_model(), "cpu_seconds": round(cpu_s, 1),
             "sample": f"{ncw} codewords of the bg2 workload at Eb/N0 {CPU_EBN0} dB, full link "
@@ -511,6 +548,7 @@ def cpu_baseline_pool(qb, ncw):
             os.environ["OMP_NUM_THREADS"] = old
     n = workers * per
     return {"value": round(n * 1280 / dt / 1e9, 7), "unit": "Gbit/s", "cores": workers,
+            "codewords_per_s": round(n / dt, 2),
             "kind": "oracle", "cpu_model": _cpu_model(),
             "sample": f"{n} codewords ({workers} processes x {per}), same link as cpu_baseline, "
                       f"{dt:.1f} s wall", "block_errors": int(tot[1])}

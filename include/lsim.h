@@ -255,7 +255,8 @@ lsim_status lsim_link_run(const lsim_link_args* args, lsim_stream stream);
 
 /*
  * Plan for decoding codewords of several codes in one persistent launch
- * (layered NMS or flooding OMS).  counts[s] codewords of codes[s].  The
+ * with the layered NMS decoder (p->algo must be LSIM_NMS_F32; other
+ * algorithms return LSIM_E_UNSUPPORTED).  counts[s] codewords of codes[s].  The
  * plan owns a device work list and descriptor table.  `codewords_per_tile`
  * (nullable) fixes, per shape, how many codewords share one workgroup
  * (0 = choose from Z and LDS); `threads` (0 = default) the workgroup size.

@@ -501,6 +501,8 @@ hipError_t launch_source_bits(uint64_t seed, int64_t cw0, int64_t B, int64_t k, 
 
 hipError_t launch_encode(const DevCode& c, const uint8_t* u, int64_t B, uint8_t* cw,
                          hipStream_t s) {
+  hipError_t e = ensure_dyn_lds((const void*)encode_kernel, enc_lds_bytes(c));
+  if (e != hipSuccess) return e;
   encode_kernel<<<(unsigned)B, kEncThreads, enc_lds_bytes(c), s>>>(c, u, cw);
   return hipGetLastError();
 }
@@ -510,6 +512,10 @@ hipError_t launch_link_tx(const DevCode& c, int m, int method, uint64_t seed, in
                           float* llr, int8_t* q, float scale, int sat, hipStream_t s) {
   const size_t lds = enc_lds_bytes(c);
   const unsigned g = (unsigned)B;
+  const void* k = m == 1 ? (const void*)link_tx_kernel<1> : m == 2 ? (const void*)link_tx_kernel<2>
+                : m == 4 ? (const void*)link_tx_kernel<4> : (const void*)link_tx_kernel<6>;
+  hipError_t e = ensure_dyn_lds(k, lds);
+  if (e != hipSuccess) return e;
   switch (m) {
     case 1: link_tx_kernel<1><<<g, kEncThreads, lds, s>>>(c, seed, cw0, no, method, u, cw, y, llr, q, scale, sat); break;
     case 2: link_tx_kernel<2><<<g, kEncThreads, lds, s>>>(c, seed, cw0, no, method, u, cw, y, llr, q, scale, sat); break;
