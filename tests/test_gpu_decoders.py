@@ -183,3 +183,43 @@ def test_nms_layered_few_layers(case):
         assert np.array_equal(lp.cpu().numpy(), -hist[t - 1][1]), t
     bits, _ = lsim.decode(code, tl, lsim.params(lsim.NMS_F32, iters=20, alpha=0.75))
     assert np.array_equal(bits.cpu().numpy(), D.hard_bits(app, g.k))
+
+
+@pytest.mark.parametrize("offset,sat", [(0, 31), (2, 31), (1, 15), (1, 127)])
+def test_oms_parameters_bit_exact(offset, sat):
+    """int8 offset min-sum with other offsets and saturation levels (the
+    packed 16-bit kernel keeps every value exact up to sat = 127)."""
+    qb, g, code = gcode("bg2")
+    tx = oracle_llrs("bg2", 11, 3.0, 83)
+    q = modem.quantize(tx["L"].astype(np.float32), 2.0, sat)
+    app = D.oms_flood(g, D.channel_lam(g, q, np.int64), 20, offset=offset, sat=sat)
+    p = lsim.params(lsim.OMS_I8, iters=20, offset=offset, sat=sat)
+    bits, lp = lsim.decode(code, T(q).to(dev), p, want_app=True)
+    assert np.array_equal(lp.cpu().numpy(), -app)
+    assert np.array_equal(bits.cpu().numpy(), D.hard_bits(app, g.k))
+
+
+@pytest.mark.parametrize("alpha", [0.5, 1.0])
+def test_nms_alpha_bit_exact(alpha):
+    qb, g, code = gcode("bg2")
+    tx = oracle_llrs("bg2", 9, 3.0, 89)
+    L32 = tx["L"].astype(np.float32)
+    app = D.nms_layered(g, D.channel_lam(g, L32, dtype=np.float32), 20, alpha=alpha, mode="fp32")
+    _, lp = lsim.decode(code, T(L32).to(dev), lsim.params(lsim.NMS_F32, alpha=alpha),
+                        want_app=True)
+    assert np.array_equal(lp.cpu().numpy(), -app)
+
+
+def test_spa_other_clamp():
+    """Sum-product with messages clamped at 10 instead of 20."""
+    qb, g, code = gcode("bg2")
+    tx = oracle_llrs("bg2", 32, 3.5, 97)
+    L32 = tx["L"].astype(np.float32)
+    app = D.spa_flood(g, D.channel_lam(g, L32.astype(np.float64)), 20, llr_max=10.0)
+    hard = (app < 0).astype(np.uint8)
+    conv = ~qc.syndrome(qb.base[:g.rows, :g.cols], qb.Z, hard).any(axis=1)
+    assert conv.sum() >= 8
+    _, lp = lsim.decode(code, T(L32).to(dev), lsim.params(lsim.SPA_F32, llr_max=10.0),
+                        want_app=True)
+    ok, w = rel_close(lp.cpu().numpy()[conv], -app[conv], 1e-4)
+    assert ok, w
