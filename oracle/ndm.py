@@ -30,9 +30,17 @@ def forward_torch(params, y, n0):
     """LLRs ``[B][S*4]`` (float64 torch) from symbols ``y[B][S]`` complex."""
     import torch
 
-    W1, b1, W2, b2, W3, b3 = unpack(params)
     yr = torch.as_tensor(np.real(y), dtype=torch.float64)
     yi = torch.as_tensor(np.imag(y), dtype=torch.float64)
+    return forward_torch_xy(params, yr, yi, n0)
+
+
+def forward_torch_xy(params, yr, yi, n0):
+    """As ``forward_torch`` with the symbol's real and imaginary parts given
+    as float64 torch tensors (so gradients can flow into them)."""
+    import torch
+
+    W1, b1, W2, b2, W3, b3 = unpack(params)
     ln0 = torch.log(torch.as_tensor(np.asarray(n0, dtype=np.float64))).reshape(-1, 1).expand_as(yr)
     x = torch.stack([yr, yi, ln0], dim=-1)                   # (B, S, 3)
     h1 = torch.relu(x @ W1.T + b1)
