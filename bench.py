@@ -11,7 +11,8 @@ Philox in-kernel), resident in HBM before the timed region.
 Printed: one JSON line with the decoded-information throughput (Gbit/s),
 the decoder kernel's roofline position, the oracle's CPU baseline on a
 bounded sample, and secondary legs (int8 offset min-sum, layered NMS on the
-BG1-shaped code, mixed-shape persistent batch, weighted BP fwd/fwd+bwd).
+BG1-shaped code, mixed-shape persistent batch, weighted BP fwd/fwd+bwd,
+trainable constellation with the neural demapper).
 """
 from __future__ import annotations
 
@@ -74,8 +75,8 @@ def parse():
                     help="also time the oracle in a process pool over the host's cores")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB of a plain device copy run first (reference for HBM counters)")
-    ap.add_argument("--legs", default="bler,oms,nms,mixed,wbp",
-                    help="secondary legs: bler,oms,nms,mixed,wbp (empty = none)")
+    ap.add_argument("--legs", default="bler,oms,nms,mixed,wbp,const",
+                    help="secondary legs: bler,oms,nms,mixed,wbp,const (empty = none)")
     return ap.parse_args()
 
 
@@ -237,6 +238,9 @@ def main():
     if "wbp" in legs:
         extra["wbp_ndm_bg2"] = {f"T{t}": wbp_leg(torch, lsim, dev, code, qb, t) for t in (10, 20)}
         log(f"[bench] wbp: {extra['wbp_ndm_bg2']}")
+    if "const" in legs:
+        extra["constellation_ndm_bg2"] = const_leg(torch, lsim, dev, code, qb)
+        log(f"[bench] constellation: {extra['constellation_ndm_bg2']}")
 
     if cpu is not None:
         j = int(np.where(np.isclose(pts, CPU_EBN0))[0][0])
@@ -453,6 +457,91 @@ def wbp_leg(torch, lsim, dev, code, qb, T=10):
             "plain_spa_ms": round(ms_plain, 4),
             "plain_spa_gbps": round(info / (ms_plain * 1e-3) / 1e9, 3),
             "loss_after_timing_steps": round(l0, 6)}
+
+
+def const_leg(torch, lsim, dev, code, qb, steps=50):
+    """End-to-end learning of the constellation with the neural demapper
+    (16 trainable points, batch 2048 codewords of the bg2 code's coded bits,
+    Eb/N0 ~ U[1, 4] dB): one training step (mapper with the point table,
+    demapper, BCE, demapper backward with dL/dy, points adjoint, two Adam
+    updates) against the same step with the fixed Gray mapper."""
+    from inputs import rand
+    from inputs.workloads import data_seed
+
+    B, m = 2048, 4
+    r = rand.rng(6006)
+    no = torch.tensor(lsim.ebn0_to_n0(r.uniform(1.0, 4.0, B), code.k / code.e_tx, m),
+                      dtype=torch.float32, device=dev)
+    seed = data_seed(6, 0)
+    c = lsim.encode(code, lsim.source_bits(seed, 0, B, code.k, dev))
+    ctx = c[:, code.tx_lo:]
+    S = code.e_tx // m
+    gray = torch.tensor(_gray_points(m), dtype=torch.float32, device=dev)
+    pts = gray.clone()
+    params = torch.tensor(glorot_params(6007), dtype=torch.float32, device=dev)
+    pm, pv = torch.zeros_like(pts), torch.zeros_like(pts)
+    wm, wv = torch.zeros_like(params), torch.zeros_like(params)
+    y = torch.empty((B, S, 2), dtype=torch.float32, device=dev)
+    llr = torch.empty((B, code.e_tx), dtype=torch.float32, device=dev)
+    gy = torch.empty_like(y)
+    nwork = torch.empty(lsim.ndm_workspace(B, S), dtype=torch.uint8, device=dev)
+    pwork = torch.empty(lsim.points_workspace(code, m, B), dtype=torch.uint8, device=dev)
+    gpts = torch.empty_like(pts)
+    scale = 1.0 / (B * code.e_tx)
+    state = {"step": 0}
+
+    def step(trainable=True):
+        state["step"] += 1
+        if trainable:
+            lsim.map_points(code, m, pts, c, no, seed, state["step"] * B, out=y)
+        else:
+            lsim.map_awgn(code, m, c, no, seed, state["step"] * B, out=y)
+        lsim.ndm_forward(params, y, no, out=llr)
+        g, loss = lsim.bce_grad(llr, ctx, scale)
+        if trainable:
+            gp, _ = lsim.ndm_backward(params, y, no, g, work=nwork, gy=gy)
+            lsim.points_grad(code, m, pts, c, gy, out=gpts, work=pwork)
+            lsim.adam_step(pts, gpts, pm, pv, state["step"], lr=1e-2)
+        else:
+            gp = lsim.ndm_backward(params, y, no, g, work=nwork)
+        lsim.adam_step(params, gp, wm, wv, state["step"], lr=1e-2)
+        return loss
+
+    l_first = float(step().item())
+    for _ in range(steps - 1):
+        loss = step()
+    l_last = float(loss.item())
+    ms_t = _elapsed(torch, step, 5)
+    ms_map = _elapsed(torch, lambda: lsim.map_points(code, m, pts, c, no, seed, 0, out=y), 5)
+    ms_pg = _elapsed(torch, lambda: lsim.points_grad(code, m, pts, c, gy, out=gpts, work=pwork), 5)
+    ms_f = _elapsed(torch, lambda: step(False), 5)
+    nsym = B * S
+    return {"batch": B, "symbols": nsym, "step_ms": round(ms_t, 4),
+            "fixed_gray_step_ms": round(ms_f, 4),
+            "map_points_ms": round(ms_map, 4), "points_grad_ms": round(ms_pg, 4),
+            "step_msym_per_s": round(nsym / (ms_t * 1e-3) / 1e6, 1),
+            "loss_first_step": round(l_first, 5), f"loss_after_{steps}_steps": round(l_last, 5)}
+
+
+def _gray_points(m):
+    """Initial constellation: the mapper's square Gray QAM (3GPP TS 38.211
+    Sec. 5.1) by label, first bit most significant; I takes bits 0, 2, ..,
+    Q bits 1, 3, ..; per axis level (1-2a0)(2^(h-1) - (1-2a1)(2^(h-2) - ..))
+    over 2^h levels, scaled to unit average energy."""
+    h = m // 2
+
+    def level(a):
+        v = 1
+        for q in range(h - 1, 0, -1):
+            v = (1 << (h - q)) - (1 - 2 * a[q]) * v
+        return (1 - 2 * a[0]) * v
+
+    norm = math.sqrt(2.0 * (4 ** h - 1) / 3.0)
+    out = np.zeros((1 << m, 2))
+    for lab in range(1 << m):
+        bits = [(lab >> (m - 1 - i)) & 1 for i in range(m)]
+        out[lab] = (level(bits[0::2]) / norm, level(bits[1::2]) / norm)
+    return out
 
 
 def glorot_params(seed):

@@ -121,6 +121,34 @@ lsim_status lsim_map_awgn(const lsim_code* code, int bits_per_sym, const uint8_t
                           const float* d_no, uint64_t seed, int64_t cw0, int64_t B, float* d_y,
                           lsim_stream stream);
 
+/*
+ * Mapper with a trainable constellation (Sec. III-C "Hello, World!": the
+ * constellation's points become trainable variables, Listing 2) + AWGN.
+ * d_points f32[K][2] (Re, Im), K = 2^m, m = bits_per_sym in 1..6, indexed
+ * by the label of the symbol's m transmitted bits read first bit most
+ * significant; the mapper uses them scaled to unit average energy,
+ * x_k = p_k / sqrt(mean_j |p_j|^2) (a table of all zeros gives NaN).  The
+ * noise is that of lsim_map_awgn, bit for bit (same Philox counters and
+ * Box-Muller), so with the Gray QAM points of lsim_map_awgn the outputs
+ * agree to rounding.  d_y f32[B][S][2], S = e_tx / m, 8-byte aligned.
+ */
+lsim_status lsim_map_points(const lsim_code* code, int bits_per_sym, const float* d_points,
+                            const uint8_t* d_c, const float* d_no, uint64_t seed, int64_t cw0,
+                            int64_t B, float* d_y, lsim_stream stream);
+/*
+ * Adjoint of lsim_map_points with respect to the points (the noise does
+ * not depend on them): d_gpoints f32[K][2] (overwritten) = dLoss/dp for the
+ * upstream d_gy = dLoss/dy f32[B][S][2].  With G_k the sum of d_gy over the
+ * symbols of label k and s the normalisation,
+ * dLoss/dp_j = (G_j - x_j sum_k <G_k, x_k> / K) / s.  Sums run in a fixed
+ * order (deterministic).  d_work needs lsim_points_workspace() bytes.
+ */
+lsim_status lsim_points_workspace(const lsim_code* code, int bits_per_sym, int64_t B,
+                                  size_t* bytes);
+lsim_status lsim_points_grad(const lsim_code* code, int bits_per_sym, const float* d_points,
+                             const uint8_t* d_c, const float* d_gy, int64_t B, float* d_gpoints,
+                             void* d_work, size_t work_bytes, lsim_stream stream);
+
 enum { LSIM_DEMAP_EXACT = 0, LSIM_DEMAP_MAXLOG = 1 };
 
 /*
@@ -316,11 +344,13 @@ lsim_status lsim_wbp_backward(const lsim_code* code, int T, const float* d_w, co
 lsim_status lsim_ndm_forward(const float* d_params, const float* d_y, const float* d_no,
                              int64_t B, int64_t S, float* d_llr, lsim_stream stream);
 /* dLoss/dparams for upstream d_gllr f32[B][S*4]; d_gparams overwritten
- * (fixed-order reduction); d_work needs lsim_ndm_workspace() bytes. */
+ * (fixed-order reduction); d_gy (nullable, 8-byte aligned) receives
+ * dLoss/dy f32[B][S][2], the gradient that flows on into a trainable
+ * mapper.  d_work needs lsim_ndm_workspace() bytes. */
 lsim_status lsim_ndm_workspace(int64_t B, int64_t S, size_t* bytes);
 lsim_status lsim_ndm_backward(const float* d_params, const float* d_y, const float* d_no,
                               const float* d_gllr, int64_t B, int64_t S, float* d_gparams,
-                              void* d_work, size_t work_bytes, lsim_stream stream);
+                              float* d_gy, void* d_work, size_t work_bytes, lsim_stream stream);
 
 /*
  * Binary cross-entropy on logits (Listing 2 loss) against code bits:

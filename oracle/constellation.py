@@ -68,10 +68,11 @@ def _torch_chain(p, params, t, m, n0, g):
 
 
 def loss_and_grads(p: np.ndarray, params: np.ndarray, t: np.ndarray, m: int, n0: np.ndarray,
-                   g: np.ndarray):
+                   g: np.ndarray, keep: np.ndarray | None = None):
     """(loss, d loss / d points ``[K][2]``, d loss / d params) of the mean BCE
     between coded bits ``t`` and the demapper LLRs; ``g`` complex standard
-    normals ``[B][S]`` (E|g|^2 = 2)."""
+    normals ``[B][S]`` (E|g|^2 = 2).  Symbols where ``keep`` (bool ``[B][S]``)
+    is False count in the loss but not in the gradients."""
     import torch
 
     pt = torch.tensor(np.asarray(p, dtype=np.float64), requires_grad=True)
@@ -79,9 +80,15 @@ def loss_and_grads(p: np.ndarray, params: np.ndarray, t: np.ndarray, m: int, n0:
     yr, yi = _torch_chain(pt, wt, t, m, n0, g)
     llr = ndm.forward_torch_xy(wt, yr, yi, n0)
     tt = torch.as_tensor(np.asarray(t, dtype=np.float64))
-    loss = (torch.nn.functional.softplus(llr) - tt * llr).mean()
-    loss.backward()
-    return float(loss), pt.grad.numpy(), wt.grad.numpy()
+    terms = torch.nn.functional.softplus(llr) - tt * llr
+    loss = terms.mean()
+    if keep is not None:
+        B, S = np.shape(keep)
+        w = torch.as_tensor(np.repeat(np.asarray(keep, dtype=np.float64), m, axis=1).reshape(B, S * m))
+        (terms * w).sum().div(terms.numel()).backward()
+    else:
+        loss.backward()
+    return float(loss.detach()), pt.grad.numpy(), wt.grad.numpy()
 
 
 def points_vjp(p: np.ndarray, t: np.ndarray, m: int, gy: np.ndarray) -> np.ndarray:

@@ -57,6 +57,9 @@ _SIGS = {
     "lsim_source_bits": [_U64, _I64, _I64, _I64, _P, _P],
     "lsim_encode": [_P, _P, _I64, _P, _P],
     "lsim_map_awgn": [_P, _I, _P, _P, _U64, _I64, _I64, _P, _P],
+    "lsim_map_points": [_P, _I, _P, _P, _P, _U64, _I64, _I64, _P, _P],
+    "lsim_points_workspace": [_P, _I, _I64, ctypes.POINTER(_SZ)],
+    "lsim_points_grad": [_P, _I, _P, _P, _P, _I64, _P, _P, _SZ, _P],
     "lsim_demap": [_I, _I, _P, _P, _I64, _I64, _P, _P],
     "lsim_demap_q8": [_I, _I, _P, _P, _I64, _I64, _F, _I, _P, _P],
     "lsim_quantize": [_P, _I64, _F, _I, _P, _P],
@@ -74,7 +77,7 @@ _SIGS = {
     "lsim_wbp_backward": [_P, _I, _P, _P, _P, _I64, _F, _P, _P, _P, _P, _SZ, _P],
     "lsim_ndm_forward": [_P, _P, _P, _I64, _I64, _P, _P],
     "lsim_ndm_workspace": [_I64, _I64, ctypes.POINTER(_SZ)],
-    "lsim_ndm_backward": [_P, _P, _P, _P, _I64, _I64, _P, _P, _SZ, _P],
+    "lsim_ndm_backward": [_P, _P, _P, _P, _I64, _I64, _P, _P, _P, _SZ, _P],
     "lsim_bce_workspace": [_I64, _I64, ctypes.POINTER(_SZ)],
     "lsim_bce_grad": [_P, _P, _I64, _I64, _I64, _F, _P, _P, _P, _SZ, _P],
     "lsim_adam_step": [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I, _P],
@@ -159,6 +162,11 @@ class Code:
     def handle(self):
         return self._h
 
+    @property
+    def tx_lo(self) -> int:
+        """First transmitted mother-code bit (lsim_code_create's rate matching)."""
+        return self.n_punct_cols * self.Z
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h and _lib is not None:
@@ -188,6 +196,28 @@ def map_awgn(code: Code, m: int, c, no, seed: int, cw0: int, out=None):
     _call("lsim_map_awgn", code.handle, m, _ptr(c, torch.uint8, "c"), _ptr(no, torch.float32, "no"),
           seed, cw0, B, _ptr(y, torch.float32, "y"), _stream())
     return y
+
+
+def map_points(code: Code, m: int, points, c, no, seed: int, cw0: int, out=None):
+    """Trainable-constellation mapper + AWGN: points f32[2^m][2]."""
+    B = c.shape[0]
+    S = code.e_tx // m
+    y = out if out is not None else _empty((B, S, 2), torch.float32, c.device)
+    _call("lsim_map_points", code.handle, m, _ptr(points, torch.float32, "points"),
+          _ptr(c, torch.uint8, "c"), _ptr(no, torch.float32, "no"), seed, cw0, B,
+          _ptr(y, torch.float32, "y"), _stream())
+    return y
+
+
+def points_grad(code: Code, m: int, points, c, gy, out=None, work=None):
+    """dLoss/dpoints f32[2^m][2] from dLoss/dy f32[B][S][2]."""
+    B = c.shape[0]
+    g = out if out is not None else _empty((1 << m, 2), torch.float32, gy.device)
+    work, nbytes = _work(points_workspace(code, m, B), gy.device, work)
+    _call("lsim_points_grad", code.handle, m, _ptr(points, torch.float32, "points"),
+          _ptr(c, torch.uint8, "c"), _ptr(gy, torch.float32, "gy"), B,
+          _ptr(g, torch.float32, "gpoints"), _ptr(work, None, "work"), nbytes, _stream())
+    return g
 
 
 def demap(m: int, method: int, y, no, out=None):
@@ -400,16 +430,32 @@ def ndm_forward(params, y, no, out=None):
     return L
 
 
-def ndm_backward(params, y, no, gllr, out=None, work=None):
-    B, S = y.shape[0], y.shape[1]
-    g = out if out is not None else _empty((NDM_PARAMS,), torch.float32, y.device)
+def ndm_workspace(B: int, S: int) -> int:
     n = ctypes.c_size_t()
     _call("lsim_ndm_workspace", B, S, ctypes.byref(n))
-    work, nbytes = _work(n.value, y.device, work)
+    return n.value
+
+
+def points_workspace(code: Code, m: int, B: int) -> int:
+    n = ctypes.c_size_t()
+    _call("lsim_points_workspace", code.handle, m, B, ctypes.byref(n))
+    return n.value
+
+
+def ndm_backward(params, y, no, gllr, out=None, work=None, gy=None):
+    """dLoss/dparams; with ``gy`` (f32[B][S][2], or True to allocate) also
+    dLoss/dy, returned as a second value."""
+    B, S = y.shape[0], y.shape[1]
+    g = out if out is not None else _empty((NDM_PARAMS,), torch.float32, y.device)
+    if gy is True:
+        gy = _empty((B, S, 2), torch.float32, y.device)
+    work, nbytes = _work(ndm_workspace(B, S), y.device, work)
     _call("lsim_ndm_backward", _ptr(params, torch.float32, "params"), _ptr(y, torch.float32, "y"),
           _ptr(no, torch.float32, "no"), _ptr(gllr, torch.float32, "gllr"), B, S,
-          _ptr(g, torch.float32, "gparams"), _ptr(work, None, "work"), nbytes, _stream())
-    return g
+          _ptr(g, torch.float32, "gparams"),
+          _ptr(gy, torch.float32, "gy") if gy is not None else None,
+          _ptr(work, None, "work"), nbytes, _stream())
+    return (g, gy) if gy is not None else g
 
 
 def bce_grad(lpost, c, scale: float, want_loss: bool = True, g=None, loss=None, work=None):
@@ -469,6 +515,9 @@ class NDMFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gllr):
         params, y, no = ctx.saved_tensors
+        if ctx.needs_input_grad[1]:
+            gp, gy = ndm_backward(params, y, no, gllr.contiguous(), gy=True)
+            return gp, gy, None
         return ndm_backward(params, y, no, gllr.contiguous()), None, None
 
 

@@ -365,6 +365,44 @@ lsim_status lsim_map_awgn(const lsim_code* code, int bits_per_sym, const uint8_t
       "map_awgn");
 }
 
+lsim_status lsim_map_points(const lsim_code* code, int bits_per_sym, const float* d_points,
+                            const uint8_t* d_c, const float* d_no, uint64_t seed, int64_t cw0,
+                            int64_t B, float* d_y, lsim_stream stream) {
+  if (!code || !d_points || !d_c || !d_no || !d_y || B < 1 || cw0 < 0)
+    return fail(LSIM_E_INVAL, "bad map_points arguments");
+  const int m = bits_per_sym;
+  if (m < 1 || m > 6) return fail(LSIM_E_UNSUPPORTED, "bits_per_sym must be 1..6");
+  if (code->dev.e_tx % m) return fail(LSIM_E_INVAL, "e_tx is not a multiple of bits_per_sym");
+  if (((uintptr_t)d_y) & 7) return fail(LSIM_E_INVAL, "d_y must be 8-byte aligned");
+  return dev_status(lsim::launch_map_points(code->dev, m, d_points, d_c, d_no, seed, cw0, B, d_y,
+                                            as_stream(stream)),
+                    "map_points");
+}
+
+lsim_status lsim_points_workspace(const lsim_code* code, int bits_per_sym, int64_t B,
+                                  size_t* bytes) {
+  if (!code || !bytes || B < 1 || bits_per_sym < 1 || bits_per_sym > 6)
+    return fail(LSIM_E_INVAL, "bad workspace query");
+  *bytes = lsim::points_work_bytes(code->dev, bits_per_sym, B);
+  return LSIM_OK;
+}
+
+lsim_status lsim_points_grad(const lsim_code* code, int bits_per_sym, const float* d_points,
+                             const uint8_t* d_c, const float* d_gy, int64_t B, float* d_gpoints,
+                             void* d_work, size_t work_bytes, lsim_stream stream) {
+  if (!code || !d_points || !d_c || !d_gy || !d_gpoints || B < 1)
+    return fail(LSIM_E_INVAL, "bad points_grad arguments");
+  const int m = bits_per_sym;
+  if (m < 1 || m > 6) return fail(LSIM_E_UNSUPPORTED, "bits_per_sym must be 1..6");
+  if (code->dev.e_tx % m) return fail(LSIM_E_INVAL, "e_tx is not a multiple of bits_per_sym");
+  if (((uintptr_t)d_gy) & 7) return fail(LSIM_E_INVAL, "d_gy must be 8-byte aligned");
+  if (!d_work || work_bytes < lsim::points_work_bytes(code->dev, m, B))
+    return fail(LSIM_E_NOMEM, "workspace smaller than lsim_points_workspace()");
+  return dev_status(lsim::launch_points_grad(code->dev, m, d_points, d_c, d_gy, B, d_gpoints,
+                                             d_work, as_stream(stream)),
+                    "points_grad");
+}
+
 static lsim_status check_demap(int m, int method, const void* y, const float* no, int64_t B,
                                int64_t S, const void* out) {
   if (!y || !no || !out || B < 1 || S < 1) return fail(LSIM_E_INVAL, "bad demap arguments");
@@ -716,12 +754,13 @@ lsim_status lsim_ndm_workspace(int64_t B, int64_t S, size_t* bytes) {
 
 lsim_status lsim_ndm_backward(const float* d_params, const float* d_y, const float* d_no,
                               const float* d_gllr, int64_t B, int64_t S, float* d_gparams,
-                              void* d_work, size_t work_bytes, lsim_stream stream) {
+                              float* d_gy, void* d_work, size_t work_bytes, lsim_stream stream) {
   if (!d_params || !d_y || !d_no || !d_gllr || !d_gparams || B < 1 || S < 1)
     return fail(LSIM_E_INVAL, "bad ndm_backward arguments");
+  if (((uintptr_t)d_gy) & 7) return fail(LSIM_E_INVAL, "d_gy must be 8-byte aligned");
   if (!d_work || work_bytes < lsim::ndm_work_bytes(B, S))
     return fail(LSIM_E_NOMEM, "workspace smaller than lsim_ndm_workspace()");
-  return dev_status(lsim::launch_ndm_backward(d_params, d_y, d_no, d_gllr, B, S, d_gparams,
+  return dev_status(lsim::launch_ndm_backward(d_params, d_y, d_no, d_gllr, B, S, d_gparams, d_gy,
                                               d_work, as_stream(stream)),
                     "ndm_backward");
 }

@@ -19,7 +19,9 @@
 // the K axis.  db2, db1, dW1, dW3, db3 are summed per lane over its symbols
 // and across the 16 lanes of a row group at the end.  Every wavefront writes
 // one partial-gradient row; rows are then summed in a fixed order, so the
-// result is deterministic.
+// result is deterministic.  On request the gradient with respect to the
+// received symbol, dy = W1[:, 0:2]^T D1, comes out of one more product per
+// tile whose weight operand is W1's first two columns padded to 16 rows.
 #include <hip/hip_runtime.h>
 
 #include "lsim_internal.h"
@@ -112,13 +114,16 @@ constexpr int kTS = 32;                  // symbols per wavefront step
 constexpr int kPW = H + 4;               // LDS pitch of W2 and W2^T
 constexpr int kPS = kTS + 4;             // LDS pitch of the per-wave transposes
 
+constexpr int kW1Rows = 16;              // W1 columns 0, 1 as rows, zero-padded
+
 __host__ __device__ constexpr size_t ndm_bwd_lds() {
-  return (size_t)(2 * H * kPW + kBwdWaves * 2 * H * kPS) * 4;
+  return (size_t)(2 * H * kPW + kBwdWaves * 2 * H * kPS + kW1Rows * kPW) * 4;
 }
 
 __global__ __launch_bounds__(kBwdThreads) void ndm_backward_kernel(
     const float* __restrict__ P, const float* __restrict__ y, const float* __restrict__ no,
-    const float* __restrict__ gllr, int64_t B, int64_t S, float* __restrict__ part) {
+    const float* __restrict__ gllr, int64_t B, int64_t S, float* __restrict__ part,
+    float* __restrict__ gy) {
   extern __shared__ __align__(16) float sm[];
   float* w2s = sm;               // W2[out][in], pitch kPW
   float* w2t = sm + H * kPW;     // W2^T[in][out]
@@ -126,11 +131,16 @@ __global__ __launch_bounds__(kBwdThreads) void ndm_backward_kernel(
   const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
   float* h1u = sm + 2 * H * kPW + wave * 2 * H * kPS;  // H1[in][symbol]
   float* d2u = h1u + H * kPS;                          // D2[out][symbol]
+  float* w1p = sm + 2 * H * kPW + kBwdWaves * 2 * H * kPS;  // [k][unit] = W1[unit][k], k < 2
   for (int t = threadIdx.x; t < H * H; t += kBwdThreads) {
     const int o = t >> 6, i = t & 63;
     const float w = P[OW2 + t];
     w2s[o * kPW + i] = w;
     w2t[i * kPW + o] = w;
+  }
+  for (int t = threadIdx.x; t < kW1Rows * H; t += kBwdThreads) {
+    const int k = t >> 6, unit = t & 63;
+    w1p[k * kPW + unit] = k < 2 ? P[OW1 + 3 * unit + k] : 0.f;
   }
   __syncthreads();
 
@@ -239,10 +249,28 @@ __global__ __launch_bounds__(kBwdThreads) void ndm_backward_kernel(
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const float d = h1[u][t][v] > 0.f ? d1[u][t][v] : 0.f;
+          d1[u][t][v] = d;
           pb1[u][v] += d;
 #pragma unroll
           for (int k = 0; k < 3; ++k) pw1[u][k][v] += d * xk[t][k];
         }
+    if (gy) {
+      // rows 0, 1 of W1[:, 0:2]^T D1: lanes 0..15 hold (dRe y, dIm y)
+      f4 dx[2] = {zero, zero};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const f4 w = *reinterpret_cast<const f4*>(w1p + c * kPW + 16 * u + 4 * g);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int t = 0; t < 2; ++t) dx[t] = mfma(w[v], d1[u][t][v], dx[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int64_t sym = st * kTS + 16 * t + c;
+        if (g == 0 && sym < n) reinterpret_cast<float2*>(gy)[sym] = make_float2(dx[t][0], dx[t][1]);
+      }
+    }
     // transpose H1 and D2 through this wavefront's LDS tiles
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -425,13 +453,13 @@ hipError_t launch_ndm_forward(const float* params, const float* y, const float* 
 
 hipError_t launch_ndm_backward(const float* params, const float* y, const float* no,
                                const float* gllr, int64_t B, int64_t S, float* gparams,
-                               void* work, hipStream_t s) {
+                               float* gy, void* work, hipStream_t s) {
   const int nb = ndm_bwd_blocks(B * S);
   const int rows = nb * kBwdWaves;
   float* part = reinterpret_cast<float*>(work);
   hipError_t e = ensure_dyn_lds((const void*)ndm_backward_kernel, ndm_bwd_lds());
   if (e != hipSuccess) return e;
-  ndm_backward_kernel<<<nb, kBwdThreads, ndm_bwd_lds(), s>>>(params, y, no, gllr, B, S, part);
+  ndm_backward_kernel<<<nb, kBwdThreads, ndm_bwd_lds(), s>>>(params, y, no, gllr, B, S, part, gy);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   float* slices = part + (size_t)rows * NP;

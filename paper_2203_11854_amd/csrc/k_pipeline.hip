@@ -10,8 +10,6 @@ namespace lsim {
 
 namespace {
 
-constexpr float kTwoPow32Inv = 2.3283064365386963e-10f;  // 2^-32
-
 // ----------------------------------------------------------------- source
 
 // 32 information bits of codeword cw, word w (bit i of the word is
@@ -186,11 +184,8 @@ __device__ __forceinline__ float qam_inv_scale(int h) {
 // words (xa, xb).
 __device__ __forceinline__ float2 map_symbol(int m, const uint8_t* bits, int s, uint32_t xa,
                                              uint32_t xb, float sig) {
-  const float ua = fmaf((float)xa, kTwoPow32Inv, kTwoPow32Inv);
-  const float ub = (float)xb * kTwoPow32Inv;
-  const float rho = sqrtf(-2.0f * logf(ua));
-  float sn, cs;
-  sincospif(2.0f * ub, &sn, &cs);
+  const Polar bm = box_muller(xa, xb);
+  const float rho = bm.rho, sn = bm.sn, cs = bm.cs;
   float xr, xi;
   if (m == 1) {
     xr = 1.0f - 2.0f * (float)bits[s];

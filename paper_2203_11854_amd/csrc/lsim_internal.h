@@ -136,11 +136,18 @@ hipError_t launch_ndm_forward(const float* params, const float* y, const float* 
                               int64_t S, float* llr, hipStream_t s);
 hipError_t launch_ndm_backward(const float* params, const float* y, const float* no,
                                const float* gllr, int64_t B, int64_t S, float* gparams,
-                               void* work, hipStream_t s);
+                               float* gy, void* work, hipStream_t s);
 size_t bce_work_bytes(int64_t B, int64_t n);
 hipError_t launch_bce_grad(const float* lpost, const uint8_t* c, int64_t c_stride, int64_t B,
                            int64_t n, float scale, float* g, float* loss, void* work,
                            hipStream_t s);
+// Trainable constellation (k_const.hip)
+hipError_t launch_map_points(const DevCode& c, int m, const float* pts, const uint8_t* cw,
+                             const float* no, uint64_t seed, int64_t cw0, int64_t B, float* y,
+                             hipStream_t s);
+size_t points_work_bytes(const DevCode& c, int m, int64_t B);
+hipError_t launch_points_grad(const DevCode& c, int m, const float* pts, const uint8_t* cw,
+                              const float* gy, int64_t B, float* gp, void* work, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr,
                        float b1, float b2, float eps, int step, hipStream_t s);
 

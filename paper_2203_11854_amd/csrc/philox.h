@@ -34,4 +34,21 @@ __device__ __forceinline__ U4 philox_at(uint64_t seed, uint32_t block, uint64_t 
                   (uint32_t)(seed >> 32));
 }
 
+// Box-Muller pair of standard normals from two Philox words:
+// u_a = (x_a + 1) 2^-32 in (0, 1], u_b = x_b 2^-32; radius sqrt(-2 ln u_a),
+// angle 2 pi u_b.  The normals are rho*cs and rho*sn.
+struct Polar {
+  float rho, sn, cs;
+};
+
+__device__ __forceinline__ Polar box_muller(uint32_t xa, uint32_t xb) {
+  constexpr float kInv32 = 2.3283064365386963e-10f;  // 2^-32
+  const float ua = fmaf((float)xa, kInv32, kInv32);
+  const float ub = (float)xb * kInv32;
+  Polar p;
+  p.rho = sqrtf(-2.0f * logf(ua));
+  sincospif(2.0f * ub, &p.sn, &p.cs);
+  return p;
+}
+
 }  // namespace lsim

@@ -27,7 +27,7 @@ def declared():
 def test_exports_every_declared_symbol():
     lib = L.lib()
     names = declared()
-    assert len(names) >= 29
+    assert len(names) >= 32
     for n in sorted(names):
         assert hasattr(lib, n), n
     assert lib.lsim_version().startswith(b"lsim")
@@ -74,6 +74,13 @@ def test_calls_validate_before_device():
     assert lib.lsim_ndm_forward(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 1, 1,
                                 ctypes.c_void_p(20), None) == INVAL   # misaligned output
     assert "aligned" in lib.lsim_last_error().decode()
+    v = ctypes.c_void_p(16)
+    assert lib.lsim_ndm_backward(v, v, v, v, 1, 1, v, ctypes.c_void_p(20), v, 1 << 30,
+                                 None) == INVAL   # misaligned dL/dy
+    assert lib.lsim_map_points(None, 4, v, v, v, 0, 0, 1, v, None) == INVAL
+    assert lib.lsim_points_grad(None, 4, v, v, v, 1, v, v, 0, None) == INVAL
+    n = ctypes.c_size_t()
+    assert lib.lsim_points_workspace(None, 4, 1, ctypes.byref(n)) == INVAL
 
 
 def test_binding_fails_loudly_without_device_tensors():

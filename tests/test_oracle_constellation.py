@@ -88,3 +88,24 @@ def test_ndm_input_gradient_matches_finite_differences():
 
     assert np.allclose(gy[..., 0], _fd(f_re, y.real.copy()).reshape(B, S), rtol=1e-5, atol=1e-8)
     assert np.allclose(gy[..., 1], _fd(f_im, y.imag.copy()).reshape(B, S), rtol=1e-5, atol=1e-8)
+
+
+def test_keep_mask_drops_symbols_from_the_gradient_only():
+    m, B, S = 4, 2, 5
+    params = _glorot(11)
+    p = oc.qam_points(m)
+    t = rand.bits(12, (B, S * m))
+    n0 = np.array([0.4, 0.7])
+    g = rand.gaussian(13, (B, S)) + 1j * rand.gaussian(14, (B, S))
+    full = oc.loss_and_grads(p, params, t, m, n0, g)
+    same = oc.loss_and_grads(p, params, t, m, n0, g, keep=np.ones((B, S), bool))
+    none = oc.loss_and_grads(p, params, t, m, n0, g, keep=np.zeros((B, S), bool))
+    assert same[0] == full[0] and np.array_equal(same[1], full[1]) and np.array_equal(same[2], full[2])
+    assert none[0] == full[0] and not none[1].any() and not none[2].any()
+    # dropping one symbol removes exactly its own contribution (linearity)
+    keep = np.ones((B, S), bool)
+    keep[1, 3] = False
+    part = oc.loss_and_grads(p, params, t, m, n0, g, keep=keep)
+    only = oc.loss_and_grads(p, params, t, m, n0, g, keep=~keep)
+    assert np.allclose(part[2] + only[2], full[2], atol=1e-15)
+    assert np.allclose(part[1] + only[1], full[1], atol=1e-15)
