@@ -95,6 +95,40 @@ def demap_bruteforce(y: np.ndarray, n0: np.ndarray, m: int, method: str) -> np.n
     return L.reshape(B, S * m)
 
 
+def demap_prior_bruteforce(y: np.ndarray, n0: np.ndarray, m: int, method: str, La: np.ndarray,
+                           extrinsic: bool = False) -> np.ndarray:
+    """Demapper with prior ("Demapper with prior", Sec. III-B): bitwise LLRs
+    ``float64[B][S*m]`` given a-priori LLRs ``La[B][S*m]`` (logits of bit 1)
+    of the symbol's bits, by enumerating all 2^m points.  Each point's
+    metric is ``-|y-x|^2/N0 + sum_j b_j(x) La_j`` (ln P(b_j) = b_j La_j -
+    ln(1 + e^{La_j}); the second term is common to numerator and
+    denominator).
+
+    exact:   L_i = ln sum_{b_i=1} e^{metric} - ln sum_{b_i=0} e^{metric}
+    maxlog:  L_i = max_{b_i=1} metric - max_{b_i=0} metric
+
+    These are a-posteriori LLRs (they include La_i); ``extrinsic`` returns
+    L_i - La_i, the part passed on in iterative demapping and decoding."""
+    pts = constellation(m)
+    lab = labels(m).astype(np.float64)                       # (2^m, m)
+    B, S = y.shape
+    La = np.asarray(La, dtype=np.float64).reshape(B, S, m)
+    n0 = np.asarray(n0, dtype=np.float64).reshape(-1, 1, 1)
+    metric = -np.abs(y[:, :, None] - pts[None, None, :]) ** 2 / n0 + La @ lab.T   # (B, S, 2^m)
+    L = np.empty((B, S, m))
+    for i in range(m):
+        one = lab[:, i] == 1
+        if method == "maxlog":
+            L[:, :, i] = metric[:, :, one].max(-1) - metric[:, :, ~one].max(-1)
+        elif method == "exact":
+            L[:, :, i] = _lse(metric[:, :, one]) - _lse(metric[:, :, ~one])
+        else:
+            raise ValueError(method)
+    if extrinsic:
+        L = L - La
+    return L.reshape(B, S * m)
+
+
 def _lse(a: np.ndarray) -> np.ndarray:
     mx = a.max(-1)
     return mx + np.log(np.exp(a - mx[..., None]).sum(-1))

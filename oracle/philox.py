@@ -19,6 +19,7 @@ Listing 1; it fixes no generator):
   (2, 3) and forms u_a = (x_a + 1) 2^-32 in (0, 1], u_b = x_b 2^-32,
   rho = sqrt(-2 ln u_a), g = rho (cos 2 pi u_b + j sin 2 pi u_b)
   (Box & Muller 1958).
+* stream 2: real normals for a-priori LLRs (``normals_real``).
 """
 from __future__ import annotations
 
@@ -81,3 +82,24 @@ def normals(seed: int, cw0: int, B: int, S: int) -> np.ndarray:
     ub = xb * 2.0 ** -32
     rho = np.sqrt(-2.0 * np.log(ua))
     return rho * np.cos(2 * np.pi * ub) + 1j * rho * np.sin(2 * np.pi * ub)
+
+
+def normals_real(seed: int, cw0: int, B: int, n: int, stream: int = 2) -> np.ndarray:
+    """Real standard normals ``float64[B][n]`` (stream 2: the a-priori LLRs
+    of EXIT simulations).  Entries 4j .. 4j+3 of codeword b come from
+    Philox(key, (j, b, stream)): Box-Muller on words (0, 1) gives entries
+    4j (cosine) and 4j+1 (sine), on words (2, 3) entries 4j+2 and 4j+3, with
+    u_a, u_b as for the channel noise."""
+    k0, k1 = _key(seed)
+    nblk = -(-n // 4)
+    b = (np.arange(B, dtype=np.uint64) + np.uint64(cw0))[:, None]
+    j = np.arange(nblk, dtype=np.uint64)[None, :]
+    x0, x1, x2, x3 = philox4x32_10(j, b & MASK, b >> SH, np.uint64(stream), k0, k1)
+    out = np.empty((B, nblk, 4))
+    for col, (xa, xb) in enumerate(((x0, x1), (x2, x3))):
+        ua = (xa.astype(np.float64) + 1.0) * 2.0 ** -32
+        ub = xb.astype(np.float64) * 2.0 ** -32
+        rho = np.sqrt(-2.0 * np.log(ua))
+        out[:, :, 2 * col] = rho * np.cos(2 * np.pi * ub)
+        out[:, :, 2 * col + 1] = rho * np.sin(2 * np.pi * ub)
+    return out.reshape(B, nblk * 4)[:, :n]
