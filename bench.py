@@ -12,7 +12,8 @@ Printed: one JSON line with the decoded-information throughput (Gbit/s),
 the decoder kernel's roofline position, the oracle's CPU baseline on a
 bounded sample, and secondary legs (int8 offset min-sum, layered NMS on the
 BG1-shaped code, mixed-shape persistent batch, weighted BP fwd/fwd+bwd,
-trainable constellation with the neural demapper).
+trainable constellation with the neural demapper, EXIT curves and
+iterative demapping and decoding).
 """
 from __future__ import annotations
 
@@ -75,8 +76,8 @@ def parse():
                     help="also time the oracle in a process pool over the host's cores")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB of a plain device copy run first (reference for HBM counters)")
-    ap.add_argument("--legs", default="bler,oms,nms,mixed,wbp,const",
-                    help="secondary legs: bler,oms,nms,mixed,wbp,const (empty = none)")
+    ap.add_argument("--legs", default="bler,oms,nms,mixed,wbp,const,exit",
+                    help="secondary legs: bler,oms,nms,mixed,wbp,const,exit (empty = none)")
     return ap.parse_args()
 
 
@@ -238,6 +239,9 @@ def main():
     if "wbp" in legs:
         extra["wbp_ndm_bg2"] = {f"T{t}": wbp_leg(torch, lsim, dev, code, qb, t) for t in (10, 20)}
         log(f"[bench] wbp: {extra['wbp_ndm_bg2']}")
+    if "exit" in legs:
+        extra["exit_bicm_id_bg2"] = exit_leg(torch, lsim, dev, code, qb)
+        log(f"[bench] exit: {extra['exit_bicm_id_bg2']}")
     if "const" in legs:
         extra["constellation_ndm_bg2"] = const_leg(torch, lsim, dev, code, qb)
         log(f"[bench] constellation: {extra['constellation_ndm_bg2']}")
@@ -457,6 +461,105 @@ def wbp_leg(torch, lsim, dev, code, qb, T=10):
             "plain_spa_ms": round(ms_plain, 4),
             "plain_spa_gbps": round(info / (ms_plain * 1e-3) / 1e9, 3),
             "loss_after_timing_steps": round(l0, 6)}
+
+
+def exit_leg(torch, lsim, dev, code, qb):
+    """EXIT chart simulation and iterative demapping and decoding on the
+    bg2 code with Gray 16-QAM, batch 4096.
+
+    * Demapper and decoder transfer curves in one batched pass each: the
+      codewords are split over 11 a-priori strengths sigma_A = 0, 0.6, ..,
+      6 (bin b mod 11); I_A and I_E are measured (per-bin mean of the
+      mutual-information estimate) on the a-priori and extrinsic LLRs.  The
+      demapper sees the channel at Eb/N0 3 dB; the decoder (sum-product,
+      20 iterations) sees only the a-priori LLRs.
+    * BICM-ID: 3 passes of demapper with prior + decoder (20 iterations) +
+      extrinsic at Eb/N0 3 dB against one plain pass and against one
+      60-iteration decoder run on the same data (BLER and time)."""
+    from inputs.workloads import data_seed
+
+    B, m, nb = 4096, 4, 11
+    S = code.e_tx // m
+    seed = data_seed(7, 0)
+    bins = torch.tensor(np.arange(B) % nb, dtype=torch.int32, device=dev)
+    sig_pts = np.linspace(0.0, 6.0, nb)
+    sigma = torch.tensor(sig_pts[np.arange(B) % nb], dtype=torch.float32, device=dev)
+    no = torch.full((B,), float(lsim.ebn0_to_n0(3.0, code.k / code.e_tx, m)), dtype=torch.float32,
+                    device=dev)
+    u = lsim.source_bits(seed, 0, B, code.k, dev)
+    c = lsim.encode(code, u)
+    ctx = c[:, code.tx_lo:]
+    y = lsim.map_awgn(code, m, c, no, seed, 0)
+    la = torch.empty((B, code.e_tx), dtype=torch.float32, device=dev)
+    le = torch.empty_like(la)
+    app = torch.empty((B, code.n_dec), dtype=torch.float32, device=dev)
+    bits = torch.empty((B, code.k), dtype=torch.uint8, device=dev)
+    mi_cw = torch.empty((B,), dtype=torch.float32, device=dev)
+    ia = torch.empty((nb,), dtype=torch.float64, device=dev)
+    ie = torch.empty_like(ia)
+    p = lsim.params(lsim.SPA_F32, iters=20)
+    work = torch.empty(max(1, lsim.decode_workspace(code, p, B)), dtype=torch.uint8, device=dev)
+
+    def demapper_curve():
+        lsim.apriori_llrs(code, c, sigma, seed, 0, out=la)
+        lsim.mutual_info(la, ctx, bins, nb, mi_cw=mi_cw, mi_bins=ia)
+        lsim.demap_prior(m, lsim.DEMAP_EXACT, y, no, la, out=le)
+        lsim.mutual_info(le, ctx, bins, nb, mi_cw=mi_cw, mi_bins=ie)
+
+    def decoder_curve():
+        lsim.apriori_llrs(code, c, sigma, seed, 0, out=la)
+        lsim.mutual_info(la, ctx, bins, nb, mi_cw=mi_cw, mi_bins=ia)
+        lsim.decode(code, la, p, want_bits=False, want_app=True, app=app, work=work)
+        lsim.extrinsic(code, app, la, out=le)
+        lsim.mutual_info(le, ctx, bins, nb, mi_cw=mi_cw, mi_bins=ie)
+
+    demapper_curve()
+    dem = (ia.cpu().numpy(), ie.cpu().numpy())
+    ms_dem = _elapsed(torch, demapper_curve, 5)
+    decoder_curve()
+    dec = (ia.cpu().numpy(), ie.cpu().numpy())
+    ms_dec = _elapsed(torch, decoder_curve, 5)
+
+    prior = torch.zeros((B, code.e_tx), dtype=torch.float32, device=dev)
+    llr = torch.empty_like(prior)
+    counts = torch.zeros((1, 3), dtype=torch.int64, device=dev)
+
+    def bicm(passes):
+        prior.zero_()
+        for i in range(passes):
+            lsim.demap_prior(m, lsim.DEMAP_EXACT, y, no, prior, out=llr)
+            lsim.decode(code, llr, p, want_bits=(i == passes - 1), want_app=(i < passes - 1),
+                        bits=bits, app=app, work=work)
+            if i < passes - 1:
+                lsim.extrinsic(code, app, llr, out=prior)
+
+    def score():
+        counts.zero_()
+        lsim.count_errors(u, bits, counts=counts)
+        cnt = counts.cpu().numpy()[0]
+        return {"bler": round(float(cnt[1] / cnt[2]), 5),
+                "ber": round(float(cnt[0] / (cnt[2] * code.k)), 7)}
+
+    res = {}
+    for passes in (1, 3):
+        bicm(passes)
+        res[f"passes_{passes}"] = {"ms": round(_elapsed(torch, lambda: bicm(passes), 3), 4),
+                                   **score()}
+    # the same 60 decoder iterations in one run, without demapper feedback
+    p60 = lsim.params(lsim.SPA_F32, iters=60)
+    lsim.demap_prior(m, lsim.DEMAP_EXACT, y, no, torch.zeros_like(prior), out=llr)
+    lsim.decode(code, llr, p60, bits=bits, work=work)
+    res["plain_60_iters"] = {"ms": round(_elapsed(torch, lambda: lsim.decode(code, llr, p60, bits=bits,
+                                                                             work=work), 3), 4),
+                             **score()}
+    return {"batch": B, "sigma_a": [round(float(x), 2) for x in sig_pts],
+            "demapper_ebn0_db": 3.0,
+            "demapper_IA": [round(float(x), 5) for x in dem[0]],
+            "demapper_IE": [round(float(x), 5) for x in dem[1]],
+            "decoder_IA": [round(float(x), 5) for x in dec[0]],
+            "decoder_IE": [round(float(x), 5) for x in dec[1]],
+            "demapper_curve_ms": round(ms_dem, 4), "decoder_curve_ms": round(ms_dec, 4),
+            "bicm_id_ebn0_db": 3.0, "bicm_id": res}
 
 
 def const_leg(torch, lsim, dev, code, qb, steps=50):

@@ -161,6 +161,20 @@ enum { LSIM_DEMAP_EXACT = 0, LSIM_DEMAP_MAXLOG = 1 };
 lsim_status lsim_demap(int bits_per_sym, int method, const float* d_y, const float* d_no,
                        int64_t B, int64_t S, float* d_llr, lsim_stream stream);
 
+/*
+ * Demapper with prior (Sec. III-B lists it among the FEC features):
+ * bitwise LLRs given a-priori LLRs d_la f32[B][S*m] (logits of bit 1, the
+ * symbol's bits in mapping order).  Each point's metric is
+ * -|y-x|^2/N0 + sum_j b_j(x) La_j; exact: log-sum-exp over the points with
+ * bit i = 1 minus that over bit i = 0; max-log: max - max.  extrinsic != 0
+ * writes L_i - La_i (computed with bit i's own prior left out of the
+ * metric), else the a-posteriori L_i.  Gray QAM and BPSK as lsim_demap;
+ * d_la and d_llr aligned as lsim_demap's d_llr.
+ */
+lsim_status lsim_demap_prior(int bits_per_sym, int method, const float* d_y, const float* d_no,
+                             const float* d_la, int64_t B, int64_t S, int extrinsic, float* d_llr,
+                             lsim_stream stream);
+
 /* Demapper fused with the int8 quantizer below: d_q i8[B][S*m]. */
 lsim_status lsim_demap_q8(int bits_per_sym, int method, const float* d_y, const float* d_no,
                           int64_t B, int64_t S, float scale, int sat, int8_t* d_q,
@@ -368,6 +382,42 @@ lsim_status lsim_bce_grad(const float* d_lpost, const uint8_t* d_c, int64_t c_st
 lsim_status lsim_adam_step(float* d_p, const float* d_g, float* d_m, float* d_v, int64_t n,
                            float lr, float beta1, float beta2, float eps, int step,
                            lsim_stream stream);
+
+/* ------------------------------------------------------ EXIT pieces */
+
+/*
+ * A-priori LLRs for EXIT chart simulations (Sec. III-B): consistent
+ * Gaussian LLRs La = (2c - 1) sigma^2/2 + sigma n of the transmitted bits
+ * of d_c u8[B][n_mother], sigma = d_sigma[b] per codeword, n standard
+ * normal from Philox stream 2: bits 4j..4j+3 take Box-Muller on words
+ * (0, 1) then (2, 3) of counter (j, cw lo, cw hi, 2) (cosine, sine).
+ * d_la f32[B][e_tx].
+ */
+lsim_status lsim_apriori_llrs(const lsim_code* code, const uint8_t* d_c, const float* d_sigma,
+                              uint64_t seed, int64_t cw0, int64_t B, float* d_la,
+                              lsim_stream stream);
+/*
+ * Mutual information between code bits and LLRs (EXIT charts): per row b,
+ * d_mi_cw[b] = 1 - (1/n) sum_i log2(1 + exp(-(2c_i - 1) L_i)) for
+ * L = d_llr f32 (row stride llr_stride) and c = d_c u8 (row stride
+ * c_stride).  d_mi_bins (nullable) f64[nbins] gets the mean of d_mi_cw over
+ * the rows with d_bin[b] == k (all rows when d_bin is NULL and nbins = 1;
+ * NaN for an empty bin); rows with a bin outside [0, nbins) are left out.
+ * Fixed-order sums (deterministic).
+ */
+lsim_status lsim_mutual_info(const float* d_llr, int64_t llr_stride, const uint8_t* d_c,
+                             int64_t c_stride, int64_t B, int64_t n, const int32_t* d_bin,
+                             int nbins, float* d_mi_cw, double* d_mi_bins, lsim_stream stream);
+/*
+ * Extrinsic output of a decoder on the transmitted bits (iterative
+ * demapping and decoding): d_out[b][i] = L_post[b][tx_lo + i] - L_in[b][i]
+ * for d_app = L_post f32[B][n_dec] (lsim_decode's d_app) and its input
+ * d_llr_in f32[B][e_tx], with L_in as the decoder used it: clamped to
+ * +-llr_max when llr_max > 0 (pass the decoder's llr_max for the float
+ * decoders, 0 for none); 0 where tx_lo + i >= n_dec.
+ */
+lsim_status lsim_extrinsic(const lsim_code* code, const float* d_app, const float* d_llr_in,
+                           float llr_max, int64_t B, float* d_out, lsim_stream stream);
 
 /* ---------------------------------------------------------------- misc */
 

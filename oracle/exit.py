@@ -17,7 +17,9 @@ in the LLR convention of the boundary (logit of bit 1):
 * the mutual information between code bits c and LLRs L is estimated by
   the time average 1 - mean log2(1 + e^{-(2c-1) L});
 * the decoder's extrinsic output on the transmitted bits is
-  L_post - L_in (zero for transmitted bits outside the decoded graph);
+  L_post - L_in with L_in as the decoder used it (clamped to +-20 by the
+  sum-product decoders; zero for transmitted bits outside the decoded
+  graph);
 * iterative demapping and decoding (BICM-ID) feeds the decoder's extrinsic
   back to the demapper as its prior and the demapper's extrinsic to the
   decoder as its input.
@@ -84,15 +86,21 @@ def J_inv(I: float, tol: float = 1e-12) -> float:
     return 0.5 * (lo + hi)
 
 
-def decoder_extrinsic(g: qc.Graph, app: np.ndarray, L_in: np.ndarray) -> np.ndarray:
+def decoder_extrinsic(g: qc.Graph, app: np.ndarray, L_in: np.ndarray,
+                      llr_max: float | None = decoders.LLR_MAX) -> np.ndarray:
     """Extrinsic LLRs ``[B][e_tx]`` of the transmitted bits from the
     decoder's internal APP (``-L_post``, as returned by ``oracle.decoders``)
-    and its input ``L_in[B][e_tx]``."""
+    and its input ``L_in[B][e_tx]``: L_post minus the input as the decoder
+    used it (clamped to +-llr_max, as the sum-product decoders clamp their
+    channel LLRs; None: no clamp)."""
     B = L_in.shape[0]
     out = np.zeros((B, g.e_tx))
     hi = min(g.tx_lo + g.e_tx, g.n_dec)
     n = hi - g.tx_lo
-    out[:, :n] = -np.asarray(app, dtype=np.float64)[:, g.tx_lo:hi] - np.asarray(L_in, dtype=np.float64)[:, :n]
+    lin = np.asarray(L_in, dtype=np.float64)[:, :n]
+    if llr_max is not None:
+        lin = np.clip(lin, -llr_max, llr_max)
+    out[:, :n] = -np.asarray(app, dtype=np.float64)[:, g.tx_lo:hi] - lin
     return out
 
 

@@ -58,6 +58,10 @@ _SIGS = {
     "lsim_encode": [_P, _P, _I64, _P, _P],
     "lsim_map_awgn": [_P, _I, _P, _P, _U64, _I64, _I64, _P, _P],
     "lsim_map_points": [_P, _I, _P, _P, _P, _U64, _I64, _I64, _P, _P],
+    "lsim_demap_prior": [_I, _I, _P, _P, _P, _I64, _I64, _I, _P, _P],
+    "lsim_apriori_llrs": [_P, _P, _P, _U64, _I64, _I64, _P, _P],
+    "lsim_mutual_info": [_P, _I64, _P, _I64, _I64, _I64, _P, _I, _P, _P, _P],
+    "lsim_extrinsic": [_P, _P, _P, _F, _I64, _P, _P],
     "lsim_points_workspace": [_P, _I, _I64, ctypes.POINTER(_SZ)],
     "lsim_points_grad": [_P, _I, _P, _P, _P, _I64, _P, _P, _SZ, _P],
     "lsim_demap": [_I, _I, _P, _P, _I64, _I64, _P, _P],
@@ -226,6 +230,55 @@ def demap(m: int, method: int, y, no, out=None):
     _call("lsim_demap", m, method, _ptr(y, torch.float32, "y"), _ptr(no, torch.float32, "no"), B, S,
           _ptr(L, torch.float32, "llr"), _stream())
     return L
+
+
+def demap_prior(m: int, method: int, y, no, la, extrinsic: bool = True, out=None):
+    """Demapper with prior: extrinsic (default) or a-posteriori LLRs."""
+    B, S = y.shape[0], y.shape[1]
+    L = out if out is not None else _empty((B, S * m), torch.float32, y.device)
+    _call("lsim_demap_prior", m, method, _ptr(y, torch.float32, "y"), _ptr(no, torch.float32, "no"),
+          _ptr(la, torch.float32, "la"), B, S, int(bool(extrinsic)), _ptr(L, torch.float32, "llr"),
+          _stream())
+    return L
+
+
+def apriori_llrs(code: Code, c, sigma, seed: int, cw0: int, out=None):
+    """Consistent Gaussian a-priori LLRs f32[B][e_tx] of the transmitted bits."""
+    B = c.shape[0]
+    la = out if out is not None else _empty((B, code.e_tx), torch.float32, c.device)
+    _call("lsim_apriori_llrs", code.handle, _ptr(c, torch.uint8, "c"),
+          _ptr(sigma, torch.float32, "sigma"), seed, cw0, B, _ptr(la, torch.float32, "la"),
+          _stream())
+    return la
+
+
+def mutual_info(llr, c, bins=None, nbins: int = 1, mi_cw=None, mi_bins=None, want_bins=True):
+    """(per-row MI f32[B], per-bin mean MI f64[nbins] or None); rows of c
+    may be wider than llr's (only the first n columns are read)."""
+    B, n = llr.shape
+    if c.dtype != torch.uint8 or c.stride(1) != 1 or llr.stride(1) != 1:
+        raise LsimError("llr f32 and labels u8 need unit column stride")
+    if mi_cw is None:
+        mi_cw = _empty((B,), torch.float32, llr.device)
+    if want_bins and mi_bins is None:
+        mi_bins = _empty((nbins,), torch.float64, llr.device)
+    _call("lsim_mutual_info", _ptr(llr, torch.float32, "llr"), llr.stride(0),
+          ctypes.c_void_p(c.data_ptr()), c.stride(0), B, n,
+          _ptr(bins, torch.int32, "bins") if bins is not None else None, nbins,
+          _ptr(mi_cw, torch.float32, "mi_cw"),
+          _ptr(mi_bins, torch.float64, "mi_bins") if want_bins else None, _stream())
+    return mi_cw, (mi_bins if want_bins else None)
+
+
+def extrinsic(code: Code, app, llr_in, llr_max: float = 20.0, out=None):
+    """Decoder extrinsic on the transmitted bits: L_post[tx] - L_in, L_in
+    clamped to +-llr_max as the float decoders clamp it (0: no clamp)."""
+    B = llr_in.shape[0]
+    o = out if out is not None else _empty((B, code.e_tx), torch.float32, llr_in.device)
+    _call("lsim_extrinsic", code.handle, _ptr(app, torch.float32, "app"),
+          _ptr(llr_in, torch.float32, "llr_in"), llr_max, B, _ptr(o, torch.float32, "out"),
+          _stream())
+    return o
 
 
 def demap_q8(m: int, method: int, y, no, scale: float = 2.0, sat: int = 31, out=None):

@@ -499,6 +499,51 @@ lsim_status lsim_decode_state(const lsim_code* code, const lsim_decode_params* p
                        work_bytes, stream);
 }
 
+lsim_status lsim_demap_prior(int bits_per_sym, int method, const float* d_y, const float* d_no,
+                             const float* d_la, int64_t B, int64_t S, int extrinsic, float* d_llr,
+                             lsim_stream stream) {
+  lsim_status st = check_demap(bits_per_sym, method, d_y, d_no, B, S, d_llr);
+  if (st != LSIM_OK) return st;
+  if (!d_la) return fail(LSIM_E_INVAL, "null a-priori LLRs");
+  if (!llr_aligned(bits_per_sym, d_llr) || !llr_aligned(bits_per_sym, d_la) || ((uintptr_t)d_y & 7))
+    return fail(LSIM_E_INVAL,
+                "d_llr and d_la must be aligned to 4*m bytes (16 for m=4, 8 for m=2,6), d_y to 8");
+  return dev_status(lsim::launch_demap_prior(bits_per_sym, method == LSIM_DEMAP_EXACT, d_y, d_no,
+                                             d_la, B, S, extrinsic != 0, d_llr, as_stream(stream)),
+                    "demap_prior");
+}
+
+lsim_status lsim_apriori_llrs(const lsim_code* code, const uint8_t* d_c, const float* d_sigma,
+                              uint64_t seed, int64_t cw0, int64_t B, float* d_la,
+                              lsim_stream stream) {
+  if (!code || !d_c || !d_sigma || !d_la || B < 1 || cw0 < 0)
+    return fail(LSIM_E_INVAL, "bad apriori_llrs arguments");
+  return dev_status(lsim::launch_apriori(code->dev, d_c, d_sigma, seed, cw0, B, d_la,
+                                         as_stream(stream)),
+                    "apriori_llrs");
+}
+
+lsim_status lsim_mutual_info(const float* d_llr, int64_t llr_stride, const uint8_t* d_c,
+                             int64_t c_stride, int64_t B, int64_t n, const int32_t* d_bin,
+                             int nbins, float* d_mi_cw, double* d_mi_bins, lsim_stream stream) {
+  if (!d_llr || !d_c || !d_mi_cw || B < 1 || n < 1 || llr_stride < n || c_stride < n)
+    return fail(LSIM_E_INVAL, "bad mutual_info arguments");
+  if (d_mi_bins && (nbins < 1 || nbins > 65535 || (!d_bin && nbins != 1)))
+    return fail(LSIM_E_INVAL, "nbins must be 1..65535 (1 without d_bin)");
+  return dev_status(lsim::launch_mutual_info(d_llr, llr_stride, d_c, c_stride, B, n, d_bin, nbins,
+                                             d_mi_cw, d_mi_bins, as_stream(stream)),
+                    "mutual_info");
+}
+
+lsim_status lsim_extrinsic(const lsim_code* code, const float* d_app, const float* d_llr_in,
+                           float llr_max, int64_t B, float* d_out, lsim_stream stream) {
+  if (!code || !d_app || !d_llr_in || !d_out || B < 1 || !(llr_max >= 0.f))
+    return fail(LSIM_E_INVAL, "bad extrinsic arguments");
+  return dev_status(lsim::launch_extrinsic(code->dev, d_app, d_llr_in, llr_max, B, d_out,
+                                           as_stream(stream)),
+                    "extrinsic");
+}
+
 lsim_status lsim_count_errors(const uint8_t* d_ref, int64_t ref_stride, const uint8_t* d_hat,
                               int64_t B, int64_t k, const int32_t* d_bin, int nbins,
                               int64_t* d_counts, lsim_stream stream) {

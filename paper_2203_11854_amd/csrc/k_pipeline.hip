@@ -5,6 +5,7 @@
 #include "dispatch.h"
 #include "lsim_internal.h"
 #include "philox.h"
+#include "qam.h"
 
 namespace lsim {
 
@@ -167,17 +168,6 @@ __global__ __launch_bounds__(kEncThreads) void encode_kernel(DevCode c, const ui
 }
 
 // ------------------------------------------------------- mapper + channel
-
-// Gray PAM level of h bits (a0 first): (1-2a0)(2^{h-1} - (1-2a1)(...)).
-__device__ __forceinline__ float pam_level(const uint32_t* a, int h) {
-  int v = 1;
-  for (int l = h - 1; l >= 1; --l) v = (1 << (h - l)) - (1 - 2 * (int)a[l]) * v;
-  return (float)((1 - 2 * (int)a[0]) * v);
-}
-
-__device__ __forceinline__ float qam_inv_scale(int h) {
-  return h == 1 ? 0.70710678118654752f : h == 2 ? 0.31622776601683794f : 0.15430334996209191f;
-}
 
 // Symbol s of a codeword whose transmitted bits start at `bits`: Gray QAM
 // (or BPSK) point plus sqrt(N0/2) times the Box-Muller pair of the Philox

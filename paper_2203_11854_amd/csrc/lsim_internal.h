@@ -141,6 +141,16 @@ size_t bce_work_bytes(int64_t B, int64_t n);
 hipError_t launch_bce_grad(const float* lpost, const uint8_t* c, int64_t c_stride, int64_t B,
                            int64_t n, float scale, float* g, float* loss, void* work,
                            hipStream_t s);
+// Demapper with prior, EXIT pieces (k_prior.hip)
+hipError_t launch_demap_prior(int m, bool exact, const float* y, const float* no, const float* la,
+                              int64_t B, int64_t S, bool extrinsic, float* out, hipStream_t s);
+hipError_t launch_apriori(const DevCode& c, const uint8_t* cw, const float* sigma, uint64_t seed,
+                          int64_t cw0, int64_t B, float* la, hipStream_t s);
+hipError_t launch_mutual_info(const float* L, int64_t L_stride, const uint8_t* c, int64_t c_stride,
+                              int64_t B, int64_t n, const int32_t* bin, int nbins, float* mi_cw,
+                              double* mi_bins, hipStream_t s);
+hipError_t launch_extrinsic(const DevCode& c, const float* app, const float* lin, float llr_max,
+                            int64_t B, float* out, hipStream_t s);
 // Trainable constellation (k_const.hip)
 hipError_t launch_map_points(const DevCode& c, int m, const float* pts, const uint8_t* cw,
                              const float* no, uint64_t seed, int64_t cw0, int64_t B, float* y,

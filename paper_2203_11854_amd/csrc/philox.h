@@ -26,7 +26,7 @@ __device__ __forceinline__ U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
 }
 
 // Stream ids of the link's counters.
-enum : uint32_t { kStreamBits = 0, kStreamNoise = 1 };
+enum : uint32_t { kStreamBits = 0, kStreamNoise = 1, kStreamPrior = 2 };
 
 __device__ __forceinline__ U4 philox_at(uint64_t seed, uint32_t block, uint64_t cw,
                                         uint32_t stream) {

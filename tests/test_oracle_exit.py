@@ -140,6 +140,24 @@ def test_decoder_extrinsic_on_tree_code_is_map(base, Z):
     assert np.allclose(Le, map_llr(g, L) - L, rtol=1e-10, atol=1e-10)
 
 
+def test_decoder_extrinsic_excludes_the_clamped_input():
+    # a degree-1 variable node next to a single parity check: its posterior
+    # is its (clamped) input plus the check message, the extrinsic part is
+    # the check message alone, whatever the input's size
+    from oracle import decoders as D
+    g = tiny_graph([[0, 0, 0]], 1)
+    L = np.array([[35.0, 2.0, -1.5], [-50.0, 0.7, 3.0]])
+    app = D.spa_flood(g, -L, iters=1)
+    Le = ox.decoder_extrinsic(g, app, L)
+    lam = np.clip(L, -D.LLR_MAX, D.LLR_MAX)
+    # check-to-variable message of an SPC in the boundary convention
+    for b in range(2):
+        for i in range(3):
+            o = [j for j in range(3) if j != i]
+            r = 2 * np.arctanh(np.prod(np.tanh(-lam[b, o] / 2)))
+            assert abs(Le[b, i] - (-r)) < 1e-9
+
+
 def test_bicm_id_with_gray_qpsk_is_plain_decoding():
     qb, g = graph("small")
     B, m = 3, 2
