@@ -13,7 +13,7 @@ the decoder kernel's roofline position, the oracle's CPU baseline on a
 bounded sample, and secondary legs (int8 offset min-sum, layered NMS on the
 BG1-shaped code, mixed-shape persistent batch, weighted BP fwd/fwd+bwd,
 trainable constellation with the neural demapper, EXIT curves and
-iterative demapping and decoding).
+iterative demapping and decoding, Polar SC / SCL / SCL-CRC).
 """
 from __future__ import annotations
 
@@ -76,8 +76,8 @@ def parse():
                     help="also time the oracle in a process pool over the host's cores")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB of a plain device copy run first (reference for HBM counters)")
-    ap.add_argument("--legs", default="bler,oms,nms,mixed,wbp,const,exit",
-                    help="secondary legs: bler,oms,nms,mixed,wbp,const,exit (empty = none)")
+    ap.add_argument("--legs", default="bler,oms,nms,mixed,wbp,const,exit,polar",
+                    help="secondary legs: bler,oms,nms,mixed,wbp,const,exit,polar (empty = none)")
     return ap.parse_args()
 
 
@@ -242,6 +242,9 @@ def main():
     if "exit" in legs:
         extra["exit_bicm_id_bg2"] = exit_leg(torch, lsim, dev, code, qb)
         log(f"[bench] exit: {extra['exit_bicm_id_bg2']}")
+    if "polar" in legs:
+        extra["polar_n1024_k512"] = polar_leg(torch, lsim, dev)
+        log(f"[bench] polar: {extra['polar_n1024_k512']}")
     if "const" in legs:
         extra["constellation_ndm_bg2"] = const_leg(torch, lsim, dev, code, qb)
         log(f"[bench] constellation: {extra['constellation_ndm_bg2']}")
@@ -461,6 +464,37 @@ def wbp_leg(torch, lsim, dev, code, qb, T=10):
             "plain_spa_ms": round(ms_plain, 4),
             "plain_spa_gbps": round(info / (ms_plain * 1e-3) / 1e9, 3),
             "loss_after_timing_steps": round(l0, 6)}
+
+
+def polar_leg(torch, lsim, dev):
+    """Polar code N = 1024, K = 512 (496 data bits + CRC-16 0x1021),
+    Bhattacharyya construction at 2 dB, QPSK over AWGN, 4096 codewords at
+    Eb/N0 1, 1.5, 2, 2.5 dB (codeword b at point b mod 4): SC, SCL-8 and
+    SCL-8-CRC decode time (one launch, event-timed) and BLER per point."""
+    from inputs.workloads import data_seed
+
+    n, K, r, poly = 10, 512, 16, 0x1021
+    N, D, B, m = 1 << n, K - r, 4096, 2
+    pc = lsim.PolarCode(n, lsim.polar_construct(n, K, 2.0), r, poly)
+    pts = np.array([1.0, 1.5, 2.0, 2.5])
+    bins = np.arange(B) % len(pts)
+    no = torch.tensor(lsim.ebn0_to_n0(pts[bins], D / N, m), dtype=torch.float32, device=dev)
+    tb = torch.tensor(bins, dtype=torch.int32, device=dev)
+    seed = data_seed(8, 0)
+    data = lsim.source_bits(seed, 0, B, D, dev)
+    x = pc.encode(data)
+    y = lsim.map_awgn_bits(m, x, no, seed, 0)
+    llr = lsim.demap(m, lsim.DEMAP_EXACT, y, no)
+    bits = torch.empty((B, D), dtype=torch.uint8, device=dev)
+    out = {"batch": B, "ebn0_db": pts.tolist(), "encode_ms": round(_elapsed(
+        torch, lambda: pc.encode(data, out=x), 5), 4)}
+    for name, L, use in (("sc", 1, False), ("scl8", 8, False), ("scl8_crc", 8, True)):
+        pc.decode(llr, L, use, bits=bits)
+        counts = lsim.count_errors(data, bits, bins=tb, nbins=len(pts)).cpu().numpy()
+        ms = _elapsed(torch, lambda: pc.decode(llr, L, use, bits=bits), 3)
+        out[name] = {"ms": round(ms, 4), "gbps": round(B * D / (ms * 1e-3) / 1e9, 3),
+                     "bler": [round(float(c[1] / c[2]), 5) for c in counts]}
+    return out
 
 
 def exit_leg(torch, lsim, dev, code, qb):

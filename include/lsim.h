@@ -419,6 +419,67 @@ lsim_status lsim_mutual_info(const float* d_llr, int64_t llr_stride, const uint8
 lsim_status lsim_extrinsic(const lsim_code* code, const float* d_app, const float* d_llr_in,
                            float llr_max, int64_t B, float* d_out, lsim_stream stream);
 
+/* ------------------------------------------------------------ Polar */
+
+/*
+ * Polar codes (Sec. III-B lists Polar codes and the SC, SCL and SCL-CRC
+ * decoders; Sec. IV-A names the SCL decoder as a custom-kernel case).
+ * Length N = 2^n (1 <= n <= 10), x = u F^{(x)n} with F = [[1,0],[1,1]]
+ * (natural order, no bit reversal), no rate matching.
+ *
+ * lsim_polar_construct (host only): writes mask u8[N] with 1 at the K most
+ * reliable indices by the Bhattacharyya parameters of the synthetic
+ * channels, z0 = exp(-(K/N) 10^(design_ebn0_db/10)) and z -> (2z - z^2,
+ * z^2) per stage (first stage = most significant index bit); equal values
+ * rank the larger index first.
+ *
+ * lsim_polar_create: mask u8[N] (host, any nonzero = information);
+ * crc_degree r in 0..24 (< K) and crc_poly = the generator's coefficients
+ * below x^r (bit j = x^j; 0 when r = 0).  The K information indices in
+ * increasing order carry K - r data bits then the r CRC bits of the data
+ * (remainder of d(x) x^r mod g(x), first data bit = highest degree, zero
+ * initial value, highest-degree CRC bit first).
+ */
+typedef struct lsim_polar lsim_polar; /* opaque, immutable after create */
+lsim_status lsim_polar_construct(int n, int K, double design_ebn0_db, uint8_t* mask);
+lsim_status lsim_polar_create(int n, const uint8_t* mask, int crc_degree, uint32_t crc_poly,
+                              lsim_polar** out);
+void lsim_polar_destroy(lsim_polar* pc);
+lsim_status lsim_polar_query(const lsim_polar* pc, int* N, int* K, int* crc_degree);
+/* d_data u8[B][K - r] (0/1) -> codewords d_x u8[B][N]. */
+lsim_status lsim_polar_encode(const lsim_polar* pc, const uint8_t* d_data, int64_t B,
+                              uint8_t* d_x, lsim_stream stream);
+/*
+ * SC (list = 1), SCL (list 2, 4, 8) and SCL-CRC (use_crc != 0) decoding of
+ * d_llr f32[B][N] (boundary LLRs of x) into the data bits d_bits
+ * u8[B][K - r].  LLR form with lambda = -L: f(a, b) = sgn(a) sgn(b)
+ * min(|a|, |b|) to the left child, g(a, b, x) = b + (1 - 2x) a to the right
+ * child; a path's metric adds |lambda| at a leaf whose bit disagrees with
+ * [lambda < 0]; at an information leaf the L candidates with the smallest
+ * metric survive (ties: lower parent slot, then bit 0; a parent whose two
+ * children survive keeps bit 0 in its slot and sends bit 1 to the lowest
+ * free slot).  The decision is the slot with the smallest metric (ties:
+ * lowest slot); SCL-CRC takes, in that order, the first slot whose CRC
+ * checks, else the first.  d_pm (nullable) f32[B][list] receives the final
+ * metrics by slot (+inf for unused slots).  One workgroup per codeword
+ * holds the list state in LDS (about N (4 + 6 list) + list K bytes);
+ * LSIM_E_UNSUPPORTED if it exceeds 160 KiB.  use_crc on a code without CRC
+ * -> LSIM_E_INVAL.
+ */
+lsim_status lsim_polar_decode(const lsim_polar* pc, int list, int use_crc, const float* d_llr,
+                              int64_t B, uint8_t* d_bits, float* d_pm, lsim_stream stream);
+
+/*
+ * Mapper + AWGN for rows of bits that are not LDPC codewords (e.g. Polar
+ * codewords): maps bits 0 .. n-1 of each row of d_bits (row stride
+ * `stride` bytes) exactly as lsim_map_awgn maps a codeword's transmitted
+ * bits (same labelling, same Philox counters and Box-Muller noise).
+ * d_y f32[B][n/m][2].
+ */
+lsim_status lsim_map_awgn_bits(int bits_per_sym, const uint8_t* d_bits, int64_t stride, int64_t n,
+                               const float* d_no, uint64_t seed, int64_t cw0, int64_t B,
+                               float* d_y, lsim_stream stream);
+
 /* ---------------------------------------------------------------- misc */
 
 const char* lsim_last_error(void);

@@ -59,6 +59,13 @@ _SIGS = {
     "lsim_map_awgn": [_P, _I, _P, _P, _U64, _I64, _I64, _P, _P],
     "lsim_map_points": [_P, _I, _P, _P, _P, _U64, _I64, _I64, _P, _P],
     "lsim_demap_prior": [_I, _I, _P, _P, _P, _I64, _I64, _I, _P, _P],
+    "lsim_map_awgn_bits": [_I, _P, _I64, _I64, _P, _U64, _I64, _I64, _P, _P],
+    "lsim_polar_construct": [_I, _I, ctypes.c_double, _P],
+    "lsim_polar_create": [_I, _P, _I, ctypes.c_uint32, ctypes.POINTER(_P)],
+    "lsim_polar_destroy": [_P],
+    "lsim_polar_query": [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)],
+    "lsim_polar_encode": [_P, _P, _I64, _P, _P],
+    "lsim_polar_decode": [_P, _I, _I, _P, _I64, _P, _P, _P],
     "lsim_apriori_llrs": [_P, _P, _P, _U64, _I64, _I64, _P, _P],
     "lsim_mutual_info": [_P, _I64, _P, _I64, _I64, _I64, _P, _I, _P, _P, _P],
     "lsim_extrinsic": [_P, _P, _P, _F, _I64, _P, _P],
@@ -222,6 +229,73 @@ def points_grad(code: Code, m: int, points, c, gy, out=None, work=None):
           _ptr(c, torch.uint8, "c"), _ptr(gy, torch.float32, "gy"), B,
           _ptr(g, torch.float32, "gpoints"), _ptr(work, None, "work"), nbytes, _stream())
     return g
+
+
+def map_awgn_bits(m: int, bits, no, seed: int, cw0: int, n: int | None = None, out=None):
+    """Mapper + AWGN on rows of bits (the first n columns of each row)."""
+    B = bits.shape[0]
+    n = bits.shape[1] if n is None else n
+    if bits.dtype != torch.uint8 or bits.stride(1) != 1:
+        raise LsimError("bits must be u8 with unit column stride")
+    y = out if out is not None else _empty((B, n // m, 2), torch.float32, bits.device)
+    _call("lsim_map_awgn_bits", m, ctypes.c_void_p(bits.data_ptr()), bits.stride(0), n,
+          _ptr(no, torch.float32, "no"), seed, cw0, B, _ptr(y, torch.float32, "y"), _stream())
+    return y
+
+
+def polar_construct(n: int, K: int, design_ebn0_db: float):
+    """Information mask (numpy u8[2^n]) by Bhattacharyya parameters."""
+    import numpy as np
+    mask = np.zeros(1 << n, dtype=np.uint8)
+    _call("lsim_polar_construct", n, K, design_ebn0_db, mask.ctypes.data_as(ctypes.c_void_p))
+    return mask
+
+
+class PolarCode:
+    """A Polar code on the current device (lsim_polar_create)."""
+
+    def __init__(self, n: int, mask, crc_degree: int = 0, crc_poly: int = 0):
+        import numpy as np
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        if m.size != (1 << n):
+            raise LsimError("mask must have 2^n entries")
+        h = ctypes.c_void_p()
+        _call("lsim_polar_create", n, m.ctypes.data_as(ctypes.c_void_p), crc_degree, crc_poly,
+              ctypes.byref(h))
+        self._h = h
+        N, K, r = _I(), _I(), _I()
+        _call("lsim_polar_query", h, ctypes.byref(N), ctypes.byref(K), ctypes.byref(r))
+        self.n, self.N, self.K, self.r = n, N.value, K.value, r.value
+        self.D = self.K - self.r
+
+    @property
+    def handle(self):
+        return self._h
+
+    def encode(self, data, out=None):
+        B = data.shape[0]
+        x = out if out is not None else _empty((B, self.N), torch.uint8, data.device)
+        _call("lsim_polar_encode", self._h, _ptr(data, torch.uint8, "data"), B,
+              _ptr(x, torch.uint8, "x"), _stream())
+        return x
+
+    def decode(self, llr, list_size: int = 1, use_crc: bool = False, bits=None, pm=None,
+               want_pm: bool = False):
+        B = llr.shape[0]
+        if bits is None:
+            bits = _empty((B, self.D), torch.uint8, llr.device)
+        if want_pm and pm is None:
+            pm = _empty((B, list_size), torch.float32, llr.device)
+        _call("lsim_polar_decode", self._h, list_size, int(bool(use_crc)),
+              _ptr(llr, torch.float32, "llr"), B, _ptr(bits, torch.uint8, "bits"),
+              _ptr(pm, torch.float32, "pm") if pm is not None else None, _stream())
+        return (bits, pm) if want_pm else bits
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.lsim_polar_destroy(h)
+            self._h = None
 
 
 def demap(m: int, method: int, y, no, out=None):

@@ -544,6 +544,25 @@ lsim_status lsim_extrinsic(const lsim_code* code, const float* d_app, const floa
                     "extrinsic");
 }
 
+lsim_status lsim_map_awgn_bits(int bits_per_sym, const uint8_t* d_bits, int64_t stride, int64_t n,
+                               const float* d_no, uint64_t seed, int64_t cw0, int64_t B,
+                               float* d_y, lsim_stream stream) {
+  if (!d_bits || !d_no || !d_y || B < 1 || n < 1 || stride < n || cw0 < 0 || n > (1 << 30) ||
+      stride > (1 << 30))
+    return fail(LSIM_E_INVAL, "bad map_awgn_bits arguments");
+  const int m = bits_per_sym;
+  if (m != 1 && m != 2 && m != 4 && m != 6)
+    return fail(LSIM_E_UNSUPPORTED, "bits_per_sym must be 1, 2, 4 or 6");
+  if (n % m) return fail(LSIM_E_INVAL, "n is not a multiple of bits_per_sym");
+  // the mapper reads row b's bits at b * n_mother + tx_lo .. + e_tx
+  DevCode dc{};
+  dc.n_mother = (int)stride;
+  dc.tx_lo = 0;
+  dc.e_tx = (int)n;
+  return dev_status(lsim::launch_map_awgn(dc, m, d_bits, d_no, seed, cw0, B, d_y, as_stream(stream)),
+                    "map_awgn_bits");
+}
+
 lsim_status lsim_count_errors(const uint8_t* d_ref, int64_t ref_stride, const uint8_t* d_hat,
                               int64_t B, int64_t k, const int32_t* d_bin, int nbins,
                               int64_t* d_counts, lsim_stream stream) {
@@ -891,3 +910,130 @@ extern "C" lsim_status lsim_link_run(const lsim_link_args* a, lsim_stream stream
                                   a->d_counts, s);
   return dev_status(e, "link_run");
 }
+
+// ------------------------------------------------------------------ Polar
+
+struct lsim_polar {
+  lsim::DevPolar dev{};
+  void* dmem = nullptr;
+  uint32_t poly = 0;
+};
+
+extern "C" {
+
+lsim_status lsim_polar_construct(int n, int K, double design_ebn0_db, uint8_t* mask) {
+  if (n < 1 || n > 10 || K < 1 || K > (1 << n) || !mask || !std::isfinite(design_ebn0_db))
+    return fail(LSIM_E_INVAL, "bad polar_construct arguments");
+  const int N = 1 << n;
+  std::vector<double> z(1, std::exp(-(double)K / N * std::pow(10.0, design_ebn0_db / 10.0)));
+  for (int st = 0; st < n; ++st) {
+    std::vector<double> nz(2 * z.size());
+    for (size_t q = 0; q < z.size(); ++q) {
+#pragma clang fp contract(off)
+      const double a = 2.0 * z[q];
+      const double b = z[q] * z[q];
+      nz[2 * q] = a - b;
+      nz[2 * q + 1] = b;
+    }
+    z.swap(nz);
+  }
+  std::vector<int> order(N);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return z[a] < z[b] || (z[a] == z[b] && a > b);
+  });
+  std::memset(mask, 0, N);
+  for (int k = 0; k < K; ++k) mask[order[k]] = 1;
+  return LSIM_OK;
+}
+
+lsim_status lsim_polar_create(int n, const uint8_t* mask, int crc_degree, uint32_t crc_poly,
+                              lsim_polar** out) {
+  if (!out || !mask || n < 1 || n > 10) return fail(LSIM_E_INVAL, "bad polar_create arguments");
+  *out = nullptr;
+  const int N = 1 << n, r = crc_degree;
+  std::vector<int16_t> info;
+  for (int i = 0; i < N; ++i)
+    if (mask[i]) info.push_back((int16_t)i);
+  const int K = (int)info.size();
+  if (K < 1) return fail(LSIM_E_INVAL, "no information index in the mask");
+  if (r < 0 || r > 24 || r >= K) return fail(LSIM_E_INVAL, "crc_degree must be 0..24 and below K");
+  if (r == 0 ? crc_poly != 0 : (crc_poly >> r) != 0)
+    return fail(LSIM_E_INVAL, "crc_poly must have its bits below x^crc_degree (0 without CRC)");
+  // remainder of x^(D-1-k+r) mod g for data bit k, by running the CRC
+  // register backwards from the last data bit
+  const int D = K - r;
+  std::vector<uint32_t> tab(std::max(D, 1), 0);
+  if (r) {
+    const uint32_t msk = r == 32 ? 0xffffffffu : ((1u << r) - 1);
+    uint32_t v = crc_poly;
+    for (int k = D - 1; k >= 0; --k) {
+      tab[k] = v;
+      const uint32_t fb = (v >> (r - 1)) & 1u;
+      v = (v << 1) & msk;
+      if (fb) v ^= crc_poly;
+    }
+  }
+  auto* pc = new lsim_polar;
+  const size_t o_mask = 0, o_info = (size_t)N, o_tab = ((o_info + 2 * K) + 3) & ~(size_t)3;
+  const size_t bytes = o_tab + tab.size() * 4;
+  std::vector<unsigned char> blob(bytes, 0);
+  std::memcpy(blob.data() + o_mask, mask, N);
+  for (int i = 0; i < N; ++i) blob[o_mask + i] = mask[i] ? 1 : 0;
+  std::memcpy(blob.data() + o_info, info.data(), 2 * (size_t)K);
+  std::memcpy(blob.data() + o_tab, tab.data(), tab.size() * 4);
+  hipError_t e = hipMalloc(&pc->dmem, bytes);
+  if (e == hipSuccess) e = hipMemcpy(pc->dmem, blob.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (pc->dmem) (void)hipFree(pc->dmem);
+    delete pc;
+    return dev_status(e, "polar table upload");
+  }
+  auto* d = reinterpret_cast<unsigned char*>(pc->dmem);
+  pc->dev.n = n;
+  pc->dev.N = N;
+  pc->dev.K = K;
+  pc->dev.r = r;
+  pc->dev.mask = d + o_mask;
+  pc->dev.info = reinterpret_cast<const int16_t*>(d + o_info);
+  pc->dev.crc_tab = reinterpret_cast<const uint32_t*>(d + o_tab);
+  pc->poly = crc_poly;
+  *out = pc;
+  return LSIM_OK;
+}
+
+void lsim_polar_destroy(lsim_polar* pc) {
+  if (!pc) return;
+  if (pc->dmem) (void)hipFree(pc->dmem);
+  delete pc;
+}
+
+lsim_status lsim_polar_query(const lsim_polar* pc, int* N, int* K, int* crc_degree) {
+  if (!pc) return fail(LSIM_E_INVAL, "null polar code");
+  if (N) *N = pc->dev.N;
+  if (K) *K = pc->dev.K;
+  if (crc_degree) *crc_degree = pc->dev.r;
+  return LSIM_OK;
+}
+
+lsim_status lsim_polar_encode(const lsim_polar* pc, const uint8_t* d_data, int64_t B,
+                              uint8_t* d_x, lsim_stream stream) {
+  if (!pc || !d_data || !d_x || B < 1) return fail(LSIM_E_INVAL, "bad polar_encode arguments");
+  return dev_status(lsim::launch_polar_encode(pc->dev, d_data, B, d_x, as_stream(stream)),
+                    "polar_encode");
+}
+
+lsim_status lsim_polar_decode(const lsim_polar* pc, int list, int use_crc, const float* d_llr,
+                              int64_t B, uint8_t* d_bits, float* d_pm, lsim_stream stream) {
+  if (!pc || !d_llr || !d_bits || B < 1) return fail(LSIM_E_INVAL, "bad polar_decode arguments");
+  if (list != 1 && list != 2 && list != 4 && list != 8)
+    return fail(LSIM_E_UNSUPPORTED, "list size must be 1, 2, 4 or 8");
+  if (use_crc && pc->dev.r == 0) return fail(LSIM_E_INVAL, "the code has no CRC");
+  if (lsim::polar_decode_lds(list, pc->dev.N, pc->dev.K) > 160 * 1024)
+    return fail(LSIM_E_UNSUPPORTED, "list state does not fit in LDS");
+  return dev_status(lsim::launch_polar_decode(pc->dev, list, use_crc, d_llr, B, d_bits, d_pm,
+                                              as_stream(stream)),
+                    "polar_decode");
+}
+
+}  // extern "C"

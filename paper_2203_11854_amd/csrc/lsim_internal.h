@@ -141,6 +141,18 @@ size_t bce_work_bytes(int64_t B, int64_t n);
 hipError_t launch_bce_grad(const float* lpost, const uint8_t* c, int64_t c_stride, int64_t B,
                            int64_t n, float scale, float* g, float* loss, void* work,
                            hipStream_t s);
+// Polar codes (k_polar.hip)
+struct DevPolar {
+  int n, N, K, r;
+  const uint8_t* mask;      // N: 1 at information indices
+  const int16_t* info;      // K: information indices, increasing
+  const uint32_t* crc_tab;  // K - r: CRC remainder contributed by each data bit
+};
+size_t polar_decode_lds(int list, int N, int K);
+hipError_t launch_polar_decode(const DevPolar& pc, int list, int use_crc, const float* llr,
+                               int64_t B, uint8_t* bits, float* pm, hipStream_t s);
+hipError_t launch_polar_encode(const DevPolar& pc, const uint8_t* data, int64_t B, uint8_t* x,
+                               hipStream_t s);
 // Demapper with prior, EXIT pieces (k_prior.hip)
 hipError_t launch_demap_prior(int m, bool exact, const float* y, const float* no, const float* la,
                               int64_t B, int64_t S, bool extrinsic, float* out, hipStream_t s);

@@ -27,7 +27,7 @@ def declared():
 def test_exports_every_declared_symbol():
     lib = L.lib()
     names = declared()
-    assert len(names) >= 36
+    assert len(names) >= 44
     for n in sorted(names):
         assert hasattr(lib, n), n
     assert lib.lsim_version().startswith(b"lsim")
@@ -87,3 +87,25 @@ def test_binding_fails_loudly_without_device_tensors():
     import torch
     with pytest.raises(L.LsimError):
         L.quantize(torch.zeros(4))                  # host tensor is rejected
+
+
+@pytest.mark.parametrize("n,K,ebn0", [(3, 4, 0.0), (6, 20, 2.0), (8, 128, 1.0), (10, 512, 2.0),
+                                      (10, 100, -1.0), (5, 32, 3.0)])
+def test_polar_construct_matches_oracle(n, K, ebn0):
+    from oracle import polar as P
+    assert np.array_equal(L.polar_construct(n, K, ebn0), P.info_mask(n, K, ebn0))
+
+
+def test_polar_create_validates_on_host():
+    lib = L.lib()
+    h = ctypes.c_void_p()
+    mask = np.zeros(8, np.uint8)
+    p = mask.ctypes.data_as(ctypes.c_void_p)
+    assert lib.lsim_polar_create(3, p, 0, 0, ctypes.byref(h)) == INVAL   # no information index
+    mask[[3, 5, 6, 7]] = 1
+    assert lib.lsim_polar_create(3, p, 4, 0x3, ctypes.byref(h)) == INVAL  # CRC as long as K
+    assert lib.lsim_polar_create(3, p, 2, 0x4, ctypes.byref(h)) == INVAL  # poly beyond x^r
+    assert lib.lsim_polar_create(11, p, 0, 0, ctypes.byref(h)) == INVAL
+    assert lib.lsim_polar_construct(3, 9, 1.0, p) == INVAL
+    assert lib.lsim_polar_decode(None, 1, 0, ctypes.c_void_p(16), 1, ctypes.c_void_p(16), None,
+                                 None) == INVAL

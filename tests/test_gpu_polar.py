@@ -1,0 +1,128 @@
+"""GPU parity of the Polar encoder and the SC / SCL / SCL-CRC decoders
+against the oracle: codewords bit for bit, decoded bits and every final path
+metric bit for bit against the oracle's float32 mode (f, the metric and
+the decisions are min, negation and single-rounding adds)."""
+import numpy as np
+import pytest
+import torch
+
+from inputs import rand
+from oracle import philox
+from oracle import polar as P
+
+pytestmark = pytest.mark.gpu
+
+lsim = pytest.importorskip("paper_2203_11854_amd")
+dev = "cuda"
+
+CRC16, CRC8 = (16, 0x1021), (8, 0x07)
+
+
+def T(x):
+    return torch.from_numpy(np.ascontiguousarray(x))
+
+
+def _code(n, K, ebn0, crc=(0, 0)):
+    mask = P.info_mask(n, K, ebn0)
+    return mask, lsim.PolarCode(n, mask, crc[0], crc[1])
+
+
+@pytest.mark.parametrize("n,K,crc", [(1, 1, (0, 0)), (3, 8, (0, 0)), (5, 16, CRC8), (8, 100, CRC16),
+                                     (10, 512, CRC16), (10, 1000, (0, 0))])
+def test_encode_exact(n, K, crc):
+    mask, pc = _code(n, K, 1.0, crc)
+    B = 9
+    data = rand.bits(n + K, (B, K - crc[0]))
+    x = pc.encode(T(data).to(dev)).cpu().numpy()
+    assert np.array_equal(x, P.encode(data, mask, crc[1], crc[0]))
+
+
+def test_map_awgn_bits_is_the_codeword_mapper():
+    from helpers import CODES
+    spec, e_tx, _ = CODES["bg2"]
+    qb = spec.load()
+    code = lsim.Code.from_qcbase(qb, e_tx)
+    B = 5
+    c = lsim.encode(code, lsim.source_bits(3, 0, B, code.k, dev))
+    no = torch.full((B,), 0.4, dtype=torch.float32, device=dev)
+    for m in (1, 2, 4):
+        a = lsim.map_awgn(code, m, c, no, 11, 7)
+        b = lsim.map_awgn_bits(m, c[:, code.tx_lo:], no, 11, 7, n=code.e_tx)
+        assert torch.equal(a, b)
+
+
+def _noisy_llrs(x, ebn0, rate, seed, cw0=0):
+    """BPSK boundary LLRs of codewords x at Eb/N0 (float32), from the
+    oracle's Philox normals."""
+    B, N = x.shape
+    n0 = 1.0 / (rate * 10 ** (ebn0 / 10))
+    g = philox.normals_real(seed, cw0, B, N, 1)
+    y = (1.0 - 2.0 * x) + np.sqrt(n0 / 2.0) * g
+    return (-4.0 * y / n0).astype(np.float32)
+
+
+def _check(pc, mask, llr, L, crc, use_crc):
+    r, poly = crc
+    bits, pm = pc.decode(T(llr).to(dev), L, use_crc, want_pm=True)
+    bits, pm = bits.cpu().numpy(), pm.cpu().numpy()
+    nact = min(L, 1 << int(mask.sum()))
+    for b in range(llr.shape[0]):
+        lam = (-llr[b]).astype(np.float32)
+        u, upm, _ = P.scl_decode(lam, mask, L, poly if use_crc else 0, r if use_crc else 0,
+                                 mode="fp32")
+        if L == 1:
+            assert np.array_equal(u, P.sc_decode(lam, mask, "fp32"))
+        assert np.array_equal(bits[b], P.data_bits(u, mask, r)), b
+        assert np.array_equal(pm[b, :nact], upm[:nact].astype(np.float32)), (b, pm[b], upm)
+        assert np.isinf(pm[b, nact:]).all()
+
+
+@pytest.mark.parametrize("n,K,L,crc,use_crc", [
+    (4, 8, 1, (0, 0), False), (5, 16, 2, (0, 0), False), (6, 32, 4, CRC8, True),
+    (7, 64, 8, CRC8, False), (7, 64, 8, CRC8, True), (8, 128, 8, CRC16, True),
+    (10, 512, 1, CRC16, False), (10, 512, 8, CRC16, True), (3, 8, 8, (0, 0), False),
+    (2, 1, 8, (0, 0), False), (1, 2, 4, (0, 0), False)])
+def test_decoders_bit_exact(n, K, L, crc, use_crc):
+    mask, pc = _code(n, K, 1.5, crc)
+    B = 6 if n >= 10 else 12
+    data = rand.bits(100 + n + L, (B, K - crc[0]))
+    x = P.encode(data, mask, crc[1], crc[0])
+    rate = (K - crc[0]) / (1 << n)
+    llr = _noisy_llrs(x, 1.0, rate, 200 + n)
+    _check(pc, mask, llr, L, crc, use_crc)
+
+
+def test_ties_and_zero_llrs():
+    """Zero and repeated LLRs make metric ties; the documented tie rules
+    decide them on both sides."""
+    n, K = 6, 40
+    mask, pc = _code(n, K, 1.0)
+    B = 8
+    llr = np.round(rand.gaussian(300, (B, 1 << n), scale=2.0)).astype(np.float32)
+    llr[:, ::5] = 0.0
+    _check(pc, mask, llr, 8, (0, 0), False)
+    _check(pc, mask, llr, 4, (0, 0), False)
+
+
+def test_full_size_batch_sampled():
+    """The benchmark's code and batch (N 1024, K 512 with CRC-16, list 8,
+    4096 codewords at Eb/N0 1.5 dB): sampled codewords against the oracle;
+    SCL-CRC is at least as good as SCL and SC on the whole batch."""
+    n, K, crc = 10, 512, CRC16
+    mask, pc = _code(n, K, 2.0, crc)
+    B = 4096
+    data = lsim.source_bits(400, 0, B, K - crc[0], dev)
+    x = pc.encode(data)
+    rate = (K - crc[0]) / 1024
+    no = torch.full((B,), float(1.0 / (rate * 10 ** 0.15)), dtype=torch.float32, device=dev)
+    y = lsim.map_awgn_bits(1, x, no, 401, 0)
+    llr = lsim.demap(1, lsim.DEMAP_EXACT, y, no)
+    errs = {}
+    for L, use in ((1, False), (8, False), (8, True)):
+        bits = pc.decode(llr, L, use)
+        errs[(L, use)] = int((bits != data).any(1).sum().item())
+    print("block errors of 4096: SC", errs[(1, False)], "SCL8", errs[(8, False)],
+          "SCL8-CRC", errs[(8, True)])
+    assert errs[(8, True)] <= errs[(8, False)] <= errs[(1, False)]
+    rows = np.array([0, 1, 2047, 4095])
+    _check(pc, mask, llr.cpu().numpy()[rows], 8, crc, True)
