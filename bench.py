@@ -46,7 +46,7 @@ LDS_PEAK_GBS = N_CU * 128 * CLOCK_GHZ
 # Valid only for the kernel sources they were taken on (hash below); any
 # change there reports null until the counters are taken again.
 FLOOD_SPA_TRAFFIC = {"bytes": (30954 * 2 + 5120) * 1024,
-                     "sources": ("k_flood.hip", "spa_math.h", "dispatch.h", "lds.h", "lsim_internal.h"),
+                     "sources": ("k_flood.hip", "spa_math.h", "dispatch.h", "lds.h", "devcode.h"),
                      "sha256_16": "cfa80c3ee9f0ea63"}
 
 # Algorithmic VALU work per edge and round:

@@ -9,40 +9,7 @@
 #include <vector>
 
 #include "../../include/lsim.h"
-
-namespace lsim {
-
-// Device view of a code: the decoded Tanner graph plus encoder tables.  All
-// pointers are device memory owned by the lsim_code.
-struct DevCode {
-  int Z, mb, nb, kb, rows, cols, nnz, E, n_dec, m_dec, k, n_mother, tx_lo, e_tx, family;
-  int max_row_deg, max_col_deg, n_cn_tasks, n_vn_tasks;
-  const int* row_ptr;    // rows+1; entries of base row i: row_ptr[i]..row_ptr[i+1]-1 (row-major)
-  const int* ent_col;    // nnz
-  const int* ent_shift;  // nnz
-  const int* col_ptr;    // cols+1
-  const int* col_ent;    // entry ids of each column, rows ascending
-  const int* cn_tasks;   // (row << 16) | lift0, heaviest first
-  const int* vn_tasks;   // (col << 16) | lift0, heaviest first
-  const int* enc_ptr;    // mb+1; encoder entries of base row i: enc_ptr[i]..enc_ptr[i+1]-1
-  const int2* enc_cz;    // (col * Z, shift) of the row's entries the encoder XORs: information
-                         // columns for the dual-diagonal rows, columns < kb+4 for extension rows
-  const int2* col_edge;  // per column entry (col_ptr order): (e * Z, shift of e)
-  const int2* ent_cz;    // per entry (row-major): (col * Z, shift)
-};
-
-// Read-only device tables through the constant address space: with a
-// wave-uniform index the compiler emits scalar loads (no VALU, no LDS).
-__device__ __forceinline__ int ld_const(const int* p, int i) {
-  return ((const __attribute__((address_space(4))) int*)p)[i];
-}
-__device__ __forceinline__ int2 ld_const(const int2* p, int i) {
-  const __attribute__((address_space(4))) int* q =
-      (const __attribute__((address_space(4))) int*)p;
-  return make_int2(q[2 * i], q[2 * i + 1]);
-}
-
-}  // namespace lsim
+#include "devcode.h"
 
 struct lsim_code {
   lsim::DevCode dev;
