@@ -47,7 +47,7 @@ LDS_PEAK_GBS = N_CU * 128 * CLOCK_GHZ
 # change there reports null until the counters are taken again.
 FLOOD_SPA_TRAFFIC = {"bytes": (30954 * 2 + 5120) * 1024,
                      "sources": ("k_flood.hip", "spa_math.h", "dispatch.h", "lds.h", "devcode.h"),
-                     "sha256_16": "cfa80c3ee9f0ea63"}
+                     "sha256_16": "6e3a9271e9364a42"}
 
 # Algorithmic VALU work per edge and round:
 # sum-product in the sum / difference form: check side 13 simple ops
