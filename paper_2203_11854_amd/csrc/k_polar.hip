@@ -4,20 +4,25 @@
 // algorithm that needs a custom kernel, Sec. IV-A).
 //
 // Decoder: one wavefront per codeword, everything in LDS.  Per list slot p
-// the LLRs of the current node at stage s (2^s values, s < n) sit at
-// alpha[p][2^s .. 2^{s+1}), the partial sums of the pending left child at
-// stage s at bl[p][2^s ..], the transient right-child sums at br[p][2^s ..];
-// the channel LLRs (stage n) are shared.  Leaf i recomputes stages
-// ctz(i) .. 0 (g at the top stage from the left sibling's sums, f below),
-// decides, and merges partial sums upward over its trailing ones.  With
-// lambda = ln P(0)/P(1): f(a, b) = sgn(a) sgn(b) min(|a|, |b|),
-// g(a, b, x) = b + (1 - 2x) a, the path metric adds |lambda| when a bit
-// disagrees with [lambda < 0].  At an information leaf the 2 * nact
-// candidates are ranked by (metric, parent slot, bit) with one shuffle
-// sweep, the best L survive; a parent whose two children survive keeps bit
-// 0 and copies its state to the lowest free slot for bit 1 (only the
-// stages still to be read: alpha above stage ctz(i + 1) and the pending
-// left sums of the set bits of i).  Active slots are always 0 .. nact - 1.
+// the LLRs of the current node at stage s (2^s values, s <= n - 2) sit at
+// alpha[p][2^s .. 2^{s+1}); stage n - 1 is never stored: it is read only
+// while stage n - 2 is computed (four times per codeword) and is formed on
+// the fly from the channel LLRs (f for the first half of the leaves, g with
+// the first half's partial sums for the second).  The partial sums of the
+// pending left child at stage s sit at bl[p][2^s ..]; the channel LLRs are
+// shared.  Leaf i recomputes stages ctz(i) .. 0 (g at the top stage from
+// the left sibling's sums, f below), decides, and writes the merged
+// partial sums of its trailing-ones subtree in one step:
+// x[e] = u_i xor (xor over s < t with bit s of e clear of bl[s][e mod 2^s]),
+// t the number of trailing ones of i.  With lambda = ln P(0)/P(1):
+// f(a, b) = sgn(a) sgn(b) min(|a|, |b|), g(a, b, x) = b + (1 - 2x) a, the
+// path metric adds |lambda| when a bit disagrees with [lambda < 0].  At an
+// information leaf the 2 * nact candidates are ranked by (metric, parent
+// slot, bit) against each other's metrics read with readlane, the best L
+// survive; a parent whose two children survive keeps bit 0 and copies its
+// state to the lowest free slot for bit 1 (only the stages still to be
+// read: alpha above stage ctz(i + 1) and the pending left sums of the set
+// bits of i).  Active slots are always 0 .. nact - 1.
 #include <hip/hip_runtime.h>
 
 #include "dispatch.h"
@@ -33,29 +38,37 @@ struct PolarLds {
   float* ch;
   float* al;
   uint8_t* bl;
-  uint8_t* br;
   uint8_t* ui;
-  int kpad;
+  int astr, kpad;
 };
 
 __host__ __device__ inline int polar_kpad(int K) { return (K + 15) & ~15; }
+// alpha stride per slot: stages 0 .. n-2 need N/2 values (N = 2: stage 0)
+__host__ __device__ inline int polar_astr(int N) { return N >= 4 ? N / 2 : 2; }
 
 template <int L>
 __host__ __device__ inline size_t polar_lds_bytes(int N, int K) {
-  return (size_t)N * 4 + (size_t)L * N * 4 + (size_t)L * N * 2 + (size_t)L * polar_kpad(K);
+  return (size_t)N * 4 + (size_t)L * polar_astr(N) * 4 + (size_t)L * N + (size_t)L * polar_kpad(K);
 }
 
 template <int L>
 __device__ __forceinline__ PolarLds polar_lds(unsigned char* sm, int N, int K) {
   PolarLds s;
+  s.astr = polar_astr(N);
+  s.kpad = polar_kpad(K);
   s.ch = reinterpret_cast<float*>(sm);
   s.al = s.ch + N;
-  s.bl = reinterpret_cast<uint8_t*>(s.al + (size_t)L * N);
-  s.br = s.bl + (size_t)L * N;
-  s.ui = s.br + (size_t)L * N;
-  s.kpad = polar_kpad(K);
+  s.bl = reinterpret_cast<uint8_t*>(s.al + (size_t)L * s.astr);
+  s.ui = s.bl + (size_t)L * N;
   return s;
 }
+
+__device__ __forceinline__ float pol_f(float a, float c) {
+  const float m = fminf(fabsf(a), fabsf(c));
+  return ((a < 0.f) != (c < 0.f)) ? -m : m;
+}
+
+__device__ __forceinline__ float pol_g(float a, float c, uint8_t x) { return x ? c - a : c + a; }
 
 template <int L>
 __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
@@ -74,24 +87,36 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
   if (lane < L) pm[lane] = 0.f;
   __syncthreads();
   int nact = 1, j = 0;
+  const int A = s.astr;
   for (int i = 0; i < N; ++i) {
-    // ---- LLRs down to the leaf
+    // ---- LLRs down to the leaf (stage n - 1 only on the fly when n >= 2)
     const int top = i == 0 ? n - 1 : __builtin_ctz(i);
     for (int st = top; st >= 0; --st) {
+      if (n >= 2 && st == n - 1) continue;
       const int h = 1 << st;
       const int cnt = nact << st;
+      const bool use_g = st == top && i != 0;
       for (int idx = lane; idx < cnt; idx += kPolThreads) {
         const int p = idx >> st, e = idx & (h - 1);
-        const float* par = st + 1 == n ? s.ch : s.al + p * N + 2 * h;
-        const float a = par[e], c = par[e + h];
-        float v;
-        if (st == top && i != 0) {
-          v = s.bl[p * N + h + e] ? c - a : c + a;
+        float a, c;
+        if (st + 1 == n) {  // n == 1: the parent is the channel
+          a = s.ch[e];
+          c = s.ch[e + h];
+        } else if (st + 1 == n - 1) {  // the parent is stage n - 1, formed here
+          const int Q = N >> 1;
+          if (i < Q) {
+            a = pol_f(s.ch[e], s.ch[e + Q]);
+            c = pol_f(s.ch[e + h], s.ch[e + h + Q]);
+          } else {
+            a = pol_g(s.ch[e], s.ch[e + Q], s.bl[p * N + Q + e]);
+            c = pol_g(s.ch[e + h], s.ch[e + h + Q], s.bl[p * N + Q + e + h]);
+          }
         } else {
-          const float m = fminf(fabsf(a), fabsf(c));
-          v = ((a < 0.f) != (c < 0.f)) ? -m : m;
+          const float* par = s.al + p * A + 2 * h;
+          a = par[e];
+          c = par[e + h];
         }
-        s.al[p * N + h + e] = v;
+        s.al[p * A + h + e] = use_g ? pol_g(a, c, s.bl[p * N + h + e]) : pol_f(a, c);
       }
       __syncthreads();
     }
@@ -99,7 +124,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
     const bool info = pc.mask[i] != 0;
     if (!info) {
       if (lane < nact) {
-        const float l = s.al[lane * N + 1];
+        const float l = s.al[lane * A + 1];
         if (l < 0.f) pm[lane] = pm[lane] + (-l);
       }
       __syncthreads();
@@ -108,13 +133,13 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
       float mc = INFINITY;
       if (lane < ncand) {
         const int p = lane >> 1, bit = lane & 1;
-        const float l = s.al[p * N + 1];
+        const float l = s.al[p * A + 1];
         const int hard = l < 0.f;
         mc = bit == hard ? pm[p] : pm[p] + fabsf(l);
       }
       int rank = 0;
       for (int c2 = 0; c2 < ncand; ++c2) {
-        const float m2 = __shfl(mc, c2, 64);
+        const float m2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mc), c2));
         rank += (m2 < mc) || (m2 == mc && c2 < lane);
       }
       const uint64_t sv = __ballot(lane < ncand && rank < L);
@@ -138,12 +163,14 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
       __syncthreads();  // every lane has read pm and the leaf LLRs
       // copies of the state still to be read
       const int t = i + 1 < N ? __builtin_ctz(i + 1) : n;
-      const int alo = 2 << t;  // alpha stages above t
+      const int alo = 2 << t;  // alpha stages above t (stored ones end at A)
+      int mydest = -1;
 #pragma unroll
       for (int p = 0; p < L; ++p) {
         const int d = dest[p];
+        if ((lane >> 1) == p) mydest = d;
         if (d < 0) continue;
-        for (int e = alo + lane; e < N; e += kPolThreads) s.al[d * N + e] = s.al[p * N + e];
+        for (int e = alo + lane; e < A; e += kPolThreads) s.al[d * A + e] = s.al[p * A + e];
         for (int st = 0; st < n; ++st) {
           if (!((i >> st) & 1)) continue;
           const int h = 1 << st;
@@ -152,39 +179,29 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
         for (int e = lane; e < j; e += kPolThreads) s.ui[d * s.kpad + e] = s.ui[p * s.kpad + e];
       }
       // metrics and the new bit of every surviving candidate
-      const float mcand = mc;
       if (lane < ncand && ((sv >> lane) & 1u)) {
         const int p = lane >> 1, bit = lane & 1;
         const bool both = ((sv >> (2 * p)) & 3u) == 3u;
-        const int slot = (both && bit) ? dest[p] : p;
-        pm[slot] = mcand;
+        const int slot = (both && bit) ? mydest : p;
+        pm[slot] = mc;
         s.ui[slot * s.kpad + j] = (uint8_t)bit;
       }
       nact = min(2 * nact, L);
       ++j;
       __syncthreads();
     }
-    // ---- partial sums upward
-    if ((i & 1) == 0) {
-      if (lane < nact) s.bl[lane * N + 1] = info ? s.ui[lane * s.kpad + j - 1] : 0;
-      __syncthreads();
-    } else {
-      if (lane < nact) s.br[lane * N + 1] = info ? s.ui[lane * s.kpad + j - 1] : 0;
-      __syncthreads();
-      for (int st = 0; st < n && ((i >> st) & 1); ++st) {
-        const int h = 1 << st;            // child size
-        const int up = st + 1;             // stage of the merged node
-        if (up == n) break;                // the whole codeword: not needed
-        uint8_t* dst = ((i >> up) & 1) ? s.br : s.bl;
-        const int cnt = nact << up;
-        for (int idx = lane; idx < cnt; idx += kPolThreads) {
-          const int p = idx >> up, e = idx & (2 * h - 1);
-          const uint8_t v = e < h ? (uint8_t)(s.bl[p * N + h + e] ^ s.br[p * N + h + e])
-                                  : s.br[p * N + h + (e - h)];
-          dst[p * N + 2 * h + e] = v;
-        }
-        __syncthreads();
+    // ---- partial sums of the trailing-ones subtree, one step
+    const int t = __builtin_ctz(~i);
+    if (t < n) {
+      const int cnt = nact << t;
+      for (int idx = lane; idx < cnt; idx += kPolThreads) {
+        const int p = idx >> t, e = idx & ((1 << t) - 1);
+        uint8_t x = info ? s.ui[p * s.kpad + j - 1] : 0;
+        for (int st = 0; st < t; ++st)
+          if (!((e >> st) & 1)) x ^= s.bl[p * N + (1 << st) + (e & ((1 << st) - 1))];
+        s.bl[p * N + (1 << t) + e] = x;
       }
+      __syncthreads();
     }
   }
   // ---- selection
