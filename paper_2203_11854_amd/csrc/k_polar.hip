@@ -38,8 +38,8 @@ struct PolarLds {
   float* ch;
   float* al;
   uint8_t* bl;
-  uint8_t* ui;
-  int astr, kpad;
+  uint8_t* rec;  // [K][L]: (parent slot << 1) | bit of every slot at each information leaf
+  int astr;
 };
 
 __host__ __device__ inline int polar_kpad(int K) { return (K + 15) & ~15; }
@@ -55,11 +55,10 @@ template <int L>
 __device__ __forceinline__ PolarLds polar_lds(unsigned char* sm, int N, int K) {
   PolarLds s;
   s.astr = polar_astr(N);
-  s.kpad = polar_kpad(K);
   s.ch = reinterpret_cast<float*>(sm);
   s.al = s.ch + N;
   s.bl = reinterpret_cast<uint8_t*>(s.al + (size_t)L * s.astr);
-  s.ui = s.bl + (size_t)L * N;
+  s.rec = s.bl + (size_t)L * N;
   return s;
 }
 
@@ -88,6 +87,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
   __syncthreads();
   int nact = 1, j = 0;
   const int A = s.astr;
+  const int lgA = N >= 4 ? n - 1 : 1;  // A = 1 << lgA
   for (int i = 0; i < N; ++i) {
     // ---- LLRs down to the leaf (stage n - 1 only on the fly when n >= 2)
     const int top = i == 0 ? n - 1 : __builtin_ctz(i);
@@ -96,27 +96,47 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
       const int h = 1 << st;
       const int cnt = nact << st;
       const bool use_g = st == top && i != 0;
-      for (int idx = lane; idx < cnt; idx += kPolThreads) {
-        const int p = idx >> st, e = idx & (h - 1);
-        float a, c;
-        if (st + 1 == n) {  // n == 1: the parent is the channel
-          a = s.ch[e];
-          c = s.ch[e + h];
-        } else if (st + 1 == n - 1) {  // the parent is stage n - 1, formed here
-          const int Q = N >> 1;
-          if (i < Q) {
-            a = pol_f(s.ch[e], s.ch[e + Q]);
-            c = pol_f(s.ch[e + h], s.ch[e + h + Q]);
-          } else {
-            a = pol_g(s.ch[e], s.ch[e + Q], s.bl[p * N + Q + e]);
-            c = pol_g(s.ch[e + h], s.ch[e + h + Q], s.bl[p * N + Q + e + h]);
+      if (st + 2 < n) {
+        // parent stored at stage st + 1 (the common case): separate f and g
+        // loops, slot rows addressed by shifts
+        if (use_g) {
+          for (int idx = lane; idx < cnt; idx += kPolThreads) {
+            const int p = idx >> st, e = idx & (h - 1);
+            const float* par = s.al + (p << lgA) + 2 * h;
+            s.al[(p << lgA) + h + e] = pol_g(par[e], par[e + h], s.bl[(p << n) + h + e]);
           }
         } else {
-          const float* par = s.al + p * A + 2 * h;
-          a = par[e];
-          c = par[e + h];
+          for (int idx = lane; idx < cnt; idx += kPolThreads) {
+            const int p = idx >> st, e = idx & (h - 1);
+            const float* par = s.al + (p << lgA) + 2 * h;
+            s.al[(p << lgA) + h + e] = pol_f(par[e], par[e + h]);
+          }
         }
-        s.al[p * A + h + e] = use_g ? pol_g(a, c, s.bl[p * N + h + e]) : pol_f(a, c);
+      } else if (st + 2 == n) {
+        // parent is stage n - 1, formed here from the channel (f for the
+        // first half of the leaves, g with the first half's sums after)
+        const int Q = N >> 1;
+        const bool second = i >= Q;
+        for (int idx = lane; idx < cnt; idx += kPolThreads) {
+          const int p = idx >> st, e = idx & (h - 1);
+          float a, c;
+          if (second) {
+            a = pol_g(s.ch[e], s.ch[e + Q], s.bl[(p << n) + Q + e]);
+            c = pol_g(s.ch[e + h], s.ch[e + h + Q], s.bl[(p << n) + Q + e + h]);
+          } else {
+            a = pol_f(s.ch[e], s.ch[e + Q]);
+            c = pol_f(s.ch[e + h], s.ch[e + h + Q]);
+          }
+          s.al[(p << lgA) + h + e] =
+              use_g ? pol_g(a, c, s.bl[(p << n) + h + e]) : pol_f(a, c);
+        }
+      } else {
+        // n == 1: the parent is the channel
+        for (int idx = lane; idx < cnt; idx += kPolThreads) {
+          const int p = idx >> st, e = idx & (h - 1);
+          const float a = s.ch[e], c = s.ch[e + h];
+          s.al[(p << lgA) + h + e] = use_g ? pol_g(a, c, s.bl[(p << n) + h + e]) : pol_f(a, c);
+        }
       }
       __syncthreads();
     }
@@ -142,49 +162,52 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
         const float m2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mc), c2));
         rank += (m2 < mc) || (m2 == mc && c2 < lane);
       }
-      const uint64_t sv = __ballot(lane < ncand && rank < L);
-      // slot plan, the same in every lane
-      int dest[L];
-      uint32_t freem = 0;
+      const uint32_t sv = (uint32_t)__ballot(lane < ncand && rank < L);
+      // parents with a surviving child / with both children surviving
+      uint32_t anyp = 0, bothp = 0;
 #pragma unroll
       for (int p = 0; p < L; ++p) {
-        const bool any = p < nact && ((sv >> (2 * p)) & 3u);
-        if (!any) freem |= 1u << p;
+        const uint32_t two = (sv >> (2 * p)) & 3u;
+        anyp |= (two != 0u) << p;
+        bothp |= (two == 3u) << p;
       }
-#pragma unroll
-      for (int p = 0; p < L; ++p) {
-        dest[p] = -1;
-        if (p < nact && ((sv >> (2 * p)) & 3u) == 3u) {
-          const int d = __builtin_ctz(freem);
-          freem &= freem - 1;
-          dest[p] = d;
-        }
-      }
+      uint32_t freem = ~anyp & ((1u << L) - 1u);
       __syncthreads();  // every lane has read pm and the leaf LLRs
-      // copies of the state still to be read
+      // each parent with two survivors copies the state still to be read
+      // (LLR stages above ctz(i + 1), and here simply its whole row of left
+      // sums) to the lowest free slot, in parent order
       const int t = i + 1 < N ? __builtin_ctz(i + 1) : n;
-      const int alo = 2 << t;  // alpha stages above t (stored ones end at A)
+      const int alo = 2 << t;
       int mydest = -1;
-#pragma unroll
-      for (int p = 0; p < L; ++p) {
-        const int d = dest[p];
+      for (uint32_t mb = bothp; mb; mb &= mb - 1u) {
+        const int p = __builtin_ctz(mb);
+        const int d = __builtin_ctz(freem);
+        freem &= freem - 1u;
         if ((lane >> 1) == p) mydest = d;
-        if (d < 0) continue;
-        for (int e = alo + lane; e < A; e += kPolThreads) s.al[d * A + e] = s.al[p * A + e];
-        for (int st = 0; st < n; ++st) {
-          if (!((i >> st) & 1)) continue;
-          const int h = 1 << st;
-          for (int e = lane; e < h; e += kPolThreads) s.bl[d * N + h + e] = s.bl[p * N + h + e];
+        float* ad = s.al + d * A;
+        const float* as = s.al + p * A;
+        if (lane >= alo && lane < 4 && lane < A) ad[lane] = as[lane];
+        if (A >= 4) {  // 16-byte rows from offset 4 on
+          const int q0 = (alo > 4 ? alo : 4) >> 2;
+          for (int q = q0 + lane; q < (A >> 2); q += kPolThreads)
+            reinterpret_cast<float4*>(ad)[q] = reinterpret_cast<const float4*>(as)[q];
         }
-        for (int e = lane; e < j; e += kPolThreads) s.ui[d * s.kpad + e] = s.ui[p * s.kpad + e];
+        uint8_t* bd = s.bl + d * N;
+        const uint8_t* bs = s.bl + p * N;
+        if (N >= 16) {
+          for (int q = lane; q < (N >> 4); q += kPolThreads)
+            reinterpret_cast<uint4*>(bd)[q] = reinterpret_cast<const uint4*>(bs)[q];
+        } else if (lane < N) {
+          bd[lane] = bs[lane];
+        }
       }
       // metrics and the new bit of every surviving candidate
       if (lane < ncand && ((sv >> lane) & 1u)) {
         const int p = lane >> 1, bit = lane & 1;
-        const bool both = ((sv >> (2 * p)) & 3u) == 3u;
+        const bool both = (bothp >> p) & 1u;
         const int slot = (both && bit) ? mydest : p;
         pm[slot] = mc;
-        s.ui[slot * s.kpad + j] = (uint8_t)bit;
+        s.rec[j * L + slot] = (uint8_t)((p << 1) | bit);
       }
       nact = min(2 * nact, L);
       ++j;
@@ -196,7 +219,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
       const int cnt = nact << t;
       for (int idx = lane; idx < cnt; idx += kPolThreads) {
         const int p = idx >> t, e = idx & ((1 << t) - 1);
-        uint8_t x = info ? s.ui[p * s.kpad + j - 1] : 0;
+        uint8_t x = info ? (uint8_t)(s.rec[(j - 1) * L + p] & 1) : 0;
         for (int st = 0; st < t; ++st)
           if (!((e >> st) & 1)) x ^= s.bl[p * N + (1 << st) + (e & ((1 << st) - 1))];
         s.bl[p * N + (1 << t) + e] = x;
@@ -204,18 +227,29 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
       __syncthreads();
     }
   }
-  // ---- selection
+  // ---- each slot's information bits by tracing its history back, into
+  // the (now unused) LLR area; then CRC checks and the decision
+  uint8_t* tb = reinterpret_cast<uint8_t*>(s.al);  // [L][K] bytes <= L * A * 4
+  if (lane < nact) {
+    int slot = lane;
+    for (int jj = K - 1; jj >= 0; --jj) {
+      const int v = s.rec[jj * L + slot];
+      tb[lane * K + jj] = (uint8_t)(v & 1);
+      slot = v >> 1;
+    }
+  }
+  __syncthreads();
   if (use_crc && r > 0) {
     const int D = K - r;
     for (int p = 0; p < nact; ++p) {
       uint32_t acc = 0;
       for (int k = lane; k < D; k += kPolThreads)
-        if (s.ui[p * s.kpad + k]) acc ^= pc.crc_tab[k];
+        if (tb[p * K + k]) acc ^= pc.crc_tab[k];
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) acc ^= __shfl_xor(acc, off, 64);
       if (lane == 0) {
         uint32_t got = 0;
-        for (int q = 0; q < r; ++q) got = (got << 1) | s.ui[p * s.kpad + D + q];
+        for (int q = 0; q < r; ++q) got = (got << 1) | tb[p * K + D + q];
         pass[p] = got == acc;
       }
     }
@@ -240,7 +274,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
     choice = best >= 0 ? best : first;
   }
   const int D = K - r;
-  for (int k = lane; k < D; k += kPolThreads) bits[b * D + k] = s.ui[choice * s.kpad + k];
+  for (int k = lane; k < D; k += kPolThreads) bits[b * D + k] = tb[choice * K + k];
   if (pm_out && lane < L) pm_out[b * L + lane] = lane < nact ? pm[lane] : INFINITY;
 }
 
