@@ -11,7 +11,8 @@ Philox in-kernel), resident in HBM before the timed region.
 Printed: one JSON line with the decoded-information throughput (Gbit/s),
 the decoder kernel's roofline position, the oracle's CPU baseline on a
 bounded sample, and secondary legs (int8 offset min-sum, layered NMS on the
-BG1-shaped code, mixed-shape persistent batch, weighted BP fwd/fwd+bwd,
+BG1-shaped code, mixed-shape persistent batch, weighted BP fwd/fwd+bwd and
+a trained WBP + demapper pair against plain decoding at equal conditions,
 trainable constellation with the neural demapper, EXIT curves and
 iterative demapping and decoding, Polar SC / SCL / SCL-CRC).
 """
@@ -76,8 +77,9 @@ def parse():
                     help="also time the oracle in a process pool over the host's cores")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB of a plain device copy run first (reference for HBM counters)")
-    ap.add_argument("--legs", default="bler,oms,nms,mixed,wbp,const,exit,polar",
-                    help="secondary legs: bler,oms,nms,mixed,wbp,const,exit,polar (empty = none)")
+    ap.add_argument("--legs", default="bler,oms,nms,mixed,wbp,wbpeval,const,exit,polar",
+                    help="secondary legs: bler,oms,nms,mixed,wbp,wbpeval,const,exit,polar "
+                         "(empty = none)")
     return ap.parse_args()
 
 
@@ -239,6 +241,9 @@ def main():
     if "wbp" in legs:
         extra["wbp_ndm_bg2"] = {f"T{t}": wbp_leg(torch, lsim, dev, code, qb, t) for t in (10, 20)}
         log(f"[bench] wbp: {extra['wbp_ndm_bg2']}")
+    if "wbpeval" in legs:
+        extra["wbp_ndm_trained_vs_spa"] = wbp_eval_leg(torch, lsim, dev, code, qb)
+        log(f"[bench] wbp eval: {extra['wbp_ndm_trained_vs_spa']}")
     if "exit" in legs:
         extra["exit_bicm_id_bg2"] = exit_leg(torch, lsim, dev, code, qb)
         log(f"[bench] exit: {extra['exit_bicm_id_bg2']}")
@@ -679,6 +684,106 @@ def _gray_points(m):
         bits = [(lab >> (m - 1 - i)) & 1 for i in range(m)]
         out[lab] = (level(bits[0::2]) / norm, level(bits[1::2]) / norm)
     return out
+
+
+def wbp_eval_leg(torch, lsim, dev, code, qb, T=10, pre_steps=300, joint_steps=300):
+    """Weighted BP (T rounds) fed by the neural demapper, trained end to end,
+    then compared with plain sum-product decoding at equal conditions.
+
+    Training (16-QAM, batch 2048, Eb/N0 ~ U[1, 4] dB, fresh codewords every
+    step): the demapper alone on the BCE of its LLRs ({pre} steps, Adam
+    1e-2), then demapper and weights jointly on the BCE of the decoder's
+    posteriors ({joint} steps, Adam 1e-3).  Evaluation on other data: 4096
+    codewords at each Eb/N0 of 0:0.5:5 dB, BLER of the trained pair, of
+    sum-product with the exact demapper at T and at 20 iterations, and the
+    Eb/N0 each needs for BLER 1e-2."""
+    from inputs import rand
+    from inputs.workloads import data_seed
+
+    B, m = 2048, 4
+    rate = code.k / code.e_tx
+    r = rand.rng(7007)
+    params = torch.tensor(glorot_params(7008), dtype=torch.float32, device=dev)
+    w = torch.ones((T, code.E), dtype=torch.float32, device=dev)
+    pm, pv = torch.zeros_like(params), torch.zeros_like(params)
+    wm, wv = torch.zeros_like(w), torch.zeros_like(w)
+    y = torch.empty((B, code.e_tx // m, 2), dtype=torch.float32, device=dev)
+    llr = torch.empty((B, code.e_tx), dtype=torch.float32, device=dev)
+    lpost = torch.empty((B, code.n_dec), dtype=torch.float32, device=dev)
+    ckpt = torch.empty((T, B, code.E), dtype=torch.float32, device=dev)
+    gwork = torch.empty(lsim.wbp_workspace(code, T, B), dtype=torch.uint8, device=dev)
+    nwork = torch.empty(lsim.ndm_workspace(B, code.e_tx // m), dtype=torch.uint8, device=dev)
+    seed = data_seed(5, 1)
+    losses = {}
+
+    def batch(step):
+        no = torch.tensor(lsim.ebn0_to_n0(r.uniform(1.0, 4.0, B), rate, m), dtype=torch.float32,
+                          device=dev)
+        c = lsim.encode(code, lsim.source_bits(seed, step * B, B, code.k, dev))
+        lsim.map_awgn(code, m, c, no, seed, step * B, out=y)
+        return c, no
+
+    t0 = time.perf_counter()
+    for step in range(1, pre_steps + 1):
+        c, no = batch(step)
+        lsim.ndm_forward(params, y, no, out=llr)
+        g, loss = lsim.bce_grad(llr, c[:, code.tx_lo:], 1.0 / (B * code.e_tx))
+        gp = lsim.ndm_backward(params, y, no, g, work=nwork)
+        lsim.adam_step(params, gp, pm, pv, step, lr=1e-2)
+        if step in (1, pre_steps):
+            losses[f"demapper_bce_step{step}"] = round(float(loss.item()), 5)
+    pm.zero_()
+    pv.zero_()
+    for step in range(1, joint_steps + 1):
+        c, no = batch(pre_steps + step)
+        lsim.ndm_forward(params, y, no, out=llr)
+        lsim.wbp_forward(code, w, llr, T, 20.0, ckpt=ckpt, lpost=lpost)
+        gpost, loss = lsim.bce_grad(lpost, c, 1.0 / (B * code.n_dec))
+        gllr, gw = lsim.wbp_backward(code, w, llr, ckpt, gpost, T, 20.0, work=gwork)
+        gp = lsim.ndm_backward(params, y, no, gllr, work=nwork)
+        lsim.adam_step(w, gw, wm, wv, step, lr=1e-3)
+        lsim.adam_step(params, gp, pm, pv, step, lr=1e-3)
+        if step in (1, joint_steps):
+            losses[f"posterior_bce_step{step}"] = round(float(loss.item()), 5)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+
+    Be = 4096
+    pts = np.arange(11) * 0.5
+    eseed = data_seed(5, 2)
+    ye = torch.empty((Be, code.e_tx // m, 2), dtype=torch.float32, device=dev)
+    le = torch.empty((Be, code.e_tx), dtype=torch.float32, device=dev)
+    lpe = torch.empty((Be, code.n_dec), dtype=torch.float32, device=dev)
+    bits = torch.empty((Be, code.k), dtype=torch.uint8, device=dev)
+    counts = torch.zeros((1, 3), dtype=torch.int64, device=dev)
+    curves = {"wbp_ndm_trained": [], f"spa_exact_{T}": [], "spa_exact_20": []}
+    spaT = lsim.params(lsim.SPA_F32, iters=T)
+    spa20 = lsim.params(lsim.SPA_F32, iters=20)
+    for j, pt in enumerate(pts):
+        no = torch.full((Be,), float(lsim.ebn0_to_n0(pt, rate, m)), dtype=torch.float32, device=dev)
+        u = lsim.source_bits(eseed + j, 0, Be, code.k, dev)
+        c = lsim.encode(code, u)
+        lsim.map_awgn(code, m, c, no, eseed + j, 0, out=ye)
+
+        def score(name):
+            counts.zero_()
+            lsim.count_errors(u, bits, counts=counts)
+            cnt = counts.cpu().numpy()[0]
+            curves[name].append(round(float(cnt[1] / cnt[2]), 5))
+
+        lsim.ndm_forward(params, ye, no, out=le)
+        lsim.wbp_forward(code, w, le, T, 20.0, lpost=lpe, want_ckpt=False)
+        lsim.hard_bits(lpe, code.k, out=bits)
+        score("wbp_ndm_trained")
+        lsim.demap(m, lsim.DEMAP_EXACT, ye, no, out=le)
+        lsim.decode(code, le, spaT, bits=bits)
+        score(f"spa_exact_{T}")
+        lsim.decode(code, le, spa20, bits=bits)
+        score("spa_exact_20")
+    return {"train_steps": {"demapper_only": pre_steps, "joint": joint_steps},
+            "train_seconds": round(train_s, 2), "losses": losses, "eval_batch_per_point": Be,
+            "ebn0_db": pts.tolist(), "bler": curves,
+            "ebn0_db_at_bler_1e-2": {k: ebn0_at_bler(pts, v) for k, v in curves.items()}}
 
 
 def glorot_params(seed):

@@ -248,6 +248,14 @@ lsim_status lsim_count_errors(const uint8_t* d_ref, int64_t ref_stride, const ui
                               int64_t* d_counts, lsim_stream stream);
 
 /*
+ * Hard decisions of boundary LLRs (e.g. lsim_wbp_forward's posteriors):
+ * d_bits u8[B][k] = [L > 0] for the first k columns of d_llr f32 rows of
+ * `stride` floats.
+ */
+lsim_status lsim_hard_bits(const float* d_llr, int64_t stride, int64_t B, int64_t k,
+                           uint8_t* d_bits, lsim_stream stream);
+
+/*
  * Syndrome weight of hard decisions over the decoded graph: d_c u8[B][n_dec]
  * (row stride `stride` bytes) -> d_unsat i32[B] unsatisfied checks.
  */

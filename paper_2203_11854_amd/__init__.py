@@ -79,6 +79,7 @@ _SIGS = {
     "lsim_decode_state": [_P, ctypes.POINTER(DecodeParams), _P, _I64, _P, _P, _P, _P, _P, _SZ, _P],
     "lsim_count_errors": [_P, _I64, _P, _I64, _I64, _P, _I, _P, _P],
     "lsim_syndrome": [_P, _P, _I64, _I64, _P, _P],
+    "lsim_hard_bits": [_P, _I64, _I64, _I64, _P, _P],
     "lsim_mixed_plan_create": [_P, _P, _I, ctypes.POINTER(DecodeParams), _P, _I, ctypes.POINTER(_P)],
     "lsim_mixed_plan_destroy": [_P],
     "lsim_mixed_workspace": [_P, ctypes.POINTER(_SZ)],
@@ -432,6 +433,17 @@ def count_errors(ref, hat, bins=None, nbins: int = 1, counts=None):
     _call("lsim_count_errors", ctypes.c_void_p(ref.data_ptr()), stride, _ptr(hat, torch.uint8, "hat"),
           B, k, _ptr(bins, torch.int32, "bins"), nbins, _ptr(counts, torch.int64, "counts"), _stream())
     return counts
+
+
+def hard_bits(llr, k: int, out=None):
+    """u8[B][k] = [L > 0] of the first k columns of f32 rows."""
+    B = llr.shape[0]
+    if llr.dtype != torch.float32 or llr.stride(1) != 1:
+        raise LsimError("llr must be f32 with unit column stride")
+    bits = out if out is not None else _empty((B, k), torch.uint8, llr.device)
+    _call("lsim_hard_bits", ctypes.c_void_p(llr.data_ptr()), llr.stride(0), B, k,
+          _ptr(bits, torch.uint8, "bits"), _stream())
+    return bits
 
 
 def syndrome(code: Code, hard):

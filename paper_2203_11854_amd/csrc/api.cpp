@@ -573,6 +573,14 @@ lsim_status lsim_count_errors(const uint8_t* d_ref, int64_t ref_stride, const ui
                     "count_errors");
 }
 
+lsim_status lsim_hard_bits(const float* d_llr, int64_t stride, int64_t B, int64_t k,
+                           uint8_t* d_bits, lsim_stream stream) {
+  if (!d_llr || !d_bits || B < 1 || k < 1 || stride < k)
+    return fail(LSIM_E_INVAL, "bad hard_bits arguments");
+  return dev_status(lsim::launch_hard_bits(d_llr, stride, B, k, d_bits, as_stream(stream)),
+                    "hard_bits");
+}
+
 lsim_status lsim_syndrome(const lsim_code* code, const uint8_t* d_c, int64_t stride, int64_t B,
                           int32_t* d_unsat, lsim_stream stream) {
   if (!code || !d_c || !d_unsat || B < 1 || stride < code->dev.n_dec)

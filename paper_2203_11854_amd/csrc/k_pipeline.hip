@@ -544,6 +544,26 @@ hipError_t launch_count_errors(const uint8_t* ref, int64_t ref_stride, const uin
   return hipGetLastError();
 }
 
+namespace {
+
+// bits[b][v] = [L[b][v] > 0] for the first k columns of each row.
+__global__ __launch_bounds__(256) void hard_bits_kernel(const float* __restrict__ L, int64_t stride,
+                                                        int64_t B, int64_t k,
+                                                        uint8_t* __restrict__ bits) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= B * k) return;
+  const int64_t b = t / k, v = t - b * k;
+  bits[t] = L[b * stride + v] > 0.f ? 1 : 0;
+}
+
+}  // namespace
+
+hipError_t launch_hard_bits(const float* L, int64_t stride, int64_t B, int64_t k, uint8_t* bits,
+                            hipStream_t s) {
+  hard_bits_kernel<<<grid_for(B * k, 256), 256, 0, s>>>(L, stride, B, k, bits);
+  return hipGetLastError();
+}
+
 hipError_t launch_syndrome(const DevCode& c, const uint8_t* cw, int64_t stride, int64_t B,
                            int32_t* unsat, hipStream_t s) {
   syndrome_kernel<<<(unsigned)B, 256, 0, s>>>(c, cw, stride, unsat);

@@ -86,6 +86,8 @@ hipError_t launch_quantize(const float* llr, int64_t n, float scale, int sat, in
 hipError_t launch_count_errors(const uint8_t* ref, int64_t ref_stride, const uint8_t* hat,
                                int64_t B, int64_t k, const int32_t* bin, int nbins,
                                int64_t* counts, hipStream_t s);
+hipError_t launch_hard_bits(const float* L, int64_t stride, int64_t B, int64_t k, uint8_t* bits,
+                            hipStream_t s);
 hipError_t launch_syndrome(const DevCode& c, const uint8_t* cw, int64_t stride, int64_t B,
                            int32_t* unsat, hipStream_t s);
 

@@ -27,7 +27,7 @@ def declared():
 def test_exports_every_declared_symbol():
     lib = L.lib()
     names = declared()
-    assert len(names) >= 44
+    assert len(names) >= 45
     for n in sorted(names):
         assert hasattr(lib, n), n
     assert lib.lsim_version().startswith(b"lsim")

@@ -197,3 +197,13 @@ def test_link_run_equals_separate_calls(name, algo):
     # codewords and channel output kept on chip: same LLRs, bits and counts
     assert torch.equal(lean.u, u) and torch.equal(lean.llr, llr)
     assert torch.equal(lean.bits, bits) and torch.equal(lean.counts, cnt)
+
+
+def test_hard_bits_exact():
+    L = rand.gaussian(61, (7, 300), scale=3.0).astype(np.float32)
+    L[:, ::7] = 0.0
+    L[:, 1::11] = -0.0
+    tl = T(L).to(dev)
+    bits = lsim.hard_bits(tl[:, :250], 200).cpu().numpy()
+    assert np.array_equal(bits, (L[:, :200] > 0).astype(np.uint8))
+
