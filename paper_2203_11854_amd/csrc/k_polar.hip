@@ -3,26 +3,31 @@
 // features, Sec. III-B; the SCL decoder is the paper's example of an
 // algorithm that needs a custom kernel, Sec. IV-A).
 //
-// Decoder: one wavefront per codeword, everything in LDS.  Per list slot p
-// the LLRs of the current node at stage s (2^s values, s <= n - 2) sit at
-// alpha[p][2^s .. 2^{s+1}); stage n - 1 is never stored: it is read only
-// while stage n - 2 is computed (four times per codeword) and is formed on
-// the fly from the channel LLRs (f for the first half of the leaves, g with
-// the first half's partial sums for the second).  The partial sums of the
-// pending left child at stage s sit at bl[p][2^s ..]; the channel LLRs are
-// shared.  Leaf i recomputes stages ctz(i) .. 0 (g at the top stage from
-// the left sibling's sums, f below), decides, and writes the merged
-// partial sums of its trailing-ones subtree in one step:
-// x[e] = u_i xor (xor over s < t with bit s of e clear of bl[s][e mod 2^s]),
-// t the number of trailing ones of i.  With lambda = ln P(0)/P(1):
-// f(a, b) = sgn(a) sgn(b) min(|a|, |b|), g(a, b, x) = b + (1 - 2x) a, the
-// path metric adds |lambda| when a bit disagrees with [lambda < 0].  At an
-// information leaf the 2 * nact candidates are ranked by (metric, parent
-// slot, bit) against each other's metrics read with readlane, the best L
-// survive; a parent whose two children survive keeps bit 0 and copies its
-// state to the lowest free slot for bit 1 (only the stages still to be
-// read: alpha above stage ctz(i + 1) and the pending left sums of the set
-// bits of i).  Active slots are always 0 .. nact - 1.
+// Decoder: one wavefront per codeword, everything in LDS.  The node LLRs
+// of stage s (2^s values) are stored for s < S0 = n - V, per list slot at
+// alpha[p][2^s .. 2^{s+1}); the top V <= 2 stages are never stored: they
+// are read only while stage S0 - 1 is computed (2^{V+1} times per codeword)
+// and are formed there on the fly from the channel LLRs.  A node at stage s
+// is the left (f) or right (g) child of its parent as bit s of the leaf
+// index is 0 or 1.  The partial sums of the pending left child of every
+// stage are bit-packed per slot (stage s in its own words: 1 word for
+// s < 5, 2^{s-5} words above), so a stage's word is written by one lane.
+// Leaf i recomputes the stored stages from min(ctz(i), S0 - 1) down,
+// decides, and writes the merged partial sums of its trailing-ones subtree
+// in one step: x[e] = u_i xor (xor over s < t with bit s of e clear of
+// bl[s][e mod 2^s]), t the number of trailing ones of i, as word
+// operations (for s < 5 the stage's 2^s bits replicated across the word
+// and masked to the positions with bit s clear).  With
+// lambda = ln P(0)/P(1): f(a, b) = sgn(a) sgn(b) min(|a|, |b|),
+// g(a, b, x) = b + (1 - 2x) a, the path metric adds |lambda| when a bit
+// disagrees with [lambda < 0].  At an information leaf the 2 * nact
+// candidates are ranked by (metric, parent slot, bit) against each other's
+// metrics read with readlane, the best L survive; a parent whose two
+// children survive keeps bit 0 and copies its state to the lowest free
+// slot for bit 1 (the stored LLR stages above ctz(i + 1) and its partial-
+// sum words).  Every information leaf records (parent slot, bit) per slot;
+// the paths' bits are traced back at the end.  Active slots are always
+// 0 .. nact - 1.
 #include <hip/hip_runtime.h>
 
 #include "dispatch.h"
@@ -34,32 +39,29 @@ namespace {
 
 constexpr int kPolThreads = 64;
 
-struct PolarLds {
-  float* ch;
-  float* al;
-  uint8_t* bl;
-  uint8_t* rec;  // [K][L]: (parent slot << 1) | bit of every slot at each information leaf
-  int astr;
-};
-
 __host__ __device__ inline int polar_kpad(int K) { return (K + 15) & ~15; }
-// alpha stride per slot: stages 0 .. n-2 need N/2 values (N = 2: stage 0)
-__host__ __device__ inline int polar_astr(int N) { return N >= 4 ? N / 2 : 2; }
-
+// top stages formed on the fly: up to vmax, leaving stage 0 stored
+__host__ __device__ inline int polar_virt(int n, int vmax) { return n - 1 < vmax ? n - 1 : vmax; }
+// alpha row per slot: stored stages 0 .. n-V-1 (stage 0 at offset 1)
+__host__ __device__ inline int polar_astr(int n, int vmax) {
+  const int s0 = n - polar_virt(n, vmax);
+  return s0 >= 1 ? (1 << s0) : 2;
+}
+// list decoders form two stages on the fly (half the LLR state, twice the
+// codewords per CU); SC, whose state is small anyway, forms one
 template <int L>
-__host__ __device__ inline size_t polar_lds_bytes(int N, int K) {
-  return (size_t)N * 4 + (size_t)L * polar_astr(N) * 4 + (size_t)L * N + (size_t)L * polar_kpad(K);
+constexpr int polar_vmax() { return L == 1 ? 1 : 2; }
+// first word of stage s's partial sums, and words per slot
+__host__ __device__ inline int polar_ws(int s) { return s < 5 ? s : 4 + (1 << (s - 5)); }
+__host__ __device__ inline int polar_wrow(int n) {
+  return n - 1 < 5 ? n : polar_ws(n - 1) + (1 << (n - 1 - 5));
 }
 
 template <int L>
-__device__ __forceinline__ PolarLds polar_lds(unsigned char* sm, int N, int K) {
-  PolarLds s;
-  s.astr = polar_astr(N);
-  s.ch = reinterpret_cast<float*>(sm);
-  s.al = s.ch + N;
-  s.bl = reinterpret_cast<uint8_t*>(s.al + (size_t)L * s.astr);
-  s.rec = s.bl + (size_t)L * N;
-  return s;
+__host__ __device__ inline size_t polar_lds_bytes(int n, int K) {
+  const int N = 1 << n;
+  return (size_t)N * 4 + (size_t)L * polar_astr(n, polar_vmax<L>()) * 4 +
+         (size_t)L * polar_wrow(n) * 4 + (size_t)L * polar_kpad(K);
 }
 
 __device__ __forceinline__ float pol_f(float a, float c) {
@@ -67,7 +69,19 @@ __device__ __forceinline__ float pol_f(float a, float c) {
   return ((a < 0.f) != (c < 0.f)) ? -m : m;
 }
 
-__device__ __forceinline__ float pol_g(float a, float c, uint8_t x) { return x ? c - a : c + a; }
+__device__ __forceinline__ float pol_g(float a, float c, uint32_t x) { return x ? c - a : c + a; }
+
+// The 2^S-bit pattern of stage S < 5 replicated across a word, kept at the
+// positions whose bit S is clear.
+template <int S>
+__device__ __forceinline__ uint32_t low_stage_term(uint32_t v) {
+  constexpr int w = 1 << S;
+  constexpr uint32_t clear[5] = {0x55555555u, 0x33333333u, 0x0F0F0F0Fu, 0x00FF00FFu, 0x0000FFFFu};
+  v &= (1u << w) - 1u;
+#pragma unroll
+  for (int k = w; k < 32; k <<= 1) v |= v << k;
+  return v & clear[S];
+}
 
 template <int L>
 __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
@@ -79,63 +93,70 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
   __shared__ float pm[L];
   __shared__ int pass[L];
   const int N = pc.N, n = pc.n, K = pc.K, r = pc.r;
-  const PolarLds s = polar_lds<L>(sm, N, K);
+  const int V = polar_virt(n, polar_vmax<L>()), S0 = n - V;
+  const int A = polar_astr(n, polar_vmax<L>()), lgA = 31 - __builtin_clz(A);
+  const int W = polar_wrow(n);
+  float* ch = reinterpret_cast<float*>(sm);
+  float* al = ch + N;
+  uint32_t* bw = reinterpret_cast<uint32_t*>(al + L * A);
+  uint8_t* rec = reinterpret_cast<uint8_t*>(bw + L * W);  // [K][L]: (parent << 1) | bit
   const int lane = threadIdx.x;
   const int64_t b = blockIdx.x;
-  for (int e = lane; e < N; e += kPolThreads) s.ch[e] = -llr[b * N + e];
+  for (int e = lane; e < N; e += kPolThreads) ch[e] = -llr[b * N + e];
   if (lane < L) pm[lane] = 0.f;
   __syncthreads();
+  auto blbit = [&](int p, int st, int e) -> uint32_t {
+    return (bw[p * W + polar_ws(st) + (e >> 5)] >> (e & 31)) & 1u;
+  };
   int nact = 1, j = 0;
-  const int A = s.astr;
-  const int lgA = N >= 4 ? n - 1 : 1;  // A = 1 << lgA
   for (int i = 0; i < N; ++i) {
-    // ---- LLRs down to the leaf (stage n - 1 only on the fly when n >= 2)
+    // ---- LLRs down to the leaf
     const int top = i == 0 ? n - 1 : __builtin_ctz(i);
-    for (int st = top; st >= 0; --st) {
-      if (n >= 2 && st == n - 1) continue;
+    for (int st = min(top, S0 - 1); st >= 0; --st) {
       const int h = 1 << st;
       const int cnt = nact << st;
-      const bool use_g = st == top && i != 0;
-      if (st + 2 < n) {
-        // parent stored at stage st + 1 (the common case): separate f and g
-        // loops, slot rows addressed by shifts
+      const bool use_g = (i >> st) & 1;
+      if (st + 1 < S0) {  // parent stored
         if (use_g) {
           for (int idx = lane; idx < cnt; idx += kPolThreads) {
             const int p = idx >> st, e = idx & (h - 1);
-            const float* par = s.al + (p << lgA) + 2 * h;
-            s.al[(p << lgA) + h + e] = pol_g(par[e], par[e + h], s.bl[(p << n) + h + e]);
+            const float* par = al + (p << lgA) + 2 * h;
+            al[(p << lgA) + h + e] = pol_g(par[e], par[e + h], blbit(p, st, e));
           }
         } else {
           for (int idx = lane; idx < cnt; idx += kPolThreads) {
             const int p = idx >> st, e = idx & (h - 1);
-            const float* par = s.al + (p << lgA) + 2 * h;
-            s.al[(p << lgA) + h + e] = pol_f(par[e], par[e + h]);
+            const float* par = al + (p << lgA) + 2 * h;
+            al[(p << lgA) + h + e] = pol_f(par[e], par[e + h]);
           }
-        }
-      } else if (st + 2 == n) {
-        // parent is stage n - 1, formed here from the channel (f for the
-        // first half of the leaves, g with the first half's sums after)
-        const int Q = N >> 1;
-        const bool second = i >= Q;
-        for (int idx = lane; idx < cnt; idx += kPolThreads) {
-          const int p = idx >> st, e = idx & (h - 1);
-          float a, c;
-          if (second) {
-            a = pol_g(s.ch[e], s.ch[e + Q], s.bl[(p << n) + Q + e]);
-            c = pol_g(s.ch[e + h], s.ch[e + h + Q], s.bl[(p << n) + Q + e + h]);
-          } else {
-            a = pol_f(s.ch[e], s.ch[e + Q]);
-            c = pol_f(s.ch[e + h], s.ch[e + h + Q]);
-          }
-          s.al[(p << lgA) + h + e] =
-              use_g ? pol_g(a, c, s.bl[(p << n) + h + e]) : pol_f(a, c);
         }
       } else {
-        // n == 1: the parent is the channel
+        // parent at stage S0: the channel (V = 0) or formed from it
+        const bool g1 = (i >> (n - 1)) & 1, g2 = n >= 2 && ((i >> (n - 2)) & 1);
+        const int Q1 = N >> 1, Q2 = N >> 2;
         for (int idx = lane; idx < cnt; idx += kPolThreads) {
           const int p = idx >> st, e = idx & (h - 1);
-          const float a = s.ch[e], c = s.ch[e + h];
-          s.al[(p << lgA) + h + e] = use_g ? pol_g(a, c, s.bl[(p << n) + h + e]) : pol_f(a, c);
+          // value of the stage-(n-1) node at x
+          auto v1 = [&](int x) {
+            return g1 ? pol_g(ch[x], ch[x + Q1], blbit(p, n - 1, x)) : pol_f(ch[x], ch[x + Q1]);
+          };
+          // value of the stage-(n-2) node at x
+          auto v2 = [&](int x) {
+            const float a2 = v1(x), c2 = v1(x + Q2);
+            return g2 ? pol_g(a2, c2, blbit(p, n - 2, x)) : pol_f(a2, c2);
+          };
+          float a, c;
+          if (V == 0) {
+            a = ch[e];
+            c = ch[e + h];
+          } else if (V == 1) {
+            a = v1(e);
+            c = v1(e + h);
+          } else {
+            a = v2(e);
+            c = v2(e + h);
+          }
+          al[(p << lgA) + h + e] = use_g ? pol_g(a, c, blbit(p, st, e)) : pol_f(a, c);
         }
       }
       __syncthreads();
@@ -144,7 +165,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
     const bool info = pc.mask[i] != 0;
     if (!info) {
       if (lane < nact) {
-        const float l = s.al[lane * A + 1];
+        const float l = al[(lane << lgA) + 1];
         if (l < 0.f) pm[lane] = pm[lane] + (-l);
       }
       __syncthreads();
@@ -153,7 +174,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
       float mc = INFINITY;
       if (lane < ncand) {
         const int p = lane >> 1, bit = lane & 1;
-        const float l = s.al[p * A + 1];
+        const float l = al[(p << lgA) + 1];
         const int hard = l < 0.f;
         mc = bit == hard ? pm[p] : pm[p] + fabsf(l);
       }
@@ -173,9 +194,8 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
       }
       uint32_t freem = ~anyp & ((1u << L) - 1u);
       __syncthreads();  // every lane has read pm and the leaf LLRs
-      // each parent with two survivors copies the state still to be read
-      // (LLR stages above ctz(i + 1), and here simply its whole row of left
-      // sums) to the lowest free slot, in parent order
+      // each parent with two survivors copies the state still to be read to
+      // the lowest free slot, in parent order
       const int t = i + 1 < N ? __builtin_ctz(i + 1) : n;
       const int alo = 2 << t;
       int mydest = -1;
@@ -184,56 +204,58 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
         const int d = __builtin_ctz(freem);
         freem &= freem - 1u;
         if ((lane >> 1) == p) mydest = d;
-        float* ad = s.al + d * A;
-        const float* as = s.al + p * A;
+        float* ad = al + (d << lgA);
+        const float* as = al + (p << lgA);
         if (lane >= alo && lane < 4 && lane < A) ad[lane] = as[lane];
         if (A >= 4) {  // 16-byte rows from offset 4 on
           const int q0 = (alo > 4 ? alo : 4) >> 2;
           for (int q = q0 + lane; q < (A >> 2); q += kPolThreads)
             reinterpret_cast<float4*>(ad)[q] = reinterpret_cast<const float4*>(as)[q];
         }
-        uint8_t* bd = s.bl + d * N;
-        const uint8_t* bs = s.bl + p * N;
-        if (N >= 16) {
-          for (int q = lane; q < (N >> 4); q += kPolThreads)
-            reinterpret_cast<uint4*>(bd)[q] = reinterpret_cast<const uint4*>(bs)[q];
-        } else if (lane < N) {
-          bd[lane] = bs[lane];
-        }
+        if (lane < W) bw[d * W + lane] = bw[p * W + lane];
       }
-      // metrics and the new bit of every surviving candidate
+      // metrics and the history of every surviving candidate
       if (lane < ncand && ((sv >> lane) & 1u)) {
         const int p = lane >> 1, bit = lane & 1;
         const bool both = (bothp >> p) & 1u;
         const int slot = (both && bit) ? mydest : p;
         pm[slot] = mc;
-        s.rec[j * L + slot] = (uint8_t)((p << 1) | bit);
+        rec[j * L + slot] = (uint8_t)((p << 1) | bit);
       }
       nact = min(2 * nact, L);
       ++j;
       __syncthreads();
     }
-    // ---- partial sums of the trailing-ones subtree, one step
+    // ---- partial sums of the trailing-ones subtree, one step, as words
     const int t = __builtin_ctz(~i);
     if (t < n) {
-      const int cnt = nact << t;
+      const int lgw = t < 5 ? 0 : t - 5;  // 2^lgw words of stage t per slot
+      const int cnt = nact << lgw;
       for (int idx = lane; idx < cnt; idx += kPolThreads) {
-        const int p = idx >> t, e = idx & ((1 << t) - 1);
-        uint8_t x = info ? (uint8_t)(s.rec[(j - 1) * L + p] & 1) : 0;
-        for (int st = 0; st < t; ++st)
-          if (!((e >> st) & 1)) x ^= s.bl[p * N + (1 << st) + (e & ((1 << st) - 1))];
-        s.bl[p * N + (1 << t) + e] = x;
+        const int p = idx >> lgw, w = idx & ((1 << lgw) - 1);
+        const uint32_t u = info ? (uint32_t)(rec[(j - 1) * L + p] & 1) : 0u;
+        uint32_t x = u ? 0xffffffffu : 0u;
+        const uint32_t* row = bw + p * W;
+        if (t > 0) x ^= low_stage_term<0>(row[0]);
+        if (t > 1) x ^= low_stage_term<1>(row[1]);
+        if (t > 2) x ^= low_stage_term<2>(row[2]);
+        if (t > 3) x ^= low_stage_term<3>(row[3]);
+        if (t > 4) x ^= low_stage_term<4>(row[4]);
+        for (int st = 5; st < t; ++st)
+          if (!((w >> (st - 5)) & 1)) x ^= row[polar_ws(st) + (w & ((1 << (st - 5)) - 1))];
+        if (t < 5) x &= (t == 5 ? 0xffffffffu : ((1u << (1 << t)) - 1u));
+        bw[p * W + polar_ws(t) + w] = x;
       }
       __syncthreads();
     }
   }
   // ---- each slot's information bits by tracing its history back, into
   // the (now unused) LLR area; then CRC checks and the decision
-  uint8_t* tb = reinterpret_cast<uint8_t*>(s.al);  // [L][K] bytes <= L * A * 4
+  uint8_t* tb = reinterpret_cast<uint8_t*>(al);  // [L][K] bytes <= L * A * 4
   if (lane < nact) {
     int slot = lane;
     for (int jj = K - 1; jj >= 0; --jj) {
-      const int v = s.rec[jj * L + slot];
+      const int v = rec[jj * L + slot];
       tb[lane * K + jj] = (uint8_t)(v & 1);
       slot = v >> 1;
     }
@@ -325,7 +347,7 @@ __global__ __launch_bounds__(kEncThreadsP) void polar_encode_kernel(DevPolar pc,
 template <int L>
 hipError_t launch_dec(const DevPolar& pc, const float* llr, int64_t B, int use_crc, uint8_t* bits,
                       float* pm, hipStream_t s) {
-  const size_t lds = polar_lds_bytes<L>(pc.N, pc.K);
+  const size_t lds = polar_lds_bytes<L>(pc.n, pc.K);
   hipError_t e = ensure_dyn_lds((const void*)polar_decode_kernel<L>, lds);
   if (e != hipSuccess) return e;
   polar_decode_kernel<L><<<(unsigned)B, kPolThreads, lds, s>>>(pc, llr, B, use_crc, bits, pm);
@@ -335,11 +357,12 @@ hipError_t launch_dec(const DevPolar& pc, const float* llr, int64_t B, int use_c
 }  // namespace
 
 size_t polar_decode_lds(int list, int N, int K) {
+  const int n = 31 - __builtin_clz((unsigned)N);
   switch (list) {
-    case 1: return polar_lds_bytes<1>(N, K);
-    case 2: return polar_lds_bytes<2>(N, K);
-    case 4: return polar_lds_bytes<4>(N, K);
-    case 8: return polar_lds_bytes<8>(N, K);
+    case 1: return polar_lds_bytes<1>(n, K);
+    case 2: return polar_lds_bytes<2>(n, K);
+    case 4: return polar_lds_bytes<4>(n, K);
+    case 8: return polar_lds_bytes<8>(n, K);
     default: return 0;
   }
 }
