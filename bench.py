@@ -691,10 +691,10 @@ def wbp_eval_leg(torch, lsim, dev, code, qb, T=10, pre_steps=300, joint_steps=30
     then compared with plain sum-product decoding at equal conditions.
 
     Training (16-QAM, batch 2048, Eb/N0 ~ U[1, 4] dB, fresh codewords every
-    step): the demapper alone on the BCE of its LLRs ({pre} steps, Adam
+    step): the demapper alone on the BCE of its LLRs (300 steps, Adam
     1e-2), then demapper and weights jointly on the BCE of the decoder's
-    posteriors ({joint} steps, Adam 1e-3).  Evaluation on other data: 4096
-    codewords at each Eb/N0 of 0:0.5:5 dB, BLER of the trained pair, of
+    posteriors (300 steps, Adam 1e-3).  Evaluation on other data: 4096
+    codewords at each Eb/N0 of 0:0.25:5 dB, BLER of the trained pair, of
     sum-product with the exact demapper at T and at 20 iterations, and the
     Eb/N0 each needs for BLER 1e-2."""
     from inputs import rand
@@ -749,7 +749,7 @@ def wbp_eval_leg(torch, lsim, dev, code, qb, T=10, pre_steps=300, joint_steps=30
     train_s = time.perf_counter() - t0
 
     Be = 4096
-    pts = np.arange(11) * 0.5
+    pts = np.arange(21) * 0.25
     eseed = data_seed(5, 2)
     ye = torch.empty((Be, code.e_tx // m, 2), dtype=torch.float32, device=dev)
     le = torch.empty((Be, code.e_tx), dtype=torch.float32, device=dev)

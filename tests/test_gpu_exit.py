@@ -83,6 +83,35 @@ def test_apriori_llrs_vs_oracle(name):
     assert (np.abs(la - ref) <= tol).all(), float((np.abs(la - ref) / tol).max())
 
 
+def test_apriori_llrs_ragged_tail():
+    """A transmitted length that is not a multiple of 4: the last Philox
+    block is used in part."""
+    spec, _, _ = CODES["small"]
+    qb = spec.load()
+    e_tx = 646
+    code = lsim.Code.from_qcbase(qb, e_tx)
+    g = qc.graph_from_qcbase(qb, e_tx)
+    B, seed = 3, 93
+    u = philox.source_bits(seed, 0, B, qb.k)
+    c = qc.encode(qb.base, qb.kb, qb.Z, qb.family, u)
+    t = c[:, g.tx_lo:g.tx_lo + g.e_tx]
+    sigma = np.array([0.5, 2.0, 5.0], np.float32)
+    la = lsim.apriori_llrs(code, T(c).to(dev), T(sigma).to(dev), seed, 0).cpu().numpy()
+    ref = ox.apriori_llrs(t, sigma.astype(np.float64), philox.normals_real(seed, 0, B, e_tx, 2))
+    assert la.shape == (B, e_tx)
+    assert (np.abs(la - ref) <= 1e-5 * sigma[:, None] + 1e-6 * np.abs(ref) + 1e-7).all()
+
+
+@pytest.mark.parametrize("B,n", [(1, 1), (5, 63), (3, 3841)])
+def test_mutual_info_ragged(B, n):
+    c = rand.bits(95 + n, (B, n))
+    L = rand.gaussian(96 + n, (B, n), scale=4.0).astype(np.float32)
+    mi_cw, mi_b = lsim.mutual_info(T(L).to(dev), T(c).to(dev))
+    ref = ox.mutual_info(L.astype(np.float64), c)
+    assert np.abs(mi_cw.cpu().numpy() - ref).max() <= 2e-6
+    assert abs(mi_b.item() - ref.mean()) <= 2e-6
+
+
 def test_mutual_info_vs_oracle_and_bins():
     B, n = 37, 3840
     c = rand.bits(93, (B, n + 256))

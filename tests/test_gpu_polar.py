@@ -126,3 +126,13 @@ def test_full_size_batch_sampled():
     assert errs[(8, True)] <= errs[(8, False)] <= errs[(1, False)]
     rows = np.array([0, 1, 2047, 4095])
     _check(pc, mask, llr.cpu().numpy()[rows], 8, crc, True)
+
+
+def test_single_codeword_and_no_frozen_bits():
+    for n, K, L in ((10, 1024, 8), (6, 64, 1), (4, 3, 2)):
+        mask, pc = _code(n, K, 1.0)
+        data = rand.bits(500 + n, (1, K))
+        x = P.encode(data, mask)
+        llr = _noisy_llrs(x, 2.0, K / (1 << n), 501 + n)
+        _check(pc, mask, llr, L, (0, 0), False)
+
