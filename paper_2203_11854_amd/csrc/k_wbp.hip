@@ -16,7 +16,8 @@
 //   qb_k  = sech^2(q_k/2) sum_{v != k} c_v cosh^2(r_v/2) prod_{j not in {v,k}} tanh(q_j/2)
 // The last sum is formed in O(d) per check from prefix/suffix products of
 // t_j = tanh(q_j/2) and prefix/suffix sums A of c_v cosh^2 times partial
-// products.  After round 1, lam_bar_v += sum_e qb_e (q^(1) = lam), and
+// products.  Once the reverse pass is through the first round,
+// lam_bar_v += sum_e qb_e (q^(1) = lam), and
 // dLoss/dL_ch = -lam_bar [|L_ch| <= L].
 //
 // The weight gradient is summed over the batch in a fixed order: every
