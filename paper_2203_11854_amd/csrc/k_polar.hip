@@ -57,11 +57,17 @@ __host__ __device__ inline int polar_wrow(int n) {
   return n - 1 < 5 ? n : polar_ws(n - 1) + (1 << (n - 1 - 5));
 }
 
+// SC keeps its partial sums one byte per bit (fewer instructions; its state
+// is small), the list decoders bit-packed (less LDS, more codewords per CU)
+template <int L>
+constexpr bool polar_bytes() { return L == 1; }
+
 template <int L>
 __host__ __device__ inline size_t polar_lds_bytes(int n, int K) {
   const int N = 1 << n;
-  return (size_t)N * 4 + (size_t)L * polar_astr(n, polar_vmax<L>()) * 4 +
-         (size_t)L * polar_wrow(n) * 4 + (size_t)L * polar_kpad(K);
+  const size_t sums = (size_t)L * 4 * (polar_bytes<L>() ? (N + 3) / 4 : polar_wrow(n));
+  return (size_t)N * 4 + (size_t)L * polar_astr(n, polar_vmax<L>()) * 4 + sums +
+         (size_t)L * polar_kpad(K);
 }
 
 __device__ __forceinline__ float pol_f(float a, float c) {
@@ -95,10 +101,12 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
   const int N = pc.N, n = pc.n, K = pc.K, r = pc.r;
   const int V = polar_virt(n, polar_vmax<L>()), S0 = n - V;
   const int A = polar_astr(n, polar_vmax<L>()), lgA = 31 - __builtin_clz(A);
-  const int W = polar_wrow(n);
+  constexpr bool kBytes = polar_bytes<L>();
+  const int W = kBytes ? (N + 3) / 4 : polar_wrow(n);  // 32-bit words of partial sums per slot
   float* ch = reinterpret_cast<float*>(sm);
   float* al = ch + N;
   uint32_t* bw = reinterpret_cast<uint32_t*>(al + L * A);
+  uint8_t* bb = reinterpret_cast<uint8_t*>(bw);  // byte form: stage s at [p][2^s ..]
   uint8_t* rec = reinterpret_cast<uint8_t*>(bw + L * W);  // [K][L]: (parent << 1) | bit
   const int lane = threadIdx.x;
   const int64_t b = blockIdx.x;
@@ -106,6 +114,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
   if (lane < L) pm[lane] = 0.f;
   __syncthreads();
   auto blbit = [&](int p, int st, int e) -> uint32_t {
+    if constexpr (kBytes) return bb[p * N + (1 << st) + e];
     return (bw[p * W + polar_ws(st) + (e >> 5)] >> (e & 31)) & 1u;
   };
   int nact = 1, j = 0;
@@ -212,7 +221,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
           for (int q = q0 + lane; q < (A >> 2); q += kPolThreads)
             reinterpret_cast<float4*>(ad)[q] = reinterpret_cast<const float4*>(as)[q];
         }
-        if (lane < W) bw[d * W + lane] = bw[p * W + lane];
+        for (int q = lane; q < W; q += kPolThreads) bw[d * W + q] = bw[p * W + q];
       }
       // metrics and the history of every surviving candidate
       if (lane < ncand && ((sv >> lane) & 1u)) {
@@ -226,25 +235,37 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
       ++j;
       __syncthreads();
     }
-    // ---- partial sums of the trailing-ones subtree, one step, as words
+    // ---- partial sums of the trailing-ones subtree, one step
     const int t = __builtin_ctz(~i);
     if (t < n) {
-      const int lgw = t < 5 ? 0 : t - 5;  // 2^lgw words of stage t per slot
-      const int cnt = nact << lgw;
-      for (int idx = lane; idx < cnt; idx += kPolThreads) {
-        const int p = idx >> lgw, w = idx & ((1 << lgw) - 1);
-        const uint32_t u = info ? (uint32_t)(rec[(j - 1) * L + p] & 1) : 0u;
-        uint32_t x = u ? 0xffffffffu : 0u;
-        const uint32_t* row = bw + p * W;
-        if (t > 0) x ^= low_stage_term<0>(row[0]);
-        if (t > 1) x ^= low_stage_term<1>(row[1]);
-        if (t > 2) x ^= low_stage_term<2>(row[2]);
-        if (t > 3) x ^= low_stage_term<3>(row[3]);
-        if (t > 4) x ^= low_stage_term<4>(row[4]);
-        for (int st = 5; st < t; ++st)
-          if (!((w >> (st - 5)) & 1)) x ^= row[polar_ws(st) + (w & ((1 << (st - 5)) - 1))];
-        if (t < 5) x &= (t == 5 ? 0xffffffffu : ((1u << (1 << t)) - 1u));
-        bw[p * W + polar_ws(t) + w] = x;
+      if constexpr (kBytes) {
+        const int cnt = nact << t;
+        for (int idx = lane; idx < cnt; idx += kPolThreads) {
+          const int p = idx >> t, e = idx & ((1 << t) - 1);
+          uint8_t x = info ? (uint8_t)(rec[(j - 1) * L + p] & 1) : 0;
+          for (int st = 0; st < t; ++st)
+            if (!((e >> st) & 1)) x ^= bb[p * N + (1 << st) + (e & ((1 << st) - 1))];
+          bb[p * N + (1 << t) + e] = x;
+        }
+      } else {
+        // as words: stage t's words written by one lane each
+        const int lgw = t < 5 ? 0 : t - 5;  // 2^lgw words of stage t per slot
+        const int cnt = nact << lgw;
+        for (int idx = lane; idx < cnt; idx += kPolThreads) {
+          const int p = idx >> lgw, w = idx & ((1 << lgw) - 1);
+          const uint32_t u = info ? (uint32_t)(rec[(j - 1) * L + p] & 1) : 0u;
+          uint32_t x = u ? 0xffffffffu : 0u;
+          const uint32_t* row = bw + p * W;
+          if (t > 0) x ^= low_stage_term<0>(row[0]);
+          if (t > 1) x ^= low_stage_term<1>(row[1]);
+          if (t > 2) x ^= low_stage_term<2>(row[2]);
+          if (t > 3) x ^= low_stage_term<3>(row[3]);
+          if (t > 4) x ^= low_stage_term<4>(row[4]);
+          for (int st = 5; st < t; ++st)
+            if (!((w >> (st - 5)) & 1)) x ^= row[polar_ws(st) + (w & ((1 << (st - 5)) - 1))];
+          if (t < 5) x &= (1u << (1 << t)) - 1u;
+          bw[p * W + polar_ws(t) + w] = x;
+        }
       }
       __syncthreads();
     }
