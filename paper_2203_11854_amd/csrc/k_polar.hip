@@ -187,8 +187,10 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
         const int hard = l < 0.f;
         mc = bit == hard ? pm[p] : pm[p] + fabsf(l);
       }
+      // lanes >= ncand hold +inf, which never ranks ahead of a candidate
       int rank = 0;
-      for (int c2 = 0; c2 < ncand; ++c2) {
+#pragma unroll
+      for (int c2 = 0; c2 < 2 * L; ++c2) {
         const float m2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mc), c2));
         rank += (m2 < mc) || (m2 == mc && c2 < lane);
       }
