@@ -89,6 +89,16 @@ __device__ __forceinline__ uint32_t low_stage_term(uint32_t v) {
   return v & clear[S];
 }
 
+// The decoder's workgroup is one wavefront, whose LDS operations the hardware
+// performs in program order: ordering its cross-lane LDS traffic only needs
+// the compiler not to move accesses across this point (no s_barrier, no
+// wait for outstanding LDS operations).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 template <int L>
 __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
                                                                    const float* __restrict__ llr,
@@ -112,7 +122,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
   const int64_t b = blockIdx.x;
   for (int e = lane; e < N; e += kPolThreads) ch[e] = -llr[b * N + e];
   if (lane < L) pm[lane] = 0.f;
-  __syncthreads();
+  wave_sync();
   auto blbit = [&](int p, int st, int e) -> uint32_t {
     if constexpr (kBytes) return bb[p * N + (1 << st) + e];
     return (bw[p * W + polar_ws(st) + (e >> 5)] >> (e & 31)) & 1u;
@@ -168,7 +178,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
           al[(p << lgA) + h + e] = use_g ? pol_g(a, c, blbit(p, st, e)) : pol_f(a, c);
         }
       }
-      __syncthreads();
+      wave_sync();
     }
     // ---- decision
     const bool info = pc.mask[i] != 0;
@@ -177,7 +187,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
         const float l = al[(lane << lgA) + 1];
         if (l < 0.f) pm[lane] = pm[lane] + (-l);
       }
-      __syncthreads();
+      wave_sync();
     } else {
       const int ncand = 2 * nact;
       float mc = INFINITY;
@@ -204,7 +214,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
         bothp |= (two == 3u) << p;
       }
       uint32_t freem = ~anyp & ((1u << L) - 1u);
-      __syncthreads();  // every lane has read pm and the leaf LLRs
+      wave_sync();  // every lane has read pm and the leaf LLRs
       // each parent with two survivors copies the state still to be read to
       // the lowest free slot, in parent order
       const int t = i + 1 < N ? __builtin_ctz(i + 1) : n;
@@ -235,7 +245,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
       }
       nact = min(2 * nact, L);
       ++j;
-      __syncthreads();
+      wave_sync();
     }
     // ---- partial sums of the trailing-ones subtree, one step
     const int t = __builtin_ctz(~i);
@@ -269,7 +279,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
           bw[p * W + polar_ws(t) + w] = x;
         }
       }
-      __syncthreads();
+      wave_sync();
     }
   }
   // ---- each slot's information bits by tracing its history back, into
@@ -283,7 +293,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
       slot = v >> 1;
     }
   }
-  __syncthreads();
+  wave_sync();
   if (use_crc && r > 0) {
     const int D = K - r;
     for (int p = 0; p < nact; ++p) {
@@ -299,7 +309,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
       }
     }
   }
-  __syncthreads();
+  wave_sync();
   int choice = 0;
   {
     // slots ordered by (metric, slot); first passing one under CRC
