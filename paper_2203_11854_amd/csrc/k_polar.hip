@@ -40,12 +40,17 @@ namespace {
 constexpr int kPolThreads = 64;
 
 __host__ __device__ inline int polar_kpad(int K) { return (K + 15) & ~15; }
-// top stages formed on the fly: up to vmax, leaving stage 0 stored
-__host__ __device__ inline int polar_virt(int n, int vmax) { return n - 1 < vmax ? n - 1 : vmax; }
-// alpha row per slot: stored stages 0 .. n-V-1 (stage 0 at offset 1)
+// top stages formed on the fly: up to vmax, leaving stages 0 and 1 stored
+// (n = 1: stage 0 only, under the channel)
+__host__ __device__ inline int polar_virt(int n, int vmax) {
+  return n <= 2 ? 0 : (n - 2 < vmax ? n - 2 : vmax);
+}
+// alpha row per slot: stored stages 1 .. n-V-1 at [2^s, 2^{s+1}); stage 0
+// (the leaf LLR) is never stored, each lane that needs it forms it from
+// stage 1
 __host__ __device__ inline int polar_astr(int n, int vmax) {
   const int s0 = n - polar_virt(n, vmax);
-  return s0 >= 1 ? (1 << s0) : 2;
+  return s0 >= 2 ? (1 << s0) : 4;
 }
 // list decoders form two stages on the fly (half the LLR state, twice the
 // codewords per CU); SC, whose state is small anyway, forms one
@@ -127,11 +132,24 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
     if constexpr (kBytes) return bb[p * N + (1 << st) + e];
     return (bw[p * W + polar_ws(st) + (e >> 5)] >> (e & 31)) & 1u;
   };
+  // leaf LLR of slot p at leaf i: f or g of the two stage-1 values (the
+  // channel when n = 1) with the leaf's left sibling's bit
+  auto leaf_llr = [&](int p, int i) -> float {
+    float a, c;
+    if (n == 1) {
+      a = ch[0];
+      c = ch[1];
+    } else {
+      a = al[(p << lgA) + 2];
+      c = al[(p << lgA) + 3];
+    }
+    return (i & 1) ? pol_g(a, c, blbit(p, 0, 0)) : pol_f(a, c);
+  };
   int nact = 1, j = 0;
   for (int i = 0; i < N; ++i) {
     // ---- LLRs down to the leaf
     const int top = i == 0 ? n - 1 : __builtin_ctz(i);
-    for (int st = min(top, S0 - 1); st >= 0; --st) {
+    for (int st = min(top, S0 - 1); st >= 1; --st) {
       const int h = 1 << st;
       const int cnt = nact << st;
       const bool use_g = (i >> st) & 1;
@@ -184,7 +202,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
     const bool info = pc.mask[i] != 0;
     if (!info) {
       if (lane < nact) {
-        const float l = al[(lane << lgA) + 1];
+        const float l = leaf_llr(lane, i);
         if (l < 0.f) pm[lane] = pm[lane] + (-l);
       }
       wave_sync();
@@ -193,7 +211,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
       float mc = INFINITY;
       if (lane < ncand) {
         const int p = lane >> 1, bit = lane & 1;
-        const float l = al[(p << lgA) + 1];
+        const float l = leaf_llr(p, i);
         const int hard = l < 0.f;
         mc = bit == hard ? pm[p] : pm[p] + fabsf(l);
       }
