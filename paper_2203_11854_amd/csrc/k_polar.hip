@@ -4,7 +4,7 @@
 // algorithm that needs a custom kernel, Sec. IV-A).
 //
 // Decoder: one wavefront per codeword, everything in LDS.  The node LLRs
-// of stage s (2^s values) are stored for s < S0 = n - V, per list slot at
+// of stage s (2^s values) are stored for 1 <= s < S0 = n - V, per list slot at
 // alpha[p][2^s .. 2^{s+1}); the top V <= 2 stages are never stored: they
 // are read only while stage S0 - 1 is computed (2^{V+1} times per codeword)
 // and are formed there on the fly from the channel LLRs.  A node at stage s
@@ -26,8 +26,11 @@
 // children survive keeps bit 0 and copies its state to the lowest free
 // slot for bit 1 (the stored LLR stages above ctz(i + 1) and its partial-
 // sum words).  Every information leaf records (parent slot, bit) per slot;
-// the paths' bits are traced back at the end.  Active slots are always
-// 0 .. nact - 1.
+// the paths' bits are traced back at the end.  The leaf LLR (stage 0) is
+// never stored: each lane that needs it forms it from its path's two
+// stage-1 values; the list decoders do not store stage-0 partial sums
+// either (an odd leaf's left sibling bit is the path's bit at leaf i - 1,
+// found in the history).  Active slots are always 0 .. nact - 1.
 #include <hip/hip_runtime.h>
 
 #include "dispatch.h"
@@ -132,9 +135,16 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
     if constexpr (kBytes) return bb[p * N + (1 << st) + e];
     return (bw[p * W + polar_ws(st) + (e >> 5)] >> (e & 31)) & 1u;
   };
+  // The stage-0 partial sum (the left sibling's bit of an odd leaf) is not
+  // stored: it is the bit the path decided at leaf i - 1, read from the
+  // history (0 when that leaf is frozen).  `jr` is the history index of
+  // leaf i - 1 for the slot's path and `q` its slot there.
+  auto prev_bit = [&](bool prev_info, int jr, int q) -> uint32_t {
+    return prev_info ? (uint32_t)(rec[jr * L + q] & 1) : 0u;
+  };
   // leaf LLR of slot p at leaf i: f or g of the two stage-1 values (the
   // channel when n = 1) with the leaf's left sibling's bit
-  auto leaf_llr = [&](int p, int i) -> float {
+  auto leaf_llr = [&](int p, int i, uint32_t ub) -> float {
     float a, c;
     if (n == 1) {
       a = ch[0];
@@ -143,7 +153,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
       a = al[(p << lgA) + 2];
       c = al[(p << lgA) + 3];
     }
-    return (i & 1) ? pol_g(a, c, blbit(p, 0, 0)) : pol_f(a, c);
+    return (i & 1) ? pol_g(a, c, ub) : pol_f(a, c);
   };
   int nact = 1, j = 0;
   for (int i = 0; i < N; ++i) {
@@ -200,9 +210,16 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
     }
     // ---- decision
     const bool info = pc.mask[i] != 0;
+    const bool prev_info = i > 0 && pc.mask[i - 1] != 0;
+    // the left sibling's bit of an odd leaf for slot p (before this leaf's
+    // slot changes): stored by SC, from the history for the lists
+    auto left_bit = [&](int p) -> uint32_t {
+      if constexpr (kBytes) return bb[p * N + 1];
+      return prev_bit(prev_info, j - 1, p);
+    };
     if (!info) {
       if (lane < nact) {
-        const float l = leaf_llr(lane, i);
+        const float l = leaf_llr(lane, i, (i & 1) ? left_bit(lane) : 0u);
         if (l < 0.f) pm[lane] = pm[lane] + (-l);
       }
       wave_sync();
@@ -211,7 +228,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
       float mc = INFINITY;
       if (lane < ncand) {
         const int p = lane >> 1, bit = lane & 1;
-        const float l = leaf_llr(p, i);
+        const float l = leaf_llr(p, i, (i & 1) ? left_bit(p) : 0u);
         const int hard = l < 0.f;
         mc = bit == hard ? pm[p] : pm[p] + fabsf(l);
       }
@@ -265,9 +282,13 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
       ++j;
       wave_sync();
     }
-    // ---- partial sums of the trailing-ones subtree, one step
+    // ---- partial sums of the trailing-ones subtree, one step (for the
+    // lists an even leaf stores none: its bit is read from the history)
     const int t = __builtin_ctz(~i);
-    if (t < n) {
+    // the path now in slot p came from slot q at leaf i - 1
+    auto from_slot = [&](int p) { return info ? (int)(rec[(j - 1) * L + p] >> 1) : p; };
+    const int jprev = info ? j - 2 : j - 1;
+    if (t < n && (kBytes || t >= 1)) {
       if constexpr (kBytes) {
         const int cnt = nact << t;
         for (int idx = lane; idx < cnt; idx += kPolThreads) {
@@ -286,7 +307,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
           const uint32_t u = info ? (uint32_t)(rec[(j - 1) * L + p] & 1) : 0u;
           uint32_t x = u ? 0xffffffffu : 0u;
           const uint32_t* row = bw + p * W;
-          if (t > 0) x ^= low_stage_term<0>(row[0]);
+          x ^= low_stage_term<0>(prev_bit(prev_info, jprev, from_slot(p)));
           if (t > 1) x ^= low_stage_term<1>(row[1]);
           if (t > 2) x ^= low_stage_term<2>(row[2]);
           if (t > 3) x ^= low_stage_term<3>(row[3]);
