@@ -10,9 +10,10 @@
 // and are formed there on the fly from the channel LLRs.  A node at stage s
 // is the left (f) or right (g) child of its parent as bit s of the leaf
 // index is 0 or 1.  The partial sums of the pending left child of every
-// stage are bit-packed per slot (stage s in its own words: 1 word for
-// s < 5, 2^{s-5} words above), so a stage's word is written by one lane.
-// Leaf i recomputes the stored stages from min(ctz(i), S0 - 1) down,
+// stage are bit-packed per slot in the list decoders (stage s in its own
+// words: 1 word for s < 5, 2^{s-5} words above, so a stage's word is
+// written by one lane) and one byte each in SC.  Leaf i recomputes the
+// stored stages from min(ctz(i), S0 - 1) down to stage 1,
 // decides, and writes the merged partial sums of its trailing-ones subtree
 // in one step: x[e] = u_i xor (xor over s < t with bit s of e clear of
 // bl[s][e mod 2^s]), t the number of trailing ones of i, as word
@@ -43,8 +44,9 @@ namespace {
 constexpr int kPolThreads = 64;
 
 __host__ __device__ inline int polar_kpad(int K) { return (K + 15) & ~15; }
-// top stages formed on the fly: up to vmax, leaving stages 0 and 1 stored
-// (n = 1: stage 0 only, under the channel)
+// top stages formed on the fly: up to vmax, leaving at least stage 1
+// stored (n <= 2: none formed; n = 1 stores nothing, its leaves read the
+// channel)
 __host__ __device__ inline int polar_virt(int n, int vmax) {
   return n <= 2 ? 0 : (n - 2 < vmax ? n - 2 : vmax);
 }
