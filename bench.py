@@ -343,7 +343,9 @@ def _elapsed(torch, fn, reps):
 def mixed_leg(torch, lsim, dev):
     """Eight BG-shaped codes (Z 16..384, rates 1/3..8/9), counts drawn
     log-uniform in [16, 4096], QPSK/16-QAM per codeword, Eb/N0 ~ U[0, 6] dB:
-    one persistent graph-replayed launch vs one launch per shape."""
+    one persistent graph-replayed launch vs one launch per shape, with the
+    layered NMS decoder (and the autotuner), and with int8 offset min-sum
+    over the shapes whose state fits the LDS."""
     from inputs import rand
     from inputs.workloads import data_seed, mixed_counts, mixed_specs
 
@@ -406,6 +408,30 @@ def mixed_leg(torch, lsim, dev):
     same = all(torch.equal(bits[o:o + bb.numel()], bb.reshape(-1))
                for o, bb in zip(plan.bits_offsets, sep_bits))
     info = sum(cnt * cd.k for cd, cnt in zip(codes, counts))
+    # the int8 offset min-sum decoder (flooding, codeword pairs in packed
+    # 16-bit lanes, whole state in LDS) over the shapes whose state fits the
+    # LDS: persistent launch vs one per shape
+    po = lsim.params(lsim.OMS_I8, iters=20)
+    keep = [s for s, cd in enumerate(codes) if 4 * (cd.E + cd.n_dec) <= 160 * 1024 - 96]
+    ocodes = [codes[s] for s in keep]
+    ocounts = [counts[s] for s in keep]
+    q8 = [lsim.quantize(parts[s]) for s in keep]
+    qcat = torch.cat([x.reshape(-1) for x in q8])
+    oplan = lsim.MixedPlan(ocodes, ocounts, po)
+    owork = oplan.workspace(dev)
+    obits = torch.empty(oplan.n_bits, dtype=torch.uint8, device=dev)
+    ms_oms = _elapsed(torch, lambda: oplan.decode(qcat, bits=obits, work=owork), 5)
+    osep = [torch.empty((cnt, cd.k), dtype=torch.uint8, device=dev)
+            for cd, cnt in zip(ocodes, ocounts)]
+
+    def per_shape_oms():
+        for cd, x, bb in zip(ocodes, q8, osep):
+            lsim.decode(cd, x, po, bits=bb)
+
+    ms_oms_sep = _elapsed(torch, per_shape_oms, 5)
+    osame = all(torch.equal(obits[o:o + bb.numel()], bb.reshape(-1))
+                for o, bb in zip(oplan.bits_offsets, osep))
+    oinfo = sum(cnt * cd.k for cd, cnt in zip(ocodes, ocounts))
     return {"codewords": int(sum(counts)), "counts": counts, "info_bits": int(info),
             "graph_ms": round(ms_graph, 4), "persistent_ms": round(ms_pers, 4),
             "per_shape_ms": round(ms_sep, 4),
@@ -414,7 +440,12 @@ def mixed_leg(torch, lsim, dev):
             "bit_identical_to_per_shape": bool(same),
             "autotuned": {"threads": best["threads"], "codewords_per_tile": best["codewords_per_tile"],
                           "persistent": best["persistent"], "ms": round(ms_tuned, 4),
-                          "bit_identical": bool(torch.equal(tbits, bits))}}
+                          "bit_identical": bool(torch.equal(tbits, bits))},
+            "oms_i8": {"shapes": keep, "codewords": int(sum(ocounts)),
+                       "persistent_ms": round(ms_oms, 4), "per_shape_ms": round(ms_oms_sep, 4),
+                       "persistent_gbps": round(oinfo / (ms_oms * 1e-3) / 1e9, 3),
+                       "per_shape_gbps": round(oinfo / (ms_oms_sep * 1e-3) / 1e9, 3),
+                       "bit_identical_to_per_shape": bool(osame)}}
 
 
 def wbp_leg(torch, lsim, dev, code, qb, T=10):

@@ -511,7 +511,8 @@ class MixedPlan:
             work = self.workspace(llr.device)
         if work.numel() * work.element_size() < self.work_bytes:
             raise LsimError("workspace too small")
-        _call("lsim_mixed_decode", self._h, _ptr(llr, torch.float32, "llr"),
+        dt = torch.int8 if self.p.algo == OMS_I8 else torch.float32
+        _call("lsim_mixed_decode", self._h, _ptr(llr, dt, "llr"),
               _ptr(bits, torch.uint8, "bits"), _ptr(app, torch.float32, "app"),
               _ptr(work, None, "work"), work.numel(), 1 if persistent else 0, _stream())
         return bits, app

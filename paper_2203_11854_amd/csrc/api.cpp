@@ -623,15 +623,25 @@ lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t*
   *out = nullptr;
   lsim_status st = check_params(codes[0], p);
   if (st != LSIM_OK) return st;
-  if (p->algo != LSIM_NMS_F32)
-    return fail(LSIM_E_UNSUPPORTED, "mixed batches decode with the layered NMS decoder");
+  if (p->algo != LSIM_NMS_F32 && p->algo != LSIM_OMS_I8)
+    return fail(LSIM_E_UNSUPPORTED,
+                "mixed batches decode with the layered NMS or the flooding int8 OMS decoder");
+  const bool oms = p->algo == LSIM_OMS_I8;
   int zmax = 0, dmax = 0;
   for (int s = 0; s < nshapes; ++s) {
     if (!codes[s] || counts[s] < 0) return fail(LSIM_E_INVAL, "null code or negative count");
     zmax = std::max(zmax, codes[s]->dev.Z);
-    dmax = std::max(dmax, codes[s]->dev.max_row_deg);
+    dmax = std::max(dmax, oms ? std::max(codes[s]->dev.max_row_deg, codes[s]->dev.max_col_deg)
+                              : codes[s]->dev.max_row_deg);
   }
-  if (threads == 0) {
+  if (oms) {
+    // flooding OMS: a tile is a codeword pair in packed 16-bit lanes; the
+    // waves stride over (row, lift chunk) tasks, so any Z fits any width
+    if (threads == 0) threads = 512;
+    if (threads != 256 && threads != 512 && threads != 1024)
+      return fail(LSIM_E_INVAL, "threads must be 256, 512 or 1024 for the OMS decoder");
+    if (dmax > 32) return fail(LSIM_E_UNSUPPORTED, "node degree > 32");
+  } else if (threads == 0) {
     const int cand[5] = {256, 384, 512, 768, 1024};
     threads = 1024;
     for (int x : cand)
@@ -640,9 +650,10 @@ lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t*
         break;
       }
   }
-  if (threads != 256 && threads != 384 && threads != 512 && threads != 768 && threads != 1024)
+  if (!oms && threads != 256 && threads != 384 && threads != 512 && threads != 768 &&
+      threads != 1024)
     return fail(LSIM_E_INVAL, "threads must be 256, 384, 512, 768 or 1024");
-  if (threads < zmax) return fail(LSIM_E_INVAL, "threads < largest Z");
+  if (!oms && threads < zmax) return fail(LSIM_E_INVAL, "threads < largest Z");
   const size_t lds_cap = 160 * 1024 - 64;  // room for the kernel's static LDS
   auto* plan = new lsim_plan();
   plan->p = *p;
@@ -650,13 +661,25 @@ lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t*
   int64_t llr_off = 0, bits_off = 0, app_off = 0, state_off = 0, tile0 = 0;
   for (int s = 0; s < nshapes; ++s) {
     const DevCode& c = codes[s]->dev;
-    int G = codewords_per_tile && codewords_per_tile[s] > 0 ? codewords_per_tile[s]
-                                                            : threads / c.Z;
-    if (!codewords_per_tile || codewords_per_tile[s] <= 0)
-      while (G > 1 && lsim::layered_tile_lds(c, G) > lds_cap / 2) --G;  // two workgroups per CU
-    if (G < 1 || G * c.Z > threads || lsim::layered_tile_lds(c, G) > lds_cap) {
-      delete plan;
-      return fail(LSIM_E_INVAL, "codewords_per_tile does not fit the workgroup or the LDS");
+    int G;
+    size_t tile_lds;
+    if (oms) {
+      G = 2;
+      tile_lds = lsim::oms2_lds_bytes(c);
+      if ((codewords_per_tile && codewords_per_tile[s] > 0 && codewords_per_tile[s] != 2) ||
+          tile_lds > lds_cap - 16) {
+        delete plan;
+        return fail(LSIM_E_INVAL, "the OMS decoder takes codeword pairs that fit the LDS");
+      }
+    } else {
+      G = codewords_per_tile && codewords_per_tile[s] > 0 ? codewords_per_tile[s] : threads / c.Z;
+      if (!codewords_per_tile || codewords_per_tile[s] <= 0)
+        while (G > 1 && lsim::layered_tile_lds(c, G) > lds_cap / 2) --G;  // two workgroups per CU
+      if (G < 1 || G * c.Z > threads || lsim::layered_tile_lds(c, G) > lds_cap) {
+        delete plan;
+        return fail(LSIM_E_INVAL, "codewords_per_tile does not fit the workgroup or the LDS");
+      }
+      tile_lds = lsim::layered_tile_lds(c, G);
     }
     lsim::LayerShape sh;
     sh.code = c;
@@ -667,11 +690,11 @@ lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t*
     sh.bits_off = bits_off;
     sh.app_off = app_off;
     sh.state_off = state_off;
-    plan->lds = std::max(plan->lds, lsim::layered_tile_lds(c, G));
+    plan->lds = std::max(plan->lds, tile_lds);
     llr_off += counts[s] * c.e_tx;
     bits_off += counts[s] * c.k;
     app_off += counts[s] * c.n_dec;
-    state_off += (int64_t)lsim::layered_state_words(c, counts[s]);
+    if (!oms) state_off += (int64_t)lsim::layered_state_words(c, counts[s]);
     tile0 += (counts[s] + G - 1) / G;
     plan->shapes.push_back(sh);
   }
@@ -750,6 +773,13 @@ lsim_status lsim_mixed_decode(lsim_plan* plan, const void* d_llr_concat, uint8_t
     return fail(LSIM_E_NOMEM, "workspace smaller than lsim_mixed_workspace()");
   if (plan->ntiles == 0) return LSIM_OK;
   char* w = (char*)d_work;
+  if (plan->p.algo == LSIM_OMS_I8)
+    return dev_status(
+        lsim::launch_mixed_oms(plan->d_shapes, plan->d_tile_shape, plan->d_tile_local, plan->ntiles,
+                               plan->threads, plan->lds, plan->p, (const int8_t*)d_llr_concat,
+                               d_bits_concat, d_app_concat, (int*)w, persistent ? 1 : 0,
+                               plan->grid, plan->dmax, as_stream(stream)),
+        "mixed decode");
   hipError_t e = lsim::launch_mixed(
       plan->d_shapes, (int)plan->shapes.size(), plan->d_tile_shape, plan->d_tile_local,
       plan->ntiles, plan->threads, plan->lds, plan->p, d_llr_concat, d_bits_concat, d_app_concat,

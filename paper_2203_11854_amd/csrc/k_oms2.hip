@@ -62,12 +62,13 @@ __host__ __device__ inline size_t oms2_lds(const DevCode& c) {
   return align16((size_t)c.E * 4) + align16((size_t)c.n_dec * 4);
 }
 
-// ZC: compile-time lift size or 0 (read from the code).  LDS: messages at
-// byte 0, channel values at lam_b (kernel has no static LDS).
+// One codeword pair (2 pair, 2 pair + 1) of code c.  ZC: compile-time lift
+// size or 0 (read from the code).  LDS: messages at byte 0, channel values
+// at lam_b (the calling kernel has no static LDS).
 template <int NT, int DMAX, int ZC>
-__global__ __launch_bounds__(NT) void oms2_kernel(DevCode c, Oms2Args a) {
+__device__ __forceinline__ void oms2_pair(const DevCode& c, const Oms2Args& a, int64_t pair,
+                                          unsigned char* smem) {
   constexpr int NW = NT / 64;
-  extern __shared__ __align__(16) unsigned char smem[];
   s16x2* msg = reinterpret_cast<s16x2*>(smem);
   s16x2* lam = reinterpret_cast<s16x2*>(smem + align16((size_t)c.E * 4));
   const int lam_b = (int)align16((size_t)c.E * 4);
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(NT) void oms2_kernel(DevCode c, Oms2Args a) {
   const int Z = ZC ? ZC : c.Z;
   const int zm = Z - 1;
   const bool zpow2 = (Z & zm) == 0;
-  const int64_t b0 = 2 * (int64_t)blockIdx.x;
+  const int64_t b0 = 2 * pair;
   const bool has1 = b0 + 1 < a.B;
   const int sat = a.sat;
   const s16x2 psat = pk(sat, sat), nsat = pk(-sat, -sat);
@@ -240,6 +241,45 @@ __global__ __launch_bounds__(NT) void oms2_kernel(DevCode c, Oms2Args a) {
   }
 }
 
+__global__ void oms2_reset_counter_kernel(int* counter) { *counter = 0; }
+
+template <int NT, int DMAX, int ZC>
+__global__ __launch_bounds__(NT) void oms2_kernel(DevCode c, Oms2Args a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  oms2_pair<NT, DMAX, ZC>(c, a, blockIdx.x, smem);
+}
+
+// Persistent decoder over a work list of (shape, codeword pair) items, as
+// the layered mixed kernel: workgroups take items from a device counter
+// (reset by oms2_reset_counter_kernel just before, so the pair of launches can
+// be captured in a graph); the item taken by thread 0 is broadcast through
+// the word at next_off of the dynamic LDS.
+template <int NT, int DMAX>
+__global__ __launch_bounds__(NT) void oms2_mixed_kernel(
+    const LayerShape* __restrict__ shapes, const int* __restrict__ tile_shape,
+    const int64_t* __restrict__ tile_local, int64_t ntiles, const int8_t* llr, uint8_t* bits,
+    float* lpost, int* counter, int persistent, int iters, int offset, int sat, int next_off) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int* next = reinterpret_cast<int*>(smem + next_off);
+  int64_t item = persistent ? -1 : (int64_t)blockIdx.x;
+  for (;;) {
+    if (persistent) {
+      if (threadIdx.x == 0) *next = atomicAdd(counter, 1);
+      __syncthreads();
+      item = *next;
+      __syncthreads();
+    }
+    if (item >= ntiles) break;
+    const LayerShape& sh = shapes[tile_shape[item]];
+    Oms2Args a{llr + sh.llr_off, sh.count, bits ? bits + sh.bits_off : nullptr,
+               lpost ? lpost + sh.app_off : nullptr, nullptr, nullptr, nullptr, iters, offset,
+               sat};
+    oms2_pair<NT, DMAX, 0>(sh.code, a, tile_local[item], smem);
+    __syncthreads();
+    if (!persistent) break;
+  }
+}
+
 template <int NT, int DMAX, int ZC>
 hipError_t launch_t(const DevCode& c, const Oms2Args& a, size_t lds, hipStream_t s) {
   const void* k = (const void*)oms2_kernel<NT, DMAX, ZC>;
@@ -253,6 +293,52 @@ hipError_t launch_t(const DevCode& c, const Oms2Args& a, size_t lds, hipStream_t
 }  // namespace
 
 size_t oms2_lds_bytes(const DevCode& c) { return oms2_lds(c); }
+
+template <int NT, int DMAX>
+hipError_t launch_mixed_oms_t(const LayerShape* d_shapes, const int* d_tile_shape,
+                              const int64_t* d_tile_local, int64_t ntiles, size_t lds,
+                              const lsim_decode_params& p, const int8_t* llr, uint8_t* bits,
+                              float* lpost, int* counter, int persistent, int grid,
+                              hipStream_t s) {
+  const void* k = (const void*)oms2_mixed_kernel<NT, DMAX>;
+  const int next_off = (int)align16(lds);
+  const size_t lds_all = (size_t)next_off + 16;
+  hipError_t e = require_lds_at_zero(k);
+  if (e == hipSuccess) e = ensure_dyn_lds(k, lds_all);
+  if (e != hipSuccess) return e;
+  if (persistent) {
+    oms2_reset_counter_kernel<<<1, 1, 0, s>>>(counter);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const unsigned g = persistent ? (unsigned)grid : (unsigned)ntiles;
+  oms2_mixed_kernel<NT, DMAX><<<g, NT, lds_all, s>>>(d_shapes, d_tile_shape, d_tile_local, ntiles,
+                                                     llr, bits, lpost, counter, persistent,
+                                                     p.iters, (int)p.offset, p.sat, next_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_mixed_oms(const LayerShape* d_shapes, const int* d_tile_shape,
+                            const int64_t* d_tile_local, int64_t ntiles, int threads, size_t lds,
+                            const lsim_decode_params& p, const int8_t* llr, uint8_t* bits,
+                            float* lpost, int* counter, int persistent, int grid, int dmax,
+                            hipStream_t s) {
+#define LSIM_OMS2_MIXED(NT_, D_)                                                               \
+  if (threads == NT_ && dmax <= D_)                                                            \
+    return launch_mixed_oms_t<NT_, D_>(d_shapes, d_tile_shape, d_tile_local, ntiles, lds, p,   \
+                                       llr, bits, lpost, counter, persistent, grid, s);
+  LSIM_OMS2_MIXED(256, 16)
+  LSIM_OMS2_MIXED(256, 24)
+  LSIM_OMS2_MIXED(256, 32)
+  LSIM_OMS2_MIXED(512, 16)
+  LSIM_OMS2_MIXED(512, 24)
+  LSIM_OMS2_MIXED(512, 32)
+  LSIM_OMS2_MIXED(1024, 16)
+  LSIM_OMS2_MIXED(1024, 24)
+  LSIM_OMS2_MIXED(1024, 32)
+#undef LSIM_OMS2_MIXED
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_oms2(const DevCode& c, const lsim_decode_params& p, const int8_t* llr, int64_t B,
                        uint8_t* bits, float* lpost, const int8_t* q_in, int8_t* r_out,

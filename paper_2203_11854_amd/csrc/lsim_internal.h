@@ -61,6 +61,11 @@ size_t layered_tile_lds(const DevCode& c, int G);
 hipError_t launch_layered(const DevCode& c, const lsim_decode_params& p, const float* llr,
                           int64_t B, uint8_t* bits, float* lpost, float* r_out, uint32_t* state,
                           hipStream_t s, std::string* why);
+hipError_t launch_mixed_oms(const LayerShape* d_shapes, const int* d_tile_shape,
+                            const int64_t* d_tile_local, int64_t ntiles, int threads, size_t lds,
+                            const lsim_decode_params& p, const int8_t* llr, uint8_t* bits,
+                            float* lpost, int* counter, int persistent, int grid, int dmax,
+                            hipStream_t s);
 hipError_t launch_mixed(const LayerShape* d_shapes, int nshapes, const int* d_tile_shape,
                         const int64_t* d_tile_local, int64_t ntiles, int threads,
                         size_t lds_bytes, const lsim_decode_params& p, const void* llr,

@@ -91,6 +91,73 @@ def test_mixed_graph_replay():
         torch.cuda.synchronize()
 
 
+def oms_fit(codes, llrs, graphs, counts):
+    """The shapes whose packed int8 state (4 B per edge and per variable
+    node for a codeword pair) fits the 160 KiB of LDS."""
+    keep = [s for s, c in enumerate(codes) if 4 * (c.E + c.n_dec) <= 160 * 1024 - 96]
+    assert len(keep) >= 4
+    return ([codes[s] for s in keep], [llrs[s] for s in keep], [graphs[s] for s in keep],
+            [counts[s] for s in keep])
+
+
+@pytest.mark.parametrize("threads", [0, 256, 1024])
+def test_mixed_oms_equals_per_shape_and_oracle(threads):
+    """The int8 offset min-sum decoder over the shapes whose state fits the
+    LDS, in one persistent launch (odd counts leave a half-empty last pair):
+    bits and posteriors equal the per-shape launches and the oracle bit for
+    bit."""
+    codes, llrs, graphs, _ = mixed_inputs([5, 9, 3, 7, 4, 6, 2, 3], seed=75)
+    codes, llrs, graphs, counts = oms_fit(codes, llrs, graphs, [5, 9, 3, 7, 4, 6, 2, 3])
+    p = lsim.params(lsim.OMS_I8, iters=20, offset=1.0, sat=31)
+    q8 = [lsim.quantize(T(L).to(dev)) for L in llrs]
+    plan = lsim.MixedPlan(codes, counts, p, threads=threads)
+    cat = torch.cat([q.reshape(-1) for q in q8])
+    bits = torch.zeros(plan.n_bits, dtype=torch.uint8, device=dev)
+    app = torch.zeros(plan.n_app, dtype=torch.float32, device=dev)
+    plan.decode(cat, bits=bits, app=app, persistent=True)
+    bits2, app2 = torch.zeros_like(bits), torch.zeros_like(app)
+    plan.decode(cat, bits=bits2, app=app2, persistent=False)
+    assert torch.equal(bits, bits2) and torch.equal(app, app2)
+    for s, (code, q, g) in enumerate(zip(codes, q8, graphs)):
+        b1, a1 = lsim.decode(code, q, p, want_app=True)
+        lo, n = plan.app_offsets[s], counts[s] * code.n_dec
+        assert torch.equal(app[lo:lo + n].view(counts[s], -1), a1), s
+        bo = plan.bits_offsets[s]
+        assert torch.equal(bits[bo:bo + counts[s] * code.k].view(counts[s], -1), b1), s
+        ref = D.oms_flood(g, D.channel_lam(g, q.cpu().numpy(), dtype=np.int64), 20)
+        assert np.array_equal(a1.cpu().numpy(), -ref.astype(np.float32)), s
+
+
+def test_mixed_oms_graph_replay():
+    codes, llrs, graphs, _ = mixed_inputs([4, 3, 5, 2, 3, 2, 1, 2], seed=91)
+    codes, llrs, _, counts = oms_fit(codes, llrs, graphs, [4, 3, 5, 2, 3, 2, 1, 2])
+    p = lsim.params(lsim.OMS_I8, iters=20)
+    plan = lsim.MixedPlan(codes, counts, p)
+    cat = torch.cat([lsim.quantize(T(L).to(dev)).reshape(-1) for L in llrs])
+    work = plan.workspace(dev)
+    ref = torch.zeros(plan.n_bits, dtype=torch.uint8, device=dev)
+    plan.decode(cat, bits=ref, work=work)
+    torch.cuda.synchronize()
+    out = torch.zeros_like(ref)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.decode(cat, bits=out, work=work)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.decode(cat, bits=out, work=work)
+    for rep in range(3):
+        out.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), rep
+        _ = (cat.float() * 2).sum()
+        torch.cuda.synchronize()
+
+
 def wbp_case(B=5, Tn=3, ebn0=1.0, seed=81):
     qb = BG2.load()
     g = qc.graph_from_qcbase(qb, 3840)
