@@ -64,10 +64,16 @@ def _tile_options(Z, threads):
 
 def tune_mixed(codes, counts, p, llr_concat, cache_path: str | None = DEFAULT_CACHE,
                threads_options=(384, 512, 768, 1024), reps: int = 3, verbose: bool = False):
-    """Best (threads, codewords_per_tile, persistent) for a mixed batch."""
+    """Best (threads, codewords_per_tile, persistent) for a mixed batch.
+    For the int8 offset min-sum decoder the tile is always a codeword pair
+    and the workgroup sizes are 256, 512 and 1024."""
+    from . import OMS_I8
+    oms = p.algo == OMS_I8
+    if oms:
+        threads_options = (256, 512, 1024)
     zmax = max(c.Z for c in codes)
     key = _key(["mixed", [(c.Z, c.rows, c.cols, c.E, c.e_tx) for c in codes], list(counts),
-                [p.algo, p.iters, p.alpha]])
+                [p.algo, p.iters, p.alpha, p.offset, p.sat]])
     cache = _load(cache_path) if cache_path else {}
     if key in cache:
         return cache[key]
@@ -75,11 +81,12 @@ def tune_mixed(codes, counts, p, llr_concat, cache_path: str | None = DEFAULT_CA
     best = None
     n_bits = sum(int(k) * c.k for c, k in zip(codes, counts))
     for threads in threads_options:
-        if threads < zmax:
+        if not oms and threads < zmax:
             continue
         # uniform tile shrink factors keep the search small
-        for shrink in (1, 2):
-            cpt = [max(1, (threads // c.Z) // shrink) for c in codes]
+        for shrink in ((1,) if oms else (1, 2)):
+            cpt = ([2] * len(codes) if oms
+                   else [max(1, (threads // c.Z) // shrink) for c in codes])
             try:
                 plan = MixedPlan(codes, counts, p, codewords_per_tile=cpt, threads=threads)
             except Exception:

@@ -158,6 +158,22 @@ def test_mixed_oms_graph_replay():
         torch.cuda.synchronize()
 
 
+def test_autotuner_mixed_oms():
+    from paper_2203_11854_amd import autotune
+    codes, llrs, graphs, _ = mixed_inputs([3, 4, 5, 2, 3, 2, 3, 2], seed=93)
+    codes, llrs, _, counts = oms_fit(codes, llrs, graphs, [3, 4, 5, 2, 3, 2, 3, 2])
+    p = lsim.params(lsim.OMS_I8, iters=20)
+    cat = torch.cat([lsim.quantize(T(L).to(dev)).reshape(-1) for L in llrs])
+    best = autotune.tune_mixed(codes, counts, p, cat, cache_path=None)
+    assert best["threads"] in (256, 512, 1024) and best["codewords_per_tile"] == [2] * len(codes)
+    ref = lsim.MixedPlan(codes, counts, p).decode(cat, bits=torch.zeros(
+        sum(c.k * k for c, k in zip(codes, counts)), dtype=torch.uint8, device=dev))[0]
+    tuned = lsim.MixedPlan(codes, counts, p, codewords_per_tile=best["codewords_per_tile"],
+                           threads=best["threads"])
+    out = tuned.decode(cat, bits=torch.zeros_like(ref), persistent=best["persistent"])[0]
+    assert torch.equal(out, ref)
+
+
 def wbp_case(B=5, Tn=3, ebn0=1.0, seed=81):
     qb = BG2.load()
     g = qc.graph_from_qcbase(qb, 3840)
