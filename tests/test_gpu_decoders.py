@@ -223,3 +223,25 @@ def test_spa_other_clamp():
                         want_app=True)
     ok, w = rel_close(lp.cpu().numpy()[conv], -app[conv], 1e-4)
     assert ok, w
+
+
+def test_layered_at_the_largest_lift():
+    """The 11n-style base matrix lifted by Z = 1024 (the largest lift the
+    library takes; n = 24576): layered NMS with 1024 threads, bit for bit
+    against the oracle's single-precision mode."""
+    qb, _ = graph("small")
+    Z = 1024
+    n = qb.base.shape[1] * Z
+    code = lsim.Code(qb.base, Z, qb.family, 0, n)
+    g = qc.make_graph(qb.base, qb.kb, Z, 0, n, family=qb.family)
+    B = 2
+    u = np.random.default_rng(11).integers(0, 2, (B, qb.kb * Z)).astype(np.uint8)
+    c = qc.encode(qb.base, qb.kb, Z, qb.family, u)
+    n0 = float(modem.ebn0_to_n0(2.0, 0.5, 1))
+    y = (1.0 - 2.0 * c) + np.sqrt(n0 / 2.0) * np.random.default_rng(12).standard_normal(c.shape)
+    L = (-4.0 * y / n0).astype(np.float32)
+    p = lsim.params(lsim.NMS_F32, iters=20, alpha=0.75, threads=1024)
+    bits, app = lsim.decode(code, T(L).to(dev), p, want_app=True)
+    ref = D.nms_layered(g, D.channel_lam(g, L, dtype=np.float32), 20, 0.75, mode="fp32")
+    assert np.array_equal(app.cpu().numpy(), -ref)
+    assert np.array_equal(bits.cpu().numpy(), D.hard_bits(ref, code.k))
