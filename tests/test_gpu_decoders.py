@@ -245,3 +245,28 @@ def test_layered_at_the_largest_lift():
     ref = D.nms_layered(g, D.channel_lam(g, L, dtype=np.float32), 20, 0.75, mode="fp32")
     assert np.array_equal(app.cpu().numpy(), -ref)
     assert np.array_equal(bits.cpu().numpy(), D.hard_bits(ref, code.k))
+
+
+def test_spa_one_round_with_the_largest_lds_state():
+    """The BG2-shaped base lifted by Z = 256 (31.2 k edges: 122 KiB of
+    messages plus 32 KiB of channel values, 154 KiB of the 160 KiB of LDS,
+    a runtime lift): one sum-product round from an oracle state against
+    the oracle, 1e-4 relative."""
+    qb, _ = graph("bg2")
+    Z = 256
+    e_tx = 30 * Z
+    code = lsim.Code(qb.base, Z, qb.family, qb.n_punct_cols, e_tx)
+    g = qc.make_graph(qb.base, qb.kb, Z, qb.n_punct_cols, e_tx, family=qb.family)
+    assert 4 * (g.E + g.n_dec) > 128 * 1024
+    B = 3
+    rng = np.random.default_rng(21)
+    L32 = (rng.standard_normal((B, e_tx)) * 4.0).astype(np.float32)
+    lam = np.clip(D.channel_lam(g, L32.astype(np.float64)), -20, 20)
+    _, _, qs = D.spa_flood(g, lam, 3, trace=True)
+    q32 = qs[2].astype(np.float32)
+    r_ref, app_ref, q_ref = D.spa_iteration(g, lam, q32.astype(np.float64))
+    p = lsim.params(lsim.SPA_F32, iters=1, llr_max=20.0)
+    r, qq, lp = lsim.decode_state(code, T(L32).to(dev), p, q_in=T(q32).to(dev))
+    for got, ref in ((r, r_ref), (qq, q_ref), (lp, -app_ref)):
+        ok, w = rel_close(got.cpu().numpy(), ref, 1e-4)
+        assert ok, w
