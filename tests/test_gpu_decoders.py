@@ -270,3 +270,26 @@ def test_spa_one_round_with_the_largest_lds_state():
     for got, ref in ((r, r_ref), (qq, q_ref), (lp, -app_ref)):
         ok, w = rel_close(got.cpu().numpy(), ref, 1e-4)
         assert ok, w
+
+
+def test_oms_with_the_largest_lds_state():
+    """int8 offset min-sum on the BG2-shaped base at Z = 256 (packed pair
+    state 154 KiB of LDS, runtime lift), three codewords (the second pair
+    half empty): posteriors and bits equal the oracle's after 20 rounds."""
+    qb, _ = graph("bg2")
+    Z = 256
+    e_tx = 30 * Z
+    code = lsim.Code(qb.base, Z, qb.family, qb.n_punct_cols, e_tx)
+    g = qc.make_graph(qb.base, qb.kb, Z, qb.n_punct_cols, e_tx, family=qb.family)
+    B = 3
+    rng = np.random.default_rng(22)
+    u = rng.integers(0, 2, (B, qb.kb * Z)).astype(np.uint8)
+    c = qc.encode(qb.base, qb.kb, Z, qb.family, u)
+    t = c[:, g.tx_lo:g.tx_lo + e_tx].astype(np.float64)
+    L = (2.0 * t - 1.0) * 2.0 + rng.standard_normal(t.shape) * 2.0
+    q = modem.quantize(L.astype(np.float32))
+    p = lsim.params(lsim.OMS_I8, iters=20)
+    bits, lp = lsim.decode(code, T(q).to(dev), p, want_app=True)
+    ref = D.oms_flood(g, D.channel_lam(g, q, dtype=np.int64), 20)
+    assert np.array_equal(lp.cpu().numpy(), -ref.astype(np.float32))
+    assert np.array_equal(bits.cpu().numpy(), D.hard_bits(ref, code.k))
