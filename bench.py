@@ -505,8 +505,9 @@ def wbp_leg(torch, lsim, dev, code, qb, T=10):
 def polar_leg(torch, lsim, dev):
     """Polar code N = 1024, K = 512 (496 data bits + CRC-16 0x1021),
     Bhattacharyya construction at 2 dB, QPSK over AWGN, 4096 codewords at
-    Eb/N0 1, 1.5, 2, 2.5 dB (codeword b at point b mod 4): SC, SCL-8 and
-    SCL-8-CRC decode time (one launch, event-timed) and BLER per point."""
+    Eb/N0 1, 1.5, 2, 2.5 dB (codeword b at point b mod 4): SC, SCL-8,
+    SCL-8-CRC and SCL-32-CRC decode time (one launch, event-timed) and BLER
+    per point."""
     from inputs.workloads import data_seed
 
     n, K, r, poly = 10, 512, 16, 0x1021
@@ -524,7 +525,8 @@ def polar_leg(torch, lsim, dev):
     bits = torch.empty((B, D), dtype=torch.uint8, device=dev)
     out = {"batch": B, "ebn0_db": pts.tolist(), "encode_ms": round(_elapsed(
         torch, lambda: pc.encode(data, out=x), 5), 4)}
-    for name, L, use in (("sc", 1, False), ("scl8", 8, False), ("scl8_crc", 8, True)):
+    for name, L, use in (("sc", 1, False), ("scl8", 8, False), ("scl8_crc", 8, True),
+                         ("scl32_crc", 32, True)):
         pc.decode(llr, L, use, bits=bits)
         counts = lsim.count_errors(data, bits, bins=tb, nbins=len(pts)).cpu().numpy()
         ms = _elapsed(torch, lambda: pc.decode(llr, L, use, bits=bits), 3)

@@ -462,7 +462,7 @@ lsim_status lsim_polar_query(const lsim_polar* pc, int* N, int* K, int* crc_degr
 lsim_status lsim_polar_encode(const lsim_polar* pc, const uint8_t* d_data, int64_t B,
                               uint8_t* d_x, lsim_stream stream);
 /*
- * SC (list = 1), SCL (list 2, 4, 8) and SCL-CRC (use_crc != 0) decoding of
+ * SC (list = 1), SCL (list 2, 4, 8, 16, 32) and SCL-CRC (use_crc != 0) decoding of
  * d_llr f32[B][N] (boundary LLRs of x) into the data bits d_bits
  * u8[B][K - r].  LLR form with lambda = -L: f(a, b) = sgn(a) sgn(b)
  * min(|a|, |b|) to the left child, g(a, b, x) = b + (1 - 2x) a to the right

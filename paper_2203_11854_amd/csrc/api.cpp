@@ -1064,8 +1064,8 @@ lsim_status lsim_polar_encode(const lsim_polar* pc, const uint8_t* d_data, int64
 lsim_status lsim_polar_decode(const lsim_polar* pc, int list, int use_crc, const float* d_llr,
                               int64_t B, uint8_t* d_bits, float* d_pm, lsim_stream stream) {
   if (!pc || !d_llr || !d_bits || B < 1) return fail(LSIM_E_INVAL, "bad polar_decode arguments");
-  if (list != 1 && list != 2 && list != 4 && list != 8)
-    return fail(LSIM_E_UNSUPPORTED, "list size must be 1, 2, 4 or 8");
+  if (list != 1 && list != 2 && list != 4 && list != 8 && list != 16 && list != 32)
+    return fail(LSIM_E_UNSUPPORTED, "list size must be 1, 2, 4, 8, 16 or 32");
   if (use_crc && pc->dev.r == 0) return fail(LSIM_E_INVAL, "the code has no CRC");
   if (lsim::polar_decode_lds(list, pc->dev.N, pc->dev.K) > 160 * 1024)
     return fail(LSIM_E_UNSUPPORTED, "list state does not fit in LDS");

@@ -241,16 +241,16 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
         const float m2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mc), c2));
         rank += (m2 < mc) || (m2 == mc && c2 < lane);
       }
-      const uint32_t sv = (uint32_t)__ballot(lane < ncand && rank < L);
+      const uint64_t sv = __ballot(lane < ncand && rank < L);
       // parents with a surviving child / with both children surviving
       uint32_t anyp = 0, bothp = 0;
 #pragma unroll
       for (int p = 0; p < L; ++p) {
-        const uint32_t two = (sv >> (2 * p)) & 3u;
+        const uint32_t two = (uint32_t)(sv >> (2 * p)) & 3u;
         anyp |= (two != 0u) << p;
         bothp |= (two == 3u) << p;
       }
-      uint32_t freem = ~anyp & ((1u << L) - 1u);
+      uint32_t freem = ~anyp & (L == 32 ? 0xffffffffu : ((1u << L) - 1u));
       wave_sync();  // every lane has read pm and the leaf LLRs
       // each parent with two survivors copies the state still to be read to
       // the lowest free slot, in parent order
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
         for (int q = lane; q < W; q += kPolThreads) bw[d * W + q] = bw[p * W + q];
       }
       // metrics and the history of every surviving candidate
-      if (lane < ncand && ((sv >> lane) & 1u)) {
+      if (lane < ncand && ((sv >> lane) & 1ull)) {
         const int p = lane >> 1, bit = lane & 1;
         const bool both = (bothp >> p) & 1u;
         const int slot = (both && bit) ? mydest : p;
@@ -351,24 +351,22 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
     }
   }
   wave_sync();
-  int choice = 0;
-  {
-    // slots ordered by (metric, slot); first passing one under CRC
-    int best = -1, first = -1;
-    for (int q = 0; q < nact; ++q) {
-      // q-th slot in the order
-      int sel = -1;
-      for (int p = 0; p < nact; ++p) {
-        int rk = 0;
-        for (int p2 = 0; p2 < nact; ++p2)
-          rk += (pm[p2] < pm[p]) || (pm[p2] == pm[p] && p2 < p);
-        if (rk == q) sel = p;
-      }
-      if (first < 0) first = sel;
-      if (use_crc && r > 0 && best < 0 && pass[sel]) best = sel;
-    }
-    choice = best >= 0 ? best : first;
+  // slots ordered by (metric, slot): lane p < nact finds its rank; the
+  // decision is rank 0, or under CRC the passing slot of smallest rank
+  int key = 0x7fffffff, key_crc = 0x7fffffff;
+  if (lane < nact) {
+    int rk = 0;
+    for (int p2 = 0; p2 < nact; ++p2)
+      rk += (pm[p2] < pm[lane]) || (pm[p2] == pm[lane] && p2 < lane);
+    key = (rk << 8) | lane;
+    if (use_crc && r > 0 && pass[lane]) key_crc = key;
   }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    key = min(key, __shfl_xor(key, off, 64));
+    key_crc = min(key_crc, __shfl_xor(key_crc, off, 64));
+  }
+  const int choice = (key_crc != 0x7fffffff ? key_crc : key) & 0xff;
   const int D = K - r;
   for (int k = lane; k < D; k += kPolThreads) bits[b * D + k] = tb[choice * K + k];
   if (pm_out && lane < L) pm_out[b * L + lane] = lane < nact ? pm[lane] : INFINITY;
@@ -437,6 +435,8 @@ size_t polar_decode_lds(int list, int N, int K) {
     case 2: return polar_lds_bytes<2>(n, K);
     case 4: return polar_lds_bytes<4>(n, K);
     case 8: return polar_lds_bytes<8>(n, K);
+    case 16: return polar_lds_bytes<16>(n, K);
+    case 32: return polar_lds_bytes<32>(n, K);
     default: return 0;
   }
 }
@@ -448,6 +448,8 @@ hipError_t launch_polar_decode(const DevPolar& pc, int list, int use_crc, const 
     case 2: return launch_dec<2>(pc, llr, B, use_crc, bits, pm, s);
     case 4: return launch_dec<4>(pc, llr, B, use_crc, bits, pm, s);
     case 8: return launch_dec<8>(pc, llr, B, use_crc, bits, pm, s);
+    case 16: return launch_dec<16>(pc, llr, B, use_crc, bits, pm, s);
+    case 32: return launch_dec<32>(pc, llr, B, use_crc, bits, pm, s);
     default: return hipErrorInvalidValue;
   }
 }

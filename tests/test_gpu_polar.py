@@ -81,7 +81,9 @@ def _check(pc, mask, llr, L, crc, use_crc):
     (4, 8, 1, (0, 0), False), (5, 16, 2, (0, 0), False), (6, 32, 4, CRC8, True),
     (7, 64, 8, CRC8, False), (7, 64, 8, CRC8, True), (8, 128, 8, CRC16, True),
     (10, 512, 1, CRC16, False), (10, 512, 8, CRC16, True), (3, 8, 8, (0, 0), False),
-    (2, 1, 8, (0, 0), False), (1, 2, 4, (0, 0), False)])
+    (2, 1, 8, (0, 0), False), (1, 2, 4, (0, 0), False),
+    (8, 128, 16, CRC16, True), (10, 512, 16, CRC16, True), (9, 256, 32, CRC8, True),
+    (10, 1000, 32, (0, 0), False), (4, 5, 32, (0, 0), False)])
 def test_decoders_bit_exact(n, K, L, crc, use_crc):
     mask, pc = _code(n, K, 1.5, crc)
     B = 6 if n >= 10 else 12
@@ -136,3 +138,11 @@ def test_single_codeword_and_no_frozen_bits():
         llr = _noisy_llrs(x, 2.0, K / (1 << n), 501 + n)
         _check(pc, mask, llr, L, (0, 0), False)
 
+
+
+def test_unsupported_list_sizes_are_rejected():
+    mask, pc = _code(6, 32, 1.0)
+    llr = torch.zeros((2, 64), dtype=torch.float32, device=dev)
+    for L in (3, 64):
+        with pytest.raises(lsim.LsimError, match="list size"):
+            pc.decode(llr, L)
