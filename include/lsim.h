@@ -474,7 +474,8 @@ lsim_status lsim_polar_encode(const lsim_polar* pc, const uint8_t* d_data, int64
  * lowest slot); SCL-CRC takes, in that order, the first slot whose CRC
  * checks, else the first.  d_pm (nullable) f32[B][list] receives the final
  * metrics by slot (+inf for unused slots).  One workgroup per codeword
- * holds the list state in LDS (about N (4 + 6 list) + list K bytes);
+ * holds the list state in LDS (about 7 N + K bytes for SC, 4 N + list
+ * (1.15 N + K) for the lists: 56.5 KiB at N = 1024, K = 512, list 32);
  * LSIM_E_UNSUPPORTED if it exceeds 160 KiB.  use_crc on a code without CRC
  * -> LSIM_E_INVAL.
  */
