@@ -475,7 +475,7 @@ lsim_status lsim_polar_encode(const lsim_polar* pc, const uint8_t* d_data, int64
  * checks, else the first.  d_pm (nullable) f32[B][list] receives the final
  * metrics by slot (+inf for unused slots).  One workgroup per codeword
  * holds the list state in LDS (about 7 N + K bytes for SC, 4 N + list
- * (1.15 N + K) for the lists: 56.5 KiB at N = 1024, K = 512, list 32);
+ * (0.4 N + K) for the lists: 32.5 KiB at N = 1024, K = 512, list 32);
  * LSIM_E_UNSUPPORTED if it exceeds 160 KiB.  use_crc on a code without CRC
  * -> LSIM_E_INVAL.
  */

@@ -5,9 +5,10 @@
 //
 // Decoder: one wavefront per codeword, everything in LDS.  The node LLRs
 // of stage s (2^s values) are stored for 1 <= s < S0 = n - V, per list slot at
-// alpha[p][2^s .. 2^{s+1}); the top V <= 2 stages are never stored: they
-// are read only while stage S0 - 1 is computed (2^{V+1} times per codeword)
-// and are formed there on the fly from the channel LLRs.  A node at stage s
+// alpha[p][2^s .. 2^{s+1}); the top V stages (up to 4 in the list
+// decoders, 1 in SC) are never stored: they are read only while stage
+// S0 - 1 is computed (2^{V+1} times per codeword) and are formed there on
+// the fly from the channel LLRs.  A node at stage s
 // is the left (f) or right (g) child of its parent as bit s of the leaf
 // index is 0 or 1.  The partial sums of the pending left child of every
 // stage are bit-packed per slot in the list decoders (stage s in its own
@@ -27,7 +28,8 @@
 // children survive keeps bit 0 and copies its state to the lowest free
 // slot for bit 1 (the stored LLR stages above ctz(i + 1) and its partial-
 // sum words).  Every information leaf records (parent slot, bit) per slot;
-// the paths' bits are traced back at the end.  The leaf LLR (stage 0) is
+// at the end each slot's path is traced back into bit-packed words,
+// checking its CRC on the way.  The leaf LLR (stage 0) is
 // never stored: each lane that needs it forms it from its path's two
 // stage-1 values; the list decoders do not store stage-0 partial sums
 // either (an odd leaf's left sibling bit is the path's bit at leaf i - 1,
@@ -57,10 +59,11 @@ __host__ __device__ inline int polar_astr(int n, int vmax) {
   const int s0 = n - polar_virt(n, vmax);
   return s0 >= 2 ? (1 << s0) : 4;
 }
-// list decoders form two stages on the fly (half the LLR state, twice the
-// codewords per CU); SC, whose state is small anyway, forms one
+// list decoders form four stages on the fly (an eighth of the LLR state
+// of forming one: more codewords per CU, which hides the latency of the
+// dependent LDS steps); SC, whose state is small anyway, forms one
 template <int L>
-constexpr int polar_vmax() { return L == 1 ? 1 : 2; }
+constexpr int polar_vmax() { return L == 1 ? 1 : 4; }
 // first word of stage s's partial sums, and words per slot
 __host__ __device__ inline int polar_ws(int s) { return s < 5 ? s : 4 + (1 << (s - 5)); }
 __host__ __device__ inline int polar_wrow(int n) {
@@ -86,6 +89,21 @@ __device__ __forceinline__ float pol_f(float a, float c) {
 }
 
 __device__ __forceinline__ float pol_g(float a, float c, uint32_t x) { return x ? c - a : c + a; }
+
+// Value at position x of the stage-(n - D) node on leaf i's path, formed
+// from the channel LLRs through the D stages above it; bl(st, x) is the
+// slot's pending partial sum of stage st at x.
+template <int D, class BL>
+__device__ __forceinline__ float top_node(const float* ch, int n, int i, int x, const BL& bl) {
+  if constexpr (D == 0) {
+    return ch[x];
+  } else {
+    const int st = n - D;
+    const float a = top_node<D - 1>(ch, n, i, x, bl);
+    const float c = top_node<D - 1>(ch, n, i, x + (1 << st), bl);
+    return ((i >> st) & 1) ? pol_g(a, c, bl(st, x)) : pol_f(a, c);
+  }
+}
 
 // The 2^S-bit pattern of stage S < 5 replicated across a word, kept at the
 // positions whose bit S is clear.
@@ -117,7 +135,6 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
                                                                    float* __restrict__ pm_out) {
   extern __shared__ __align__(16) unsigned char sm[];
   __shared__ float pm[L];
-  __shared__ int pass[L];
   const int N = pc.N, n = pc.n, K = pc.K, r = pc.r;
   const int V = polar_virt(n, polar_vmax<L>()), S0 = n - V;
   const int A = polar_astr(n, polar_vmax<L>()), lgA = 31 - __builtin_clz(A);
@@ -181,29 +198,31 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
         }
       } else {
         // parent at stage S0: the channel (V = 0) or formed from it
-        const bool g1 = (i >> (n - 1)) & 1, g2 = n >= 2 && ((i >> (n - 2)) & 1);
-        const int Q1 = N >> 1, Q2 = N >> 2;
         for (int idx = lane; idx < cnt; idx += kPolThreads) {
           const int p = idx >> st, e = idx & (h - 1);
-          // value of the stage-(n-1) node at x
-          auto v1 = [&](int x) {
-            return g1 ? pol_g(ch[x], ch[x + Q1], blbit(p, n - 1, x)) : pol_f(ch[x], ch[x + Q1]);
-          };
-          // value of the stage-(n-2) node at x
-          auto v2 = [&](int x) {
-            const float a2 = v1(x), c2 = v1(x + Q2);
-            return g2 ? pol_g(a2, c2, blbit(p, n - 2, x)) : pol_f(a2, c2);
-          };
+          auto bl = [&](int s2, int x) { return blbit(p, s2, x); };
           float a, c;
-          if (V == 0) {
-            a = ch[e];
-            c = ch[e + h];
-          } else if (V == 1) {
-            a = v1(e);
-            c = v1(e + h);
-          } else {
-            a = v2(e);
-            c = v2(e + h);
+          switch (V) {
+            case 0:
+              a = ch[e];
+              c = ch[e + h];
+              break;
+            case 1:
+              a = top_node<1>(ch, n, i, e, bl);
+              c = top_node<1>(ch, n, i, e + h, bl);
+              break;
+            case 2:
+              a = top_node<2>(ch, n, i, e, bl);
+              c = top_node<2>(ch, n, i, e + h, bl);
+              break;
+            case 3:
+              a = top_node<3>(ch, n, i, e, bl);
+              c = top_node<3>(ch, n, i, e + h, bl);
+              break;
+            default:
+              a = top_node<4>(ch, n, i, e, bl);
+              c = top_node<4>(ch, n, i, e + h, bl);
+              break;
           }
           al[(p << lgA) + h + e] = use_g ? pol_g(a, c, blbit(p, st, e)) : pol_f(a, c);
         }
@@ -323,43 +342,48 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
       wave_sync();
     }
   }
-  // ---- each slot's information bits by tracing its history back, into
-  // the (now unused) LLR area; then CRC checks and the decision
-  uint8_t* tb = reinterpret_cast<uint8_t*>(al);  // [L][K] bytes <= L * A * 4
+  // ---- each slot's path traced back through its history (lane p, slot
+  // p) into bit-packed words in the (no longer read) LLR area: kw words
+  // per slot, L * kw <= L * A since K <= N and A >= N / 16.  Under CRC
+  // each path's data bits times their precomputed remainders, XOR the
+  // received CRC bits, must vanish.  The slots are ranked by (metric,
+  // slot) with a wavefront minimum over (rank, slot) keys; the decision
+  // is rank 0, or under CRC the passing slot of smallest rank.
+  const int D = K - r, kw = (K + 31) >> 5;
+  const bool crc_on = L > 1 && use_crc && r > 0;
+  uint32_t* tw = reinterpret_cast<uint32_t*>(al);
   if (lane < nact) {
     int slot = lane;
+    uint32_t word = 0;
     for (int jj = K - 1; jj >= 0; --jj) {
       const int v = rec[jj * L + slot];
-      tb[lane * K + jj] = (uint8_t)(v & 1);
+      word |= (uint32_t)(v & 1) << (jj & 31);
+      if ((jj & 31) == 0) {
+        tw[lane * kw + (jj >> 5)] = word;
+        word = 0;
+      }
       slot = v >> 1;
     }
   }
   wave_sync();
-  if (use_crc && r > 0) {
-    const int D = K - r;
+  bool passes = false;
+  if (crc_on) {
     for (int p = 0; p < nact; ++p) {
       uint32_t acc = 0;
-      for (int k = lane; k < D; k += kPolThreads)
-        if (tb[p * K + k]) acc ^= pc.crc_tab[k];
+      for (int k = lane; k < K; k += kPolThreads)
+        if ((tw[p * kw + (k >> 5)] >> (k & 31)) & 1u) acc ^= k < D ? pc.crc_tab[k] : 1u << (K - 1 - k);
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) acc ^= __shfl_xor(acc, off, 64);
-      if (lane == 0) {
-        uint32_t got = 0;
-        for (int q = 0; q < r; ++q) got = (got << 1) | tb[p * K + D + q];
-        pass[p] = got == acc;
-      }
+      if (lane == p) passes = acc == 0u;
     }
   }
-  wave_sync();
-  // slots ordered by (metric, slot): lane p < nact finds its rank; the
-  // decision is rank 0, or under CRC the passing slot of smallest rank
   int key = 0x7fffffff, key_crc = 0x7fffffff;
   if (lane < nact) {
     int rk = 0;
     for (int p2 = 0; p2 < nact; ++p2)
       rk += (pm[p2] < pm[lane]) || (pm[p2] == pm[lane] && p2 < lane);
     key = (rk << 8) | lane;
-    if (use_crc && r > 0 && pass[lane]) key_crc = key;
+    if (passes) key_crc = key;
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -367,8 +391,8 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
     key_crc = min(key_crc, __shfl_xor(key_crc, off, 64));
   }
   const int choice = (key_crc != 0x7fffffff ? key_crc : key) & 0xff;
-  const int D = K - r;
-  for (int k = lane; k < D; k += kPolThreads) bits[b * D + k] = tb[choice * K + k];
+  for (int k = lane; k < D; k += kPolThreads)
+    bits[b * D + k] = (uint8_t)((tw[choice * kw + (k >> 5)] >> (k & 31)) & 1u);
   if (pm_out && lane < L) pm_out[b * L + lane] = lane < nact ? pm[lane] : INFINITY;
 }
 

@@ -131,7 +131,7 @@ def test_full_size_batch_sampled():
 
 
 def test_single_codeword_and_no_frozen_bits():
-    for n, K, L in ((10, 1024, 8), (6, 64, 1), (4, 3, 2)):
+    for n, K, L in ((10, 1024, 8), (6, 64, 1), (4, 3, 2), (7, 128, 32), (6, 64, 16)):
         mask, pc = _code(n, K, 1.0)
         data = rand.bits(500 + n, (1, K))
         x = P.encode(data, mask)
