@@ -107,9 +107,9 @@ def test_ties_and_zero_llrs():
 
 
 def test_full_size_batch_sampled():
-    """The benchmark's code and batch (N 1024, K 512 with CRC-16, list 8,
-    4096 codewords at Eb/N0 1.5 dB): sampled codewords against the oracle;
-    SCL-CRC is at least as good as SCL and SC on the whole batch."""
+    """The benchmark's code and batch (N 1024, K 512 with CRC-16, lists 8
+    and 32, 4096 codewords at Eb/N0 1.5 dB): sampled codewords against the
+    oracle; SCL-CRC is at least as good as SCL and SC on the whole batch."""
     n, K, crc = 10, 512, CRC16
     mask, pc = _code(n, K, 2.0, crc)
     B = 4096
@@ -128,6 +128,8 @@ def test_full_size_batch_sampled():
     assert errs[(8, True)] <= errs[(8, False)] <= errs[(1, False)]
     rows = np.array([0, 1, 2047, 4095])
     _check(pc, mask, llr.cpu().numpy()[rows], 8, crc, True)
+    # the list-32 decoder at the same size, two sampled codewords
+    _check(pc, mask, llr.cpu().numpy()[rows[[0, 3]]], 32, crc, True)
 
 
 def test_single_codeword_and_no_frozen_bits():
