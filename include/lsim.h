@@ -221,6 +221,28 @@ lsim_status lsim_decode(const lsim_code* code, const lsim_decode_params* p, cons
                         size_t work_bytes, lsim_stream stream);
 
 /*
+ * lsim_decode without a workspace argument, for callers that cannot
+ * allocate device memory: code under hipGraph capture, tight serving loops,
+ * harnesses that forbid allocation.  Arguments and outputs as lsim_decode.
+ * The layered decoder (LSIM_NMS_F32) keeps its per-check state in a
+ * library-owned static device buffer of LSIM_NOALLOC_SCRATCH_BYTES, one per
+ * GPU, held from the library's load until the process ends; the flooding
+ * decoders need none.  The call runs on the current device, which must be
+ * the code's device.  Nothing in the buffer has to start at zero (the state
+ * is written before it is read), so calls need no clearing in between.
+ * Calls that overlap in time on one GPU (other streams, other host threads)
+ * share the buffer and race: serialize them.
+ * Errors: LSIM_E_NOMEM when lsim_decode_workspace() for (code, p, B)
+ * exceeds LSIM_NOALLOC_SCRATCH_BYTES (nothing is launched; split the
+ * batch); LSIM_E_INVAL when the current device is not the code's; otherwise
+ * as lsim_decode.  Allocates nothing (no hipMalloc, no library allocation).
+ */
+#define LSIM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+lsim_status lsim_decode_noalloc(const lsim_code* code, const lsim_decode_params* p,
+                                const void* d_llr, int64_t B, uint8_t* d_bits, float* d_app,
+                                lsim_stream stream);
+
+/*
  * Decoder state in canonical edge order (base nonzeros row-major, edge
  * e*Z + r for lift index r), for per-iteration parity checks.  Flooding
  * decoders: d_q_in (nullable, f32 or i8 [B][E]) replaces the initial

@@ -76,6 +76,7 @@ _SIGS = {
     "lsim_quantize": [_P, _I64, _F, _I, _P, _P],
     "lsim_decode_workspace": [_P, ctypes.POINTER(DecodeParams), _I64, ctypes.POINTER(_SZ)],
     "lsim_decode": [_P, ctypes.POINTER(DecodeParams), _P, _I64, _P, _P, _P, _SZ, _P],
+    "lsim_decode_noalloc": [_P, ctypes.POINTER(DecodeParams), _P, _I64, _P, _P, _P],
     "lsim_decode_state": [_P, ctypes.POINTER(DecodeParams), _P, _I64, _P, _P, _P, _P, _P, _SZ, _P],
     "lsim_count_errors": [_P, _I64, _P, _I64, _I64, _P, _I, _P, _P],
     "lsim_syndrome": [_P, _P, _I64, _I64, _P, _P],
@@ -406,6 +407,16 @@ def decode(code: Code, llr, p: DecodeParams, want_bits=True, want_app=False, bit
           _ptr(bits, torch.uint8, "bits") if want_bits else None,
           _ptr(app, torch.float32, "app") if want_app else None,
           _ptr(work, None, "work"), nbytes, _stream())
+    return bits, app
+
+
+def decode_noalloc(code: Code, llr, p: DecodeParams, bits, app=None):
+    """lsim_decode_noalloc: as decode(), into caller-provided outputs, with the
+    layered decoder's state in the library's static device scratch."""
+    B = llr.shape[0]
+    dt = torch.int8 if p.algo == OMS_I8 else torch.float32
+    _call("lsim_decode_noalloc", code.handle, ctypes.byref(p), _ptr(llr, dt, "llr"), B,
+          _ptr(bits, torch.uint8, "bits"), _ptr(app, torch.float32, "app"), _stream())
     return bits, app
 
 

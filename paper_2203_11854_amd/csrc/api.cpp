@@ -491,6 +491,34 @@ lsim_status lsim_decode(const lsim_code* code, const lsim_decode_params* p, cons
                        work_bytes, stream);
 }
 
+lsim_status lsim_decode_noalloc(const lsim_code* code, const lsim_decode_params* p,
+                                const void* d_llr, int64_t B, uint8_t* d_bits, float* d_app,
+                                lsim_stream stream) {
+  lsim_status st = check_params(code, p);
+  if (st != LSIM_OK) return st;
+  if (!d_llr || B < 1) return fail(LSIM_E_INVAL, "null llr or B < 1");
+  if (p->algo != LSIM_NMS_F32)  // the flooding decoders need no workspace
+    return decode_common(code, p, d_llr, B, d_bits, d_app, nullptr, nullptr, nullptr, nullptr, 0,
+                         stream);
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return dev_status(e, "decode_noalloc");
+  if (dev != code->device)
+    return fail(LSIM_E_INVAL, "decode_noalloc: the current device is not the code's device");
+  const size_t need = lsim::layered_state_words(code->dev, B) * 4;
+  if (need > LSIM_NOALLOC_SCRATCH_BYTES)
+    return fail(LSIM_E_NOMEM, "decode_noalloc: the layered decoder state for this batch (" +
+                                  std::to_string(need) + " bytes) exceeds the " +
+                                  std::to_string((size_t)LSIM_NOALLOC_SCRATCH_BYTES) +
+                                  "-byte device scratch; split the batch");
+  void* scratch = nullptr;
+  size_t bytes = 0;
+  e = lsim::noalloc_scratch(&scratch, &bytes);
+  if (e != hipSuccess) return dev_status(e, "decode_noalloc scratch lookup");
+  return decode_common(code, p, d_llr, B, d_bits, d_app, nullptr, nullptr, nullptr, scratch, bytes,
+                       stream);
+}
+
 lsim_status lsim_decode_state(const lsim_code* code, const lsim_decode_params* p,
                               const void* d_llr, int64_t B, const void* d_q_in, void* d_r_out,
                               void* d_q_out, float* d_app, void* d_work, size_t work_bytes,

@@ -45,6 +45,10 @@ hipError_t launch_oms2(const DevCode& c, const lsim_decode_params& p, const int8
                        int8_t* q_out, hipStream_t s, std::string* why);
 size_t oms2_lds_bytes(const DevCode& c);
 
+// Device address (on the current device) and size of the library-owned
+// scratch of lsim_decode_noalloc (k_noalloc.hip); looked up once per device.
+hipError_t noalloc_scratch(void** ptr, size_t* bytes);
+
 // Layered decoder and mixed batches (k_layered.hip)
 struct LayerShape {
   DevCode code;
