@@ -108,6 +108,18 @@ lsim_status lsim_encode(const lsim_code* code, const uint8_t* d_u, int64_t B, ui
                         lsim_stream stream);
 
 /*
+ * Noise variance of the AWGN channel for an Eb/N0 in dB (Listing 1 passes
+ * the channel its noise variance `no`; the link's symbols have unit average
+ * energy, so one information bit carries 1 / (rate * m) of a symbol's energy):
+ * no[i] = 1 / (rate * m * 10^(ebn0_db[i] / 10)).  Host arrays ebn0_db[n] ->
+ * no[n] (double), rate = k / e_tx of the code, m = bits per symbol.  Runs on
+ * the host, touches no device memory.  Errors: LSIM_E_INVAL on a null
+ * pointer, n < 0, rate not in (0, 1], m < 1 or a non-finite result.
+ */
+lsim_status lsim_ebn0_to_n0(const double* ebn0_db, int64_t n, double rate, int bits_per_sym,
+                            double* no);
+
+/*
  * Mapper + AWGN (Listing 1, AWGN takes the noise variance N0): takes the
  * transmitted slice of d_c u8[B][n_mother], maps m = bits_per_sym bits per
  * symbol (1 = BPSK x = 1-2c; 2, 4, 6 = square Gray QAM of 3GPP TS 38.211

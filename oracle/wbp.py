@@ -49,8 +49,13 @@ def loss_numpy(g: Graph, L_ch: np.ndarray, w: np.ndarray, c: np.ndarray) -> floa
     return bce_with_logits(-app, c)
 
 
-def grad_autograd(g: Graph, L_ch: np.ndarray, w: np.ndarray, c: np.ndarray):
-    """(loss, dloss/dL_ch, dloss/dw, clamp_hits) by torch float64 autograd.
+def grad_autograd(g: Graph, L_ch: np.ndarray, w: np.ndarray, c: np.ndarray,
+                  want_margin: bool = False):
+    """(loss, dloss/dL_ch, dloss/dw, clamp_hits) by torch float64 autograd;
+    with ``want_margin`` also, per codeword, the smallest distance of any
+    clamped value (channel input, check output, variable output) to the
+    clamp threshold -- where it is small, a single-precision forward may take
+    the other side of the clamp, and with it a different derivative.
 
     The check update is written in the tanh form
     r_v = 2 atanh(prod_{v' != v} tanh(q_v'/2)), whose derivative is finite
@@ -65,8 +70,14 @@ def grad_autograd(g: Graph, L_ch: np.ndarray, w: np.ndarray, c: np.ndarray):
     vn = torch.tensor(g.edge_vn(), dtype=torch.long)
     rows = [torch.tensor(g.row_edge_ids(i), dtype=torch.long) for i in range(g.rows)]
     hits = 0
+    margin = torch.full((Lt.shape[0],), float("inf"), dtype=dt)
+
+    def near(x):
+        return torch.minimum(margin, (x.detach().abs() - LLR_MAX).abs().amin(dim=1))
+
     lam_raw = -Lt
     hits += int((lam_raw.abs() > LLR_MAX).sum())
+    margin = near(lam_raw)
     lam = torch.clamp(lam_raw, -LLR_MAX, LLR_MAX)
     q = lam[:, vn]
     app = lam
@@ -86,16 +97,20 @@ def grad_autograd(g: Graph, L_ch: np.ndarray, w: np.ndarray, c: np.ndarray):
         # order is the canonical order
         r_list = torch.cat([val.reshape(val.shape[0], -1) for _, val in parts], dim=1)
         hits += int((r_list.abs() > LLR_MAX).sum())
+        margin = near(r_list)
         r = torch.clamp(r_list, -LLR_MAX, LLR_MAX)
         wr = r * wt[t][None, :]
         app = lam.index_add(1, vn, wr)
         qn = app[:, vn] - wr
-        hits += int((qn.abs() > LLR_MAX).sum()) if t + 1 < wt.shape[0] else 0
+        if t + 1 < wt.shape[0]:
+            hits += int((qn.abs() > LLR_MAX).sum())
+            margin = near(qn)
         q = torch.clamp(qn, -LLR_MAX, LLR_MAX)
     Lp = -app
     loss = torch.mean(torch.nn.functional.softplus(Lp) - ct * Lp)
     loss.backward()
-    return float(loss), Lt.grad.numpy().copy(), wt.grad.numpy().copy(), hits
+    out = (float(loss.detach()), Lt.grad.numpy().copy(), wt.grad.numpy().copy(), hits)
+    return out + (margin.numpy().copy(),) if want_margin else out
 
 
 def fd_grad(fun, x: np.ndarray, idx: np.ndarray, h: float = 1e-6) -> np.ndarray:

@@ -81,6 +81,7 @@ _SIGS = {
     "lsim_count_errors": [_P, _I64, _P, _I64, _I64, _P, _I, _P, _P],
     "lsim_syndrome": [_P, _P, _I64, _I64, _P, _P],
     "lsim_hard_bits": [_P, _I64, _I64, _I64, _P, _P],
+    "lsim_ebn0_to_n0": [_P, _I64, ctypes.c_double, _I, _P],
     "lsim_mixed_plan_create": [_P, _P, _I, ctypes.POINTER(DecodeParams), _P, _I, ctypes.POINTER(_P)],
     "lsim_mixed_plan_destroy": [_P],
     "lsim_mixed_workspace": [_P, ctypes.POINTER(_SZ)],
@@ -468,9 +469,14 @@ def syndrome(code: Code, hard):
 
 
 def ebn0_to_n0(ebn0_db, rate: float, m: int):
-    """N0 = 1 / (R m 10^(EbN0/10)) for unit-energy symbols (host helper)."""
+    """Noise variance N0 per Eb/N0 in dB (lsim_ebn0_to_n0); a scalar in gives
+    a float, an array in gives a float64 array of its shape."""
     import numpy as np
-    return 1.0 / (rate * m * 10.0 ** (np.asarray(ebn0_db, dtype=np.float64) / 10.0))
+    shape = np.shape(ebn0_db)
+    x = np.ascontiguousarray(np.asarray(ebn0_db, dtype=np.float64).reshape(-1))
+    out = np.empty_like(x)
+    _call("lsim_ebn0_to_n0", x.ctypes.data, x.size, float(rate), int(m), out.ctypes.data)
+    return float(out[0]) if shape == () else out.reshape(shape)
 
 
 # ----------------------------------------------------------- mixed batches

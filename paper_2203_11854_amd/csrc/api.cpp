@@ -601,6 +601,19 @@ lsim_status lsim_count_errors(const uint8_t* d_ref, int64_t ref_stride, const ui
                     "count_errors");
 }
 
+lsim_status lsim_ebn0_to_n0(const double* ebn0_db, int64_t n, double rate, int bits_per_sym,
+                            double* no) {
+  if (!ebn0_db || !no || n < 0 || !(rate > 0.0 && rate <= 1.0) || bits_per_sym < 1)
+    return fail(LSIM_E_INVAL, "bad ebn0_to_n0 arguments");
+  for (int64_t i = 0; i < n; ++i) {
+    // energy per information bit = symbol energy (1) / (rate * m)
+    const double v = 1.0 / (rate * bits_per_sym * std::pow(10.0, ebn0_db[i] / 10.0));
+    if (!std::isfinite(v)) return fail(LSIM_E_INVAL, "Eb/N0 gives a non-finite noise variance");
+    no[i] = v;
+  }
+  return LSIM_OK;
+}
+
 lsim_status lsim_hard_bits(const float* d_llr, int64_t stride, int64_t B, int64_t k,
                            uint8_t* d_bits, lsim_stream stream) {
   if (!d_llr || !d_bits || B < 1 || k < 1 || stride < k)

@@ -109,3 +109,19 @@ def test_polar_create_validates_on_host():
     assert lib.lsim_polar_construct(3, 9, 1.0, p) == INVAL
     assert lib.lsim_polar_decode(None, 1, 0, ctypes.c_void_p(16), 1, ctypes.c_void_p(16), None,
                                  None) == INVAL
+
+
+def test_ebn0_to_n0_matches_the_oracle_and_rejects_bad_arguments():
+    from oracle import modem
+    pts = np.arange(-2.0, 6.01, 0.5)
+    for rate, m in ((1 / 3, 4), (0.5, 1), (8448 / 25344, 6), (1.0, 2)):
+        got = L.ebn0_to_n0(pts, rate, m)
+        ref = modem.ebn0_to_n0(pts, rate, m)
+        assert got.shape == pts.shape and np.allclose(got, ref, rtol=1e-15, atol=0)
+    assert isinstance(L.ebn0_to_n0(3.0, 0.5, 4), float)
+    assert L.ebn0_to_n0(np.zeros((2, 3)), 0.5, 2).shape == (2, 3)
+    for rate, m in ((0.0, 4), (1.5, 4), (0.5, 0)):
+        with pytest.raises(L.LsimError, match="status 1"):
+            L.ebn0_to_n0(1.0, rate, m)
+    with pytest.raises(L.LsimError, match="status 1"):
+        L.ebn0_to_n0(-4000.0, 0.5, 4)

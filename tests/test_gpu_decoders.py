@@ -142,8 +142,10 @@ def test_workgroup_size_invariance():
 
 
 def test_layered_large_lift_tile_invariance():
-    """BG1 (Z=384): one codeword per workgroup (384 threads) and two per
-    workgroup (768 and 1024 threads) give the same bits and posteriors."""
+    """BG1 (Z=384): the default launch and launches of 384, 768 and 1024
+    threads give the same bits and posteriors (a BG1 codeword's posteriors
+    take 104 KB of LDS, so every one of them decodes one codeword per
+    workgroup; the wider ones leave lanes idle)."""
     qb, g, code = gcode("bg1")
     tx = oracle_llrs("bg1", 3, 2.5, 67)
     llr = T(tx["L"].astype(np.float32)).to(dev)

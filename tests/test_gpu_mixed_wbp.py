@@ -222,6 +222,78 @@ def test_wbp_gradient_vs_autograd():
         assert rel <= 1e-3 and cos >= 0.99999
 
 
+def _elementwise(got, ref, what, tol=1e-3):
+    """|got - ref| <= tol * max(|ref|, 0.01 * rms(ref)) for every element;
+    prints and returns the worst element's ratio."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    rms = float(np.sqrt(np.mean(ref ** 2)))
+    floor = np.maximum(np.abs(ref), 0.01 * rms)
+    ratio = np.abs(got - ref) / np.where(floor > 0, floor, 1.0)
+    i = np.unravel_index(int(np.argmax(ratio)), ratio.shape)
+    print(f"{what}: worst |d|/floor {ratio[i]:.2e} at {tuple(int(x) for x in i)} "
+          f"(got {got[i]:.6e}, ref {ref[i]:.6e}, rms {rms:.3e})")
+    assert ratio[i] <= tol, (what, i, got[i], ref[i])
+    return float(ratio[i])
+
+
+@pytest.mark.parametrize("Tn", [10, 20])
+def test_wbp_adjoint_at_the_training_launch(Tn):
+    """The adjoint at the training step's launch (BG2 code, B = 2048, T = 10,
+    and T = 20 as the bench also times): the loss gradient is nonzero only on
+    a few sampled codewords, so dL/dw equals the oracle's float64 autograd
+    over those codewords alone.  dL/dL_ch of the sampled rows and dL/dw are
+    compared element by element; every other row's dL/dL_ch must be exactly
+    zero.  Sampled rows are taken only where no clamped value of the oracle's
+    forward lies within 1e-3 of the clamp threshold (there float32 and
+    float64 may take different sides)."""
+    qb = BG2.load()
+    g = qc.graph_from_qcbase(qb, 3840)
+    code = lsim.Code.from_qcbase(qb, 3840)
+    B, m = 2048, 4
+    rows = np.array([5, 700, 1401, 2046, 333, 1999])
+    ebn0 = np.array([1.0, 1.6, 2.2, 2.8, 3.4, 4.0])
+    seed = 0x2203118500000590 + Tn
+    w = rand.uniform(seed + 1, (Tn, g.E), 0.7, 1.3).astype(np.float32)
+    pool = [pipeline.transmit(g, qb.family, seed, int(b), 1,
+                              np.array([pipeline.n0_for(g, e, m)]), m, "maxlog")
+            for b, e in zip(rows, ebn0)]
+    L32 = np.concatenate([t["L"] for t in pool]).astype(np.float32)
+    c = np.concatenate([t["c"][:, :g.n_dec] for t in pool]).astype(np.float64)
+    Lch = np.zeros((len(rows), g.n_dec))
+    Lch[:, g.tx_lo:g.tx_lo + g.e_tx] = L32
+    *_, margin = wbp.grad_autograd(g, Lch, w.astype(np.float64), c, want_margin=True)
+    keep = margin >= 1e-3
+    print("clamp margins", margin, "kept", int(keep.sum()))
+    assert keep.sum() >= 3
+    rows, L32, c, Lch = rows[keep], L32[keep], c[keep], Lch[keep]
+    K = len(rows)
+    loss_ref, gL_ref, gw_ref, hits = wbp.grad_autograd(g, Lch, w.astype(np.float64), c)
+    print("clamp hits on the kept rows", hits)
+    # the full batch: the sampled rows carry the oracle's LLRs, the others
+    # seeded Gaussian LLRs
+    full = rand.gaussian(seed + 2, (B, g.e_tx), scale=4.0).astype(np.float32)
+    full[rows] = L32
+    labels = np.zeros((B, g.n_dec), dtype=np.uint8)
+    labels[rows] = c.astype(np.uint8)
+    tl, tw = T(full).to(dev), T(w).to(dev)
+    lp, ck = lsim.wbp_forward(code, tw, tl, Tn)
+    gpost, _ = lsim.bce_grad(lp, T(labels).to(dev), 1.0 / (K * g.n_dec))
+    mask = torch.zeros((B, 1), dtype=torch.float32, device=dev)
+    mask[T(rows).to(dev)] = 1.0
+    gpost = (gpost * mask).contiguous()
+    gllr, gw = lsim.wbp_backward(code, tw, tl, ck, gpost, Tn)
+    gllr, gw = gllr.cpu().numpy(), gw.cpu().numpy()
+    other = np.ones(B, dtype=bool)
+    other[rows] = False
+    assert not np.any(gllr[other]), "rows with zero output gradient got a nonzero dL/dL_ch"
+    _elementwise(gllr[rows], gL_ref[:, g.tx_lo:g.tx_lo + g.e_tx], f"dL/dL_ch T={Tn}")
+    _elementwise(gw, gw_ref, f"dL/dw T={Tn}")
+    # checkpoints on and off: the same posteriors bit for bit
+    lp2, _ = lsim.wbp_forward(code, tw, tl, Tn, want_ckpt=False)
+    assert torch.equal(lp, lp2)
+
+
 def test_wbp_autograd_function_and_determinism():
     qb, g, L32, w, c = wbp_case(B=4, Tn=2)
     code = lsim.Code.from_qcbase(qb, 3840)
@@ -265,6 +337,7 @@ def test_ndm_forward_backward_vs_oracle():
     rel = np.linalg.norm(gp - gref) / np.linalg.norm(gref)
     assert rel <= 1e-5, rel
     _check_groups(gp, gref, 1e-5)
+    _elementwise(gp, gref, "NDM dL/dparams", tol=1e-4)
 
 
 def _check_groups(gp, gref, tol):
@@ -314,6 +387,7 @@ def test_ndm_full_size():
                             n0.astype(np.float64), gl.astype(np.float64))
     print("symbols next to a kink:", int(near.sum()))
     _check_groups(gp, gref, 1e-5)
+    _elementwise(gp, gref, "NDM dL/dparams, full size", tol=1e-3)
 
 
 def test_bce_and_adam():
