@@ -85,6 +85,9 @@ typedef struct {
   int64_t m_dec;      /* decoded checks */
   int64_t n_edges;    /* edges of the decoded graph, E */
   int32_t Z, mb, nb, kb, rows, cols, n_punct_cols, max_row_deg, max_col_deg;
+  /* layered decoder's placement: columns whose posteriors it keeps in LDS,
+   * rows whose last column (degree one) travels with the check state */
+  int32_t n_shared_cols, n_private_rows;
 } lsim_code_info;
 
 lsim_status lsim_code_query(const lsim_code* code, lsim_code_info* info);
@@ -223,8 +226,10 @@ typedef struct {
  * (SPA, NMS) or i8[B][e_tx] (OMS, quantized LLRs).  Outputs: d_bits
  * u8[B][k] hard decisions [L_post > 0] of the information bits (nullable),
  * d_app f32[B][n_dec] posteriors L_post (nullable; integers for OMS).
- * d_work: device workspace of at least lsim_decode_workspace() bytes (the
- * layered decoder keeps its per-check state there; others need 0 bytes).
+ * d_work: device workspace of at least lsim_decode_workspace() bytes,
+ * 16-byte aligned (the layered decoder keeps one 16-byte record per check
+ * there; the others need 0 bytes).  An unaligned or short workspace for the
+ * layered decoder -> LSIM_E_INVAL / LSIM_E_NOMEM.
  */
 lsim_status lsim_decode_workspace(const lsim_code* code, const lsim_decode_params* p, int64_t B,
                                   size_t* bytes);
@@ -356,7 +361,8 @@ lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t*
                                    const int32_t* codewords_per_tile, int threads,
                                    lsim_plan** out);
 void lsim_mixed_plan_destroy(lsim_plan* plan);
-/* Bytes of device workspace the plan's decode needs. */
+/* Bytes of device workspace the plan's decode needs (pass it 16-byte
+ * aligned). */
 lsim_status lsim_mixed_workspace(const lsim_plan* plan, size_t* bytes);
 /*
  * One persistent launch over the plan's work list: a small kernel resets the
@@ -528,6 +534,39 @@ lsim_status lsim_map_awgn_bits(int bits_per_sym, const uint8_t* d_bits, int64_t 
                                float* d_y, lsim_stream stream);
 
 /* ---------------------------------------------------------------- misc */
+
+/* ------------------------------------------------------ peak-rate probes */
+
+/*
+ * Roofline denominators measured on the device itself (the decoders' rates
+ * are reported as fractions of these beside the published peaks).  One
+ * launch of `grid` workgroups of 256 threads on `stream`; *units receives
+ * the work the launch does, to be divided by its event-timed duration:
+ *  LSIM_PROBE_COPY   d_src -> d_dst, `bytes` (a multiple of 16) each; units =
+ *                    bytes read + written.
+ *  LSIM_PROBE_READ   reads `bytes` of d_src; d_dst u32[grid*256] receives one
+ *                    word per thread; units = bytes read.
+ *  LSIM_PROBE_LDS_READ / LSIM_PROBE_LDS_WRITE  each thread reads / writes 16
+ *                    bytes of its workgroup's 64 KB of LDS 8*rounds times,
+ *                    lane-consecutive (no bank conflicts); d_dst u32[grid*256];
+ *                    units = LDS bytes.
+ *  LSIM_PROBE_FMA / LSIM_PROBE_EXP2  8 independent chains per thread of
+ *                    `rounds` fused multiply-adds / base-2 exponentials;
+ *                    d_dst f32[grid*256]; units = VALU lane operations.
+ * Errors: LSIM_E_INVAL on an unknown kind, grid outside 1..65536, rounds < 1,
+ * a null d_dst, or (copy, read) a null d_src or bytes not a positive multiple
+ * of 16.
+ */
+enum {
+  LSIM_PROBE_COPY = 0,
+  LSIM_PROBE_READ = 1,
+  LSIM_PROBE_LDS_READ = 2,
+  LSIM_PROBE_LDS_WRITE = 3,
+  LSIM_PROBE_FMA = 4,
+  LSIM_PROBE_EXP2 = 5
+};
+lsim_status lsim_probe(int kind, const void* d_src, void* d_dst, int64_t bytes, int rounds,
+                       int grid, int64_t* units, lsim_stream stream);
 
 const char* lsim_last_error(void);
 const char* lsim_version(void);

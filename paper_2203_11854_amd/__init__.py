@@ -34,7 +34,8 @@ class CodeInfo(ctypes.Structure):
                 ("Z", ctypes.c_int32), ("mb", ctypes.c_int32), ("nb", ctypes.c_int32),
                 ("kb", ctypes.c_int32), ("rows", ctypes.c_int32), ("cols", ctypes.c_int32),
                 ("n_punct_cols", ctypes.c_int32), ("max_row_deg", ctypes.c_int32),
-                ("max_col_deg", ctypes.c_int32)]
+                ("max_col_deg", ctypes.c_int32), ("n_shared_cols", ctypes.c_int32),
+                ("n_private_rows", ctypes.c_int32)]
 
 
 class DecodeParams(ctypes.Structure):
@@ -82,6 +83,7 @@ _SIGS = {
     "lsim_syndrome": [_P, _P, _I64, _I64, _P, _P],
     "lsim_hard_bits": [_P, _I64, _I64, _I64, _P, _P],
     "lsim_ebn0_to_n0": [_P, _I64, ctypes.c_double, _I, _P],
+    "lsim_probe": [_I, _P, _P, _I64, _I, _I, ctypes.POINTER(_I64), _P],
     "lsim_mixed_plan_create": [_P, _P, _I, ctypes.POINTER(DecodeParams), _P, _I, ctypes.POINTER(_P)],
     "lsim_mixed_plan_destroy": [_P],
     "lsim_mixed_workspace": [_P, ctypes.POINTER(_SZ)],
@@ -477,6 +479,19 @@ def ebn0_to_n0(ebn0_db, rate: float, m: int):
     out = np.empty_like(x)
     _call("lsim_ebn0_to_n0", x.ctypes.data, x.size, float(rate), int(m), out.ctypes.data)
     return float(out[0]) if shape == () else out.reshape(shape)
+
+
+PROBE_COPY, PROBE_READ, PROBE_LDS_READ, PROBE_LDS_WRITE, PROBE_FMA, PROBE_EXP2 = range(6)
+
+
+def probe(kind: int, dst, src=None, nbytes: int = 0, rounds: int = 1, grid: int = 1024) -> int:
+    """One peak-rate probe launch (lsim_probe) on the current stream; returns
+    the work units it does (bytes or lane operations)."""
+    units = _I64()
+    _call("lsim_probe", kind, _ptr(src, None, "src") if src is not None else None,
+          _ptr(dst, None, "dst"), int(nbytes), int(rounds), int(grid), ctypes.byref(units),
+          _stream())
+    return units.value
 
 
 # ----------------------------------------------------------- mixed batches

@@ -243,6 +243,31 @@ lsim_status lsim_code_create(const int16_t* base, int mb, int nb, int Z, int fam
     ecz[2 * e] = c->ent_col[e] * Z;
     ecz[2 * e + 1] = c->ent_shift[e];
   }
+  // layered decoder: private rows (last entry in a column of degree one) and
+  // LDS slots of the shared columns
+  std::vector<int> row_priv(rows, -1), priv_row, shared_col;
+  std::vector<char> is_priv_col(cols, 0);
+  for (int i = 0; i < rows; ++i) {
+    const int j = c->ent_col[c->row_ptr[i + 1] - 1];
+    if (col_deg[j] == 1) {
+      row_priv[i] = (int)priv_row.size();
+      priv_row.push_back(i);
+      is_priv_col[j] = 1;
+    }
+  }
+  std::vector<int> col_slot(cols, -1);
+  for (int j = 0; j < cols; ++j)
+    if (!is_priv_col[j]) {
+      col_slot[j] = (int)shared_col.size();
+      shared_col.push_back(j);
+    }
+  std::vector<int> elz(2 * (size_t)nnz);
+  for (int e = 0; e < nnz; ++e) {
+    const int j = c->ent_col[e];
+    elz[2 * e] = (is_priv_col[j] ? j : col_slot[j]) * Z;
+    elz[2 * e + 1] = c->ent_shift[e];
+  }
+  size_t o_rp = push(row_priv), o_sc = push(shared_col), o_pr = push(priv_row);
   if (blob.size() & 1) blob.push_back(0);  // 8-byte alignment of the int2 tables
   // encoder lists: the dual-diagonal rows (all rows of the 11n family, the
   // four core rows of the BG shape) XOR information columns; extension rows
@@ -263,6 +288,8 @@ lsim_status lsim_code_create(const int16_t* base, int mb, int nb, int Z, int fam
   size_t o_ecz = push(ecz);
   size_t o_encz = push(enc_cz);
   size_t o_encp = push(enc_ptr);
+  if (blob.size() & 1) blob.push_back(0);
+  size_t o_elz = push(elz);
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) e = hipMalloc(&c->dmem, blob.size() * sizeof(int));
   if (e == hipSuccess)
@@ -304,6 +331,12 @@ lsim_status lsim_code_create(const int16_t* base, int mb, int nb, int Z, int fam
   dc.enc_cz = reinterpret_cast<const int2*>(d + o_encz);
   dc.col_edge = reinterpret_cast<const int2*>(d + o_ce2);
   dc.ent_cz = reinterpret_cast<const int2*>(d + o_ecz);
+  dc.n_shared = (int)shared_col.size();
+  dc.n_priv = (int)priv_row.size();
+  dc.row_priv = d + o_rp;
+  dc.shared_col = d + o_sc;
+  dc.priv_row = d + o_pr;
+  dc.ent_lz = reinterpret_cast<const int2*>(d + o_elz);
   lsim_code_info& in = c->info;
   in.k = dc.k;
   in.n_mother = dc.n_mother;
@@ -320,6 +353,8 @@ lsim_status lsim_code_create(const int16_t* base, int mb, int nb, int Z, int fam
   in.n_punct_cols = n_punct_cols;
   in.max_row_deg = max_row;
   in.max_col_deg = max_col;
+  in.n_shared_cols = dc.n_shared;
+  in.n_private_rows = dc.n_priv;
   *out = c;
   return LSIM_OK;
 }
@@ -474,6 +509,7 @@ static lsim_status decode_common(const lsim_code* code, const lsim_decode_params
     const size_t need = lsim::layered_state_words(code->dev, B) * 4;
     if (!d_work || work_bytes < need)
       return fail(LSIM_E_NOMEM, "workspace smaller than lsim_decode_workspace()");
+    if ((uintptr_t)d_work & 15) return fail(LSIM_E_INVAL, "d_work must be 16-byte aligned");
     e = lsim::launch_layered(code->dev, *p, (const float*)d_llr, B, d_bits, d_app, (float*)r_out,
                              (uint32_t*)d_work, as_stream(stream), &why);
   } else {
@@ -601,6 +637,18 @@ lsim_status lsim_count_errors(const uint8_t* d_ref, int64_t ref_stride, const ui
                     "count_errors");
 }
 
+lsim_status lsim_probe(int kind, const void* d_src, void* d_dst, int64_t bytes, int rounds,
+                       int grid, int64_t* units, lsim_stream stream) {
+  if (kind < LSIM_PROBE_COPY || kind > LSIM_PROBE_EXP2 || grid < 1 || grid > 65536 || rounds < 1 ||
+      !d_dst || !units)
+    return fail(LSIM_E_INVAL, "bad probe arguments");
+  if (kind <= LSIM_PROBE_READ && (!d_src || bytes < 16 || (bytes & 15)))
+    return fail(LSIM_E_INVAL, "copy and read probes take a source of a positive multiple of 16 bytes");
+  return dev_status(lsim::launch_probe(kind, d_src, d_dst, bytes, rounds, grid, as_stream(stream),
+                                       units),
+                    "probe");
+}
+
 lsim_status lsim_ebn0_to_n0(const double* ebn0_db, int64_t n, double rate, int bits_per_sym,
                             double* no) {
   if (!ebn0_db || !no || n < 0 || !(rate > 0.0 && rate <= 1.0) || bits_per_sym < 1)
@@ -639,6 +687,7 @@ struct lsim_plan {
   lsim_decode_params p;
   int threads = 0;
   int dmax = 0;
+  int max_priv = 0;  // most private rows of any shape (layered decoder)
   size_t lds = 0;
   int grid = 0;
   int64_t ntiles = 0;
@@ -683,11 +732,10 @@ lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t*
       return fail(LSIM_E_INVAL, "threads must be 256, 512 or 1024 for the OMS decoder");
     if (dmax > 32) return fail(LSIM_E_UNSUPPORTED, "node degree > 32");
   } else if (threads == 0) {
-    const int cand[5] = {256, 384, 512, 768, 1024};
-    threads = 1024;
-    for (int x : cand)
-      if (x >= zmax) {
-        threads = x;
+    // the default launch shape of the shape with the largest lift
+    for (int s = 0; s < nshapes; ++s)
+      if (codes[s]->dev.Z == zmax) {
+        threads = lsim::layered_default_threads(codes[s]->dev);
         break;
       }
   }
@@ -725,6 +773,7 @@ lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t*
     lsim::LayerShape sh;
     sh.code = c;
     sh.G = G;
+    plan->max_priv = std::max(plan->max_priv, c.n_priv);
     sh.count = counts[s];
     sh.tile0 = tile0;
     sh.llr_off = llr_off;
@@ -812,6 +861,7 @@ lsim_status lsim_mixed_decode(lsim_plan* plan, const void* d_llr_concat, uint8_t
   const size_t need = kCounterBytes + plan->state_words * 4;
   if (!d_work || work_bytes < need)
     return fail(LSIM_E_NOMEM, "workspace smaller than lsim_mixed_workspace()");
+  if ((uintptr_t)d_work & 15) return fail(LSIM_E_INVAL, "d_work must be 16-byte aligned");
   if (plan->ntiles == 0) return LSIM_OK;
   char* w = (char*)d_work;
   if (plan->p.algo == LSIM_OMS_I8)
@@ -825,7 +875,7 @@ lsim_status lsim_mixed_decode(lsim_plan* plan, const void* d_llr_concat, uint8_t
       plan->d_shapes, (int)plan->shapes.size(), plan->d_tile_shape, plan->d_tile_local,
       plan->ntiles, plan->threads, plan->lds, plan->p, d_llr_concat, d_bits_concat, d_app_concat,
       (uint32_t*)(w + kCounterBytes), (int*)w, persistent ? 1 : 0, plan->grid, plan->dmax,
-      as_stream(stream));
+      plan->max_priv, as_stream(stream));
   return dev_status(e, "mixed decode");
 }
 
@@ -967,6 +1017,7 @@ extern "C" lsim_status lsim_link_run(const lsim_link_args* a, lsim_stream stream
     const size_t need = lsim::layered_state_words(c, a->B) * 4;
     if (!a->d_work || a->work_bytes < need)
       return fail(LSIM_E_NOMEM, "workspace smaller than lsim_decode_workspace()");
+    if ((uintptr_t)a->d_work & 15) return fail(LSIM_E_INVAL, "d_work must be 16-byte aligned");
   }
   hipStream_t s = as_stream(stream);
   const int64_t S = c.e_tx / m;

@@ -23,7 +23,18 @@ struct DevCode {
                          // columns for the dual-diagonal rows, columns < kb+4 for extension rows
   const int2* col_edge;  // per column entry (col_ptr order): (e * Z, shift of e)
   const int2* ent_cz;    // per entry (row-major): (col * Z, shift)
+  // Layered decoder: a row whose last entry lies in a column of degree one
+  // owns that column ("private"); its posteriors need no LDS and travel with
+  // the row's check state.  Every other column is "shared" and gets an LDS
+  // slot.
+  int n_shared, n_priv;
+  const int* row_priv;    // rows: private slot of the row (0..n_priv-1) or -1
+  const int* shared_col;  // n_shared: column of each LDS slot, ascending
+  const int* priv_row;    // n_priv: row of each private slot, ascending
+  const int2* ent_lz;     // per entry (row-major): (LDS slot * Z, shift) of a shared
+                          // column; (col * Z, shift) of a private one
 };
+
 
 // Read-only device tables through the constant address space: with a
 // wave-uniform index the compiler emits scalar loads (no VALU, no LDS).

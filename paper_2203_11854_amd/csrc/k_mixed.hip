@@ -1,0 +1,87 @@
+// Persistent mixed-shape layered decoder: codewords of several codes in one
+// launch (the tile decoder and its data layout are in layered_tile.h).
+#include "layered_tile.h"
+
+namespace lsim {
+
+using namespace layered;
+
+namespace {
+
+// Persistent decoder over a work list of (shape, tile) items.  Workgroups
+// take items from a device counter until the list is drained; the counter
+// is reset by reset_counter_kernel launched just before, so the pair can be
+// captured in a graph.
+template <int NT, int DMAX>
+__global__ __launch_bounds__(NT) void mixed_kernel(const LayerShape* __restrict__ shapes,
+                                                   const int* __restrict__ tile_shape,
+                                                   const int64_t* __restrict__ tile_local,
+                                                   int64_t ntiles, const float* llr,
+                                                   uint8_t* bits, float* lpost, uint32_t* state,
+                                                   int* counter, int persistent, int iters,
+                                                   float alpha, int next_off) {
+  // dynamic LDS only (tiles address it from offset 0); the work item taken
+  // by thread 0 is broadcast through the word at next_off
+  extern __shared__ __align__(16) unsigned char smem[];
+  int* next = reinterpret_cast<int*>(smem + next_off);
+  int64_t item = persistent ? -1 : (int64_t)blockIdx.x;
+  for (;;) {
+    if (persistent) {
+      if (threadIdx.x == 0) *next = atomicAdd(counter, 1);
+      __syncthreads();
+      item = *next;
+      __syncthreads();
+    }
+    if (item >= ntiles) break;
+    const int s = tile_shape[item];
+    const LayerShape& sh = shapes[s];
+    TileIO io;
+    io.llr = llr + sh.llr_off;
+    io.bits = bits ? bits + sh.bits_off : nullptr;
+    io.lpost = lpost ? lpost + sh.app_off : nullptr;
+    io.r_out = nullptr;
+    io.state = reinterpret_cast<uint4*>(state + sh.state_off);
+    io.count = sh.count;
+    decode_tile<NT, DMAX>(sh.code, sh.G, tile_local[item], io, iters, alpha);
+    __syncthreads();
+    if (!persistent) break;
+  }
+}
+
+__global__ void reset_counter_kernel(int* counter) { *counter = 0; }
+
+}  // namespace
+
+hipError_t launch_mixed(const LayerShape* d_shapes, int nshapes, const int* d_tile_shape,
+                        const int64_t* d_tile_local, int64_t ntiles, int threads,
+                        size_t lds_bytes, const lsim_decode_params& p, const void* llr,
+                        uint8_t* bits, float* lpost, uint32_t* state, int* counter,
+                        int persistent, int grid, int dmax, int max_priv, hipStream_t s) {
+  (void)nshapes;
+  if (persistent) {
+    reset_counter_kernel<<<1, 1, 0, s>>>(counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const unsigned g = persistent ? (unsigned)grid : (unsigned)ntiles;
+  const int next_off = (int)((lds_bytes + 15) & ~(size_t)15);
+  const size_t lds_all = (size_t)next_off + 16;
+  const int D = dmax <= 16 ? 16 : dmax <= 24 ? 24 : 27;
+#define LSIM_MIXED_CASE(NT_, D_)                                                       \
+  if (threads == NT_ && D == D_ ) {                                              \
+    const void* k = (const void*)mixed_kernel<NT_, D_>;                                \
+    hipError_t e = require_lds_at_zero(k);                                                 \
+    if (e == hipSuccess) e = ensure_dyn_lds(k, lds_all);                                   \
+    if (e != hipSuccess) return e;                                                         \
+    mixed_kernel<NT_, D_><<<g, NT_, lds_all, s>>>(d_shapes, d_tile_shape, d_tile_local, \
+                                                      ntiles, (const float*)llr, bits,     \
+                                                      lpost, state, counter, persistent,   \
+                                                      p.iters, p.alpha, next_off);         \
+    return hipGetLastError();                                                              \
+  }
+  LSIM_LAYERED_INSTANCES(LSIM_MIXED_CASE)
+#undef LSIM_MIXED_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lsim

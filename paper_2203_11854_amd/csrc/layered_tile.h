@@ -1,0 +1,260 @@
+// Layered normalized min-sum (FP32) tile decoder shared by the one-code
+// launch (k_layered.hip) and the persistent mixed-shape launch (k_mixed.hip).
+//
+// A tile is G codewords of one code decoded by one workgroup: lane
+// (g, r) = (tid / Z, tid % Z) owns check r of every layer of codeword g.  A
+// QC row block meets each variable node at most once, so the Z checks of a
+// layer update the posteriors without conflicts and one barrier separates
+// consecutive layers.
+//
+// Posteriors live where their readers are.  A column met by several rows is
+// read by every lane of those rows, so its Z posteriors sit in LDS ("shared"
+// columns, one LDS slot each).  A column of degree one that is the last entry
+// of its row (the extension parity columns of a BG-shaped code) is read and
+// written only by lane r of that row ("private" column): its posterior for
+// variable node (col, (r + shift) mod Z) travels with the check's state.  For
+// the BG1-shaped workload (26 shared of 68 columns at Z = 384) a codeword's
+// LDS shrinks from 104 KB to 39 KB, so more codewords are resident per CU.
+//
+// The state of check (i, r) between iterations is one 16-byte record
+// (alpha*m1, alpha*m2, sign bits | i1 << 27, private posterior) streamed
+// through device memory in [codeword][layer][Z] order: one coalesced 16-byte
+// load and store per lane and layer.
+//
+// Arithmetic follows the layered min-sum update one IEEE single-precision
+// operation at a time (no fused multiply-add): t = APP - r_old;
+// r_new = sign * (alpha * (v == i1 ? m2 : m1)); APP = t + r_new.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "dispatch.h"
+#include "lds.h"
+#include "lsim_internal.h"
+
+// one IEEE single-precision operation at a time in everything below
+#pragma clang fp contract(off)
+
+namespace lsim {
+namespace layered {
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+__host__ __device__ inline size_t tile_lds_bytes(const DevCode& c, int G) {
+  return align16((size_t)G * c.n_shared * c.Z * 4);
+}
+
+struct TileIO {
+  const float* llr;     // [count][e_tx] of this shape
+  uint8_t* bits;        // [count][k]
+  float* lpost;         // [count][n_dec]
+  float* r_out;         // [count][E]
+  uint4* state;         // [count][rows][Z] check records
+  int64_t count;
+};
+
+__device__ __forceinline__ int rot_lift(int r, int s, int Z) {
+  const int x = r + s;
+  return x >= Z ? x - Z : x;
+}
+
+template <int NT, int DMAX>
+__device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t tile, const TileIO& io,
+                                            int iters, float alpha) {
+  const int Z = c.Z;
+  const int tid = threadIdx.x;
+  const int64_t cw0 = tile * G;
+  const int gmax = (int)min<int64_t>(G, io.count - cw0);
+  const int nsz = c.n_shared * Z;  // shared posteriors per codeword
+
+  // shared posteriors from the channel (punctured and unsent nodes: 0); the
+  // tile's LDS starts at byte 0 (the kernels have no static LDS)
+  for (int idx = tid; idx < G * nsz; idx += NT) {
+    const int g = idx / nsz, rem = idx - g * nsz;
+    const int slot = rem / Z, z = rem - slot * Z;
+    const int x = c.shared_col[slot] * Z + z - c.tx_lo;
+    float l = 0.f;
+    if (g < gmax && x >= 0 && x < c.e_tx) l = -io.llr[(cw0 + g) * c.e_tx + x];
+    lds_st<float>(idx * 4, l);
+  }
+  __syncthreads();
+
+  const int g = tid / Z;
+  const int r = tid - g * Z;
+  const bool active = g < gmax;
+  const int64_t cw = cw0 + (active ? g : 0);
+  // LDS byte address of this lane's codeword's shared posteriors
+  const int app_b = vreg((active ? g : 0) * nsz * 4);
+  const int Z4 = Z * 4, zm4 = (Z - 1) * 4, r4 = vreg(r * 4);
+  const bool zpow2 = (Z & (Z - 1)) == 0;
+  uint4* st = io.state + (size_t)cw * c.rows * Z + r;
+  const float* llr_cw = io.llr + cw * c.e_tx;
+
+  // Variable node of the private entry of row i at this lane.
+  auto priv_vn = [&](int i) {
+    const int2 en = ld_const(c.ent_lz, uni(ld_const(c.row_ptr, i + 1)) - 1);
+    return en.x + rot_lift(r, en.y, Z);
+  };
+
+  // The record of the next layer is loaded one layer ahead so its memory
+  // latency overlaps the current layer.  A decoded graph has at least three
+  // layers, so a prefetched layer was stored at least two layers earlier.
+  // In the first iteration the check state is zero and a private posterior
+  // is the channel value.
+  const int rows = c.rows;
+  uint4 nrec = make_uint4(0u, 0u, 0u, 0u);
+  auto fetch = [&](int ni, int nit) {
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (active && nit < iters) {
+      if (nit >= 1) {
+        v = st[(size_t)ni * Z];
+      } else if (uni(ld_const(c.row_priv, ni)) >= 0) {
+        const int x = priv_vn(ni) - c.tx_lo;
+        if (x >= 0 && x < c.e_tx) v.w = __float_as_uint(-llr_cw[x]);
+      }
+    }
+    return v;
+  };
+  nrec = fetch(0, 0);
+  for (int it = 0; it < iters; ++it) {
+    for (int i = 0; i < rows; ++i) {
+      const int e0 = uni(ld_const(c.row_ptr, i));
+      const int d = uni(ld_const(c.row_ptr, i + 1)) - e0;
+      const bool priv = uni(ld_const(c.row_priv, i)) >= 0;
+      const uint4 rec = nrec;
+      {
+        int ni = i + 1, nit = it;
+        if (ni == rows) {
+          ni = 0;
+          ++nit;
+        }
+        nrec = fetch(ni, nit);
+      }
+      const float a1 = __uint_as_float(rec.x), a2 = __uint_as_float(rec.y);
+      const uint32_t pk = rec.z;
+      // One check update of degree D; with PRIV the last entry's posterior
+      // comes from and goes back to the record, the others are in LDS.
+      auto update = [&](auto deg, auto privc) {
+        constexpr int D = decltype(deg)::value;
+        constexpr bool PRIV = decltype(privc)::value;
+        constexpr int DL = PRIV ? D - 1 : D;  // entries whose posterior is in LDS
+        if constexpr (DL >= 1) {
+          int addr[DL];
+          float tv[D];
+          // LDS byte address of the variable node of entry e at lift r:
+          // app_b + slot*Z*4 + ((r + shift) mod Z)*4; the reduction is a mask
+          // for a power-of-two lift, else min(x, x - Z*4) on unsigned x
+          if (zpow2) {
+#pragma unroll
+            for (int q = 0; q < DL; ++q) {
+              const int2 en = ld_const(c.ent_lz, e0 + q);
+              addr[q] = app_b + en.x * 4 + ((r4 + en.y * 4) & zm4);
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < DL; ++q) {
+              const int2 en = ld_const(c.ent_lz, e0 + q);
+              const uint32_t x = (uint32_t)(r4 + en.y * 4);
+              addr[q] = app_b + en.x * 4 + (int)min(x, x - (uint32_t)Z4);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < DL; ++q) tv[q] = lds_ld<float>(addr[q]);
+          if constexpr (PRIV) tv[D - 1] = __uint_as_float(rec.w);
+          const int i1_old = (int)(pk >> 27);
+          // sign of a zero never reaches a nonzero value (a zero input forces
+          // every other output magnitude to zero), so sign bits are used as is
+          uint32_t sx = 0;
+          float m1 = INFINITY, m2 = INFINITY;
+#pragma unroll
+          for (int q = 0; q < D; ++q) {
+            const float mag = q == i1_old ? a2 : a1;
+            const float rold = __uint_as_float(__float_as_uint(mag) | ((pk << (31 - q)) & 0x80000000u));
+            const float t = __fsub_rn(tv[q], rold);
+            tv[q] = t;
+            sx ^= __float_as_uint(t);
+            const float at = fabsf(t);
+            m2 = __builtin_amdgcn_fmed3f(m1, at, m2);
+            m1 = fminf(m1, at);
+          }
+          const float b1 = __fmul_rn(alpha, m1);
+          const float b2 = __fmul_rn(alpha, m2);
+          // Outputs in reverse order: the input at the minimum gets alpha*m2,
+          // the others alpha*m1, and i1 ends on the first index at the minimum.
+          // A repeated minimum makes m2 == m1, so every tie gets the same value.
+          int i1 = 0;
+          uint32_t npk = 0;
+          float pout = 0.f;
+#pragma unroll
+          for (int q = D - 1; q >= 0; --q) {
+            const bool at_min = fabsf(tv[q]) == m1;
+            const float mag = at_min ? b2 : b1;
+            i1 = at_min ? q : i1;
+            const uint32_t sg = (sx ^ __float_as_uint(tv[q])) & 0x80000000u;
+            const float out = __fadd_rn(tv[q], __uint_as_float(__float_as_uint(mag) | sg));
+            if (PRIV && q == D - 1)
+              pout = out;
+            else
+              lds_st<float>(addr[q < DL ? q : 0], out);
+            npk |= sg >> (31 - q);
+          }
+          npk |= (uint32_t)i1 << 27;
+          // the last iteration's records are read only by the state export
+          if (it < iters - 1 || io.r_out)
+            st[(size_t)i * Z] = make_uint4(__float_as_uint(b1), __float_as_uint(b2), npk,
+                                           __float_as_uint(pout));
+          if (PRIV && it == iters - 1) {
+            // the private posterior is final: write it out now
+            const int v = priv_vn(i);
+            if (io.bits && v < c.k) io.bits[cw * c.k + v] = pout < 0.f;
+            if (io.lpost) io.lpost[cw * c.n_dec + v] = -pout;
+          }
+        }
+      };
+      if (active) {
+        with_degree<DMAX>(d, [&](auto deg) {
+          if (priv)
+            update(deg, std::true_type{});
+          else
+            update(deg, std::false_type{});
+        });
+      }
+      lds_barrier();
+    }
+  }
+
+  // shared posteriors out of LDS (private ones were written in the last
+  // iteration)
+  for (int idx = tid; idx < gmax * nsz; idx += NT) {
+    const int gg = idx / nsz, rem = idx - gg * nsz;
+    const int slot = rem / Z, z = rem - slot * Z;
+    const int v = c.shared_col[slot] * Z + z;
+    const float x = lds_ld<float>(idx * 4);
+    if (io.bits && v < c.k) io.bits[(cw0 + gg) * c.k + v] = x < 0.f;
+    if (io.lpost) io.lpost[(cw0 + gg) * c.n_dec + v] = -x;
+  }
+  if (io.r_out && active) {
+    for (int i = 0; i < c.rows; ++i) {
+      const uint4 rc = st[(size_t)i * Z];
+      const float a1 = __uint_as_float(rc.x), a2 = __uint_as_float(rc.y);
+      const uint32_t pk = rc.z;
+      const int i1 = (int)(pk >> 27);
+      const int rb = c.row_ptr[i];
+      for (int e = rb; e < c.row_ptr[i + 1]; ++e) {
+        const int q = e - rb;
+        const float mag = q == i1 ? a2 : a1;
+        io.r_out[cw * (int64_t)c.E + (int64_t)e * Z + r] = ((pk >> q) & 1u) ? -mag : mag;
+      }
+    }
+  }
+}
+
+// Instances: threads x largest row degree.
+#define LSIM_LAYERED_INSTANCES(X) \
+  X(256, 16) X(256, 24) X(256, 27) X(384, 16) X(384, 24) X(384, 27) X(512, 16) X(512, 24) \
+  X(512, 27) X(768, 16) X(768, 24) X(768, 27) X(1024, 16) X(1024, 24) X(1024, 27)
+
+}  // namespace layered
+}  // namespace lsim

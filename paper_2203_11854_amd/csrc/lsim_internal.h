@@ -62,6 +62,7 @@ struct LayerShape {
 };
 size_t layered_state_words(const DevCode& c, int64_t B);
 size_t layered_tile_lds(const DevCode& c, int G);
+int layered_default_threads(const DevCode& c);
 hipError_t launch_layered(const DevCode& c, const lsim_decode_params& p, const float* llr,
                           int64_t B, uint8_t* bits, float* lpost, float* r_out, uint32_t* state,
                           hipStream_t s, std::string* why);
@@ -74,7 +75,11 @@ hipError_t launch_mixed(const LayerShape* d_shapes, int nshapes, const int* d_ti
                         const int64_t* d_tile_local, int64_t ntiles, int threads,
                         size_t lds_bytes, const lsim_decode_params& p, const void* llr,
                         uint8_t* bits, float* lpost, uint32_t* state, int* counter,
-                        int persistent, int grid, int dmax, hipStream_t s);
+                        int persistent, int grid, int dmax, int max_priv, hipStream_t s);
+
+// Peak-rate probes (k_probe.hip)
+hipError_t launch_probe(int kind, const void* src, void* dst, int64_t bytes, int rounds, int grid,
+                        hipStream_t s, int64_t* units);
 
 // Pipeline kernels (k_pipeline.hip)
 hipError_t launch_source_bits(uint64_t seed, int64_t cw0, int64_t B, int64_t k, uint8_t* u,

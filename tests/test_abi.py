@@ -81,6 +81,12 @@ def test_calls_validate_before_device():
     assert lib.lsim_points_grad(None, 4, v, v, v, 1, v, v, 0, None) == INVAL
     n = ctypes.c_size_t()
     assert lib.lsim_points_workspace(None, 4, 1, ctypes.byref(n)) == INVAL
+    u = ctypes.c_int64()
+    assert lib.lsim_probe(9, v, v, 16, 1, 1, ctypes.byref(u), None) == INVAL      # unknown kind
+    assert lib.lsim_probe(0, None, v, 16, 1, 1, ctypes.byref(u), None) == INVAL   # no source
+    assert lib.lsim_probe(1, v, v, 20, 1, 1, ctypes.byref(u), None) == INVAL      # not x16
+    assert lib.lsim_probe(4, None, v, 0, 0, 1, ctypes.byref(u), None) == INVAL    # rounds < 1
+    assert lib.lsim_probe(4, None, v, 0, 1, 0, ctypes.byref(u), None) == INVAL    # empty grid
 
 
 def test_binding_fails_loudly_without_device_tensors():
