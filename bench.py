@@ -50,10 +50,10 @@ LDS_PEAK_GBS = N_CU * 128 * CLOCK_GHZ
 # for the copy probe of known size (factors below).  Valid only for the
 # kernel sources they were taken on (hash); any change there reports null
 # until the counters are taken again.
-LAYERED_TRAFFIC = {"bytes": None,
+LAYERED_TRAFFIC = {"bytes": (2735951 * 2 + 5378304) * 1024,
                    "sources": ("layered_tile.h", "k_layered.hip", "dispatch.h", "lds.h",
                                "devcode.h"),
-                   "sha256_16": None}
+                   "sha256_16": "c47633403ce74083"}
 FLOOD_SPA_TRAFFIC = {"bytes": (30954 * 2 + 5120) * 1024,
                      "sources": ("k_flood.hip", "spa_math.h", "dispatch.h", "lds.h", "devcode.h"),
                      "sha256_16": "6e3a9271e9364a42"}
@@ -176,7 +176,7 @@ def main():
         lk_pt.run(data_seed(3, 77), 0)
         snr_ms[f"{pt:.1f}"] = round(_median_ms(
             torch, lambda: lsim.decode(code, lk_pt.llr, p_nms, bits=bits, work=work), 20, 5), 4)
-    roofline = layered_roofline(code, B, T, dec_ms, peaks)
+    roofline = layered_roofline(code, B, T, dec_ms, peaks, lsim.decode_launch(code, p_nms))
     roofline.update({"kernel_ms_median20": round(dec_med, 4),
                      "kernel_ms_median20_by_ebn0": snr_ms})
     curve = [cnt[j, 1] / max(1, cnt[j, 2]) for j in range(9)]
@@ -268,24 +268,28 @@ def measure_peaks(torch, lsim, dev):
     return res
 
 
-def layered_roofline(code, B, T, ms, peaks):
+def layered_roofline(code, B, T, ms, peaks, launch):
     """Roofline position of one layered-decoder launch.  HBM algorithmic
-    bytes: the check records (read in iterations 2..T, written in 1..T-1),
-    the LLRs in and the bits out.  LDS: one 4-byte read and one write per
-    edge and iteration whose posterior is in LDS.  VALU: 12 lane operations
-    per edge and iteration."""
-    rec = B * (T - 1) * 2 * NMS_RECORD_BYTES * code.m_dec
+    bytes: the 16-byte check records of the rows that stream through device
+    memory (read in iterations 2..T, written in 1..T-1), the LLRs in and the
+    bits out.  LDS: one 4-byte read and one write per edge and iteration
+    whose posterior is in LDS, plus the records of the rows kept in LDS.
+    VALU: 12 lane operations per edge and iteration."""
+    K = launch["lds_rows"]
+    rec = B * (T - 1) * 2 * NMS_RECORD_BYTES * (code.rows - K) * code.Z
     io = B * (4 * code.e_tx + code.k)
     hbm = rec + io
     s = ms * 1e-3
     lds_edges = code.E - code.n_private_rows * code.Z
-    lds = B * T * 8 * lds_edges
+    lds = B * T * (8 * lds_edges + 2 * NMS_RECORD_BYTES * K * code.Z)
     valu = B * T * code.E * NMS_SLOTS_PER_EDGE
     achieved = hbm / s / 1e9
+    D = 16 if code.max_row_deg <= 16 else 24 if code.max_row_deg <= 24 else 27
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": _traffic(LAYERED_TRAFFIC),
-            "kernel": "layered_kernel<768,24>", "kernel_ms": round(ms, 4),
+            "kernel": f"layered_kernel<{launch['threads']},{D}>", "launch": launch,
+            "kernel_ms": round(ms, 4),
             "hbm_algorithmic_bytes": int(hbm),
             "measured_peak": peaks["hbm_copy_gbs"],
             "frac_of_measured": round(achieved / peaks["hbm_copy_gbs"], 4),

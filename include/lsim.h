@@ -218,6 +218,10 @@ typedef struct {
   float llr_max; /* SPA clamp, > 0 */
   int sat;       /* OMS saturation, 1..127 */
   int threads;   /* workgroup size; 0 = library default */
+  int lds_rows;  /* layered decoder: rows 0 .. lds_rows-1 keep their check records
+                    in LDS between iterations instead of device memory; 0 = library
+                    default (as many as fit without fewer workgroups per CU), -1 =
+                    none; more rows than fit the LDS -> LSIM_E_INVAL */
 } lsim_decode_params;
 
 /*
@@ -236,6 +240,17 @@ lsim_status lsim_decode_workspace(const lsim_code* code, const lsim_decode_param
 lsim_status lsim_decode(const lsim_code* code, const lsim_decode_params* p, const void* d_llr,
                         int64_t B, uint8_t* d_bits, float* d_app, void* d_work,
                         size_t work_bytes, lsim_stream stream);
+
+/*
+ * Launch shape lsim_decode takes for the layered decoder (LSIM_NMS_F32) with
+ * these parameters: workgroup size, codewords per workgroup and rows whose
+ * check records stay in LDS (rows >= lds_rows stream through d_work).
+ * Needs the code's device current (it asks the runtime for occupancy).
+ * Errors: LSIM_E_UNSUPPORTED for the flooding decoders or a shape that does
+ * not fit; LSIM_E_INVAL on bad parameters.
+ */
+lsim_status lsim_decode_launch(const lsim_code* code, const lsim_decode_params* p,
+                               int* threads, int* codewords_per_tile, int* lds_rows);
 
 /*
  * lsim_decode without a workspace argument, for callers that cannot
@@ -503,7 +518,8 @@ lsim_status lsim_polar_encode(const lsim_polar* pc, const uint8_t* d_data, int64
                               uint8_t* d_x, lsim_stream stream);
 /*
  * SC (list = 1), SCL (list 2, 4, 8, 16, 32) and SCL-CRC (use_crc != 0) decoding of
- * d_llr f32[B][N] (boundary LLRs of x) into the data bits d_bits
+ * d_llr f32[B][N] (boundary LLRs of x; NaN is read as 0 and values are
+ * clamped to +-2^100, so infinite inputs decode) into the data bits d_bits
  * u8[B][K - r].  LLR form with lambda = -L: f(a, b) = sgn(a) sgn(b)
  * min(|a|, |b|) to the left child, g(a, b, x) = b + (1 - 2x) a to the right
  * child; a path's metric adds |lambda| at a leaf whose bit disagrees with

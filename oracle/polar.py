@@ -34,6 +34,11 @@ The paper prints none of the algorithms; these are the textbook ones:
   metric (ties: lowest slot); SCL-CRC takes, in that order, the first path
   whose CRC checks, else the first path.
 
+Channel values are read with NaN as 0 and clamped to +-2^100 (the paper
+says nothing of non-finite inputs; with the clamp every intermediate LLR and
+metric stays finite, at most 2^100 times the 2N terms a node and a metric
+sum, so no value is ever inf - inf).
+
 Two arithmetic modes: "fp64" (float64) and "fp32" (every operation in IEEE
 single precision, as the device computes it; f, the path metric and the
 decisions involve only min, negation and one rounding per add, so the
@@ -146,11 +151,18 @@ def _g(a, b, x, dt):
     return np.where(x.astype(bool), b - a, b + a).astype(dt)
 
 
+def read_channel(lam, dt):
+    """Channel LLRs as the decoders read them: NaN -> 0, clamped to
+    +-2^100."""
+    lam = np.asarray(lam, dtype=dt)
+    return np.clip(np.where(np.isnan(lam), dt(0), lam), dt(-2.0 ** 100), dt(2.0 ** 100)).astype(dt)
+
+
 def sc_decode(lam: np.ndarray, mask: np.ndarray, mode: str = "fp64") -> np.ndarray:
     """Successive cancellation: ``u_hat u8[N]`` for channel LLRs
     ``lam[N]`` (ln P(0)/P(1))."""
     dt = np.float32 if mode == "fp32" else np.float64
-    lam = np.asarray(lam, dtype=dt)
+    lam = read_channel(lam, dt)
 
     def rec(l, m):
         N = l.size
@@ -171,7 +183,7 @@ def scl_decode(lam: np.ndarray, mask: np.ndarray, L: int, poly: int = 0, r: int 
     r > 0).  Returns (u_hat u8[N] of the chosen path, metrics of the final
     list by slot, u_hat of every slot)."""
     dt = np.float32 if mode == "fp32" else np.float64
-    lam = np.asarray(lam, dtype=dt)
+    lam = read_channel(lam, dt)
     mask = np.asarray(mask)
     N = lam.size
     n = N.bit_length() - 1

@@ -41,7 +41,7 @@ class CodeInfo(ctypes.Structure):
 class DecodeParams(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int), ("iters", ctypes.c_int), ("offset", ctypes.c_float),
                 ("alpha", ctypes.c_float), ("llr_max", ctypes.c_float), ("sat", ctypes.c_int),
-                ("threads", ctypes.c_int)]
+                ("threads", ctypes.c_int), ("lds_rows", ctypes.c_int)]
 
 
 _P = ctypes.c_void_p
@@ -77,6 +77,8 @@ _SIGS = {
     "lsim_quantize": [_P, _I64, _F, _I, _P, _P],
     "lsim_decode_workspace": [_P, ctypes.POINTER(DecodeParams), _I64, ctypes.POINTER(_SZ)],
     "lsim_decode": [_P, ctypes.POINTER(DecodeParams), _P, _I64, _P, _P, _P, _SZ, _P],
+    "lsim_decode_launch": [_P, ctypes.POINTER(DecodeParams), ctypes.POINTER(_I), ctypes.POINTER(_I),
+                           ctypes.POINTER(_I)],
     "lsim_decode_noalloc": [_P, ctypes.POINTER(DecodeParams), _P, _I64, _P, _P, _P],
     "lsim_decode_state": [_P, ctypes.POINTER(DecodeParams), _P, _I64, _P, _P, _P, _P, _P, _SZ, _P],
     "lsim_count_errors": [_P, _I64, _P, _I64, _I64, _P, _I, _P, _P],
@@ -378,8 +380,17 @@ def quantize(L, scale: float = 2.0, sat: int = 31, out=None):
 # --------------------------------------------------------------- decoders
 
 def params(algo: int, iters: int = 20, offset: float = 1.0, alpha: float = 0.75,
-           llr_max: float = 20.0, sat: int = 31, threads: int = 0) -> DecodeParams:
-    return DecodeParams(algo, iters, offset, alpha, llr_max, sat, threads)
+           llr_max: float = 20.0, sat: int = 31, threads: int = 0,
+           lds_rows: int = 0) -> DecodeParams:
+    return DecodeParams(algo, iters, offset, alpha, llr_max, sat, threads, lds_rows)
+
+
+def decode_launch(code: Code, p: DecodeParams) -> dict:
+    """Launch shape of the layered decoder (lsim_decode_launch)."""
+    t, g, k = _I(), _I(), _I()
+    _call("lsim_decode_launch", code.handle, ctypes.byref(p), ctypes.byref(t), ctypes.byref(g),
+          ctypes.byref(k))
+    return {"threads": t.value, "codewords_per_tile": g.value, "lds_rows": k.value}
 
 
 def decode_workspace(code: Code, p: DecodeParams, B: int) -> int:

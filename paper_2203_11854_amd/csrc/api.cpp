@@ -143,6 +143,7 @@ lsim_status check_params(const lsim_code* code, const lsim_decode_params* p) {
     default:
       return fail(LSIM_E_INVAL, "unknown algo");
   }
+  if (p->lds_rows < -1) return fail(LSIM_E_INVAL, "lds_rows must be >= -1");
   const int t = p->threads;
   const bool layered_ok = t == 384 || t == 768;
   if (t != 0 && t != 256 && t != 512 && t != 1024 && !(layered_ok && p->algo == LSIM_NMS_F32))
@@ -494,6 +495,21 @@ lsim_status lsim_decode_workspace(const lsim_code* code, const lsim_decode_param
   return LSIM_OK;
 }
 
+lsim_status lsim_decode_launch(const lsim_code* code, const lsim_decode_params* p,
+                               int* threads, int* codewords_per_tile, int* lds_rows) {
+  lsim_status st = check_params(code, p);
+  if (st != LSIM_OK) return st;
+  if (!threads || !codewords_per_tile || !lds_rows) return fail(LSIM_E_INVAL, "null output");
+  if (p->algo != LSIM_NMS_F32)
+    return fail(LSIM_E_UNSUPPORTED, "launch shapes are reported for the layered decoder");
+  std::string why;
+  hipError_t e = lsim::layered_launch_shape(code->dev, *p, threads, codewords_per_tile, lds_rows,
+                                            &why);
+  if (e != hipSuccess) return dev_status(e, "layered launch shape");
+  if (!why.empty()) return fail(LSIM_E_UNSUPPORTED, why);
+  return LSIM_OK;
+}
+
 static lsim_status decode_common(const lsim_code* code, const lsim_decode_params* p,
                                  const void* d_llr, int64_t B, uint8_t* d_bits, float* d_app,
                                  const void* q_in, void* r_out, void* q_out, void* d_work,
@@ -687,7 +703,6 @@ struct lsim_plan {
   lsim_decode_params p;
   int threads = 0;
   int dmax = 0;
-  int max_priv = 0;  // most private rows of any shape (layered decoder)
   size_t lds = 0;
   int grid = 0;
   int64_t ntiles = 0;
@@ -773,13 +788,13 @@ lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t*
     lsim::LayerShape sh;
     sh.code = c;
     sh.G = G;
-    plan->max_priv = std::max(plan->max_priv, c.n_priv);
     sh.count = counts[s];
     sh.tile0 = tile0;
     sh.llr_off = llr_off;
     sh.bits_off = bits_off;
     sh.app_off = app_off;
     sh.state_off = state_off;
+    sh.lds_rows = 0;
     plan->lds = std::max(plan->lds, tile_lds);
     llr_off += counts[s] * c.e_tx;
     bits_off += counts[s] * c.k;
@@ -791,6 +806,50 @@ lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t*
   plan->ntiles = tile0;
   plan->state_words = (size_t)state_off;
   plan->dmax = dmax;
+  int occ = 0;
+  hipError_t e = hipSuccess;
+  if (!oms) {
+    // check records kept in LDS (p->lds_rows): by default as many rows per
+    // shape as fit the LDS a workgroup has at the occupancy the shared
+    // posteriors allow
+    e = lsim::mixed_occupancy(threads, dmax, plan->lds, &occ);
+    if (e == hipSuccess && occ < 1) e = hipErrorInvalidConfiguration;
+    if (e != hipSuccess) {
+      delete plan;
+      return dev_status(e, "mixed plan occupancy");
+    }
+    const size_t budget = std::min(lds_cap, (size_t)(160 * 1024) / occ) - 32;  // 32: the work-item word
+    for (int shrink = 0;; ++shrink) {
+      size_t lds = 0;
+      for (auto& sh : plan->shapes) {
+        const DevCode& c = sh.code;
+        const size_t base = lsim::layered_tile_lds(c, sh.G), per_row = (size_t)sh.G * c.Z * 16;
+        int K = 0;
+        if (p->lds_rows == 0)
+          K = std::max(0, (int)std::min<size_t>(c.rows, budget > base ? (budget - base) / per_row
+                                                                      : 0) - shrink);
+        else if (p->lds_rows > 0)
+          K = std::min(p->lds_rows, c.rows);
+        sh.lds_rows = K;
+        lds = std::max(lds, lsim::layered_tile_lds(c, sh.G, K));
+      }
+      if (lds > lds_cap) {
+        delete plan;
+        return fail(LSIM_E_INVAL, "lds_rows: the check records of that many rows do not fit the LDS");
+      }
+      int occ2 = 0;
+      e = lsim::mixed_occupancy(threads, dmax, lds, &occ2);
+      if (e != hipSuccess) {
+        delete plan;
+        return dev_status(e, "mixed plan occupancy");
+      }
+      if (occ2 >= occ || p->lds_rows != 0 || shrink > 64) {
+        plan->lds = lds;
+        occ = occ2;
+        break;
+      }
+    }
+  }
   // work list, heaviest tiles first: a tile costs about one pass over the
   // base nonzeros plus one barrier per layer, per iteration
   std::vector<int> order(nshapes);
@@ -810,11 +869,15 @@ lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t*
     }
   }
   int dev = 0, ncu = 256;
-  hipError_t e = hipGetDevice(&dev);
+  e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const int by_lds = std::max(1, (int)((160 * 1024) / (plan->lds + 64)));
-  const int by_waves = std::max(1, 32 / (threads / 64));
-  plan->grid = ncu * std::min(by_lds, by_waves);
+  if (oms) {
+    const int by_lds = std::max(1, (int)((160 * 1024) / (plan->lds + 64)));
+    const int by_waves = std::max(1, 32 / (threads / 64));
+    plan->grid = ncu * std::min(by_lds, by_waves);
+  } else {
+    plan->grid = ncu * std::max(1, occ);  // every workgroup resident at once
+  }
   const size_t b_shapes = nshapes * sizeof(lsim::LayerShape);
   const size_t b_ts = tile_shape.size() * sizeof(int);
   const size_t b_tl = tile_local.size() * sizeof(int64_t);
@@ -875,7 +938,7 @@ lsim_status lsim_mixed_decode(lsim_plan* plan, const void* d_llr_concat, uint8_t
       plan->d_shapes, (int)plan->shapes.size(), plan->d_tile_shape, plan->d_tile_local,
       plan->ntiles, plan->threads, plan->lds, plan->p, d_llr_concat, d_bits_concat, d_app_concat,
       (uint32_t*)(w + kCounterBytes), (int*)w, persistent ? 1 : 0, plan->grid, plan->dmax,
-      plan->max_priv, as_stream(stream));
+      as_stream(stream));
   return dev_status(e, "mixed decode");
 }
 

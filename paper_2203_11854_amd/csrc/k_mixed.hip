@@ -42,6 +42,7 @@ __global__ __launch_bounds__(NT) void mixed_kernel(const LayerShape* __restrict_
     io.r_out = nullptr;
     io.state = reinterpret_cast<uint4*>(state + sh.state_off);
     io.count = sh.count;
+    io.lds_rows = sh.lds_rows;
     decode_tile<NT, DMAX>(sh.code, sh.G, tile_local[item], io, iters, alpha);
     __syncthreads();
     if (!persistent) break;
@@ -56,7 +57,7 @@ hipError_t launch_mixed(const LayerShape* d_shapes, int nshapes, const int* d_ti
                         const int64_t* d_tile_local, int64_t ntiles, int threads,
                         size_t lds_bytes, const lsim_decode_params& p, const void* llr,
                         uint8_t* bits, float* lpost, uint32_t* state, int* counter,
-                        int persistent, int grid, int dmax, int max_priv, hipStream_t s) {
+                        int persistent, int grid, int dmax, hipStream_t s) {
   (void)nshapes;
   if (persistent) {
     reset_counter_kernel<<<1, 1, 0, s>>>(counter);
@@ -64,11 +65,11 @@ hipError_t launch_mixed(const LayerShape* d_shapes, int nshapes, const int* d_ti
     if (e != hipSuccess) return e;
   }
   const unsigned g = persistent ? (unsigned)grid : (unsigned)ntiles;
-  const int next_off = (int)((lds_bytes + 15) & ~(size_t)15);
+  const int next_off = (int)align16(lds_bytes);
   const size_t lds_all = (size_t)next_off + 16;
   const int D = dmax <= 16 ? 16 : dmax <= 24 ? 24 : 27;
 #define LSIM_MIXED_CASE(NT_, D_)                                                       \
-  if (threads == NT_ && D == D_ ) {                                              \
+  if (threads == NT_ && D == D_) {                                                         \
     const void* k = (const void*)mixed_kernel<NT_, D_>;                                \
     hipError_t e = require_lds_at_zero(k);                                                 \
     if (e == hipSuccess) e = ensure_dyn_lds(k, lds_all);                                   \
@@ -81,6 +82,22 @@ hipError_t launch_mixed(const LayerShape* d_shapes, int nshapes, const int* d_ti
   }
   LSIM_LAYERED_INSTANCES(LSIM_MIXED_CASE)
 #undef LSIM_MIXED_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t mixed_occupancy(int threads, int dmax, size_t lds, int* occ) {
+  const size_t lds_all = align16(lds) + 16;
+  const int D = dmax <= 16 ? 16 : dmax <= 24 ? 24 : 27;
+  *occ = 0;
+#define LSIM_MIXED_OCC(NT_, D_)                                                       \
+  if (threads == NT_ && D == D_) {                                                    \
+    const void* k = (const void*)mixed_kernel<NT_, D_>;                               \
+    hipError_t e = ensure_dyn_lds(k, kLdsBytes); /* the query honours the limit */    \
+    if (e != hipSuccess) return e;                                                    \
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k, NT_, lds_all);        \
+  }
+  LSIM_LAYERED_INSTANCES(LSIM_MIXED_OCC)
+#undef LSIM_MIXED_OCC
   return hipErrorInvalidValue;
 }
 

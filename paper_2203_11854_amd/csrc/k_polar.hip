@@ -147,7 +147,12 @@ __global__ __launch_bounds__(kPolThreads) void polar_decode_kernel(DevPolar pc,
   uint8_t* rec = reinterpret_cast<uint8_t*>(bw + L * W);  // [K][L]: (parent << 1) | bit
   const int lane = threadIdx.x;
   const int64_t b = blockIdx.x;
-  for (int e = lane; e < N; e += kPolThreads) ch[e] = -llr[b * N + e];
+  // NaN reads as 0 and the channel is clamped to +-2^100, so no node LLR or
+  // metric is ever inf - inf (at most 2N clamped terms add up)
+  for (int e = lane; e < N; e += kPolThreads) {
+    const float v = -llr[b * N + e];
+    ch[e] = v != v ? 0.f : fminf(fmaxf(v, -0x1p100f), 0x1p100f);
+  }
   if (lane < L) pm[lane] = 0.f;
   wave_sync();
   auto blbit = [&](int p, int st, int e) -> uint32_t {

@@ -42,8 +42,12 @@ namespace layered {
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-__host__ __device__ inline size_t tile_lds_bytes(const DevCode& c, int G) {
-  return align16((size_t)G * c.n_shared * c.Z * 4);
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS per CU (and per workgroup) on gfx950
+
+// LDS of a tile: the shared posteriors of its G codewords, then the check
+// records of the rows kept in LDS (K of them per codeword).
+__host__ __device__ inline size_t tile_lds_bytes(const DevCode& c, int G, int K = 0) {
+  return align16((size_t)G * c.n_shared * c.Z * 4) + (size_t)G * K * c.Z * 16;
 }
 
 struct TileIO {
@@ -51,8 +55,9 @@ struct TileIO {
   uint8_t* bits;        // [count][k]
   float* lpost;         // [count][n_dec]
   float* r_out;         // [count][E]
-  uint4* state;         // [count][rows][Z] check records
+  uint4* state;         // [count][rows][Z] check records (rows >= lds_rows)
   int64_t count;
+  int lds_rows;         // rows whose records stay in LDS
 };
 
 __device__ __forceinline__ int rot_lift(int r, int s, int Z) {
@@ -91,6 +96,10 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
   const bool zpow2 = (Z & (Z - 1)) == 0;
   uint4* st = io.state + (size_t)cw * c.rows * Z + r;
   const float* llr_cw = io.llr + cw * c.e_tx;
+  // records of rows 0 .. K-1 in LDS after the shared posteriors, lane-private
+  // (written and read back by the same lane, so no barrier orders them)
+  const int K = io.lds_rows;
+  const int rec_b = (int)align16((size_t)G * nsz * 4) + (((active ? g : 0) * K) * Z + r) * 16;
 
   // Variable node of the private entry of row i at this lane.
   auto priv_vn = [&](int i) {
@@ -109,7 +118,7 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
     uint4 v = make_uint4(0u, 0u, 0u, 0u);
     if (active && nit < iters) {
       if (nit >= 1) {
-        v = st[(size_t)ni * Z];
+        v = ni < K ? lds_ld<uint4>(rec_b + ni * Z * 16) : st[(size_t)ni * Z];
       } else if (uni(ld_const(c.row_priv, ni)) >= 0) {
         const int x = priv_vn(ni) - c.tx_lo;
         if (x >= 0 && x < c.e_tx) v.w = __float_as_uint(-llr_cw[x]);
@@ -201,10 +210,12 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
             npk |= sg >> (31 - q);
           }
           npk |= (uint32_t)i1 << 27;
-          // the last iteration's records are read only by the state export
-          if (it < iters - 1 || io.r_out)
-            st[(size_t)i * Z] = make_uint4(__float_as_uint(b1), __float_as_uint(b2), npk,
-                                           __float_as_uint(pout));
+          const uint4 nr = make_uint4(__float_as_uint(b1), __float_as_uint(b2), npk,
+                                      __float_as_uint(pout));
+          if (i < K)
+            lds_st<uint4>(rec_b + i * Z * 16, nr);
+          else if (it < iters - 1 || io.r_out)  // the last records serve only the export
+            st[(size_t)i * Z] = nr;
           if (PRIV && it == iters - 1) {
             // the private posterior is final: write it out now
             const int v = priv_vn(i);
@@ -237,7 +248,7 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
   }
   if (io.r_out && active) {
     for (int i = 0; i < c.rows; ++i) {
-      const uint4 rc = st[(size_t)i * Z];
+      const uint4 rc = i < K ? lds_ld<uint4>(rec_b + i * Z * 16) : st[(size_t)i * Z];
       const float a1 = __uint_as_float(rc.x), a2 = __uint_as_float(rc.y);
       const uint32_t pk = rc.z;
       const int i1 = (int)(pk >> 27);

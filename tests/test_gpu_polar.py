@@ -61,12 +61,14 @@ def _noisy_llrs(x, ebn0, rate, seed, cw0=0):
     return (-4.0 * y / n0).astype(np.float32)
 
 
-def _check(pc, mask, llr, L, crc, use_crc):
+def _check(pc, mask, llr, L, crc, use_crc, rows=None):
+    """Decode every row of llr in one launch; compare the given rows (all by
+    default) with the oracle's float32 mode."""
     r, poly = crc
     bits, pm = pc.decode(T(llr).to(dev), L, use_crc, want_pm=True)
     bits, pm = bits.cpu().numpy(), pm.cpu().numpy()
     nact = min(L, 1 << int(mask.sum()))
-    for b in range(llr.shape[0]):
+    for b in (range(llr.shape[0]) if rows is None else rows):
         lam = (-llr[b]).astype(np.float32)
         u, upm, _ = P.scl_decode(lam, mask, L, poly if use_crc else 0, r if use_crc else 0,
                                  mode="fp32")
@@ -107,29 +109,50 @@ def test_ties_and_zero_llrs():
 
 
 def test_full_size_batch_sampled():
-    """The benchmark's code and batch (N 1024, K 512 with CRC-16, lists 8
-    and 32, 4096 codewords at Eb/N0 1.5 dB): sampled codewords against the
-    oracle; SCL-CRC is at least as good as SCL and SC on the whole batch."""
+    """The benchmark's code and batch (N 1024, K 512 with CRC-16, lists 1, 8
+    and 32, 4096 codewords at Eb/N0 1.5 dB): sampled rows of the full-batch
+    launches against the oracle; SCL-CRC is at least as good as SCL and SC
+    on the whole batch."""
     n, K, crc = 10, 512, CRC16
     mask, pc = _code(n, K, 2.0, crc)
     B = 4096
-    data = lsim.source_bits(400, 0, B, K - crc[0], dev)
-    x = pc.encode(data)
+    data = rand.bits(400, (B, K - crc[0]))
+    x = P.encode(data, mask, crc[1], crc[0])
     rate = (K - crc[0]) / 1024
-    no = torch.full((B,), float(1.0 / (rate * 10 ** 0.15)), dtype=torch.float32, device=dev)
-    y = lsim.map_awgn_bits(1, x, no, 401, 0)
-    llr = lsim.demap(1, lsim.DEMAP_EXACT, y, no)
+    llr = _noisy_llrs(x, 1.5, rate, 401)
     errs = {}
+    tl = T(llr).to(dev)
     for L, use in ((1, False), (8, False), (8, True)):
-        bits = pc.decode(llr, L, use)
-        errs[(L, use)] = int((bits != data).any(1).sum().item())
+        bits = pc.decode(tl, L, use).cpu().numpy()
+        errs[(L, use)] = int((bits != data).any(1).sum())
     print("block errors of 4096: SC", errs[(1, False)], "SCL8", errs[(8, False)],
           "SCL8-CRC", errs[(8, True)])
     assert errs[(8, True)] <= errs[(8, False)] <= errs[(1, False)]
-    rows = np.array([0, 1, 2047, 4095])
-    _check(pc, mask, llr.cpu().numpy()[rows], 8, crc, True)
-    # the list-32 decoder at the same size, two sampled codewords
-    _check(pc, mask, llr.cpu().numpy()[rows[[0, 3]]], 32, crc, True)
+    rows = [0, 1, 2047, 4095]
+    _check(pc, mask, llr, 1, crc, False, rows=rows)
+    _check(pc, mask, llr, 8, crc, True, rows=rows)
+    _check(pc, mask, llr, 32, crc, True, rows=rows)
+
+
+def test_non_finite_llrs():
+    """Infinite and NaN channel LLRs: the decoders read NaN as 0 and clamp
+    +-inf to +-2^100 (so no intermediate value is inf - inf), as the oracle
+    does; with opposite-sign infinities every list size still matches it bit
+    for bit, metrics included."""
+    n, K = 6, 32
+    mask, pc = _code(n, K, 1.0, CRC8)
+    B = 6
+    data = rand.bits(510, (B, K - 8))
+    x = P.encode(data, mask, 0x07, 8)
+    llr = _noisy_llrs(x, 1.0, (K - 8) / 64, 511)
+    llr[0, 0], llr[0, 32] = np.inf, -np.inf          # g(a, b) would be inf - inf
+    llr[1, ::7] = np.inf
+    llr[2, 1::5] = -np.inf
+    llr[3, 3] = np.nan
+    llr[4, :] = np.nan
+    llr[5, :32], llr[5, 32:] = np.inf, -np.inf
+    for L, use in ((1, False), (8, False), (8, True), (32, True)):
+        _check(pc, mask, llr, L, CRC8, use)
 
 
 def test_single_codeword_and_no_frozen_bits():

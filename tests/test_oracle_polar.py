@@ -166,3 +166,28 @@ def test_scl_crc_picks_a_passing_path():
             assert np.array_equal(u, uh[best])
             hits += int(not np.array_equal(uh[best], uh[min(range(8), key=lambda s: (pm[s], s))]))
     assert hits > 0          # the CRC changed the decision at least once
+
+
+def test_non_finite_channel_values_stay_finite():
+    """NaN reads as 0, +-inf as +-2^100; with opposite-sign infinities under
+    one node (the right child's g would be inf - inf) every metric of every
+    list size stays finite, and an all-NaN channel decodes as all zeros."""
+    import numpy as np
+    from oracle import polar as P
+    lam = np.array([np.nan, np.inf, -np.inf, 1.0], dtype=np.float32)
+    rc = P.read_channel(lam, np.float32)
+    assert rc[0] == 0 and rc[1] == np.float32(2.0 ** 100) and rc[2] == -np.float32(2.0 ** 100)
+    assert rc[3] == 1.0
+    n, K = 5, 12
+    mask = P.info_mask(n, K, 1.0)
+    r = np.random.default_rng(7)
+    for trial in range(8):
+        lam = r.normal(1.0, 2.0, 1 << n)
+        pos = r.choice(1 << n, 6, replace=False)
+        lam[pos[:3]] = np.inf
+        lam[pos[3:]] = -np.inf
+        for L in (1, 4, 8):
+            u, pm, _ = P.scl_decode(lam, mask, L, mode="fp32")
+            assert np.isfinite(pm[:min(L, 1 << K)]).all(), (trial, L, pm)
+    u = P.sc_decode(np.full(1 << n, np.nan), mask, "fp32")
+    assert not u.any()
