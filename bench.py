@@ -592,7 +592,7 @@ def mixed_leg(torch, lsim, dev):
 
     specs = mixed_specs()
     counts = mixed_counts()
-    codes, parts = [], []
+    codes, parts, us = [], [], []
     p = lsim.params(lsim.NMS_F32, iters=20, alpha=0.75)
     for s, ((spec, e_tx), cnt) in enumerate(zip(specs, counts)):
         qb = spec.load()
@@ -603,6 +603,7 @@ def mixed_leg(torch, lsim, dev):
         ebn0 = r.uniform(0.0, 6.0, cnt)
         seed = data_seed(4, s)
         u = lsim.source_bits(seed, 0, cnt, code.k, dev)
+        us.append(u)
         c = lsim.encode(code, u)
         llr = torch.empty((cnt, code.e_tx), dtype=torch.float32, device=dev)
         for lo, hi, m in ((0, n_qpsk, 2), (n_qpsk, cnt, 4)):
@@ -673,6 +674,29 @@ def mixed_leg(torch, lsim, dev):
     osame = all(torch.equal(obits[o:o + bb.numel()], bb.reshape(-1))
                 for o, bb in zip(oplan.bits_offsets, osep))
     oinfo = sum(cnt * cd.k for cd, cnt in zip(ocodes, ocounts))
+    # schedule and placement tuning: per shape layered NMS or flooding int8
+    # OMS (accepted only inside NMS's Wilson 95% BLER interval on this data),
+    # check records in LDS or streamed; the chosen schedule's bits against
+    # the per-shape decoders it names
+    sched = autotune.tune_schedule(codes, counts, parts, us, p)
+    lp = lsim.params(lsim.NMS_F32, iters=20, alpha=0.75, lds_rows=sched["lds_rows"])
+    sm = autotune.ScheduledMixed(codes, counts, sched["schedule"], lp, po)
+    io = sm.inputs(parts)
+    sm.decode(io)
+    sbits = sm.bits(io)
+    sched_same = True
+    for s_, (cd, x) in enumerate(zip(codes, parts)):
+        if sched["schedule"][s_] == "oms":
+            rb, _ = lsim.decode(cd, lsim.quantize(x), po)
+        else:
+            rb = sep_bits[s_]
+        sched_same = sched_same and torch.equal(sbits[s_], rb)
+    ms_sched = _elapsed(torch, lambda: sm.decode(io), 5)
+    blk = {"default_nms": 0, "scheduled": 0}
+    for s_, sh in enumerate(sched["shapes"]):
+        blk["default_nms"] += sh["nms_block_errors"]
+        blk["scheduled"] += (sh["oms_block_errors"] if sched["schedule"][s_] == "oms"
+                             else sh["nms_block_errors"])
     return {"codewords": int(sum(counts)), "counts": counts, "info_bits": int(info),
             "graph_ms": round(ms_graph, 4), "persistent_ms": round(ms_pers, 4),
             "per_shape_ms": round(ms_sep, 4),
@@ -682,6 +706,13 @@ def mixed_leg(torch, lsim, dev):
             "autotuned": {"threads": best["threads"], "codewords_per_tile": best["codewords_per_tile"],
                           "persistent": best["persistent"], "ms": round(ms_tuned, 4),
                           "bit_identical": bool(torch.equal(tbits, bits))},
+            "schedule_tuned": {"schedule": sched["schedule"], "lds_rows": sched["lds_rows"],
+                               "ms": round(ms_sched, 4),
+                               "gbps": round(info / (ms_sched * 1e-3) / 1e9, 3),
+                               "default_persistent_ms": round(ms_pers, 4),
+                               "block_errors": blk, "codewords": int(sum(counts)),
+                               "per_shape": sched["shapes"], "candidates": sched["tried"],
+                               "bit_identical_to_named_decoders": bool(sched_same)},
             "oms_i8": {"shapes": keep, "codewords": int(sum(ocounts)),
                        "persistent_ms": round(ms_oms, 4), "per_shape_ms": round(ms_oms_sep, 4),
                        "persistent_gbps": round(oinfo / (ms_oms * 1e-3) / 1e9, 3),
@@ -997,6 +1028,20 @@ def wbp_eval_leg(torch, lsim, dev, code, qb, T=10, pre_steps=300, joint_steps=30
         lsim.map_awgn(code, m, c, no, seed, step * B, out=y)
         return c, no
 
+    # one fixed evaluation batch (other seeds, Eb/N0 ~ U[1, 4] dB) on which the
+    # posterior loss is taken before and after the joint stage
+    fseed = data_seed(5, 3)
+    fno = torch.tensor(lsim.ebn0_to_n0(rand.rng(7009).uniform(1.0, 4.0, B), rate, m),
+                       dtype=torch.float32, device=dev)
+    fc = lsim.encode(code, lsim.source_bits(fseed, 0, B, code.k, dev))
+    fy = lsim.map_awgn(code, m, fc, fno, fseed, 0)
+
+    def fixed_bce(wt):
+        fl = lsim.ndm_forward(params, fy, fno)
+        fp, _ = lsim.wbp_forward(code, wt, fl, T, 20.0, want_ckpt=False)
+        _, fl_loss = lsim.bce_grad(fp, fc, 1.0 / (B * code.n_dec))
+        return round(float(fl_loss.item()), 6)
+
     t0 = time.perf_counter()
     for step in range(1, pre_steps + 1):
         c, no = batch(step)
@@ -1008,6 +1053,8 @@ def wbp_eval_leg(torch, lsim, dev, code, qb, T=10, pre_steps=300, joint_steps=30
             losses[f"demapper_bce_step{step}"] = round(float(loss.item()), 5)
     pm.zero_()
     pv.zero_()
+    ones = torch.ones_like(w)
+    fixed = {"posterior_bce_before_joint": fixed_bce(ones)}
     for step in range(1, joint_steps + 1):
         c, no = batch(pre_steps + step)
         lsim.ndm_forward(params, y, no, out=llr)
@@ -1021,6 +1068,13 @@ def wbp_eval_leg(torch, lsim, dev, code, qb, T=10, pre_steps=300, joint_steps=30
             losses[f"posterior_bce_step{step}"] = round(float(loss.item()), 5)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
+    fixed["posterior_bce_after_joint"] = fixed_bce(w)
+    fixed["posterior_bce_after_joint_unit_weights"] = fixed_bce(ones)
+    dw = (w - 1.0).double()
+    fixed["weights"] = {"l2_norm_w_minus_1": round(float(dw.norm()), 5),
+                        "max_abs_w_minus_1": round(float(dw.abs().max()), 5),
+                        "mean_abs_w_minus_1": round(float(dw.abs().mean()), 6),
+                        "count": int(w.numel())}
 
     Be = 4096
     pts = np.arange(21) * 0.25
@@ -1055,7 +1109,8 @@ def wbp_eval_leg(torch, lsim, dev, code, qb, T=10, pre_steps=300, joint_steps=30
         lsim.decode(code, le, spa20, bits=bits)
         score("spa_exact_20")
     return {"train_steps": {"demapper_only": pre_steps, "joint": joint_steps},
-            "train_seconds": round(train_s, 2), "losses": losses, "eval_batch_per_point": Be,
+            "train_seconds": round(train_s, 2), "losses": losses, "fixed_batch": fixed,
+            "eval_batch_per_point": Be,
             "ebn0_db": pts.tolist(), "bler": curves,
             "ebn0_db_at_bler_1e-2": {k: ebn0_at_bler(pts, v) for k, v in curves.items()}}
 

@@ -1,6 +1,6 @@
-"""Autotuner for the decoders' result-invariant launch knobs.
+"""Autotuner for the decoders' launch knobs and schedules.
 
-Knobs that cannot change any output bit:
+Knobs that cannot change any output bit (``tune_mixed``, ``tune_decode``):
 
 * workgroup size of the flooding and layered decoders,
 * for the mixed-shape persistent decoder, the workgroup size and the number
@@ -11,7 +11,14 @@ Every candidate is timed with HIP events on the current stream and its
 output is compared bit for bit with the first (reference) candidate; a
 candidate that disagrees is rejected (it would mean a kernel bug).  The
 winner is cached in a JSON file keyed by the code shapes, counts and
-decoder parameters.
+decoder parameters (no cache unless a path is given).
+
+``tune_schedule`` also tunes knobs that change results: per shape of a
+mixed batch, the layered normalized min-sum decoder (FP32, the default) or
+the flooding int8 offset min-sum decoder; and where the layered decoder
+keeps its check records (LDS or device memory, result-invariant).  A shape
+may move to offset min-sum only if its block error rate on the plan's data
+lies inside the default decoder's Wilson 95% interval on the same data.
 """
 from __future__ import annotations
 
@@ -23,7 +30,6 @@ import torch
 
 from . import MixedPlan, decode, params as make_params  # noqa: F401
 
-DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 
 def _key(parts) -> str:
@@ -62,7 +68,7 @@ def _tile_options(Z, threads):
     return opts
 
 
-def tune_mixed(codes, counts, p, llr_concat, cache_path: str | None = DEFAULT_CACHE,
+def tune_mixed(codes, counts, p, llr_concat, cache_path: str | None = None,
                threads_options=(384, 512, 768, 1024), reps: int = 3, verbose: bool = False):
     """Best (threads, codewords_per_tile, persistent) for a mixed batch.
     For the int8 offset min-sum decoder the tile is always a codeword pair
@@ -112,7 +118,7 @@ def tune_mixed(codes, counts, p, llr_concat, cache_path: str | None = DEFAULT_CA
     return best
 
 
-def tune_decode(code, llr, p, cache_path: str | None = DEFAULT_CACHE, reps: int = 3,
+def tune_decode(code, llr, p, cache_path: str | None = None, reps: int = 3,
                 verbose: bool = False):
     """Best workgroup size for lsim_decode of one code."""
     from . import NMS_F32, params, decode_workspace
@@ -125,7 +131,7 @@ def tune_decode(code, llr, p, cache_path: str | None = DEFAULT_CACHE, reps: int 
     for t in opts:
         if p.algo == NMS_F32 and t < code.Z:
             continue
-        q = params(p.algo, p.iters, p.offset, p.alpha, p.llr_max, p.sat, t)
+        q = params(p.algo, p.iters, p.offset, p.alpha, p.llr_max, p.sat, t, p.lds_rows)
         work = None
         nb = decode_workspace(code, q, llr.shape[0])
         if nb:
@@ -147,3 +153,140 @@ def tune_decode(code, llr, p, cache_path: str | None = DEFAULT_CACHE, reps: int 
         cache[key] = best
         _store(cache_path, cache)
     return best
+
+
+def wilson(k: int, n: int, z: float = 1.959963984540054):
+    """Wilson score interval of a binomial proportion k / n."""
+    if n <= 0:
+        return 0.0, 1.0
+    p = k / n
+    den = 1.0 + z * z / n
+    mid = (p + z * z / (2 * n)) / den
+    half = z * ((p * (1 - p) / n + z * z / (4 * n * n)) ** 0.5) / den
+    return max(0.0, mid - half), min(1.0, mid + half)
+
+
+def oms_fits(code) -> bool:
+    """The flooding int8 decoder keeps a codeword pair's whole state in LDS."""
+    return 4 * (code.E + code.n_dec) <= 160 * 1024 - 96
+
+
+class ScheduledMixed:
+    """A mixed batch decoded under a schedule: the shapes marked "nms" in one
+    persistent layered-NMS launch, the shapes marked "oms" quantized and
+    decoded in one persistent int8 offset min-sum launch.  LLRs come per
+    shape (f32 [count][e_tx]); bits go out per shape."""
+
+    def __init__(self, codes, counts, schedule, p_nms, p_oms, threads: int = 0):
+        from . import MixedPlan
+        self.codes, self.counts, self.schedule = list(codes), list(counts), list(schedule)
+        self.nms_idx = [s for s, a in enumerate(schedule) if a == "nms"]
+        self.oms_idx = [s for s, a in enumerate(schedule) if a == "oms"]
+        self.nplan = (MixedPlan([codes[s] for s in self.nms_idx], [counts[s] for s in self.nms_idx],
+                                p_nms, threads=threads) if self.nms_idx else None)
+        self.oplan = (MixedPlan([codes[s] for s in self.oms_idx], [counts[s] for s in self.oms_idx],
+                                p_oms) if self.oms_idx else None)
+        self.p_oms = p_oms
+        self.nwork = self.nplan.workspace() if self.nplan else None
+        self.owork = self.oplan.workspace() if self.oplan else None
+
+    def inputs(self, parts):
+        """The launches' concatenated inputs from per-shape f32 LLRs (the int8
+        ones are filled by ``decode``)."""
+        f = torch.cat([parts[s].reshape(-1) for s in self.nms_idx]) if self.nms_idx else None
+        o = torch.cat([parts[s].reshape(-1) for s in self.oms_idx]) if self.oms_idx else None
+        q = torch.empty(o.shape, dtype=torch.int8, device=o.device) if o is not None else None
+        nb = (torch.empty(self.nplan.n_bits, dtype=torch.uint8, device=parts[0].device)
+              if self.nplan else None)
+        ob = (torch.empty(self.oplan.n_bits, dtype=torch.uint8, device=parts[0].device)
+              if self.oplan else None)
+        return {"f32": f, "oms_f32": o, "oms_q": q, "nms_bits": nb, "oms_bits": ob}
+
+    def decode(self, io, persistent=True):
+        from . import quantize
+        if self.nplan:
+            self.nplan.decode(io["f32"], bits=io["nms_bits"], work=self.nwork, persistent=persistent)
+        if self.oplan:
+            quantize(io["oms_f32"], 2.0, self.p_oms.sat, out=io["oms_q"])
+            self.oplan.decode(io["oms_q"], bits=io["oms_bits"], work=self.owork,
+                              persistent=persistent)
+
+    def bits(self, io):
+        """Per-shape views of the decoded bits."""
+        out = [None] * len(self.codes)
+        for plan, idx, key in ((self.nplan, self.nms_idx, "nms_bits"),
+                               (self.oplan, self.oms_idx, "oms_bits")):
+            if plan is None:
+                continue
+            for j, s in enumerate(idx):
+                o = plan.bits_offsets[j]
+                out[s] = io[key][o:o + self.counts[s] * self.codes[s].k].view(self.counts[s], -1)
+        return out
+
+
+def _block_errors(ref, hat):
+    return int((ref != hat).any(dim=1).sum().item())
+
+
+def tune_schedule(codes, counts, parts, ref_bits, p_nms, p_oms=None, reps: int = 3,
+                  verbose: bool = False):
+    """Schedule (decoder per shape) and placement for a mixed batch.
+
+    parts: per-shape f32 LLRs [count][e_tx]; ref_bits: per-shape transmitted
+    information bits [count][k].  Returns the chosen schedule, the NMS
+    plan's lds_rows setting, per-shape block errors of both decoders with
+    the default's Wilson interval, and the time of every candidate timed.
+    Candidates start from every shape on layered NMS; shapes whose offset
+    min-sum BLER is accepted are moved to it one at a time, heaviest first,
+    and a move is kept when the schedule gets faster."""
+    from . import OMS_I8, decode, decode_workspace, params, quantize
+    if p_oms is None:
+        p_oms = params(OMS_I8, iters=p_nms.iters, offset=1, sat=31)
+    dev = parts[0].device
+    per_shape = []
+    for s, (code, x, u) in enumerate(zip(codes, parts, ref_bits)):
+        n = int(counts[s])
+        work = torch.empty(max(1, decode_workspace(code, p_nms, n)), dtype=torch.uint8, device=dev)
+        bn, _ = decode(code, x, p_nms, work=work)
+        en = _block_errors(u, bn)
+        lo, hi = wilson(en, n)
+        info = {"shape": s, "Z": code.Z, "codewords": n, "nms_block_errors": en,
+                "nms_ci95": [round(lo, 5), round(hi, 5)], "oms_fits": oms_fits(code)}
+        if info["oms_fits"]:
+            bo, _ = decode(code, quantize(x, 2.0, p_oms.sat), p_oms)
+            eo = _block_errors(u, bo)
+            info["oms_block_errors"] = eo
+            info["oms_accepted"] = bool(lo - 1e-12 <= eo / n <= hi + 1e-12)
+        else:
+            info["oms_accepted"] = False
+        per_shape.append(info)
+
+    def timed(schedule, lds_rows):
+        pn = params(p_nms.algo, p_nms.iters, p_nms.offset, p_nms.alpha, p_nms.llr_max, p_nms.sat,
+                    p_nms.threads, lds_rows)
+        sm = ScheduledMixed(codes, counts, schedule, pn, p_oms)
+        io = sm.inputs(parts)
+        return _time(lambda: sm.decode(io), reps), sm, io
+
+    tried = []
+    best_lds, best_t = 0, None
+    base = ["nms"] * len(codes)
+    for lds_rows in (0, -1):
+        t, _, _ = timed(base, lds_rows)
+        tried.append({"schedule": list(base), "lds_rows": lds_rows, "ms": round(t, 4)})
+        if best_t is None or t < best_t:
+            best_t, best_lds = t, lds_rows
+    schedule = list(base)
+    order = sorted((i for i in per_shape if i["oms_accepted"]),
+                   key=lambda i: -i["codewords"] * codes[i["shape"]].E)
+    for info in order:
+        cand = list(schedule)
+        cand[info["shape"]] = "oms"
+        t, _, _ = timed(cand, best_lds)
+        tried.append({"schedule": cand, "lds_rows": best_lds, "ms": round(t, 4)})
+        if verbose:
+            print(tried[-1], flush=True)
+        if t < best_t:
+            best_t, schedule = t, cand
+    return {"schedule": schedule, "lds_rows": best_lds, "ms": round(best_t, 4),
+            "shapes": per_shape, "tried": tried}

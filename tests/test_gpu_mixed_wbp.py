@@ -444,3 +444,44 @@ def test_autotuner_mixed_and_decode(tmp_path):
     for algo in (lsim.SPA_F32, lsim.NMS_F32):
         bd = autotune.tune_decode(code, llr, lsim.params(algo), cache_path=cache)
         assert bd["threads"] in (256, 384, 512, 768, 1024)
+
+
+def test_schedule_tuner():
+    """Result-changing knobs of the mixed batch: a shape moves from layered
+    NMS to flooding int8 offset min-sum only when its block error rate lies
+    inside NMS's Wilson 95% interval on the same data, and the scheduled
+    launches give, shape by shape, exactly the bits of the decoders the
+    schedule names.  A schedule with every shape on NMS is the mixed plan."""
+    from paper_2203_11854_amd import autotune
+    counts = [40, 24, 30, 12, 10, 8, 16, 6]
+    codes, llrs, graphs, qbs = mixed_inputs(counts, seed=131)
+    parts, us = [], []
+    for s, (code, L, g, qb) in enumerate(zip(codes, llrs, graphs, qbs)):
+        parts.append(T(L).to(dev))
+    # the transmitted bits of mixed_inputs' codewords, from the oracle's link
+    for s, (g, qb) in enumerate(zip(graphs, qbs)):
+        from oracle import philox
+        us.append(T(philox.source_bits(131 + 100 + s, 0, counts[s], g.k)).to(dev))
+    pn = lsim.params(lsim.NMS_F32, iters=20, alpha=0.75)
+    res = autotune.tune_schedule(codes, counts, parts, us, pn)
+    po = lsim.params(lsim.OMS_I8, iters=20, offset=1, sat=31)
+    for s, info in enumerate(res["shapes"]):
+        if res["schedule"][s] == "oms":
+            assert info["oms_fits"] and info["oms_accepted"]
+            lo, hi = info["nms_ci95"]
+            assert lo - 1e-9 <= info["oms_block_errors"] / counts[s] <= hi + 1e-9
+    assert res["lds_rows"] in (0, -1)
+    for schedule in (res["schedule"], ["nms"] * len(codes),
+                     ["oms" if autotune.oms_fits(c) else "nms" for c in codes]):
+        sm = autotune.ScheduledMixed(codes, counts, schedule,
+                                     lsim.params(lsim.NMS_F32, iters=20, alpha=0.75,
+                                                 lds_rows=res["lds_rows"]), po)
+        io = sm.inputs(parts)
+        sm.decode(io)
+        got = sm.bits(io)
+        for s, (code, x) in enumerate(zip(codes, parts)):
+            if schedule[s] == "oms":
+                ref, _ = lsim.decode(code, lsim.quantize(x), po)
+            else:
+                ref, _ = lsim.decode(code, x, pn)
+            assert torch.equal(got[s], ref), (schedule, s)
