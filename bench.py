@@ -50,13 +50,13 @@ LDS_PEAK_GBS = N_CU * 128 * CLOCK_GHZ
 # for the copy probe of known size (factors below).  Valid only for the
 # kernel sources they were taken on (hash); any change there reports null
 # until the counters are taken again.
-LAYERED_TRAFFIC = {"bytes": (2735951 * 2 + 5378304) * 1024,
+LAYERED_TRAFFIC = {"bytes": (2385738 * 2 + 4677888) * 1024,
                    "sources": ("layered_tile.h", "k_layered.hip", "dispatch.h", "lds.h",
                                "devcode.h"),
-                   "sha256_16": "c47633403ce74083"}
-FLOOD_SPA_TRAFFIC = {"bytes": (30954 * 2 + 5120) * 1024,
+                   "sha256_16": "01e3ce4fcfbfcfac"}
+FLOOD_SPA_TRAFFIC = {"bytes": (30955 * 2 + 5120) * 1024,
                      "sources": ("k_flood.hip", "spa_math.h", "dispatch.h", "lds.h", "devcode.h"),
-                     "sha256_16": "6e3a9271e9364a42"}
+                     "sha256_16": "6ed092d8b835b5bc"}
 
 # Algorithmic VALU work per edge and round:
 # sum-product in the sum / difference form: check side 13 simple ops
