@@ -651,10 +651,10 @@ def mixed_leg(torch, lsim, dev):
                for o, bb in zip(plan.bits_offsets, sep_bits))
     info = sum(cnt * cd.k for cd, cnt in zip(codes, counts))
     # the int8 offset min-sum decoder (flooding, codeword pairs in packed
-    # 16-bit lanes, whole state in LDS) over the shapes whose state fits the
-    # LDS: persistent launch vs one per shape
+    # 16-bit lanes, or one codeword per tile where a pair does not fit, whole
+    # state in LDS) over every shape: persistent launch vs one per shape
     po = lsim.params(lsim.OMS_I8, iters=20)
-    keep = [s for s, cd in enumerate(codes) if 4 * (cd.E + cd.n_dec) <= 160 * 1024 - 96]
+    keep = [s for s, cd in enumerate(codes) if autotune.oms_fits(cd)]
     ocodes = [codes[s] for s in keep]
     ocounts = [counts[s] for s in keep]
     q8 = [lsim.quantize(parts[s]) for s in keep]

@@ -361,12 +361,13 @@ lsim_status lsim_link_run(const lsim_link_args* args, lsim_stream stream);
  * Plan for decoding codewords of several codes in one persistent launch
  * with the layered NMS decoder (LSIM_NMS_F32, f32 LLRs) or the flooding
  * int8 offset min-sum decoder (LSIM_OMS_I8, i8 LLRs, codeword pairs in
- * packed 16-bit lanes); LSIM_SPA_F32 returns LSIM_E_UNSUPPORTED.  Results
+ * packed 16-bit lanes, or one codeword per tile where a pair's state does not
+ * fit the LDS); LSIM_SPA_F32 returns LSIM_E_UNSUPPORTED.  Results
  * per codeword are those of lsim_decode with the same parameters.
  * counts[s] codewords of codes[s].  The plan owns a device work list and
  * descriptor table.  `codewords_per_tile` (nullable) fixes, per shape, how
  * many codewords share one workgroup (NMS: 0 = choose from Z and LDS; OMS:
- * 0 or 2); `threads` (0 = default) the workgroup size (NMS 256, 384, 512,
+ * 0 = a pair where it fits the LDS, else one; 1; 2); `threads` (0 = default) the workgroup size (NMS 256, 384, 512,
  * 768 or 1024 and at least every Z; OMS 256, 512 or 1024).  LLRs and bits
  * are concatenated by shape: shape s starts at sum_{t<s} counts[t]*e_tx[t]
  * LLRs and sum_{t<s} counts[t]*k[t] bits.

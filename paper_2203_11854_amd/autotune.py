@@ -167,8 +167,9 @@ def wilson(k: int, n: int, z: float = 1.959963984540054):
 
 
 def oms_fits(code) -> bool:
-    """The flooding int8 decoder keeps a codeword pair's whole state in LDS."""
-    return 4 * (code.E + code.n_dec) <= 160 * 1024 - 96
+    """The flooding int8 decoder keeps a tile's whole state in LDS: 2 bytes
+    per edge and per variable node for one codeword (4 for a pair)."""
+    return 2 * (code.E + code.n_dec) <= 160 * 1024 - 96
 
 
 class ScheduledMixed:

@@ -768,12 +768,15 @@ lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t*
     int G;
     size_t tile_lds;
     if (oms) {
-      G = 2;
-      tile_lds = lsim::oms2_lds_bytes(c);
-      if ((codewords_per_tile && codewords_per_tile[s] > 0 && codewords_per_tile[s] != 2) ||
-          tile_lds > lds_cap - 16) {
+      // a codeword pair per tile when its packed state fits the LDS, else
+      // one codeword (16-bit values, half the state)
+      const int want = codewords_per_tile && codewords_per_tile[s] > 0 ? codewords_per_tile[s] : 0;
+      G = want ? want : (lsim::oms2_lds_bytes(c, 2) <= lds_cap - 16 ? 2 : 1);
+      tile_lds = G == 1 || G == 2 ? lsim::oms2_lds_bytes(c, G) : 0;
+      if ((G != 1 && G != 2) || tile_lds > lds_cap - 16) {
         delete plan;
-        return fail(LSIM_E_INVAL, "the OMS decoder takes codeword pairs that fit the LDS");
+        return fail(LSIM_E_INVAL,
+                    "the OMS decoder takes one codeword or a codeword pair per tile, within the LDS");
       }
     } else {
       G = codewords_per_tile && codewords_per_tile[s] > 0 ? codewords_per_tile[s] : threads / c.Z;

@@ -246,7 +246,8 @@ hipError_t dispatch(const DevCode& c, int nt, const FloodArgs& a, size_t lds, hi
 }  // namespace
 
 size_t flood_lds_bytes(const DevCode& c, int algo) {
-  return algo == LSIM_SPA_F32 ? spa_lds(c) : oms2_lds_bytes(c);
+  if (algo == LSIM_SPA_F32) return spa_lds(c);
+  return oms2_lds_bytes(c, 2) <= 160 * 1024 ? oms2_lds_bytes(c, 2) : oms2_lds_bytes(c, 1);
 }
 
 hipError_t launch_flood(const DevCode& c, const lsim_decode_params& p, const void* llr, int64_t B,

@@ -1,10 +1,13 @@
 // Flooding int8 offset min-sum, two codewords per workgroup in packed
-// 16-bit lanes.
+// 16-bit lanes (or one, for codes whose pair state does not fit the LDS).
 //
 // Every message, channel value and posterior of codeword pair (2w, 2w+1)
 // is held as a pair of signed 16-bit integers in one 32-bit word (low half:
 // codeword 2w, high half: codeword 2w+1), in LDS and in registers, so one
-// packed 16-bit instruction updates both codewords.  The values are the
+// packed 16-bit instruction updates both codewords.  The single-codeword
+// tile (W = 2 bytes per value) keeps one 16-bit value per edge and variable
+// node in LDS, half the pair's state, and runs the same packed instructions
+// with the high halves zero.  The values are the
 // int8 decoder's exactly: inputs and variable-to-check messages saturate
 // at +-sat (<= 127), check outputs are sign * max(min_excl - offset, 0),
 // posteriors are channel value + sum of check outputs (at most
@@ -58,28 +61,45 @@ struct Oms2Args {
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
-__host__ __device__ inline size_t oms2_lds(const DevCode& c) {
-  return align16((size_t)c.E * 4) + align16((size_t)c.n_dec * 4);
+// LDS of a tile: W bytes per edge and per variable node (4: a codeword
+// pair, 2: one codeword).
+__host__ __device__ inline size_t oms2_lds(const DevCode& c, int W = 4) {
+  return align16((size_t)c.E * W) + align16((size_t)c.n_dec * W);
 }
 
-// One codeword pair (2 pair, 2 pair + 1) of code c.  ZC: compile-time lift
-// size or 0 (read from the code).  LDS: messages at byte 0, channel values
-// at lam_b (the calling kernel has no static LDS).
-template <int NT, int DMAX, int ZC>
-__device__ __forceinline__ void oms2_pair(const DevCode& c, const Oms2Args& a, int64_t pair,
+// Values of a tile at an LDS byte offset: the packed pair word (W = 4), or
+// one 16-bit value in the low half with the high half zero (W = 2).
+template <int W>
+__device__ __forceinline__ s16x2 ld_val(int off) {
+  if constexpr (W == 4) return lds_ld<s16x2>(off);
+  return pk(lds_ld<short>(off), 0);
+}
+template <int W>
+__device__ __forceinline__ void st_val(int off, s16x2 v) {
+  if constexpr (W == 4)
+    lds_st<s16x2>(off, v);
+  else
+    lds_st<short>(off, v.x);
+}
+
+// Tile `tile` of code c: codewords (2 tile, 2 tile + 1) for W = 4, codeword
+// `tile` for W = 2.  ZC: compile-time lift size or 0 (read from the code).
+// LDS: messages at byte 0, channel values at lam_b (the calling kernel has
+// no static LDS).
+template <int NT, int DMAX, int ZC, int W = 4>
+__device__ __forceinline__ void oms2_pair(const DevCode& c, const Oms2Args& a, int64_t tile,
                                           unsigned char* smem) {
   constexpr int NW = NT / 64;
-  s16x2* msg = reinterpret_cast<s16x2*>(smem);
-  s16x2* lam = reinterpret_cast<s16x2*>(smem + align16((size_t)c.E * 4));
-  const int lam_b = (int)align16((size_t)c.E * 4);
+  (void)smem;
+  const int lam_b = (int)align16((size_t)c.E * W);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = uni(tid >> 6);
   const int Z = ZC ? ZC : c.Z;
   const int zm = Z - 1;
   const bool zpow2 = (Z & zm) == 0;
-  const int64_t b0 = 2 * pair;
-  const bool has1 = b0 + 1 < a.B;
+  const int64_t b0 = W == 4 ? 2 * tile : tile;
+  const bool has1 = W == 4 && b0 + 1 < a.B;
   const int sat = a.sat;
   const s16x2 psat = pk(sat, sat), nsat = pk(-sat, -sat);
   const s16x2 poff = pk(a.offset, a.offset), zero = pk(0, 0);
@@ -94,14 +114,14 @@ __device__ __forceinline__ void oms2_pair(const DevCode& c, const Oms2Args& a, i
       y0 = min(max(-(int)l0[x], -sat), sat);
       if (has1) y1 = min(max(-(int)l1[x], -sat), sat);
     }
-    lam[v] = pk(y0, y1);
+    st_val<W>(lam_b + v * W, pk(y0, y1));
   }
   if (a.q_in) {
     const int8_t* q0 = a.q_in + b0 * (int64_t)c.E;
     const int8_t* q1 = q0 + c.E;
-    for (int e = tid; e < c.E; e += NT) msg[e] = pk(q0[e], has1 ? q1[e] : 0);
+    for (int e = tid; e < c.E; e += NT) st_val<W>(e * W, pk(q0[e], has1 ? q1[e] : 0));
   } else {
-    for (int e = tid; e < c.E; e += NT) msg[e] = zero;
+    for (int e = tid; e < c.E; e += NT) st_val<W>(e * W, zero);
   }
   __syncthreads();
 
@@ -118,13 +138,13 @@ __device__ __forceinline__ void oms2_pair(const DevCode& c, const Oms2Args& a, i
           constexpr int DC = decltype(deg)::value;
           int idx[DC];
           s16x2 rv[DC];
-          // byte offset of entry e's edge at lift cc: (e*Z + (cc - shift) mod Z) * 4
+          // byte offset of entry e's edge at lift cc: (e*Z + (cc - shift) mod Z) * W
           if (zpow2) {
-            const int cc_b = vreg(cc * 4), zm_b = vreg(zm * 4);
+            const int cc_b = vreg(cc * W), zm_b = vreg(zm * W);
 #pragma unroll
             for (int q = 0; q < DC; ++q) {
               const int2 ce = ld_const(c.col_edge, cb + q);
-              idx[q] = ((cc_b - ce.y * 4) & zm_b) | (ce.x * 4);
+              idx[q] = ((cc_b - ce.y * W) & zm_b) | (ce.x * W);
             }
           } else {
 #pragma unroll
@@ -132,12 +152,12 @@ __device__ __forceinline__ void oms2_pair(const DevCode& c, const Oms2Args& a, i
               const int2 ce = ld_const(c.col_edge, cb + q);
               int x = cc - ce.y;
               x += x < 0 ? Z : 0;
-              idx[q] = (ce.x + x) * 4;
+              idx[q] = (ce.x + x) * W;
             }
           }
 #pragma unroll
-          for (int q = 0; q < DC; ++q) rv[q] = lds_ld<s16x2>(idx[q]);
-          s16x2 acc = lds_ld<s16x2>(lam_b + v * 4);
+          for (int q = 0; q < DC; ++q) rv[q] = ld_val<W>(idx[q]);
+          s16x2 acc = ld_val<W>(lam_b + v * W);
 #pragma unroll
           for (int q = 0; q < DC; ++q) acc += rv[q];
           if (write_q) {
@@ -149,7 +169,7 @@ __device__ __forceinline__ void oms2_pair(const DevCode& c, const Oms2Args& a, i
 #pragma unroll
             for (int q = 0; q < DC; ++q) rv[q] = vmax(rv[q], nsat);
 #pragma unroll
-            for (int q = 0; q < DC; ++q) lds_st<s16x2>(idx[q], rv[q]);
+            for (int q = 0; q < DC; ++q) st_val<W>(idx[q], rv[q]);
           }
           if (final_round) {
             if (a.bits && v < c.k) {
@@ -174,12 +194,12 @@ __device__ __forceinline__ void oms2_pair(const DevCode& c, const Oms2Args& a, i
       const int e0 = uni(ld_const(c.row_ptr, i));
       const int d = uni(ld_const(c.row_ptr, i + 1)) - e0;
       if (r < Z) {
-        const int row_b = (e0 * Z + r) * 4;
+        const int row_b = (e0 * Z + r) * W;
         with_degree<DMAX>(d, [&](auto deg) {
           constexpr int D = decltype(deg)::value;
           s16x2 x[D], ax[D];
 #pragma unroll
-          for (int q = 0; q < D; ++q) x[q] = lds_ld<s16x2>(row_b + q * Z * 4);
+          for (int q = 0; q < D; ++q) x[q] = ld_val<W>(row_b + q * Z * W);
           // sign parity in bits 15 and 31, the two smallest magnitudes
           uint32_t sx = 0;
           s16x2 m1 = pk(0x7fff, 0x7fff), m2 = m1;
@@ -205,7 +225,7 @@ __device__ __forceinline__ void oms2_pair(const DevCode& c, const Oms2Args& a, i
 #pragma unroll
           for (int q = 0; q < D; ++q) mag[q] = mag[q] ^ neg[q];
 #pragma unroll
-          for (int q = 0; q < D; ++q) lds_st<s16x2>(row_b + q * Z * 4, mag[q] - neg[q]);
+          for (int q = 0; q < D; ++q) st_val<W>(row_b + q * Z * W, mag[q] - neg[q]);
         });
       }
     }
@@ -222,7 +242,7 @@ __device__ __forceinline__ void oms2_pair(const DevCode& c, const Oms2Args& a, i
     if (last && a.r_out) {
       int8_t* r0 = a.r_out + b0 * (int64_t)c.E;
       for (int e = tid; e < c.E; e += NT) {
-        const s16x2 m = msg[e];
+        const s16x2 m = ld_val<W>(e * W);
         r0[e] = (int8_t)m.x;
         if (has1) r0[c.E + e] = (int8_t)m.y;
       }
@@ -234,7 +254,7 @@ __device__ __forceinline__ void oms2_pair(const DevCode& c, const Oms2Args& a, i
   if (a.q_out) {
     int8_t* q0 = a.q_out + b0 * (int64_t)c.E;
     for (int e = tid; e < c.E; e += NT) {
-      const s16x2 m = msg[e];
+      const s16x2 m = ld_val<W>(e * W);
       q0[e] = (int8_t)m.x;
       if (has1) q0[c.E + e] = (int8_t)m.y;
     }
@@ -243,10 +263,10 @@ __device__ __forceinline__ void oms2_pair(const DevCode& c, const Oms2Args& a, i
 
 __global__ void oms2_reset_counter_kernel(int* counter) { *counter = 0; }
 
-template <int NT, int DMAX, int ZC>
+template <int NT, int DMAX, int ZC, int W>
 __global__ __launch_bounds__(NT) void oms2_kernel(DevCode c, Oms2Args a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  oms2_pair<NT, DMAX, ZC>(c, a, blockIdx.x, smem);
+  oms2_pair<NT, DMAX, ZC, W>(c, a, blockIdx.x, smem);
 }
 
 // Persistent decoder over a work list of (shape, codeword pair) items, as
@@ -274,25 +294,38 @@ __global__ __launch_bounds__(NT) void oms2_mixed_kernel(
     Oms2Args a{llr + sh.llr_off, sh.count, bits ? bits + sh.bits_off : nullptr,
                lpost ? lpost + sh.app_off : nullptr, nullptr, nullptr, nullptr, iters, offset,
                sat};
-    oms2_pair<NT, DMAX, 0>(sh.code, a, tile_local[item], smem);
+    // a shape's tile is a codeword pair (G = 2) or one codeword (G = 1)
+    if (sh.G == 2)
+      oms2_pair<NT, DMAX, 0, 4>(sh.code, a, tile_local[item], smem);
+    else
+      oms2_pair<NT, DMAX, 0, 2>(sh.code, a, tile_local[item], smem);
     __syncthreads();
     if (!persistent) break;
   }
 }
 
-template <int NT, int DMAX, int ZC>
-hipError_t launch_t(const DevCode& c, const Oms2Args& a, size_t lds, hipStream_t s) {
-  const void* k = (const void*)oms2_kernel<NT, DMAX, ZC>;
+template <int NT, int DMAX, int ZC, int W>
+hipError_t launch_tw(const DevCode& c, const Oms2Args& a, size_t lds, hipStream_t s) {
+  const void* k = (const void*)oms2_kernel<NT, DMAX, ZC, W>;
   hipError_t e = require_lds_at_zero(k);
   if (e == hipSuccess) e = ensure_dyn_lds(k, lds);
   if (e != hipSuccess) return e;
-  oms2_kernel<NT, DMAX, ZC><<<(unsigned)((a.B + 1) / 2), NT, lds, s>>>(c, a);
+  const unsigned grid = (unsigned)(W == 4 ? (a.B + 1) / 2 : a.B);
+  oms2_kernel<NT, DMAX, ZC, W><<<grid, NT, lds, s>>>(c, a);
   return hipGetLastError();
+}
+
+template <int NT, int DMAX, int ZC>
+hipError_t launch_t(const DevCode& c, const Oms2Args& a, int W, hipStream_t s) {
+  return W == 4 ? launch_tw<NT, DMAX, ZC, 4>(c, a, oms2_lds(c, 4), s)
+                : launch_tw<NT, DMAX, ZC, 2>(c, a, oms2_lds(c, 2), s);
 }
 
 }  // namespace
 
-size_t oms2_lds_bytes(const DevCode& c) { return oms2_lds(c); }
+size_t oms2_lds_bytes(const DevCode& c, int cw_per_tile) {
+  return oms2_lds(c, cw_per_tile == 2 ? 4 : 2);
+}
 
 template <int NT, int DMAX>
 hipError_t launch_mixed_oms_t(const LayerShape* d_shapes, const int* d_tile_shape,
@@ -343,18 +376,20 @@ hipError_t launch_mixed_oms(const LayerShape* d_shapes, const int* d_tile_shape,
 hipError_t launch_oms2(const DevCode& c, const lsim_decode_params& p, const int8_t* llr, int64_t B,
                        uint8_t* bits, float* lpost, const int8_t* q_in, int8_t* r_out,
                        int8_t* q_out, hipStream_t s, std::string* why) {
-  const size_t lds = oms2_lds(c);
+  // a codeword pair per workgroup when its state fits the LDS, else one
+  const int W = oms2_lds(c, 4) <= 160 * 1024 ? 4 : 2;
+  const size_t lds = oms2_lds(c, W);
   if (lds > 160 * 1024) {
-    *why = "packed min-sum decoder state (" + std::to_string(lds) + " B) exceeds the 160 KiB LDS";
+    *why = "min-sum decoder state (" + std::to_string(lds) + " B) exceeds the 160 KiB LDS";
     return hipSuccess;
   }
   Oms2Args a{llr, B, bits, lpost, q_in, r_out, q_out, p.iters, (int)p.offset, p.sat};
   const int nt = p.threads ? p.threads : 512;
   const int dmax = c.max_row_deg > c.max_col_deg ? c.max_row_deg : c.max_col_deg;
-  if (c.Z == 128 && nt == 512 && dmax <= 16) return launch_t<512, 16, 128>(c, a, lds, s);
-  if (c.Z == 128 && nt == 512 && dmax <= 24) return launch_t<512, 24, 128>(c, a, lds, s);
+  if (c.Z == 128 && nt == 512 && dmax <= 16) return launch_t<512, 16, 128>(c, a, W, s);
+  if (c.Z == 128 && nt == 512 && dmax <= 24) return launch_t<512, 24, 128>(c, a, W, s);
 #define LSIM_OMS2_CASE(NT_, D_) \
-  if (nt == NT_ && dmax <= D_) return launch_t<NT_, D_, 0>(c, a, lds, s);
+  if (nt == NT_ && dmax <= D_) return launch_t<NT_, D_, 0>(c, a, W, s);
   LSIM_OMS2_CASE(256, 16)
   LSIM_OMS2_CASE(256, 24)
   LSIM_OMS2_CASE(256, 32)

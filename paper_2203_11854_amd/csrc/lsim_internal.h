@@ -43,7 +43,8 @@ size_t flood_lds_bytes(const DevCode& c, int algo);
 hipError_t launch_oms2(const DevCode& c, const lsim_decode_params& p, const int8_t* llr, int64_t B,
                        uint8_t* bits, float* lpost, const int8_t* q_in, int8_t* r_out,
                        int8_t* q_out, hipStream_t s, std::string* why);
-size_t oms2_lds_bytes(const DevCode& c);
+// LDS of one tile: a codeword pair (cw_per_tile 2) or one codeword (1).
+size_t oms2_lds_bytes(const DevCode& c, int cw_per_tile = 2);
 
 // Device address (on the current device) and size of the library-owned
 // scratch of lsim_decode_noalloc (k_noalloc.hip); looked up once per device.

@@ -10,7 +10,7 @@ from inputs import rand
 from inputs.workloads import BG2, mixed_specs
 from oracle import decoders as D
 from oracle import ndm as ondm
-from oracle import pipeline, qc, wbp
+from oracle import modem, pipeline, qc, wbp
 
 pytestmark = pytest.mark.gpu
 
@@ -124,8 +124,57 @@ def test_mixed_oms_equals_per_shape_and_oracle(threads):
         assert torch.equal(app[lo:lo + n].view(counts[s], -1), a1), s
         bo = plan.bits_offsets[s]
         assert torch.equal(bits[bo:bo + counts[s] * code.k].view(counts[s], -1), b1), s
-        ref = D.oms_flood(g, D.channel_lam(g, q.cpu().numpy(), dtype=np.int64), 20)
+        qo = modem.quantize(llrs[s])                     # the oracle's own quantizer
+        assert np.array_equal(q.cpu().numpy(), qo), s
+        ref = D.oms_flood(g, D.channel_lam(g, qo, dtype=np.int64), 20)
         assert np.array_equal(a1.cpu().numpy(), -ref.astype(np.float32)), s
+
+
+def test_mixed_oms_covers_every_shape():
+    """All eight shapes in one int8 offset min-sum launch: the shapes whose
+    pair state does not fit the LDS take one codeword per tile (16-bit
+    state); bits and posteriors equal the per-shape launches and, on
+    sampled codewords, the oracle bit for bit."""
+    counts = [5, 4, 3, 7, 3, 4, 2, 3]
+    codes, llrs, graphs, _ = mixed_inputs(counts, seed=77)
+    assert any(4 * (c.E + c.n_dec) > 160 * 1024 - 96 for c in codes)
+    p = lsim.params(lsim.OMS_I8, iters=20, offset=1.0, sat=31)
+    q8 = [T(modem.quantize(L)).to(dev) for L in llrs]
+    plan = lsim.MixedPlan(codes, counts, p)
+    cat = torch.cat([q.reshape(-1) for q in q8])
+    bits = torch.zeros(plan.n_bits, dtype=torch.uint8, device=dev)
+    app = torch.zeros(plan.n_app, dtype=torch.float32, device=dev)
+    plan.decode(cat, bits=bits, app=app)
+    for s, (code, q, g, L) in enumerate(zip(codes, q8, graphs, llrs)):
+        b1, a1 = lsim.decode(code, q, p, want_app=True)
+        lo, n = plan.app_offsets[s], counts[s] * code.n_dec
+        assert torch.equal(app[lo:lo + n].view(counts[s], -1), a1), s
+        bo = plan.bits_offsets[s]
+        assert torch.equal(bits[bo:bo + counts[s] * code.k].view(counts[s], -1), b1), s
+        rows = [0, counts[s] - 1]
+        ref = D.oms_flood(g, D.channel_lam(g, modem.quantize(L[rows]), dtype=np.int64), 20)
+        assert np.array_equal(a1.cpu().numpy()[rows], -ref.astype(np.float32)), s
+
+
+def test_oms_single_codeword_tiles_equal_pairs():
+    """Forcing one codeword per tile on shapes whose pairs fit gives the
+    pair tiles' bits and posteriors exactly, through the persistent launch
+    and one workgroup per tile."""
+    counts = [5, 9, 3, 7, 4, 6, 2, 3]
+    codes, llrs, graphs, _ = mixed_inputs(counts, seed=79)
+    codes, llrs, graphs, counts = oms_fit(codes, llrs, graphs, counts)
+    p = lsim.params(lsim.OMS_I8, iters=20)
+    cat = torch.cat([T(modem.quantize(L)).to(dev).reshape(-1) for L in llrs])
+    outs = []
+    for cpt in ([2] * len(codes), [1] * len(codes)):
+        plan = lsim.MixedPlan(codes, counts, p, codewords_per_tile=cpt)
+        for persistent in (True, False):
+            bits = torch.zeros(plan.n_bits, dtype=torch.uint8, device=dev)
+            app = torch.zeros(plan.n_app, dtype=torch.float32, device=dev)
+            plan.decode(cat, bits=bits, app=app, persistent=persistent)
+            outs.append((bits, app))
+    for b, a in outs[1:]:
+        assert torch.equal(b, outs[0][0]) and torch.equal(a, outs[0][1])
 
 
 def test_mixed_oms_graph_replay():
