@@ -288,7 +288,8 @@ def layered_roofline(code, B, T, ms, peaks, launch):
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": _traffic(LAYERED_TRAFFIC),
-            "kernel": f"layered_kernel<{launch['threads']},{D}>", "launch": launch,
+            "kernel": f"layered_kernel<{launch['threads']},{D},{launch['waves_per_simd']}>",
+            "launch": launch,
             "kernel_ms": round(ms, 4),
             "hbm_algorithmic_bytes": int(hbm),
             "measured_peak": peaks["hbm_copy_gbs"],

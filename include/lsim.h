@@ -243,14 +243,17 @@ lsim_status lsim_decode(const lsim_code* code, const lsim_decode_params* p, cons
 
 /*
  * Launch shape lsim_decode takes for the layered decoder (LSIM_NMS_F32) with
- * these parameters: workgroup size, codewords per workgroup and rows whose
- * check records stay in LDS (rows >= lds_rows stream through d_work).
- * Needs the code's device current (it asks the runtime for occupancy).
- * Errors: LSIM_E_UNSUPPORTED for the flooding decoders or a shape that does
- * not fit; LSIM_E_INVAL on bad parameters.
+ * these parameters: workgroup size, codewords per workgroup, rows whose
+ * check records stay in LDS (rows >= lds_rows stream through d_work) and
+ * the register budget the kernel is compiled for (waves_per_simd 6: at most
+ * 80 VGPRs, taken when it at least doubles the workgroups per CU; 1: the
+ * compiler's own).  Needs the code's device current (it asks the runtime for
+ * occupancy).  Errors: LSIM_E_UNSUPPORTED for the flooding decoders or a
+ * shape that does not fit; LSIM_E_INVAL on bad parameters.
  */
 lsim_status lsim_decode_launch(const lsim_code* code, const lsim_decode_params* p,
-                               int* threads, int* codewords_per_tile, int* lds_rows);
+                               int* threads, int* codewords_per_tile, int* lds_rows,
+                               int* waves_per_simd);
 
 /*
  * lsim_decode without a workspace argument, for callers that cannot

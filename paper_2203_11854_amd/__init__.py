@@ -78,7 +78,7 @@ _SIGS = {
     "lsim_decode_workspace": [_P, ctypes.POINTER(DecodeParams), _I64, ctypes.POINTER(_SZ)],
     "lsim_decode": [_P, ctypes.POINTER(DecodeParams), _P, _I64, _P, _P, _P, _SZ, _P],
     "lsim_decode_launch": [_P, ctypes.POINTER(DecodeParams), ctypes.POINTER(_I), ctypes.POINTER(_I),
-                           ctypes.POINTER(_I)],
+                           ctypes.POINTER(_I), ctypes.POINTER(_I)],
     "lsim_decode_noalloc": [_P, ctypes.POINTER(DecodeParams), _P, _I64, _P, _P, _P],
     "lsim_decode_state": [_P, ctypes.POINTER(DecodeParams), _P, _I64, _P, _P, _P, _P, _P, _SZ, _P],
     "lsim_count_errors": [_P, _I64, _P, _I64, _I64, _P, _I, _P, _P],
@@ -387,10 +387,11 @@ def params(algo: int, iters: int = 20, offset: float = 1.0, alpha: float = 0.75,
 
 def decode_launch(code: Code, p: DecodeParams) -> dict:
     """Launch shape of the layered decoder (lsim_decode_launch)."""
-    t, g, k = _I(), _I(), _I()
+    t, g, k, w = _I(), _I(), _I(), _I()
     _call("lsim_decode_launch", code.handle, ctypes.byref(p), ctypes.byref(t), ctypes.byref(g),
-          ctypes.byref(k))
-    return {"threads": t.value, "codewords_per_tile": g.value, "lds_rows": k.value}
+          ctypes.byref(k), ctypes.byref(w))
+    return {"threads": t.value, "codewords_per_tile": g.value, "lds_rows": k.value,
+            "waves_per_simd": w.value}
 
 
 def decode_workspace(code: Code, p: DecodeParams, B: int) -> int:

@@ -496,15 +496,17 @@ lsim_status lsim_decode_workspace(const lsim_code* code, const lsim_decode_param
 }
 
 lsim_status lsim_decode_launch(const lsim_code* code, const lsim_decode_params* p,
-                               int* threads, int* codewords_per_tile, int* lds_rows) {
+                               int* threads, int* codewords_per_tile, int* lds_rows,
+                               int* waves_per_simd) {
   lsim_status st = check_params(code, p);
   if (st != LSIM_OK) return st;
-  if (!threads || !codewords_per_tile || !lds_rows) return fail(LSIM_E_INVAL, "null output");
+  if (!threads || !codewords_per_tile || !lds_rows || !waves_per_simd)
+    return fail(LSIM_E_INVAL, "null output");
   if (p->algo != LSIM_NMS_F32)
     return fail(LSIM_E_UNSUPPORTED, "launch shapes are reported for the layered decoder");
   std::string why;
   hipError_t e = lsim::layered_launch_shape(code->dev, *p, threads, codewords_per_tile, lds_rows,
-                                            &why);
+                                            waves_per_simd, &why);
   if (e != hipSuccess) return dev_status(e, "layered launch shape");
   if (!why.empty()) return fail(LSIM_E_UNSUPPORTED, why);
   return LSIM_OK;
@@ -703,6 +705,7 @@ struct lsim_plan {
   lsim_decode_params p;
   int threads = 0;
   int dmax = 0;
+  int wpe = 1;  // layered kernel's register budget (wavefronts per SIMD)
   size_t lds = 0;
   int grid = 0;
   int64_t ntiles = 0;
@@ -815,7 +818,15 @@ lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t*
     // check records kept in LDS (p->lds_rows): by default as many rows per
     // shape as fit the LDS a workgroup has at the occupancy the shared
     // posteriors allow
-    e = lsim::mixed_occupancy(threads, dmax, plan->lds, &occ);
+    // register budget: 6 wavefronts per SIMD when that at least doubles
+    // the workgroups per CU
+    int occ6 = 0;
+    e = lsim::mixed_occupancy(threads, dmax, 1, plan->lds, &occ);
+    if (e == hipSuccess) e = lsim::mixed_occupancy(threads, dmax, 6, plan->lds, &occ6);
+    if (e == hipSuccess && occ6 >= 2 * occ) {
+      plan->wpe = 6;
+      occ = occ6;
+    }
     if (e == hipSuccess && occ < 1) e = hipErrorInvalidConfiguration;
     if (e != hipSuccess) {
       delete plan;
@@ -841,7 +852,7 @@ lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t*
         return fail(LSIM_E_INVAL, "lds_rows: the check records of that many rows do not fit the LDS");
       }
       int occ2 = 0;
-      e = lsim::mixed_occupancy(threads, dmax, lds, &occ2);
+      e = lsim::mixed_occupancy(threads, dmax, plan->wpe, lds, &occ2);
       if (e != hipSuccess) {
         delete plan;
         return dev_status(e, "mixed plan occupancy");
@@ -941,7 +952,7 @@ lsim_status lsim_mixed_decode(lsim_plan* plan, const void* d_llr_concat, uint8_t
       plan->d_shapes, (int)plan->shapes.size(), plan->d_tile_shape, plan->d_tile_local,
       plan->ntiles, plan->threads, plan->lds, plan->p, d_llr_concat, d_bits_concat, d_app_concat,
       (uint32_t*)(w + kCounterBytes), (int*)w, persistent ? 1 : 0, plan->grid, plan->dmax,
-      as_stream(stream));
+      plan->wpe, as_stream(stream));
   return dev_status(e, "mixed decode");
 }
 

@@ -12,9 +12,9 @@ using namespace layered;
 
 namespace {
 
-template <int NT, int DMAX>
-__global__ __launch_bounds__(NT) void layered_kernel(DevCode c, int G, TileIO io, int iters,
-                                                     float alpha) {
+template <int NT, int DMAX, int WPE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void layered_kernel(
+    DevCode c, int G, TileIO io, int iters, float alpha) {
   decode_tile<NT, DMAX>(c, G, blockIdx.x, io, iters, alpha);
 }
 
@@ -71,11 +71,12 @@ hipError_t layered_lds_rows(const void* kernel, const DevCode& c, int G, int thr
 // Workgroups of whole multiples of four wavefronts spread evenly over a CU's
 // four SIMDs; among 256, 512, 768 and 1024 threads take the one whose tile
 // (threads / Z codewords, as many as the LDS holds) leaves the fewest lanes
-// idle, nearest to 512 threads on a tie.
+// idle, the smallest on a tie (more, smaller workgroups balance better:
+// 0.94 ms at 256 against 0.99 ms at 512 threads for the BG2 code at Z = 128).
 int layered_default_threads(const DevCode& c) {
   int best = 1024;
   double best_u = -1.0;
-  for (int nt : {512, 256, 768, 1024}) {
+  for (int nt : {256, 512, 768, 1024}) {
     if (nt < c.Z) continue;
     int G = nt / c.Z;
     while (G > 1 && tile_lds_bytes(c, G) > kLdsBytes) --G;
@@ -89,10 +90,10 @@ int layered_default_threads(const DevCode& c) {
 }
 
 // The kernel instance of a launch shape.
-static const void* layered_instance(int nt, int D) {
-#define LSIM_LAYER_PTR(NT_, D_) \
-  if (nt == NT_ && D == D_) return (const void*)layered_kernel<NT_, D_>;
-  LSIM_LAYERED_INSTANCES(LSIM_LAYER_PTR)
+static const void* layered_instance(int nt, int D, int wpe) {
+#define LSIM_LAYER_PTR(NT_, D_, W_) \
+  if (nt == NT_ && D == D_ && wpe == W_) return (const void*)layered_kernel<NT_, D_, W_>;
+  LSIM_LAYERED_INSTANCES_W(LSIM_LAYER_PTR)
 #undef LSIM_LAYER_PTR
   return nullptr;
 }
@@ -101,8 +102,23 @@ static int degree_class(const DevCode& c) {
   return c.max_row_deg <= 16 ? 16 : c.max_row_deg <= 24 ? 24 : 27;
 }
 
+// Register budget of a launch: 6 wavefronts per SIMD when that at least
+// doubles the workgroups per CU the shared posteriors allow.
+hipError_t layered_budget(int nt, int D, size_t base, int* wpe) {
+  int occ1 = 0, occ6 = 0;
+  const void* k1 = layered_instance(nt, D, 1);
+  const void* k6 = layered_instance(nt, D, 6);
+  if (!k1 || !k6) return hipErrorInvalidValue;
+  hipError_t e = ensure_dyn_lds(k1, kLdsBytes);
+  if (e == hipSuccess) e = ensure_dyn_lds(k6, kLdsBytes);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ1, k1, nt, base);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ6, k6, nt, base);
+  *wpe = occ6 >= 2 * occ1 ? 6 : 1;
+  return e;
+}
+
 hipError_t layered_launch_shape(const DevCode& c, const lsim_decode_params& p, int* nt, int* G,
-                                int* K, std::string* why) {
+                                int* K, int* wpe, std::string* why) {
   *nt = p.threads ? p.threads : layered_default_threads(c);
   if (c.Z > *nt) {
     *why = "layered decoder needs threads >= Z";
@@ -114,31 +130,32 @@ hipError_t layered_launch_shape(const DevCode& c, const lsim_decode_params& p, i
     *why = "layered decoder posteriors exceed the 160 KiB LDS";
     return hipSuccess;
   }
-  const void* k = layered_instance(*nt, degree_class(c));
-  if (!k) return hipErrorInvalidValue;
-  return layered_lds_rows(k, c, *G, *nt, p.lds_rows, K, why);
+  const int D = degree_class(c);
+  hipError_t e = layered_budget(*nt, D, tile_lds_bytes(c, *G), wpe);
+  if (e != hipSuccess) return e;
+  return layered_lds_rows(layered_instance(*nt, D, *wpe), c, *G, *nt, p.lds_rows, K, why);
 }
 
 hipError_t launch_layered(const DevCode& c, const lsim_decode_params& p, const float* llr,
                           int64_t B, uint8_t* bits, float* lpost, float* r_out, uint32_t* state,
                           hipStream_t s, std::string* why) {
-  int nt = 0, G = 1, K = 0;
-  hipError_t e = layered_launch_shape(c, p, &nt, &G, &K, why);
+  int nt = 0, G = 1, K = 0, wpe = 1;
+  hipError_t e = layered_launch_shape(c, p, &nt, &G, &K, &wpe, why);
   if (e != hipSuccess || !why->empty()) return e;
   const unsigned grid = (unsigned)((B + G - 1) / G);
   const int D = degree_class(c);
   const size_t lds = tile_lds_bytes(c, G, K);
   TileIO io{llr, bits, lpost, r_out, reinterpret_cast<uint4*>(state), B, K};
-#define LSIM_LAYER_CASE(NT_, D_)                                                \
-  if (nt == NT_ && D == D_) {                                                   \
-    const void* k = (const void*)layered_kernel<NT_, D_>;                       \
-    e = require_lds_at_zero(k);                                                 \
-    if (e == hipSuccess) e = ensure_dyn_lds(k, lds);                            \
-    if (e != hipSuccess) return e;                                              \
-    layered_kernel<NT_, D_><<<grid, NT_, lds, s>>>(c, G, io, p.iters, p.alpha); \
-    return hipGetLastError();                                                   \
+#define LSIM_LAYER_CASE(NT_, D_, W_)                                                   \
+  if (nt == NT_ && D == D_ && wpe == W_) {                                             \
+    const void* k = (const void*)layered_kernel<NT_, D_, W_>;                          \
+    e = require_lds_at_zero(k);                                                        \
+    if (e == hipSuccess) e = ensure_dyn_lds(k, lds);                                   \
+    if (e != hipSuccess) return e;                                                     \
+    layered_kernel<NT_, D_, W_><<<grid, NT_, lds, s>>>(c, G, io, p.iters, p.alpha);    \
+    return hipGetLastError();                                                          \
   }
-  LSIM_LAYERED_INSTANCES(LSIM_LAYER_CASE)
+  LSIM_LAYERED_INSTANCES_W(LSIM_LAYER_CASE)
 #undef LSIM_LAYER_CASE
   return hipErrorInvalidValue;
 }

@@ -12,8 +12,8 @@ namespace {
 // take items from a device counter until the list is drained; the counter
 // is reset by reset_counter_kernel launched just before, so the pair can be
 // captured in a graph.
-template <int NT, int DMAX>
-__global__ __launch_bounds__(NT) void mixed_kernel(const LayerShape* __restrict__ shapes,
+template <int NT, int DMAX, int WPE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void mixed_kernel(const LayerShape* __restrict__ shapes,
                                                    const int* __restrict__ tile_shape,
                                                    const int64_t* __restrict__ tile_local,
                                                    int64_t ntiles, const float* llr,
@@ -57,7 +57,7 @@ hipError_t launch_mixed(const LayerShape* d_shapes, int nshapes, const int* d_ti
                         const int64_t* d_tile_local, int64_t ntiles, int threads,
                         size_t lds_bytes, const lsim_decode_params& p, const void* llr,
                         uint8_t* bits, float* lpost, uint32_t* state, int* counter,
-                        int persistent, int grid, int dmax, hipStream_t s) {
+                        int persistent, int grid, int dmax, int wpe, hipStream_t s) {
   (void)nshapes;
   if (persistent) {
     reset_counter_kernel<<<1, 1, 0, s>>>(counter);
@@ -68,35 +68,36 @@ hipError_t launch_mixed(const LayerShape* d_shapes, int nshapes, const int* d_ti
   const int next_off = (int)align16(lds_bytes);
   const size_t lds_all = (size_t)next_off + 16;
   const int D = dmax <= 16 ? 16 : dmax <= 24 ? 24 : 27;
-#define LSIM_MIXED_CASE(NT_, D_)                                                       \
-  if (threads == NT_ && D == D_) {                                                         \
-    const void* k = (const void*)mixed_kernel<NT_, D_>;                                \
-    hipError_t e = require_lds_at_zero(k);                                                 \
-    if (e == hipSuccess) e = ensure_dyn_lds(k, lds_all);                                   \
-    if (e != hipSuccess) return e;                                                         \
-    mixed_kernel<NT_, D_><<<g, NT_, lds_all, s>>>(d_shapes, d_tile_shape, d_tile_local, \
-                                                      ntiles, (const float*)llr, bits,     \
-                                                      lpost, state, counter, persistent,   \
-                                                      p.iters, p.alpha, next_off);         \
-    return hipGetLastError();                                                              \
+#define LSIM_MIXED_CASE(NT_, D_, W_)                                                   \
+  if (threads == NT_ && D == D_ && wpe == W_) {                                        \
+    const void* k = (const void*)mixed_kernel<NT_, D_, W_>;                            \
+    hipError_t e = require_lds_at_zero(k);                                             \
+    if (e == hipSuccess) e = ensure_dyn_lds(k, lds_all);                               \
+    if (e != hipSuccess) return e;                                                     \
+    mixed_kernel<NT_, D_, W_><<<g, NT_, lds_all, s>>>(d_shapes, d_tile_shape,          \
+                                                      d_tile_local, ntiles,            \
+                                                      (const float*)llr, bits, lpost,  \
+                                                      state, counter, persistent,      \
+                                                      p.iters, p.alpha, next_off);     \
+    return hipGetLastError();                                                          \
   }
-  LSIM_LAYERED_INSTANCES(LSIM_MIXED_CASE)
+  LSIM_LAYERED_INSTANCES_W(LSIM_MIXED_CASE)
 #undef LSIM_MIXED_CASE
   return hipErrorInvalidValue;
 }
 
-hipError_t mixed_occupancy(int threads, int dmax, size_t lds, int* occ) {
+hipError_t mixed_occupancy(int threads, int dmax, int wpe, size_t lds, int* occ) {
   const size_t lds_all = align16(lds) + 16;
   const int D = dmax <= 16 ? 16 : dmax <= 24 ? 24 : 27;
   *occ = 0;
-#define LSIM_MIXED_OCC(NT_, D_)                                                       \
-  if (threads == NT_ && D == D_) {                                                    \
-    const void* k = (const void*)mixed_kernel<NT_, D_>;                               \
+#define LSIM_MIXED_OCC(NT_, D_, W_)                                                   \
+  if (threads == NT_ && D == D_ && wpe == W_) {                                       \
+    const void* k = (const void*)mixed_kernel<NT_, D_, W_>;                           \
     hipError_t e = ensure_dyn_lds(k, kLdsBytes); /* the query honours the limit */    \
     if (e != hipSuccess) return e;                                                    \
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, k, NT_, lds_all);        \
   }
-  LSIM_LAYERED_INSTANCES(LSIM_MIXED_OCC)
+  LSIM_LAYERED_INSTANCES_W(LSIM_MIXED_OCC)
 #undef LSIM_MIXED_OCC
   return hipErrorInvalidValue;
 }

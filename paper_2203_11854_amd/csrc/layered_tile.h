@@ -267,5 +267,17 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
   X(256, 16) X(256, 24) X(256, 27) X(384, 16) X(384, 24) X(384, 27) X(512, 16) X(512, 24) \
   X(512, 27) X(768, 16) X(768, 24) X(768, 27) X(1024, 16) X(1024, 24) X(1024, 27)
 
+// Every instance comes in two register budgets: the compiler's own (WPE 1)
+// and at most 80 VGPRs, six wavefronts per SIMD (WPE 6), where the largest
+// degree bodies spill a few values to scratch.  The launchers take the
+// second when it at least doubles the workgroups a CU holds (the BG1 code
+// at Z = 384: two 768-thread workgroups instead of one).
+#define LSIM_LAYERED_INSTANCES_W(X) \
+  X(256, 16, 1) X(256, 24, 1) X(256, 27, 1) X(384, 16, 1) X(384, 24, 1) X(384, 27, 1) \
+  X(512, 16, 1) X(512, 24, 1) X(512, 27, 1) X(768, 16, 1) X(768, 24, 1) X(768, 27, 1) \
+  X(1024, 16, 1) X(1024, 24, 1) X(1024, 27, 1) X(256, 16, 6) X(256, 24, 6) X(256, 27, 6) \
+  X(384, 16, 6) X(384, 24, 6) X(384, 27, 6) X(512, 16, 6) X(512, 24, 6) X(512, 27, 6) \
+  X(768, 16, 6) X(768, 24, 6) X(768, 27, 6) X(1024, 16, 6) X(1024, 24, 6) X(1024, 27, 6)
+
 }  // namespace layered
 }  // namespace lsim

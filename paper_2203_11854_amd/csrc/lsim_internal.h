@@ -65,9 +65,9 @@ struct LayerShape {
 size_t layered_state_words(const DevCode& c, int64_t B);
 size_t layered_tile_lds(const DevCode& c, int G, int K = 0);
 // Launch shape of the layered decoder: threads, codewords per workgroup,
-// rows whose check records stay in LDS (k_layered.hip).
+// rows whose check records stay in LDS, register budget (k_layered.hip).
 hipError_t layered_launch_shape(const DevCode& c, const lsim_decode_params& p, int* nt, int* G,
-                                int* K, std::string* why);
+                                int* K, int* wpe, std::string* why);
 // Rows whose check records a launch keeps in LDS (k_layered.hip).
 hipError_t layered_lds_rows(const void* kernel, const DevCode& c, int G, int threads, int want,
                             int* K, std::string* why);
@@ -84,9 +84,10 @@ hipError_t launch_mixed(const LayerShape* d_shapes, int nshapes, const int* d_ti
                         const int64_t* d_tile_local, int64_t ntiles, int threads,
                         size_t lds_bytes, const lsim_decode_params& p, const void* llr,
                         uint8_t* bits, float* lpost, uint32_t* state, int* counter,
-                        int persistent, int grid, int dmax, hipStream_t s);
-// Workgroups per CU of the mixed layered kernel with `lds` bytes of tile LDS.
-hipError_t mixed_occupancy(int threads, int dmax, size_t lds, int* occ);
+                        int persistent, int grid, int dmax, int wpe, hipStream_t s);
+// Workgroups per CU of the mixed layered kernel (register budget wpe: 1 or
+// 6 wavefronts per SIMD) with `lds` bytes of tile LDS.
+hipError_t mixed_occupancy(int threads, int dmax, int wpe, size_t lds, int* occ);
 
 // Peak-rate probes (k_probe.hip)
 hipError_t launch_probe(int kind, const void* src, void* dst, int64_t bytes, int rounds, int grid,
