@@ -142,15 +142,21 @@ def test_workgroup_size_invariance():
 
 
 def test_layered_large_lift_tile_invariance():
-    """BG1 (Z=384): the default launch and launches of 384, 768 and 1024
-    threads give the same bits and posteriors (a BG1 codeword's posteriors
-    take 104 KB of LDS, so every one of them decodes one codeword per
-    workgroup; the wider ones leave lanes idle)."""
+    """BG1 (Z=384): the default launch (768 threads, two codewords per
+    workgroup, two workgroups per CU at the 80-VGPR budget) and launches of
+    384 threads (one codeword) and 1024 threads (two codewords, 256 idle
+    lanes, the compiler's register budget) give the same bits and
+    posteriors, and so do the record placements: every row streamed and the
+    first rows' records in LDS."""
     qb, g, code = gcode("bg1")
     tx = oracle_llrs("bg1", 3, 2.5, 67)
     llr = T(tx["L"].astype(np.float32)).to(dev)
-    outs = [lsim.decode(code, llr, lsim.params(lsim.NMS_F32, threads=t), want_app=True)
-            for t in (0, 384, 768, 1024)]
+    shapes = [(t, k) for t in (0, 384, 768, 1024) for k in (0, -1)] + [(1024, 4), (384, 3)]
+    outs = []
+    for t, k in shapes:
+        p = lsim.params(lsim.NMS_F32, threads=t, lds_rows=k)
+        print((t, k), lsim.decode_launch(code, p), flush=True)
+        outs.append(lsim.decode(code, llr, p, want_app=True))
     for o in outs[1:]:
         assert torch.equal(outs[0][0], o[0]) and torch.equal(outs[0][1], o[1])
 
