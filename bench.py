@@ -50,10 +50,10 @@ LDS_PEAK_GBS = N_CU * 128 * CLOCK_GHZ
 # for the copy probe of known size (factors below).  Valid only for the
 # kernel sources they were taken on (hash); any change there reports null
 # until the counters are taken again.
-LAYERED_TRAFFIC = {"bytes": (2856143 * 2 + 5415169) * 1024,
+LAYERED_TRAFFIC = {"bytes": (2779540 * 2 + 4075775) * 1024,
                    "sources": ("layered_tile.h", "k_layered.hip", "dispatch.h", "lds.h",
                                "devcode.h"),
-                   "sha256_16": "f8d51cbf2b387e0c"}
+                   "sha256_16": "a080f73ec4952bcf"}
 FLOOD_SPA_TRAFFIC = {"bytes": (30955 * 2 + 5120) * 1024,
                      "sources": ("k_flood.hip", "spa_math.h", "dispatch.h", "lds.h", "devcode.h"),
                      "sha256_16": "6ed092d8b835b5bc"}
@@ -69,8 +69,10 @@ OMS_SLOTS_PER_EDGE = 9 + 3
 # layered normalized min-sum: 12 ops per edge and layer visit.
 NMS_SLOTS_PER_EDGE = 12
 # layered decoder: bytes of the check record streamed per check and
-# iteration (alpha*m1, alpha*m2, signs | argmin, private posterior)
-NMS_RECORD_BYTES = 16
+# iteration (alpha*m1, alpha*m2, signs | argmin), and of a record kept in
+# LDS (the same three words in a 16-byte slot)
+NMS_RECORD_BYTES = 12
+NMS_LDS_RECORD_BYTES = 16
 
 # BLER validity gates: oracle sample sizes (codewords per Eb/N0 point)
 GATE_ORACLE_CW = {"cfg1": 1000, "cfg2": 96, "cfg3": 48}
@@ -270,18 +272,20 @@ def measure_peaks(torch, lsim, dev):
 
 def layered_roofline(code, B, T, ms, peaks, launch):
     """Roofline position of one layered-decoder launch.  HBM algorithmic
-    bytes: the 16-byte check records of the rows that stream through device
-    memory (read in iterations 2..T, written in 1..T-1), the LLRs in and the
-    bits out.  LDS: one 4-byte read and one write per edge and iteration
-    whose posterior is in LDS, plus the records of the rows kept in LDS.
-    VALU: 12 lane operations per edge and iteration."""
+    bytes: the 12-byte check records of the rows that stream through device
+    memory (read in iterations 2..T, written in 1..T-1), the channel LLR of
+    each private (degree-one) column read again in iterations 2..T, the LLRs
+    in once and the bits out.  LDS: one 4-byte read and one write per edge
+    and iteration whose posterior is in LDS, plus the records of the rows
+    kept in LDS.  VALU: 12 lane operations per edge and iteration."""
     K = launch["lds_rows"]
     rec = B * (T - 1) * 2 * NMS_RECORD_BYTES * (code.rows - K) * code.Z
+    priv = B * (T - 1) * 4 * code.n_private_rows * code.Z
     io = B * (4 * code.e_tx + code.k)
-    hbm = rec + io
+    hbm = rec + priv + io
     s = ms * 1e-3
     lds_edges = code.E - code.n_private_rows * code.Z
-    lds = B * T * (8 * lds_edges + 2 * NMS_RECORD_BYTES * K * code.Z)
+    lds = B * T * (8 * lds_edges + 2 * NMS_LDS_RECORD_BYTES * K * code.Z)
     valu = B * T * code.E * NMS_SLOTS_PER_EDGE
     achieved = hbm / s / 1e9
     D = 16 if code.max_row_deg <= 16 else 24 if code.max_row_deg <= 24 else 27

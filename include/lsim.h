@@ -231,9 +231,13 @@ typedef struct {
  * u8[B][k] hard decisions [L_post > 0] of the information bits (nullable),
  * d_app f32[B][n_dec] posteriors L_post (nullable; integers for OMS).
  * d_work: device workspace of at least lsim_decode_workspace() bytes,
- * 16-byte aligned (the layered decoder keeps one 16-byte record per check
+ * 16-byte aligned (the layered decoder keeps one 12-byte record per check
  * there; the others need 0 bytes).  An unaligned or short workspace for the
  * layered decoder -> LSIM_E_INVAL / LSIM_E_NOMEM.
+ * The layered decoder takes the message of a degree-one variable node to
+ * its check to be the node's channel LLR in every iteration (it has no other
+ * check); a code with a degree-one column that is not the last entry of its
+ * row -> LSIM_E_UNSUPPORTED for LSIM_NMS_F32.
  */
 lsim_status lsim_decode_workspace(const lsim_code* code, const lsim_decode_params* p, int64_t B,
                                   size_t* bytes);

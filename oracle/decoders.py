@@ -188,14 +188,19 @@ def oms_flood(g: Graph, lam: np.ndarray, iters: int = 20, offset: int = 1, sat: 
 # --------------------------------------------------------------------------
 
 def nms_layered(g: Graph, lam: np.ndarray, iters: int = 20, alpha: float = 0.75,
-                mode: str = "fp64", trace: bool = False, r0=None, app0=None):
+                mode: str = "fp64", trace: bool = False):
     """Layered normalized min-sum.
 
     State: APP (initially lam, no clamp) and per-edge r (initially 0).  Each
     iteration visits the decoded base rows in natural order; for all Z
     checks of row i at once (a QC row block meets each variable node at most
-    once): t_v = APP_v - r_v; S, m1, i1, m2 from t with sgn(x) = -1 iff
-    x < 0; r_v = (S sgn t_v) (alpha * (v == i1 ? m2 : m1)); APP_v = t_v + r_v.
+    once): t_v = APP_v - r_v, the variable-to-check message (channel value
+    plus every other check's message); S, m1, i1, m2 from t with
+    sgn(x) = -1 iff x < 0; r_v = (S sgn t_v) (alpha * (v == i1 ? m2 : m1));
+    APP_v = t_v + r_v.  A variable node met by one check only has no other
+    check message, so its t_v is the channel value lam_v itself (the same in
+    exact arithmetic; in floating point APP_v - r_v would carry the rounding
+    of the previous APP_v = t_v + r_v).
 
     ``mode="fp32"`` runs every array in IEEE single precision, each +, -, *
     rounded once (numpy does not contract), which is what a float32
@@ -204,15 +209,21 @@ def nms_layered(g: Graph, lam: np.ndarray, iters: int = 20, alpha: float = 0.75,
     iteration."""
     dt = np.float32 if mode == "fp32" else np.float64
     al = dt(alpha)
-    app = np.array(lam, dtype=dt, copy=True) if app0 is None else np.array(app0, dtype=dt, copy=True)
+    ch = np.array(lam, dtype=dt, copy=True)
+    app = ch.copy()
     B = app.shape[0]
-    r = np.zeros((B, g.E), dtype=dt) if r0 is None else np.array(r0, dtype=dt, copy=True)
+    r = np.zeros((B, g.E), dtype=dt)
     vn_all = g.edge_vn()
-    rows = [(g.row_edge_ids(i), vn_all[g.row_edge_ids(i)]) for i in range(g.rows)]
+    deg = np.bincount(g.entries[:, 1], minlength=g.cols)
+    rows = []
+    for i in range(g.rows):
+        ids = g.row_edge_ids(i)
+        one = (deg[g.entries[g.row_entries(i), 1]] == 1)[:, None]
+        rows.append((ids, vn_all[ids], one))
     hist = []
     for _ in range(iters):
-        for ids, vn in rows:
-            t = app[:, vn] - r[:, ids]
+        for ids, vn, one in rows:
+            t = np.where(one, ch[:, vn], app[:, vn] - r[:, ids])
             a = np.abs(t)
             s = np.where(t < 0, dt(-1), dt(1))
             S = np.prod(s, axis=-2, keepdims=True)

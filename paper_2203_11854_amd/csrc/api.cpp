@@ -256,6 +256,8 @@ lsim_status lsim_code_create(const int16_t* base, int mb, int nb, int Z, int fam
       is_priv_col[j] = 1;
     }
   }
+  int deg1_inner = 0;
+  for (int j = 0; j < cols; ++j) deg1_inner += col_deg[j] == 1 && !is_priv_col[j];
   std::vector<int> col_slot(cols, -1);
   for (int j = 0; j < cols; ++j)
     if (!is_priv_col[j]) {
@@ -289,8 +291,19 @@ lsim_status lsim_code_create(const int16_t* base, int mb, int nb, int Z, int fam
   size_t o_ecz = push(ecz);
   size_t o_encz = push(enc_cz);
   size_t o_encp = push(enc_ptr);
+  // per row: where lane r finds the channel LLR of the row's private column,
+  // as (col * Z - tx_lo, shift); rows without one get an offset that no lane
+  // reaches from below
+  std::vector<int> pch(2 * (size_t)rows);
+  for (int i = 0; i < rows; ++i) {
+    const int e = c->row_ptr[i + 1] - 1;
+    const bool pv = row_priv[i] >= 0;
+    pch[2 * i] = pv ? (int)(c->ent_col[e] * (int64_t)Z - tx_lo) : -(1 << 30);
+    pch[2 * i + 1] = pv ? c->ent_shift[e] : 0;
+  }
   if (blob.size() & 1) blob.push_back(0);
   size_t o_elz = push(elz);
+  size_t o_pch = push(pch);
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) e = hipMalloc(&c->dmem, blob.size() * sizeof(int));
   if (e == hipSuccess)
@@ -334,10 +347,12 @@ lsim_status lsim_code_create(const int16_t* base, int mb, int nb, int Z, int fam
   dc.ent_cz = reinterpret_cast<const int2*>(d + o_ecz);
   dc.n_shared = (int)shared_col.size();
   dc.n_priv = (int)priv_row.size();
+  dc.n_deg1_inner = deg1_inner;
   dc.row_priv = d + o_rp;
   dc.shared_col = d + o_sc;
   dc.priv_row = d + o_pr;
   dc.ent_lz = reinterpret_cast<const int2*>(d + o_elz);
+  dc.priv_ch = reinterpret_cast<const int2*>(d + o_pch);
   lsim_code_info& in = c->info;
   in.k = dc.k;
   in.n_mother = dc.n_mother;
@@ -782,6 +797,10 @@ lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t*
                     "the OMS decoder takes one codeword or a codeword pair per tile, within the LDS");
       }
     } else {
+      if (c.n_deg1_inner) {
+        delete plan;
+        return fail(LSIM_E_UNSUPPORTED, lsim::kLayeredDeg1Msg);
+      }
       G = codewords_per_tile && codewords_per_tile[s] > 0 ? codewords_per_tile[s] : threads / c.Z;
       if (!codewords_per_tile || codewords_per_tile[s] <= 0)
         while (G > 1 && lsim::layered_tile_lds(c, G) > lds_cap / 2) --G;  // two workgroups per CU

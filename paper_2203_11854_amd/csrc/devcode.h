@@ -28,11 +28,14 @@ struct DevCode {
   // the row's check state.  Every other column is "shared" and gets an LDS
   // slot.
   int n_shared, n_priv;
+  int n_deg1_inner;        // degree-one columns that do not close their row
   const int* row_priv;    // rows: private slot of the row (0..n_priv-1) or -1
   const int* shared_col;  // n_shared: column of each LDS slot, ascending
   const int* priv_row;    // n_priv: row of each private slot, ascending
   const int2* ent_lz;     // per entry (row-major): (LDS slot * Z, shift) of a shared
                           // column; (col * Z, shift) of a private one
+  const int2* priv_ch;    // rows: (col * Z - tx_lo, shift) of the private column, the
+                          // channel LLR of its node at lane r; (-2^30, 0) without one
 };
 
 

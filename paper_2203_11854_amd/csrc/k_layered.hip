@@ -20,7 +20,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
 
 }  // namespace
 
-size_t layered_state_words(const DevCode& c, int64_t B) { return (size_t)B * c.rows * 4 * c.Z; }
+size_t layered_state_words(const DevCode& c, int64_t B) { return (size_t)B * c.rows * 3 * c.Z; }
 
 size_t layered_tile_lds(const DevCode& c, int G, int K) { return tile_lds_bytes(c, G, K); }
 
@@ -120,6 +120,10 @@ hipError_t layered_budget(int nt, int D, size_t base, int* wpe) {
 hipError_t layered_launch_shape(const DevCode& c, const lsim_decode_params& p, int* nt, int* G,
                                 int* K, int* wpe, std::string* why) {
   *nt = p.threads ? p.threads : layered_default_threads(c);
+  if (c.n_deg1_inner) {
+    *why = kLayeredDeg1Msg;
+    return hipSuccess;
+  }
   if (c.Z > *nt) {
     *why = "layered decoder needs threads >= Z";
     return hipSuccess;
@@ -145,7 +149,7 @@ hipError_t launch_layered(const DevCode& c, const lsim_decode_params& p, const f
   const unsigned grid = (unsigned)((B + G - 1) / G);
   const int D = degree_class(c);
   const size_t lds = tile_lds_bytes(c, G, K);
-  TileIO io{llr, bits, lpost, r_out, reinterpret_cast<uint4*>(state), B, K};
+  TileIO io{llr, bits, lpost, r_out, state, B, K};
 #define LSIM_LAYER_CASE(NT_, D_, W_)                                                   \
   if (nt == NT_ && D == D_ && wpe == W_) {                                             \
     const void* k = (const void*)layered_kernel<NT_, D_, W_>;                          \

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     io.bits = bits ? bits + sh.bits_off : nullptr;
     io.lpost = lpost ? lpost + sh.app_off : nullptr;
     io.r_out = nullptr;
-    io.state = reinterpret_cast<uint4*>(state + sh.state_off);
+    io.state = state + sh.state_off;
     io.count = sh.count;
     io.lds_rows = sh.lds_rows;
     decode_tile<NT, DMAX>(sh.code, sh.G, tile_local[item], io, iters, alpha);

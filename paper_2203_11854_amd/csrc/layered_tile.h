@@ -11,19 +11,22 @@
 // read by every lane of those rows, so its Z posteriors sit in LDS ("shared"
 // columns, one LDS slot each).  A column of degree one that is the last entry
 // of its row (the extension parity columns of a BG-shaped code) is read and
-// written only by lane r of that row ("private" column): its posterior for
-// variable node (col, (r + shift) mod Z) travels with the check's state.  For
+// written only by lane r of that row ("private" column).  Such a variable
+// node has no other check, so the message it sends is its channel value in
+// every iteration: lane r reads it from the channel LLRs and keeps no
+// posterior for it until the last iteration writes lam + r_new out.  For
 // the BG1-shaped workload (26 shared of 68 columns at Z = 384) a codeword's
 // LDS shrinks from 104 KB to 39 KB, so more codewords are resident per CU.
 //
-// The state of check (i, r) between iterations is one 16-byte record
-// (alpha*m1, alpha*m2, sign bits | i1 << 27, private posterior) streamed
-// through device memory in [codeword][layer][Z] order: one coalesced 16-byte
-// load and store per lane and layer.
+// The state of check (i, r) between iterations is one 12-byte record
+// (alpha*m1, alpha*m2, sign bits | i1 << 27) streamed through device memory
+// in [codeword][layer][Z] order: one coalesced three-word load and store per
+// lane and layer, plus the four-byte channel value of a private column.
 //
 // Arithmetic follows the layered min-sum update one IEEE single-precision
-// operation at a time (no fused multiply-add): t = APP - r_old;
-// r_new = sign * (alpha * (v == i1 ? m2 : m1)); APP = t + r_new.
+// operation at a time (no fused multiply-add): t = APP - r_old (the channel
+// value for a private column); r_new = sign * (alpha * (v == i1 ? m2 : m1));
+// APP = t + r_new.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -55,10 +58,34 @@ struct TileIO {
   uint8_t* bits;        // [count][k]
   float* lpost;         // [count][n_dec]
   float* r_out;         // [count][E]
-  uint4* state;         // [count][rows][Z] check records (rows >= lds_rows)
+  uint32_t* state;      // [count][rows][Z][3] check records (rows >= lds_rows)
   int64_t count;
   int lds_rows;         // rows whose records stay in LDS
 };
+
+// A check record in device memory: three consecutive words, 4-byte aligned.
+struct Rec3 {
+  uint32_t x, y, z;
+};
+
+// Element `off` of an array at a base common to the workgroup: the byte
+// offset is formed in 32 bits, so the access takes the scalar-base plus
+// 32-bit-lane-offset form.
+template <typename T>
+__device__ __forceinline__ T* at32(T* base, uint32_t off) {
+  using B = std::conditional_t<std::is_const<T>::value, const char, char>;
+  return reinterpret_cast<T*>(reinterpret_cast<B*>(base) + off * (uint32_t)sizeof(T));
+}
+
+__device__ __forceinline__ uint4 ld_rec(const uint32_t* base, uint32_t off) {
+  const Rec3 v = *reinterpret_cast<const Rec3*>(at32(base, off));
+  return make_uint4(v.x, v.y, v.z, 0u);
+}
+
+__device__ __forceinline__ void st_rec(uint32_t* base, uint32_t off, uint32_t x, uint32_t y,
+                                       uint32_t z) {
+  *reinterpret_cast<Rec3*>(at32(base, off)) = Rec3{x, y, z};
+}
 
 __device__ __forceinline__ int rot_lift(int r, int s, int Z) {
   const int x = r + s;
@@ -94,8 +121,18 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
   const int app_b = vreg((active ? g : 0) * nsz * 4);
   const int Z4 = Z * 4, zm4 = (Z - 1) * 4, r4 = vreg(r * 4);
   const bool zpow2 = (Z & (Z - 1)) == 0;
-  uint4* st = io.state + (size_t)cw * c.rows * Z + r;
-  const float* llr_cw = io.llr + cw * c.e_tx;
+  // Device addresses as a base common to the workgroup (scalar registers)
+  // plus a 32-bit per-lane offset: a per-lane 64-bit pointer costs two
+  // VGPRs, and under the six-wavefront budget it would be spilled and its
+  // reload would wait on the record prefetch.
+  const int ga = active ? g : 0;
+  uint32_t* const st_t = io.state + (size_t)cw0 * c.rows * Z * 3;
+  const uint32_t st_l = (uint32_t)((ga * c.rows * Z + r) * 3);
+  const uint32_t* const llr_t = reinterpret_cast<const uint32_t*>(io.llr) + cw0 * c.e_tx;
+  const uint32_t llr_l = (uint32_t)(ga * c.e_tx);
+  uint8_t* const bits_t = io.bits ? io.bits + cw0 * c.k : nullptr;
+  float* const lpost_t = io.lpost ? io.lpost + cw0 * c.n_dec : nullptr;
+  const int Z3 = Z * 3;
   // records of rows 0 .. K-1 in LDS after the shared posteriors, lane-private
   // (written and read back by the same lane, so no barrier orders them)
   const int K = io.lds_rows;
@@ -107,22 +144,30 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
     return en.x + rot_lift(r, en.y, Z);
   };
 
-  // The record of the next layer is loaded one layer ahead so its memory
-  // latency overlaps the current layer.  A decoded graph has at least three
-  // layers, so a prefetched layer was stored at least two layers earlier.
-  // In the first iteration the check state is zero and a private posterior
-  // is the channel value.
+  // The record of the next layer (and the channel value of its private
+  // column) is loaded one layer ahead so its memory latency overlaps the
+  // current layer.  A decoded graph has at least three layers, so a
+  // prefetched layer was stored at least two layers earlier.  In the first
+  // iteration the check state is zero.
   const int rows = c.rows;
   uint4 nrec = make_uint4(0u, 0u, 0u, 0u);
+  // The channel value is kept as loaded and negated where it is used
+  // (arithmetic on it here would wait for the load); a node without one
+  // reads as -0 and so enters as +0.
   auto fetch = [&](int ni, int nit) {
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    uint4 v = make_uint4(0u, 0u, 0u, 0x80000000u);
     if (active && nit < iters) {
       if (nit >= 1) {
-        v = ni < K ? lds_ld<uint4>(rec_b + ni * Z * 16) : st[(size_t)ni * Z];
-      } else if (uni(ld_const(c.row_priv, ni)) >= 0) {
-        const int x = priv_vn(ni) - c.tx_lo;
-        if (x >= 0 && x < c.e_tx) v.w = __float_as_uint(-llr_cw[x]);
+        const uint4 rr = ni < K ? lds_ld<uint4>(rec_b + ni * Z * 16) : ld_rec(st_t, st_l + (uint32_t)(ni * Z3));
+        v.x = rr.x;
+        v.y = rr.y;
+        v.z = rr.z;
       }
+      // one table entry per row (no private column: an offset below zero),
+      // so the address waits on a single scalar load
+      const int2 pc = ld_const(c.priv_ch, ni);
+      const int x = pc.x + rot_lift(r, pc.y, Z);
+      if (x >= 0 && x < c.e_tx) v.w = *at32(llr_t, llr_l + (uint32_t)x);
     }
     return v;
   };
@@ -143,8 +188,9 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
       }
       const float a1 = __uint_as_float(rec.x), a2 = __uint_as_float(rec.y);
       const uint32_t pk = rec.z;
-      // One check update of degree D; with PRIV the last entry's posterior
-      // comes from and goes back to the record, the others are in LDS.
+      // One check update of degree D; with PRIV the last entry's message is
+      // its channel value (prefetched with the record), the others' posteriors
+      // are in LDS.
       auto update = [&](auto deg, auto privc) {
         constexpr int D = decltype(deg)::value;
         constexpr bool PRIV = decltype(privc)::value;
@@ -171,7 +217,7 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
           }
 #pragma unroll
           for (int q = 0; q < DL; ++q) tv[q] = lds_ld<float>(addr[q]);
-          if constexpr (PRIV) tv[D - 1] = __uint_as_float(rec.w);
+          if constexpr (PRIV) tv[D - 1] = -__uint_as_float(rec.w);
           const int i1_old = (int)(pk >> 27);
           // sign of a zero never reaches a nonzero value (a zero input forces
           // every other output magnitude to zero), so sign bits are used as is
@@ -179,10 +225,14 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
           float m1 = INFINITY, m2 = INFINITY;
 #pragma unroll
           for (int q = 0; q < D; ++q) {
-            const float mag = q == i1_old ? a2 : a1;
-            const float rold = __uint_as_float(__float_as_uint(mag) | ((pk << (31 - q)) & 0x80000000u));
-            const float t = __fsub_rn(tv[q], rold);
-            tv[q] = t;
+            float t = tv[q];
+            if (!(PRIV && q == D - 1)) {
+              const float mag = q == i1_old ? a2 : a1;
+              const float rold =
+                  __uint_as_float(__float_as_uint(mag) | ((pk << (31 - q)) & 0x80000000u));
+              t = __fsub_rn(t, rold);
+              tv[q] = t;
+            }
             sx ^= __float_as_uint(t);
             const float at = fabsf(t);
             m2 = __builtin_amdgcn_fmed3f(m1, at, m2);
@@ -210,17 +260,16 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
             npk |= sg >> (31 - q);
           }
           npk |= (uint32_t)i1 << 27;
-          const uint4 nr = make_uint4(__float_as_uint(b1), __float_as_uint(b2), npk,
-                                      __float_as_uint(pout));
           if (i < K)
-            lds_st<uint4>(rec_b + i * Z * 16, nr);
+            lds_st<uint4>(rec_b + i * Z * 16,
+                          make_uint4(__float_as_uint(b1), __float_as_uint(b2), npk, 0u));
           else if (it < iters - 1 || io.r_out)  // the last records serve only the export
-            st[(size_t)i * Z] = nr;
+            st_rec(st_t, st_l + (uint32_t)(i * Z3), __float_as_uint(b1), __float_as_uint(b2), npk);
           if (PRIV && it == iters - 1) {
             // the private posterior is final: write it out now
             const int v = priv_vn(i);
-            if (io.bits && v < c.k) io.bits[cw * c.k + v] = pout < 0.f;
-            if (io.lpost) io.lpost[cw * c.n_dec + v] = -pout;
+            if (bits_t && v < c.k) *at32(bits_t, (uint32_t)(ga * c.k + v)) = pout < 0.f;
+            if (lpost_t) *at32(lpost_t, (uint32_t)(ga * c.n_dec + v)) = -pout;
           }
         }
       };
@@ -248,7 +297,7 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
   }
   if (io.r_out && active) {
     for (int i = 0; i < c.rows; ++i) {
-      const uint4 rc = i < K ? lds_ld<uint4>(rec_b + i * Z * 16) : st[(size_t)i * Z];
+      const uint4 rc = i < K ? lds_ld<uint4>(rec_b + i * Z * 16) : ld_rec(st_t, st_l + (uint32_t)(i * Z3));
       const float a1 = __uint_as_float(rc.x), a2 = __uint_as_float(rc.y);
       const uint32_t pk = rc.z;
       const int i1 = (int)(pk >> 27);

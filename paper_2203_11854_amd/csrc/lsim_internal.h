@@ -62,7 +62,13 @@ struct LayerShape {
   int64_t state_off;   // offset (in 32-bit words) of the shape's check state
   int lds_rows;        // layered decoder: rows whose check records stay in LDS
 };
+// Three words per check record: [B][rows][Z][3].
 size_t layered_state_words(const DevCode& c, int64_t B);
+// The layered decoder takes the message of a degree-one variable node to be
+// its channel value, which it reads per row; a code with such a column that
+// does not close its row is outside that layout.
+constexpr const char* kLayeredDeg1Msg =
+    "layered decoder: a column of degree one must be the last entry of its row";
 size_t layered_tile_lds(const DevCode& c, int G, int K = 0);
 // Launch shape of the layered decoder: threads, codewords per workgroup,
 // rows whose check records stay in LDS, register budget (k_layered.hip).

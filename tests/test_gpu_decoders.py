@@ -193,6 +193,24 @@ def test_nms_layered_few_layers(case):
     assert np.array_equal(bits.cpu().numpy(), D.hard_bits(app, g.k))
 
 
+def test_layered_rejects_an_inner_degree_one_column():
+    """The layered decoder reads a degree-one variable node's message from
+    the channel only where the node closes its row; any other degree-one
+    column is refused (never decoded in a different arithmetic), while the
+    flooding decoders take the code."""
+    from inputs.workloads import SMALL
+    qb = SMALL.load()
+    b = qb.base.copy()
+    rows = np.nonzero(b[:, 0] >= 0)[0]
+    b[rows[1:], 0] = -1                       # information column 0 in one row only
+    code = lsim.Code(b, qb.Z, qb.family, qb.n_punct_cols, 648)
+    llr = -torch.ones(3, 648, device=dev)    # the all-zero codeword, L = ln p(1)/p(0)
+    with pytest.raises(lsim.LsimError, match="degree one"):
+        lsim.decode(code, llr, lsim.params(lsim.NMS_F32))
+    bits, _ = lsim.decode(code, llr, lsim.params(lsim.SPA_F32))
+    assert not bits.any()
+
+
 @pytest.mark.parametrize("offset,sat", [(0, 31), (2, 31), (1, 15), (1, 127)])
 def test_oms_parameters_bit_exact(offset, sat):
     """int8 offset min-sum with other offsets and saturation levels (the

@@ -180,34 +180,67 @@ def test_pruned_equals_full(algo):
 
 
 def _layered_loop(g, lam, iters, alpha):
+    """Layered min-sum one check at a time, written from the message
+    definitions: the message from variable node v to check x is v's channel
+    value plus the messages of every other check of v; a check's outputs all
+    use the messages it received before its own update."""
     ev = g.edge_vn()
     B = lam.shape[0]
-    app = lam.astype(np.float64).copy()
     r = np.zeros((B, g.E))
     Z = g.Z
+    edges_of = {}
+    for x, v in enumerate(ev):
+        edges_of.setdefault(int(v), []).append(x)
     for _ in range(iters):
         for i in range(g.rows):
             es = g.row_entries(i)
             for z in range(Z):
                 ids = [e * Z + z for e in es]
                 for b in range(B):
-                    t = [app[b, ev[x]] - r[b, x] for x in ids]
-                    for a, x in enumerate(ids):
+                    t = [lam[b, ev[x]] + sum(r[b, y] for y in edges_of[int(ev[x])] if y != x)
+                         for x in ids]
+                    new = []
+                    for a in range(len(ids)):
                         others = [t[u] for u in range(len(ids)) if u != a]
                         s = 1.0
                         for y in others:
                             s *= -1.0 if y < 0 else 1.0
-                        rn = s * alpha * min(abs(y) for y in others)
-                        r[b, x] = rn
-                        app[b, ev[x]] = t[a] + rn
+                        new.append(s * alpha * min(abs(y) for y in others))
+                    for a, x in enumerate(ids):
+                        r[b, x] = new[a]
+    app = lam.astype(np.float64).copy()
+    for x, v in enumerate(ev):
+        app[:, v] += r[:, x]
     return app
 
 
-def test_layered_equals_check_loop():
-    g = tiny_graph([[0, 1, 2, 0, -1], [2, -1, 1, 0, 0], [1, 0, -1, -1, 0]], 3)
+# the second graph has two columns of degree one (one closing its row, one
+# inside a row), the first none
+LAYERED_GRAPHS = [([[0, 1, 2, 0, -1], [2, -1, 1, 0, 0], [1, 0, -1, -1, 0]], 3),
+                  ([[0, 1, -1, 2, 0, -1], [2, -1, 1, 0, 1, -1], [1, 0, -1, 2, -1, 0]], 3)]
+
+
+@pytest.mark.parametrize("gi", [0, 1])
+def test_layered_equals_check_loop(gi):
+    g = tiny_graph(*LAYERED_GRAPHS[gi])
     lam = rand.gaussian(11, (3, g.n_dec), scale=1.5, mean=0.4)
     got = D.nms_layered(g, lam, 3, alpha=0.75)
     assert np.allclose(got, _layered_loop(g, lam, 3, 0.75), rtol=1e-12, atol=1e-12)
+
+
+def test_layered_degree_one_message_is_the_channel_value():
+    """fp32 mode: a degree-one variable node's posterior is, after every
+    iteration, its channel value plus its one check message, rounded once."""
+    g = tiny_graph(*LAYERED_GRAPHS[1])
+    deg = np.bincount(g.entries[:, 1], minlength=g.cols)
+    lam = rand.gaussian(15, (4, g.n_dec), scale=3.0, mean=0.3, dtype=np.float32)
+    _, hist = D.nms_layered(g, lam, 6, alpha=0.75, mode="fp32", trace=True)
+    ev = g.edge_vn()
+    one = [x for x in range(g.E) if deg[ev[x] // g.Z] == 1]
+    assert len(one) == 2 * g.Z
+    for r, app in hist:
+        for x in one:
+            assert np.array_equal(app[:, ev[x]], lam[:, ev[x]] + r[:, x])
 
 
 def test_layered_single_row_is_one_flood_round():
