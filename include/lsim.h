@@ -92,6 +92,29 @@ typedef struct {
 
 lsim_status lsim_code_query(const lsim_code* code, lsim_code_info* info);
 
+/*
+ * Order in which the layered decoder (LSIM_NMS_F32) visits the decoded rows
+ * of `code` in every iteration (Sec. III-B lists the BP decoder and its
+ * variants; the layered schedule's order is not fixed by it and changes
+ * the decoder's output).  Default LSIM_LAYERS_NATURAL: rows 0, 1, ...
+ * LSIM_LAYERS_GROUPED: groups of rows that meet no common multi-check
+ * column (greedy DSatur colouring of the rows' conflict graph), group after
+ * group, rows ascending in a group.  LSIM_LAYERS_CUSTOM: `order` (host,
+ * `rows` ints) is a permutation of 0..rows-1.  Whatever the order, the
+ * decoder synchronises its workgroup only between a layer and the next one
+ * that meets an LDS column of a layer since the last synchronisation (and
+ * at the end of each iteration), so an order with fewer such conflicts
+ * needs fewer barriers.  The table is copied to the code's device memory
+ * synchronously: call it while no decode of this code is in flight.
+ * Errors: LSIM_E_INVAL on an unknown mode or an order that is not a
+ * permutation; LSIM_E_DEVICE on upload failure.
+ */
+enum { LSIM_LAYERS_NATURAL = 0, LSIM_LAYERS_GROUPED = 1, LSIM_LAYERS_CUSTOM = 2 };
+lsim_status lsim_code_set_layer_order(lsim_code* code, int mode, const int* order);
+/* The current order (host, `rows` ints, nullable) and the workgroup barriers
+ * it takes per iteration (nullable). */
+lsim_status lsim_code_layer_order(const lsim_code* code, int* order, int* barriers);
+
 /* ------------------------------------------------------------- pipeline */
 
 /*

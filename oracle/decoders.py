@@ -188,11 +188,12 @@ def oms_flood(g: Graph, lam: np.ndarray, iters: int = 20, offset: int = 1, sat: 
 # --------------------------------------------------------------------------
 
 def nms_layered(g: Graph, lam: np.ndarray, iters: int = 20, alpha: float = 0.75,
-                mode: str = "fp64", trace: bool = False):
+                mode: str = "fp64", trace: bool = False, order=None):
     """Layered normalized min-sum.
 
     State: APP (initially lam, no clamp) and per-edge r (initially 0).  Each
-    iteration visits the decoded base rows in natural order; for all Z
+    iteration visits the decoded base rows in natural order (or in
+    ``order``, a permutation of the rows); for all Z
     checks of row i at once (a QC row block meets each variable node at most
     once): t_v = APP_v - r_v, the variable-to-check message (channel value
     plus every other check's message); S, m1, i1, m2 from t with
@@ -220,9 +221,12 @@ def nms_layered(g: Graph, lam: np.ndarray, iters: int = 20, alpha: float = 0.75,
         ids = g.row_edge_ids(i)
         one = (deg[g.entries[g.row_entries(i), 1]] == 1)[:, None]
         rows.append((ids, vn_all[ids], one))
+    seq = range(g.rows) if order is None else [int(i) for i in order]
+    if sorted(seq) != list(range(g.rows)):
+        raise ValueError("order must be a permutation of the decoded rows")
     hist = []
     for _ in range(iters):
-        for ids, vn, one in rows:
+        for ids, vn, one in (rows[i] for i in seq):
             t = np.where(one, ch[:, vn], app[:, vn] - r[:, ids])
             a = np.abs(t)
             s = np.where(t < 0, dt(-1), dt(1))

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "liblsim.so")
 SPA_F32, OMS_I8, NMS_F32 = 0, 1, 2
 DEMAP_EXACT, DEMAP_MAXLOG = 0, 1
 FAMILY_11N, FAMILY_BG = 0, 1
+LAYERS_NATURAL, LAYERS_GROUPED, LAYERS_CUSTOM = 0, 1, 2
 NDM_PARAMS = 4676
 
 _lib = None
@@ -55,6 +56,8 @@ _SIGS = {
     "lsim_code_create": [_P, _I, _I, _I, _I, _I, _I64, ctypes.POINTER(_P)],
     "lsim_code_destroy": [_P],
     "lsim_code_query": [_P, ctypes.POINTER(CodeInfo)],
+    "lsim_code_set_layer_order": [_P, _I, _P],
+    "lsim_code_layer_order": [_P, _P, ctypes.POINTER(ctypes.c_int)],
     "lsim_source_bits": [_U64, _I64, _I64, _I64, _P, _P],
     "lsim_encode": [_P, _P, _I64, _P, _P],
     "lsim_map_awgn": [_P, _I, _P, _P, _U64, _I64, _I64, _P, _P],
@@ -184,6 +187,28 @@ class Code:
     def tx_lo(self) -> int:
         """First transmitted mother-code bit (lsim_code_create's rate matching)."""
         return self.n_punct_cols * self.Z
+
+    def set_layer_order(self, order="natural"):
+        """Layered decoder's row order (lsim_code_set_layer_order): "natural",
+        "grouped" or a permutation of range(rows)."""
+        import numpy as np
+        if isinstance(order, str):
+            mode = {"natural": LAYERS_NATURAL, "grouped": LAYERS_GROUPED}[order]
+            _call("lsim_code_set_layer_order", self._h, mode, None)
+        else:
+            arr = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+            if arr.shape != (self.rows,):
+                raise LsimError(f"layer order needs {self.rows} rows")
+            _call("lsim_code_set_layer_order", self._h, LAYERS_CUSTOM,
+                  arr.ctypes.data_as(ctypes.c_void_p))
+
+    def layer_order(self):
+        """(order as a list of rows, workgroup barriers per iteration)."""
+        import numpy as np
+        arr = np.zeros(self.rows, dtype=np.int32)
+        nb = ctypes.c_int()
+        _call("lsim_code_layer_order", self._h, arr.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nb))
+        return arr.tolist(), nb.value
 
     def __del__(self):
         h = getattr(self, "_h", None)

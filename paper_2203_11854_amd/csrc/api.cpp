@@ -66,6 +66,87 @@ lsim_status dev_status(hipError_t e, const char* what) {
 
 hipStream_t as_stream(lsim_stream s) { return reinterpret_cast<hipStream_t>(s); }
 
+bool rows_meet(const lsim_code& c, int a, int b) {
+  for (int x : c.row_lds_cols[a])
+    for (int y : c.row_lds_cols[b])
+      if (x == y) return true;
+  return false;
+}
+
+// The layered schedule table for a visiting order: per position (row,
+// private LLR offset, shift, barrier after).  A barrier follows position p
+// when the layer at p + 1 meets an LDS column of a layer visited since the
+// last barrier (only then can one lane read a posterior another lane of
+// the previous layers writes), and always after the last position, so every
+// iteration starts from the same state of the schedule.
+std::vector<int> layer_table(const lsim_code& c, const std::vector<int>& order) {
+  const int n = (int)order.size();
+  std::vector<int> t(4 * (size_t)n);
+  std::vector<int> run;
+  for (int p = 0; p < n; ++p) {
+    const int i = order[p];
+    run.push_back(i);
+    bool sync = p == n - 1;
+    if (!sync)
+      for (int j : run)
+        if (rows_meet(c, j, order[p + 1])) {
+          sync = true;
+          break;
+        }
+    if (sync) run.clear();
+    t[4 * p] = i;
+    t[4 * p + 1] = c.row_pch[2 * i];
+    t[4 * p + 2] = c.row_pch[2 * i + 1];
+    t[4 * p + 3] = sync ? 1 : 0;
+  }
+  return t;
+}
+
+// Groups of mutually disjoint layers (rows that meet no common LDS column)
+// by DSatur greedy colouring of the conflict graph, visited group after
+// group (rows ascending inside a group): a barrier is then needed only
+// between groups.
+std::vector<int> grouped_order(const lsim_code& c) {
+  const int n = (int)c.row_lds_cols.size();
+  std::vector<std::vector<int>> adj(n);
+  for (int a = 0; a < n; ++a)
+    for (int b = a + 1; b < n; ++b)
+      if (rows_meet(c, a, b)) {
+        adj[a].push_back(b);
+        adj[b].push_back(a);
+      }
+  std::vector<int> colour(n, -1);
+  for (int step = 0; step < n; ++step) {
+    int best = -1, best_sat = -1, best_deg = -1;
+    for (int i = 0; i < n; ++i) {
+      if (colour[i] >= 0) continue;
+      std::vector<int> seen;
+      for (int j : adj[i])
+        if (colour[j] >= 0 && std::find(seen.begin(), seen.end(), colour[j]) == seen.end())
+          seen.push_back(colour[j]);
+      const int sat = (int)seen.size(), deg = (int)adj[i].size();
+      if (sat > best_sat || (sat == best_sat && deg > best_deg)) {
+        best = i;
+        best_sat = sat;
+        best_deg = deg;
+      }
+    }
+    int col = 0;
+    for (;; ++col) {
+      bool used = false;
+      for (int j : adj[best]) used |= colour[j] == col;
+      if (!used) break;
+    }
+    colour[best] = col;
+  }
+  std::vector<int> order;
+  const int ng = n ? *std::max_element(colour.begin(), colour.end()) + 1 : 0;
+  for (int g = 0; g < ng; ++g)
+    for (int i = 0; i < n; ++i)
+      if (colour[i] == g) order.push_back(i);
+  return order;
+}
+
 // Checks that the parity part of `base` has the structure of `family`.
 bool check_family(const std::vector<int16_t>& H, int mb, int nb, int family, std::string* why) {
   const int kb = nb - mb;
@@ -292,18 +373,25 @@ lsim_status lsim_code_create(const int16_t* base, int mb, int nb, int Z, int fam
   size_t o_encz = push(enc_cz);
   size_t o_encp = push(enc_ptr);
   // per row: where lane r finds the channel LLR of the row's private column,
-  // as (col * Z - tx_lo, shift); rows without one get an offset that no lane
-  // reaches from below
-  std::vector<int> pch(2 * (size_t)rows);
+  // as (col * Z - tx_lo, shift) (rows without one get an offset that no lane
+  // reaches from below), and the LDS columns the row meets; the layered
+  // schedule table starts in natural order
+  c->row_pch.assign(2 * (size_t)rows, 0);
+  c->row_lds_cols.assign(rows, {});
   for (int i = 0; i < rows; ++i) {
     const int e = c->row_ptr[i + 1] - 1;
     const bool pv = row_priv[i] >= 0;
-    pch[2 * i] = pv ? (int)(c->ent_col[e] * (int64_t)Z - tx_lo) : -(1 << 30);
-    pch[2 * i + 1] = pv ? c->ent_shift[e] : 0;
+    c->row_pch[2 * i] = pv ? (int)(c->ent_col[e] * (int64_t)Z - tx_lo) : -(1 << 30);
+    c->row_pch[2 * i + 1] = pv ? c->ent_shift[e] : 0;
+    for (int q = c->row_ptr[i]; q < c->row_ptr[i + 1]; ++q)
+      if (!is_priv_col[c->ent_col[q]]) c->row_lds_cols[i].push_back(c->ent_col[q]);
   }
+  c->layer_order.resize(rows);
+  for (int i = 0; i < rows; ++i) c->layer_order[i] = i;
   if (blob.size() & 1) blob.push_back(0);
   size_t o_elz = push(elz);
-  size_t o_pch = push(pch);
+  while (blob.size() & 3) blob.push_back(0);  // 16-byte alignment of the int4 table
+  size_t o_pos = push(layer_table(*c, c->layer_order));
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) e = hipMalloc(&c->dmem, blob.size() * sizeof(int));
   if (e == hipSuccess)
@@ -352,7 +440,8 @@ lsim_status lsim_code_create(const int16_t* base, int mb, int nb, int Z, int fam
   dc.shared_col = d + o_sc;
   dc.priv_row = d + o_pr;
   dc.ent_lz = reinterpret_cast<const int2*>(d + o_elz);
-  dc.priv_ch = reinterpret_cast<const int2*>(d + o_pch);
+  dc.layer_pos = reinterpret_cast<const int4*>(d + o_pos);
+  c->layer_pos_off = o_pos;
   lsim_code_info& in = c->info;
   in.k = dc.k;
   in.n_mother = dc.n_mother;
@@ -384,6 +473,46 @@ void lsim_code_destroy(lsim_code* code) {
 lsim_status lsim_code_query(const lsim_code* code, lsim_code_info* info) {
   if (!code || !info) return fail(LSIM_E_INVAL, "null code or info");
   *info = code->info;
+  return LSIM_OK;
+}
+
+lsim_status lsim_code_set_layer_order(lsim_code* code, int mode, const int* order) {
+  if (!code) return fail(LSIM_E_INVAL, "null code");
+  const int n = code->dev.rows;
+  std::vector<int> ord;
+  if (mode == LSIM_LAYERS_NATURAL) {
+    ord.resize(n);
+    std::iota(ord.begin(), ord.end(), 0);
+  } else if (mode == LSIM_LAYERS_GROUPED) {
+    ord = grouped_order(*code);
+  } else if (mode == LSIM_LAYERS_CUSTOM) {
+    if (!order) return fail(LSIM_E_INVAL, "custom layer order needs an order");
+    ord.assign(order, order + n);
+    std::vector<char> seen(n, 0);
+    for (int i : ord) {
+      if (i < 0 || i >= n || seen[i]) return fail(LSIM_E_INVAL, "layer order is not a permutation of the decoded rows");
+      seen[i] = 1;
+    }
+  } else {
+    return fail(LSIM_E_INVAL, "unknown layer order mode");
+  }
+  const std::vector<int> t = layer_table(*code, ord);
+  int* dst = reinterpret_cast<int*>(code->dmem) + code->layer_pos_off;
+  const hipError_t e = hipMemcpy(dst, t.data(), t.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return dev_status(e, "layer order upload");
+  code->layer_order = ord;
+  return LSIM_OK;
+}
+
+lsim_status lsim_code_layer_order(const lsim_code* code, int* order, int* barriers) {
+  if (!code) return fail(LSIM_E_INVAL, "null code");
+  if (order) std::copy(code->layer_order.begin(), code->layer_order.end(), order);
+  if (barriers) {
+    const std::vector<int> t = layer_table(*code, code->layer_order);
+    int nb = 0;
+    for (size_t p = 0; p < code->layer_order.size(); ++p) nb += t[4 * p + 3];
+    *barriers = nb;
+  }
   return LSIM_OK;
 }
 

@@ -34,8 +34,13 @@ struct DevCode {
   const int* priv_row;    // n_priv: row of each private slot, ascending
   const int2* ent_lz;     // per entry (row-major): (LDS slot * Z, shift) of a shared
                           // column; (col * Z, shift) of a private one
-  const int2* priv_ch;    // rows: (col * Z - tx_lo, shift) of the private column, the
-                          // channel LLR of its node at lane r; (-2^30, 0) without one
+  // Layered schedule, one entry per position p of the visiting order: (row,
+  // col * Z - tx_lo and shift of the row's private column -- its node at lane
+  // r has channel LLR offset col * Z - tx_lo + (r + shift) mod Z -- or
+  // (-2^30, 0) without one, and 1 when a barrier must follow position p
+  // because the next layer shares an LDS column with a layer since the last
+  // barrier; the last position always has one).
+  const int4* layer_pos;
 };
 
 
@@ -48,6 +53,11 @@ __device__ __forceinline__ int2 ld_const(const int2* p, int i) {
   const __attribute__((address_space(4))) int* q =
       (const __attribute__((address_space(4))) int*)p;
   return make_int2(q[2 * i], q[2 * i + 1]);
+}
+__device__ __forceinline__ int4 ld_const(const int4* p, int i) {
+  const __attribute__((address_space(4))) int* q =
+      (const __attribute__((address_space(4))) int*)p;
+  return make_int4(q[4 * i], q[4 * i + 1], q[4 * i + 2], q[4 * i + 3]);
 }
 
 }  // namespace lsim

@@ -4,8 +4,9 @@
 // A tile is G codewords of one code decoded by one workgroup: lane
 // (g, r) = (tid / Z, tid % Z) owns check r of every layer of codeword g.  A
 // QC row block meets each variable node at most once, so the Z checks of a
-// layer update the posteriors without conflicts and one barrier separates
-// consecutive layers.
+// layer update the posteriors without conflicts; a barrier separates a
+// layer from the next one only where they (or a layer since the last
+// barrier) meet a common LDS column, as the code's schedule table says.
 //
 // Posteriors live where their readers are.  A column met by several rows is
 // read by every lane of those rows, so its Z posteriors sit in LDS ("shared"
@@ -144,6 +145,8 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
     return en.x + rot_lift(r, en.y, Z);
   };
 
+  // Layers are visited in the code's schedule order (one table entry per
+  // position: row, private column's LLR offset and shift, barrier after).
   // The record of the next layer (and the channel value of its private
   // column) is loaded one layer ahead so its memory latency overlaps the
   // current layer.  A decoded graph has at least three layers, so a
@@ -153,38 +156,42 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
   uint4 nrec = make_uint4(0u, 0u, 0u, 0u);
   // The channel value is kept as loaded and negated where it is used
   // (arithmetic on it here would wait for the load); a node without one
-  // reads as -0 and so enters as +0.
-  auto fetch = [&](int ni, int nit) {
+  // reads as -0 and so enters as +0.  One table entry gives the row and its
+  // private column (an offset below zero without one), so the addresses wait
+  // on a single scalar load.
+  auto fetch = [&](const int4 pe, int nit) {
     uint4 v = make_uint4(0u, 0u, 0u, 0x80000000u);
     if (active && nit < iters) {
+      const int ni = pe.x;
       if (nit >= 1) {
         const uint4 rr = ni < K ? lds_ld<uint4>(rec_b + ni * Z * 16) : ld_rec(st_t, st_l + (uint32_t)(ni * Z3));
         v.x = rr.x;
         v.y = rr.y;
         v.z = rr.z;
       }
-      // one table entry per row (no private column: an offset below zero),
-      // so the address waits on a single scalar load
-      const int2 pc = ld_const(c.priv_ch, ni);
-      const int x = pc.x + rot_lift(r, pc.y, Z);
+      const int x = pe.y + rot_lift(r, pe.z, Z);
       if (x >= 0 && x < c.e_tx) v.w = *at32(llr_t, llr_l + (uint32_t)x);
     }
     return v;
   };
-  nrec = fetch(0, 0);
+  int4 pos_n = ld_const(c.layer_pos, 0);
+  nrec = fetch(pos_n, 0);
   for (int it = 0; it < iters; ++it) {
-    for (int i = 0; i < rows; ++i) {
+    for (int p = 0; p < rows; ++p) {
+      const int4 pe = pos_n;
+      const int i = uni(pe.x);
       const int e0 = uni(ld_const(c.row_ptr, i));
       const int d = uni(ld_const(c.row_ptr, i + 1)) - e0;
       const bool priv = uni(ld_const(c.row_priv, i)) >= 0;
       const uint4 rec = nrec;
       {
-        int ni = i + 1, nit = it;
-        if (ni == rows) {
-          ni = 0;
+        int np = p + 1, nit = it;
+        if (np == rows) {
+          np = 0;
           ++nit;
         }
-        nrec = fetch(ni, nit);
+        pos_n = ld_const(c.layer_pos, np);
+        nrec = fetch(pos_n, nit);
       }
       const float a1 = __uint_as_float(rec.x), a2 = __uint_as_float(rec.y);
       const uint32_t pk = rec.z;
@@ -281,7 +288,9 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
             update(deg, std::false_type{});
         });
       }
-      lds_barrier();
+      // only between layers that meet a common LDS column (and at the end
+      // of the iteration): the others' posteriors are disjoint
+      if (uni(pe.w)) lds_barrier();
     }
   }
 

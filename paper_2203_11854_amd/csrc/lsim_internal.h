@@ -16,6 +16,13 @@ struct lsim_code {
   lsim_code_info info;
   std::vector<int16_t> base;
   std::vector<int> row_ptr, ent_col, ent_shift, col_ptr, col_ent;
+  // layered schedule: per row the LDS (multi-check) columns it meets and its
+  // private column's (LLR offset, shift); the current visiting order and
+  // where the schedule table sits in dmem (in ints)
+  std::vector<std::vector<int>> row_lds_cols;
+  std::vector<int> row_pch;
+  std::vector<int> layer_order;
+  size_t layer_pos_off = 0;
   void* dmem = nullptr;
   int device = 0;
 };

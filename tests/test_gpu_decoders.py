@@ -72,6 +72,45 @@ def test_nms_layered_bit_exact(name, B, ebn0):
     assert np.array_equal(bits.cpu().numpy(), D.hard_bits(app, g.k))
 
 
+@pytest.mark.parametrize("name,B,ebn0,order", [("bg2", 19, 3.0, "grouped"), ("bg1", 3, 2.5, "grouped"),
+                                              ("bg2", 13, 3.0, "shuffled"), ("small", 11, 1.5, "grouped")])
+def test_nms_layer_order_bit_exact(name, B, ebn0, order):
+    """Other row orders (the grouped one, whose workgroup barriers fall only
+    between groups of disjoint rows, and a random permutation) against the
+    oracle in the same order, state after 1, 2 and 20 iterations; the
+    natural order is restored bit for bit."""
+    qb, g, code = gcode(name)
+    nat_order, nat_barriers = code.layer_order()
+    assert nat_order == list(range(g.rows)) and 1 <= nat_barriers <= g.rows
+    if order == "grouped":
+        code.set_layer_order("grouped")
+        perm, barriers = code.layer_order()
+        assert sorted(perm) == list(range(g.rows)) and barriers <= nat_barriers
+    else:
+        perm = np.random.default_rng(5).permutation(g.rows).tolist()
+        code.set_layer_order(perm)
+        assert code.layer_order()[0] == perm
+    print(name, order, "barriers", nat_barriers, "->", code.layer_order()[1], flush=True)
+    tx = oracle_llrs(name, B, ebn0, 59)
+    L32 = tx["L"].astype(np.float32)
+    lam = D.channel_lam(g, L32, dtype=np.float32)
+    app, hist = D.nms_layered(g, lam, 20, alpha=0.75, mode="fp32", trace=True, order=perm)
+    tl = T(L32).to(dev)
+    for t in (1, 2, 20):
+        r, _, lp = lsim.decode_state(code, tl, lsim.params(lsim.NMS_F32, iters=t, alpha=0.75))
+        assert np.array_equal(r.cpu().numpy(), hist[t - 1][0]), t
+        assert np.array_equal(lp.cpu().numpy(), -hist[t - 1][1]), t
+    bits, _ = lsim.decode(code, tl, lsim.params(lsim.NMS_F32, iters=20, alpha=0.75))
+    assert np.array_equal(bits.cpu().numpy(), D.hard_bits(app, g.k))
+    code.set_layer_order("natural")
+    assert code.layer_order() == (nat_order, nat_barriers)
+    ref = D.nms_layered(g, lam, 20, alpha=0.75, mode="fp32")
+    _, lp = lsim.decode(code, tl, lsim.params(lsim.NMS_F32, iters=20, alpha=0.75), want_app=True)
+    assert np.array_equal(lp.cpu().numpy(), -ref)
+    with pytest.raises(lsim.LsimError, match="permutation"):
+        code.set_layer_order([0] * g.rows)
+
+
 @pytest.mark.parametrize("name,B,ebn0", [("bg2", 21, 3.0), ("small", 17, 1.5)])
 def test_spa_one_round_from_oracle_state(name, B, ebn0):
     qb, g, code = gcode(name)

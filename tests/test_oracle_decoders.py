@@ -179,7 +179,7 @@ def test_pruned_equals_full(algo):
         assert np.array_equal(ap, af[:, :gp.n_dec])
 
 
-def _layered_loop(g, lam, iters, alpha):
+def _layered_loop(g, lam, iters, alpha, order=None):
     """Layered min-sum one check at a time, written from the message
     definitions: the message from variable node v to check x is v's channel
     value plus the messages of every other check of v; a check's outputs all
@@ -192,7 +192,7 @@ def _layered_loop(g, lam, iters, alpha):
     for x, v in enumerate(ev):
         edges_of.setdefault(int(v), []).append(x)
     for _ in range(iters):
-        for i in range(g.rows):
+        for i in (range(g.rows) if order is None else order):
             es = g.row_entries(i)
             for z in range(Z):
                 ids = [e * Z + z for e in es]
@@ -226,6 +226,22 @@ def test_layered_equals_check_loop(gi):
     lam = rand.gaussian(11, (3, g.n_dec), scale=1.5, mean=0.4)
     got = D.nms_layered(g, lam, 3, alpha=0.75)
     assert np.allclose(got, _layered_loop(g, lam, 3, 0.75), rtol=1e-12, atol=1e-12)
+
+
+def test_layered_order_is_the_visiting_order():
+    """Another row order follows the check-by-check loop in that order and
+    differs from the natural order's result; the natural order given
+    explicitly is the default."""
+    g = tiny_graph(*LAYERED_GRAPHS[1])
+    lam = rand.gaussian(16, (3, g.n_dec), scale=1.5, mean=0.4)
+    order = [2, 0, 1]
+    got = D.nms_layered(g, lam, 3, alpha=0.75, order=order)
+    assert np.allclose(got, _layered_loop(g, lam, 3, 0.75, order), rtol=1e-12, atol=1e-12)
+    nat = D.nms_layered(g, lam, 3, alpha=0.75)
+    assert not np.allclose(got, nat)
+    assert np.array_equal(nat, D.nms_layered(g, lam, 3, alpha=0.75, order=[0, 1, 2]))
+    with pytest.raises(ValueError):
+        D.nms_layered(g, lam, 1, order=[0, 0, 1])
 
 
 def test_layered_degree_one_message_is_the_channel_value():
