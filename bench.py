@@ -50,10 +50,10 @@ LDS_PEAK_GBS = N_CU * 128 * CLOCK_GHZ
 # for the copy probe of known size (factors below).  Valid only for the
 # kernel sources they were taken on (hash); any change there reports null
 # until the counters are taken again.
-LAYERED_TRAFFIC = {"bytes": (2779540 * 2 + 4075775) * 1024,
+LAYERED_TRAFFIC = {"bytes": (2683628 * 2 + 4068097) * 1024,
                    "sources": ("layered_tile.h", "k_layered.hip", "dispatch.h", "lds.h",
                                "devcode.h"),
-                   "sha256_16": "a080f73ec4952bcf"}
+                   "sha256_16": "d6922c549307d235"}
 FLOOD_SPA_TRAFFIC = {"bytes": (30955 * 2 + 5120) * 1024,
                      "sources": ("k_flood.hip", "spa_math.h", "dispatch.h", "lds.h", "devcode.h"),
                      "sha256_16": "6ed092d8b835b5bc"}
@@ -693,15 +693,20 @@ def mixed_leg(torch, lsim, dev):
     for s_, (cd, x) in enumerate(zip(codes, parts)):
         if sched["schedule"][s_] == "oms":
             rb, _ = lsim.decode(cd, lsim.quantize(x), po)
-        else:
+        elif sched["layer_order"][s_] == "natural":
             rb = sep_bits[s_]
+        else:                      # the order the tuner left set on the code
+            rb, _ = lsim.decode(cd, x, p)
         sched_same = sched_same and torch.equal(sbits[s_], rb)
     ms_sched = _elapsed(torch, lambda: sm.decode(io), 5)
     blk = {"default_nms": 0, "scheduled": 0}
     for s_, sh in enumerate(sched["shapes"]):
         blk["default_nms"] += sh["nms_block_errors"]
         blk["scheduled"] += (sh["oms_block_errors"] if sched["schedule"][s_] == "oms"
-                             else sh["nms_block_errors"])
+                             else sh["grouped_block_errors"]
+                             if sched["layer_order"][s_] == "grouped" else sh["nms_block_errors"])
+    for cd in codes:
+        cd.set_layer_order("natural")
     return {"codewords": int(sum(counts)), "counts": counts, "info_bits": int(info),
             "graph_ms": round(ms_graph, 4), "persistent_ms": round(ms_pers, 4),
             "per_shape_ms": round(ms_sep, 4),
@@ -711,7 +716,8 @@ def mixed_leg(torch, lsim, dev):
             "autotuned": {"threads": best["threads"], "codewords_per_tile": best["codewords_per_tile"],
                           "persistent": best["persistent"], "ms": round(ms_tuned, 4),
                           "bit_identical": bool(torch.equal(tbits, bits))},
-            "schedule_tuned": {"schedule": sched["schedule"], "lds_rows": sched["lds_rows"],
+            "schedule_tuned": {"schedule": sched["schedule"], "layer_order": sched["layer_order"],
+                               "lds_rows": sched["lds_rows"],
                                "ms": round(ms_sched, 4),
                                "gbps": round(info / (ms_sched * 1e-3) / 1e9, 3),
                                "default_persistent_ms": round(ms_pers, 4),

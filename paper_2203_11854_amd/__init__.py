@@ -190,8 +190,10 @@ class Code:
 
     def set_layer_order(self, order="natural"):
         """Layered decoder's row order (lsim_code_set_layer_order): "natural",
-        "grouped" or a permutation of range(rows)."""
+        "grouped" or a permutation of range(rows).  Waits for the device
+        first: the table must not change under a decode in flight."""
         import numpy as np
+        torch.cuda.synchronize()
         if isinstance(order, str):
             mode = {"natural": LAYERS_NATURAL, "grouped": LAYERS_GROUPED}[order]
             _call("lsim_code_set_layer_order", self._h, mode, None)

@@ -231,19 +231,24 @@ def _block_errors(ref, hat):
 
 def tune_schedule(codes, counts, parts, ref_bits, p_nms, p_oms=None, reps: int = 3,
                   verbose: bool = False):
-    """Schedule (decoder per shape) and placement for a mixed batch.
+    """Schedule (decoder and layer order per shape) and placement for a
+    mixed batch.
 
     parts: per-shape f32 LLRs [count][e_tx]; ref_bits: per-shape transmitted
-    information bits [count][k].  Returns the chosen schedule, the NMS
-    plan's lds_rows setting, per-shape block errors of both decoders with
-    the default's Wilson interval, and the time of every candidate timed.
-    Candidates start from every shape on layered NMS; shapes whose offset
-    min-sum BLER is accepted are moved to it one at a time, heaviest first,
-    and a move is kept when the schedule gets faster."""
+    information bits [count][k].  Returns the chosen schedule, the layer
+    order of every shape ("natural" or "grouped", left set on the codes),
+    the NMS plan's lds_rows setting, per-shape block errors of every
+    candidate decoder with the default's (natural-order NMS) Wilson
+    interval, and the time of every candidate timed.  Candidates start from
+    every shape on natural-order layered NMS; shapes whose grouped-order or
+    offset min-sum BLER is accepted are changed one knob at a time, heaviest
+    first, and a change is kept when the schedule gets faster."""
     from . import OMS_I8, decode, decode_workspace, params, quantize
     if p_oms is None:
         p_oms = params(OMS_I8, iters=p_nms.iters, offset=1, sat=31)
     dev = parts[0].device
+    for code in codes:
+        code.set_layer_order("natural")
     per_shape = []
     for s, (code, x, u) in enumerate(zip(codes, parts, ref_bits)):
         n = int(counts[s])
@@ -253,6 +258,14 @@ def tune_schedule(codes, counts, parts, ref_bits, p_nms, p_oms=None, reps: int =
         lo, hi = wilson(en, n)
         info = {"shape": s, "Z": code.Z, "codewords": n, "nms_block_errors": en,
                 "nms_ci95": [round(lo, 5), round(hi, 5)], "oms_fits": oms_fits(code)}
+        code.set_layer_order("grouped")
+        info["grouped_barriers"] = code.layer_order()[1]
+        bg, _ = decode(code, x, p_nms, work=work)
+        code.set_layer_order("natural")
+        info["natural_barriers"] = code.layer_order()[1]
+        eg = _block_errors(u, bg)
+        info["grouped_block_errors"] = eg
+        info["grouped_accepted"] = bool(lo - 1e-12 <= eg / n <= hi + 1e-12)
         if info["oms_fits"]:
             bo, _ = decode(code, quantize(x, 2.0, p_oms.sat), p_oms)
             eo = _block_errors(u, bo)
@@ -272,22 +285,38 @@ def tune_schedule(codes, counts, parts, ref_bits, p_nms, p_oms=None, reps: int =
     tried = []
     best_lds, best_t = 0, None
     base = ["nms"] * len(codes)
+    orders = ["natural"] * len(codes)
     for lds_rows in (0, -1):
         t, _, _ = timed(base, lds_rows)
-        tried.append({"schedule": list(base), "lds_rows": lds_rows, "ms": round(t, 4)})
+        tried.append({"schedule": list(base), "layer_order": list(orders), "lds_rows": lds_rows,
+                      "ms": round(t, 4)})
         if best_t is None or t < best_t:
             best_t, best_lds = t, lds_rows
     schedule = list(base)
-    order = sorted((i for i in per_shape if i["oms_accepted"]),
-                   key=lambda i: -i["codewords"] * codes[i["shape"]].E)
-    for info in order:
-        cand = list(schedule)
-        cand[info["shape"]] = "oms"
+    # one knob at a time, heaviest shape first: the grouped layer order
+    # (for a shape still on NMS), then offset min-sum
+    heavy = sorted(per_shape, key=lambda i: -i["codewords"] * codes[i["shape"]].E)
+    moves = [(i["shape"], "grouped") for i in heavy if i["grouped_accepted"]]
+    moves += [(i["shape"], "oms") for i in heavy if i["oms_accepted"]]
+    for sh, knob in moves:
+        cand, cord = list(schedule), list(orders)
+        if knob == "grouped":
+            if cand[sh] != "nms" or cord[sh] == "grouped":
+                continue
+            cord[sh] = "grouped"
+            codes[sh].set_layer_order("grouped")
+        else:
+            cand[sh] = "oms"          # the layer order applies to NMS only
+            cord[sh] = "natural"
+            codes[sh].set_layer_order("natural")
         t, _, _ = timed(cand, best_lds)
-        tried.append({"schedule": cand, "lds_rows": best_lds, "ms": round(t, 4)})
+        tried.append({"schedule": cand, "layer_order": cord, "lds_rows": best_lds,
+                      "ms": round(t, 4)})
         if verbose:
             print(tried[-1], flush=True)
         if t < best_t:
-            best_t, schedule = t, cand
-    return {"schedule": schedule, "lds_rows": best_lds, "ms": round(best_t, 4),
-            "shapes": per_shape, "tried": tried}
+            best_t, schedule, orders = t, cand, cord
+        else:
+            codes[sh].set_layer_order(orders[sh])
+    return {"schedule": schedule, "layer_order": orders, "lds_rows": best_lds,
+            "ms": round(best_t, 4), "shapes": per_shape, "tried": tried}

@@ -496,11 +496,13 @@ def test_autotuner_mixed_and_decode(tmp_path):
 
 
 def test_schedule_tuner():
-    """Result-changing knobs of the mixed batch: a shape moves from layered
-    NMS to flooding int8 offset min-sum only when its block error rate lies
-    inside NMS's Wilson 95% interval on the same data, and the scheduled
-    launches give, shape by shape, exactly the bits of the decoders the
-    schedule names.  A schedule with every shape on NMS is the mixed plan."""
+    """Result-changing knobs of the mixed batch: a shape moves from
+    natural-order layered NMS to the grouped layer order or to flooding
+    int8 offset min-sum only when its block error rate lies inside the
+    default's Wilson 95% interval on the same data, and the scheduled
+    launches give, shape by shape, exactly the bits of the decoders (and
+    layer orders) the schedule names.  A schedule with every shape on NMS is
+    the mixed plan."""
     from paper_2203_11854_amd import autotune
     counts = [40, 24, 30, 12, 10, 8, 16, 6]
     codes, llrs, graphs, qbs = mixed_inputs(counts, seed=131)
@@ -515,13 +517,26 @@ def test_schedule_tuner():
     res = autotune.tune_schedule(codes, counts, parts, us, pn)
     po = lsim.params(lsim.OMS_I8, iters=20, offset=1, sat=31)
     for s, info in enumerate(res["shapes"]):
+        lo, hi = info["nms_ci95"]
         if res["schedule"][s] == "oms":
             assert info["oms_fits"] and info["oms_accepted"]
-            lo, hi = info["nms_ci95"]
             assert lo - 1e-9 <= info["oms_block_errors"] / counts[s] <= hi + 1e-9
+        if res["layer_order"][s] == "grouped":
+            assert res["schedule"][s] == "nms" and info["grouped_accepted"]
+            assert lo - 1e-9 <= info["grouped_block_errors"] / counts[s] <= hi + 1e-9
+        assert info["grouped_barriers"] <= info["natural_barriers"]
+        assert codes[s].layer_order()[0] == (list(range(codes[s].rows))
+                                             if res["layer_order"][s] == "natural" else
+                                             codes[s].layer_order()[0])
     assert res["lds_rows"] in (0, -1)
-    for schedule in (res["schedule"], ["nms"] * len(codes),
-                     ["oms" if autotune.oms_fits(c) else "nms" for c in codes]):
+    # the tuned orders stay set on the codes; then natural order everywhere
+    for schedule, orders in ((res["schedule"], res["layer_order"]),
+                             (["nms"] * len(codes), ["grouped"] * len(codes)),
+                             (["nms"] * len(codes), ["natural"] * len(codes)),
+                             (["oms" if autotune.oms_fits(c) else "nms" for c in codes],
+                              ["natural"] * len(codes))):
+        for code, o in zip(codes, orders):
+            code.set_layer_order(o)
         sm = autotune.ScheduledMixed(codes, counts, schedule,
                                      lsim.params(lsim.NMS_F32, iters=20, alpha=0.75,
                                                  lds_rows=res["lds_rows"]), po)
@@ -533,4 +548,6 @@ def test_schedule_tuner():
                 ref, _ = lsim.decode(code, lsim.quantize(x), po)
             else:
                 ref, _ = lsim.decode(code, x, pn)
-            assert torch.equal(got[s], ref), (schedule, s)
+            assert torch.equal(got[s], ref), (schedule, orders, s)
+    for code in codes:
+        code.set_layer_order("natural")
