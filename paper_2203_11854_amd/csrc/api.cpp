@@ -926,9 +926,9 @@ lsim_status lsim_mixed_plan_create(const lsim_code* const* codes, const int64_t*
                     "the OMS decoder takes one codeword or a codeword pair per tile, within the LDS");
       }
     } else {
-      if (c.n_deg1_inner) {
+      if (c.n_deg1_inner || c.rows < 3) {
         delete plan;
-        return fail(LSIM_E_UNSUPPORTED, lsim::kLayeredDeg1Msg);
+        return fail(LSIM_E_UNSUPPORTED, c.rows < 3 ? lsim::kLayeredRowsMsg : lsim::kLayeredDeg1Msg);
       }
       G = codewords_per_tile && codewords_per_tile[s] > 0 ? codewords_per_tile[s] : threads / c.Z;
       if (!codewords_per_tile || codewords_per_tile[s] <= 0)

@@ -120,8 +120,8 @@ hipError_t layered_budget(int nt, int D, size_t base, int* wpe) {
 hipError_t layered_launch_shape(const DevCode& c, const lsim_decode_params& p, int* nt, int* G,
                                 int* K, int* wpe, std::string* why) {
   *nt = p.threads ? p.threads : layered_default_threads(c);
-  if (c.n_deg1_inner) {
-    *why = kLayeredDeg1Msg;
+  if (c.n_deg1_inner || c.rows < 3) {
+    *why = c.rows < 3 ? kLayeredRowsMsg : kLayeredDeg1Msg;
     return hipSuccess;
   }
   if (c.Z > *nt) {

@@ -169,13 +169,26 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
         v.y = rr.y;
         v.z = rr.z;
       }
-      const int x = pe.y + rot_lift(r, pe.z, Z);
-      if (x >= 0 && x < c.e_tx) v.w = *at32(llr_t, llr_l + (uint32_t)x);
+      // (r + shift) mod Z as min(x, x - Z) on unsigned x; one unsigned
+      // compare covers both ends of the range and the rows without a
+      // private column
+      const uint32_t xr = (uint32_t)(r + pe.z);
+      const int x = pe.y + (int)min(xr, xr - (uint32_t)Z);
+      if ((uint32_t)x < (uint32_t)c.e_tx) v.w = *at32(llr_t, llr_l + (uint32_t)x);
     }
     return v;
   };
   int4 pos_n = ld_const(c.layer_pos, 0);
   nrec = fetch(pos_n, 0);
+  // The record a layer computes is stored at the start of the next layer,
+  // beside that layer's prefetch.  Stores and loads share one counter, so
+  // the wait for the prefetched record at the top of a layer also waits for
+  // every store in flight; a store issued at the end of the layer it was
+  // computed in would stall the next layer, one issued a layer earlier has
+  // had the whole layer to complete.  The same lane reads the record back at
+  // least two layers later (a decoded graph has at least three layers).
+  bool pend = false;
+  uint32_t pend_off = 0, pend_x = 0, pend_y = 0, pend_z = 0;
   for (int it = 0; it < iters; ++it) {
     for (int p = 0; p < rows; ++p) {
       const int4 pe = pos_n;
@@ -192,6 +205,8 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
         }
         pos_n = ld_const(c.layer_pos, np);
         nrec = fetch(pos_n, nit);
+        if (pend) st_rec(st_t, pend_off, pend_x, pend_y, pend_z);
+        pend = false;
       }
       const float a1 = __uint_as_float(rec.x), a2 = __uint_as_float(rec.y);
       const uint32_t pk = rec.z;
@@ -270,8 +285,13 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
           if (i < K)
             lds_st<uint4>(rec_b + i * Z * 16,
                           make_uint4(__float_as_uint(b1), __float_as_uint(b2), npk, 0u));
-          else if (it < iters - 1 || io.r_out)  // the last records serve only the export
-            st_rec(st_t, st_l + (uint32_t)(i * Z3), __float_as_uint(b1), __float_as_uint(b2), npk);
+          else if (it < iters - 1 || io.r_out) {  // the last records serve only the export
+            pend = true;
+            pend_off = st_l + (uint32_t)(i * Z3);
+            pend_x = __float_as_uint(b1);
+            pend_y = __float_as_uint(b2);
+            pend_z = npk;
+          }
           if (PRIV && it == iters - 1) {
             // the private posterior is final: write it out now
             const int v = priv_vn(i);
@@ -293,6 +313,8 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
       if (uni(pe.w)) lds_barrier();
     }
   }
+
+  if (pend) st_rec(st_t, pend_off, pend_x, pend_y, pend_z);
 
   // shared posteriors out of LDS (private ones were written in the last
   // iteration)

@@ -76,6 +76,9 @@ size_t layered_state_words(const DevCode& c, int64_t B);
 // does not close its row is outside that layout.
 constexpr const char* kLayeredDeg1Msg =
     "layered decoder: a column of degree one must be the last entry of its row";
+// Its check records are read back two layers after they are stored, so it
+// needs three layers (code creation already requires three rows).
+constexpr const char* kLayeredRowsMsg = "layered decoder: fewer than three decoded rows";
 size_t layered_tile_lds(const DevCode& c, int G, int K = 0);
 // Launch shape of the layered decoder: threads, codewords per workgroup,
 // rows whose check records stay in LDS, register budget (k_layered.hip).
