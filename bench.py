@@ -141,6 +141,8 @@ def main():
     no = torch.tensor(n0_pts[bins], dtype=torch.float32, device=dev)
     tbins = torch.tensor(bins, dtype=torch.int32, device=dev)
     p_nms = lsim.params(lsim.NMS_F32, iters=T, alpha=0.75)
+    order_tuning = layer_order_tuning(torch, lsim, dev, code, p_nms)
+    log(f"[bench] layer order: {order_tuning}")
     link = lsim.Link(code, m, lsim.DEMAP_MAXLOG, p_nms, B, no, bins=tbins, nbins=9, device=dev)
 
     def step(i):
@@ -189,8 +191,9 @@ def main():
              "bler_by_ebn0": {f"{pts[j]:.1f}": [int(cnt[j, 1]), int(cnt[j, 2])] for j in range(9)},
              "ber_by_ebn0": {f"{pts[j]:.1f}": float(cnt[j, 0]) / max(1, cnt[j, 2] * k)
                              for j in range(9)},
-             "ebn0_db_at_bler_1e-2": None if e12 is None else round(e12, 3)}
-    gpu_curves = {("cfg3", "nms"): cnt}
+             "ebn0_db_at_bler_1e-2": None if e12 is None else round(e12, 3),
+             "layer_order": order_tuning}
+    gpu_curves = {("cfg3", "nms" if order_tuning["chosen"] == "natural" else "nms_grouped"): cnt}
 
     if "bg2" in legs or "bler" in legs:
         extra["bg2"], bg2_counts = bg2_leg(torch, lsim, dev, args.steps, "bler" in legs)
@@ -233,8 +236,9 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "bg1-shaped QC-LDPC 46x68 Z=384 (k=8448, n=26112, 25344 tx bits, "
                                "rate 1/3), Gray 64-QAM, max-log demapper, layered normalized "
-                               "min-sum FP32 alpha 0.75, 20 iters, Eb/N0 1:0.5:5 dB, whole link "
-                               "per step",
+                               "min-sum FP32 alpha 0.75, 20 iters, layer order chosen by the "
+                               "schedule tuner (" + order_tuning["chosen"] + "), Eb/N0 1:0.5:5 dB, "
+                               "whole link per step",
                    "global_batch": B, "seq_len": None, "parallelism": "none (1 GPU)"},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -385,6 +389,22 @@ def bg2_leg(torch, lsim, dev, steps, bler_legs):
 
 # ------------------------------------------------------ BLER validity gates
 
+def layer_order_tuning(torch, lsim, dev, code, p):
+    """The schedule tuner's layer order for the headline code (natural or
+    grouped, lsim.autotune.tune_layer_order) on its own batch: 2048
+    codewords of the same link at 5.5 dB, where the BLER curve falls (at the
+    workload's 1..5 dB every frame fails, so there the orders cannot be told
+    apart)."""
+    from inputs.workloads import data_seed
+    from paper_2203_11854_amd import autotune
+    nb, m = 2048, 6
+    no = torch.full((nb,), float(lsim.ebn0_to_n0(5.5, code.k / code.e_tx, m)),
+                    dtype=torch.float32, device=dev)
+    lk = lsim.Link(code, m, lsim.DEMAP_MAXLOG, p, nb, no, device=dev)
+    lk.run(data_seed(3, 500), 0)
+    return autotune.tune_layer_order(code, lk.llr, lk.u, p)
+
+
 def _gate_configs():
     """(spec, e_tx, m, demap, Eb/N0 points, workload number, GPU batch).
     The BG1-shaped workload's grid runs on to 6 dB: at 1..5 dB its BLER is
@@ -404,7 +424,8 @@ def gate_plan(steps):
     from inputs.workloads import data_seed
     cfgs = _gate_configs()
     plan = []
-    for cfg, algos in (("cfg1", ("spa",)), ("cfg2", ("spa", "oms", "nms")), ("cfg3", ("nms",))):
+    for cfg, algos in (("cfg1", ("spa",)), ("cfg2", ("spa", "oms", "nms")),
+                       ("cfg3", ("nms", "nms_grouped"))):
         npts = len(cfgs[cfg][4])
         n = GATE_ORACLE_CW[cfg] * npts
         seed = data_seed(cfgs[cfg][5], 1000)
@@ -469,12 +490,15 @@ def gate_results(torch, lsim, dev, plan, oracle, gpu_curves, steps):
     from inputs.workloads import data_seed
     from oracle import stats
     cfgs = _gate_configs()
-    algos = {"spa": lsim.SPA_F32, "oms": lsim.OMS_I8, "nms": lsim.NMS_F32}
+    algos = {"spa": lsim.SPA_F32, "oms": lsim.OMS_I8, "nms": lsim.NMS_F32,
+             "nms_grouped": lsim.NMS_F32}
     points, curves = [], {}
     for gp in plan:
         cfg, algo, seed, n = gp["cfg"], gp["algo"], gp["seed"], gp["n"]
         spec, e_tx, m, demap, pts, wl, batch = cfgs[cfg]
         code = lsim.Code.from_qcbase(spec.load(), e_tx)
+        if algo == "nms_grouped":
+            code.set_layer_order("grouped")
         npts = len(pts)
         n0_pts = lsim.ebn0_to_n0(pts, code.k / code.e_tx, m)
         p = lsim.params(algos[algo], iters=20, alpha=0.75, offset=1, sat=31)

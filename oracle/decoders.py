@@ -241,6 +241,37 @@ def nms_layered(g: Graph, lam: np.ndarray, iters: int = 20, alpha: float = 0.75,
     return (app, hist) if trace else app
 
 
+def grouped_order(g: Graph) -> list:
+    """A row order for the layered schedule that visits groups of rows with
+    no common column one group after another.  Rows conflict when they meet
+    a common column; groups are the colour classes of DSatur greedy
+    colouring of that conflict graph (Brelaz, CACM 1979): repeatedly colour
+    the uncoloured row with the most distinct colours among its neighbours,
+    ties to the row with the most neighbours, then to the lowest index, with
+    the smallest colour no neighbour has.  Groups in colour order, rows
+    ascending within a group."""
+    rows = [set(int(j) for j in g.entries[g.row_entries(i), 1]) for i in range(g.rows)]
+    n = g.rows
+    adj = [[b for b in range(n) if b != a and rows[a] & rows[b]] for a in range(n)]
+    colour = [-1] * n
+    for _ in range(n):
+        best = None
+        for i in range(n):
+            if colour[i] >= 0:
+                continue
+            sat = len({colour[j] for j in adj[i] if colour[j] >= 0})
+            key = (sat, len(adj[i]))
+            if best is None or key > best[0]:
+                best = (key, i)
+        i = best[1]
+        used = {colour[j] for j in adj[i]}
+        c = 0
+        while c in used:
+            c += 1
+        colour[i] = c
+    return [i for c in range(max(colour) + 1) for i in range(n) if colour[i] == c]
+
+
 def hard_bits(app: np.ndarray, k: int) -> np.ndarray:
     """b_hat_v = [APP_v < 0] for the information VNs 0..k-1."""
     return (np.asarray(app)[:, :k] < 0).astype(np.uint8)

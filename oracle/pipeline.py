@@ -44,6 +44,9 @@ def decode(g: qc.Graph, L: np.ndarray, algo: str, iters: int = 20):
         app = decoders.oms_flood(g, decoders.channel_lam(g, q, dtype=np.int64), iters)
     elif algo == "nms":
         app = decoders.nms_layered(g, decoders.channel_lam(g, L), iters, mode="fp64")
+    elif algo == "nms_grouped":
+        app = decoders.nms_layered(g, decoders.channel_lam(g, L), iters, mode="fp64",
+                                   order=decoders.grouped_order(g))
     elif algo == "nms32":
         lam = decoders.channel_lam(g, np.asarray(L, dtype=np.float32), dtype=np.float32)
         app = decoders.nms_layered(g, lam, iters, mode="fp32")

@@ -229,6 +229,39 @@ def _block_errors(ref, hat):
     return int((ref != hat).any(dim=1).sum().item())
 
 
+def tune_layer_order(code, llr, ref_bits, p, reps: int = 5, rounds: int = 3):
+    """Layer order of one code for the layered decoder: natural (the
+    default) or grouped.  The grouped order is accepted only if its block
+    error rate on (llr, ref_bits) lies inside the natural order's Wilson 95%
+    interval on the same frames, and taken only if it decodes faster (median
+    over `rounds` interleaved timings of `reps` launches).  Leaves the chosen
+    order set on the code and returns both orders' block errors, barriers
+    per iteration and times."""
+    from . import decode, decode_workspace
+    n = int(llr.shape[0])
+    work = torch.empty(max(1, decode_workspace(code, p, n)), dtype=torch.uint8, device=llr.device)
+    bits = torch.empty((n, code.k), dtype=torch.uint8, device=llr.device)
+    out = {"codewords": n}
+    times = {"natural": [], "grouped": []}
+    for r in range(rounds):
+        for order in ("natural", "grouped"):
+            code.set_layer_order(order)
+            if r == 0:
+                b, _ = decode(code, llr, p, bits=bits, work=work)
+                out[order] = {"block_errors": _block_errors(ref_bits, b),
+                              "barriers_per_iteration": code.layer_order()[1]}
+            times[order].append(_time(lambda: decode(code, llr, p, bits=bits, work=work), reps))
+    for order in times:
+        out[order]["ms"] = round(sorted(times[order])[len(times[order]) // 2], 4)
+    lo, hi = wilson(out["natural"]["block_errors"], n)
+    acc = bool(lo - 1e-12 <= out["grouped"]["block_errors"] / n <= hi + 1e-12)
+    out["natural_ci95"] = [round(lo, 5), round(hi, 5)]
+    out["grouped_accepted"] = acc
+    out["chosen"] = "grouped" if acc and out["grouped"]["ms"] < out["natural"]["ms"] else "natural"
+    code.set_layer_order(out["chosen"])
+    return out
+
+
 def tune_schedule(codes, counts, parts, ref_bits, p_nms, p_oms=None, reps: int = 3,
                   verbose: bool = False):
     """Schedule (decoder and layer order per shape) and placement for a

@@ -232,6 +232,19 @@ def test_nms_layered_few_layers(case):
     assert np.array_equal(bits.cpu().numpy(), D.hard_bits(app, g.k))
 
 
+def test_grouped_order_equals_the_oracles():
+    """The library's grouped layer order (its own DSatur colouring) is the
+    oracle's on every workload code and mixed shape."""
+    from inputs.workloads import BG1, BG2, SMALL, mixed_specs
+    cases = [(BG1, 25344), (BG2, 3840), (SMALL, 648)] + list(mixed_specs())
+    for spec, e_tx in cases:
+        qb = spec.load()
+        g = qc.graph_from_qcbase(qb, e_tx)
+        code = lsim.Code.from_qcbase(qb, e_tx)
+        code.set_layer_order("grouped")
+        assert code.layer_order()[0] == D.grouped_order(g), spec.name
+
+
 def test_layered_rejects_an_inner_degree_one_column():
     """The layered decoder reads a degree-one variable node's message from
     the channel only where the node closes its row; any other degree-one

@@ -551,3 +551,36 @@ def test_schedule_tuner():
             assert torch.equal(got[s], ref), (schedule, orders, s)
     for code in codes:
         code.set_layer_order("natural")
+
+
+def test_layer_order_tuner():
+    """One code's layer order: grouped is taken only when its block error
+    rate lies inside the natural order's Wilson 95% interval on the same
+    frames and it decodes faster; the chosen order is left set on the code,
+    and decoding with it equals the oracle in that order."""
+    from paper_2203_11854_amd import autotune
+    from inputs.workloads import BG2
+    qb = BG2.load()
+    g = qc.graph_from_qcbase(qb, 3840)
+    code = lsim.Code.from_qcbase(qb, 3840)
+    B = 512
+    n0 = pipeline.n0_for(g, np.full(B, 3.0), 4)
+    tx = pipeline.transmit(g, qb.family, 141, 0, B, n0, 4, "maxlog")
+    L = tx["L"].astype(np.float32)
+    x, u = T(L).to(dev), T(tx["u"]).to(dev)
+    pn = lsim.params(lsim.NMS_F32, iters=20, alpha=0.75)
+    res = autotune.tune_layer_order(code, x, u, pn)
+    lo, hi = res["natural_ci95"]
+    inside = lo - 1e-9 <= res["grouped"]["block_errors"] / B <= hi + 1e-9
+    assert res["grouped_accepted"] == inside
+    if res["chosen"] == "grouped":
+        assert inside and res["grouped"]["ms"] < res["natural"]["ms"]
+    assert res["grouped"]["barriers_per_iteration"] <= res["natural"]["barriers_per_iteration"]
+    order = code.layer_order()[0]
+    assert order == (D.grouped_order(g) if res["chosen"] == "grouped" else list(range(g.rows)))
+    rows = [0, 1, B - 1]
+    lam = D.channel_lam(g, L[rows], dtype=np.float32)
+    ref = D.nms_layered(g, lam, 20, 0.75, mode="fp32", order=order)
+    _, lp = lsim.decode(code, x[rows].contiguous(), pn, want_app=True)
+    assert np.array_equal(lp.cpu().numpy(), -ref)
+    code.set_layer_order("natural")

@@ -244,6 +244,39 @@ def test_layered_order_is_the_visiting_order():
         D.nms_layered(g, lam, 1, order=[0, 0, 1])
 
 
+def test_grouped_order_on_a_five_cycle():
+    """Rows i and i+1 (mod 5) share column i+1: the conflict graph is a
+    five-cycle, which DSatur colours 0, 1, 0, 1, 2 for rows 0..4 (row 0
+    first, then the saturated rows in index order), so the groups are
+    {0, 2}, {1, 3}, {4}.  Each row also has a column of its own."""
+    base = -np.ones((5, 10), dtype=int)
+    for i in range(5):
+        base[i, i] = 0
+        base[i, (i - 1) % 5] = 0
+        base[i, 5 + i] = 0
+    g = tiny_graph(base, 3)
+    assert D.grouped_order(g) == [0, 2, 1, 3, 4]
+
+
+@pytest.mark.parametrize("name", ["bg2", "bg1", "small"])
+def test_grouped_order_is_a_proper_colouring(name):
+    """On the workload codes: a permutation of the rows whose consecutive
+    groups (maximal runs of rows with no common column) never put two rows
+    with a common column together, and with fewer groups than rows."""
+    from inputs.workloads import BG1
+    spec, e_tx = {"bg2": (BG2, 3840), "bg1": (BG1, 25344), "small": (SMALL, 648)}[name]
+    g = qc.graph_from_qcbase(spec.load(), e_tx)
+    order = D.grouped_order(g)
+    assert sorted(order) == list(range(g.rows))
+    cols = [set(g.entries[g.row_entries(i), 1].tolist()) for i in order]
+    groups, cur = 0, set()
+    for c in cols:
+        if c & cur:
+            groups, cur = groups + 1, set()
+        cur |= c
+    assert groups + 1 < g.rows
+
+
 def test_layered_degree_one_message_is_the_channel_value():
     """fp32 mode: a degree-one variable node's posterior is, after every
     iteration, its channel value plus its one check message, rounded once."""
