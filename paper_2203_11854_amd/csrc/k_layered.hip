@@ -15,7 +15,7 @@ namespace {
 template <int NT, int DMAX, int WPE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void layered_kernel(
     DevCode c, int G, TileIO io, int iters, float alpha) {
-  decode_tile<NT, DMAX>(c, G, blockIdx.x, io, iters, alpha);
+  decode_tile<NT, DMAX, WPE == 6>(c, G, blockIdx.x, io, iters, alpha);
 }
 
 }  // namespace

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE))) void 
     io.state = state + sh.state_off;
     io.count = sh.count;
     io.lds_rows = sh.lds_rows;
-    decode_tile<NT, DMAX>(sh.code, sh.G, tile_local[item], io, iters, alpha);
+    decode_tile<NT, DMAX, false>(sh.code, sh.G, tile_local[item], io, iters, alpha);
     __syncthreads();
     if (!persistent) break;
   }

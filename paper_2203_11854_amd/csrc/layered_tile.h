@@ -93,7 +93,7 @@ __device__ __forceinline__ int rot_lift(int r, int s, int Z) {
   return x >= Z ? x - Z : x;
 }
 
-template <int NT, int DMAX>
+template <int NT, int DMAX, bool LATE_STORE>
 __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t tile, const TileIO& io,
                                             int iters, float alpha) {
   const int Z = c.Z;
@@ -180,13 +180,17 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
   };
   int4 pos_n = ld_const(c.layer_pos, 0);
   nrec = fetch(pos_n, 0);
-  // The record a layer computes is stored at the start of the next layer,
-  // beside that layer's prefetch.  Stores and loads share one counter, so
-  // the wait for the prefetched record at the top of a layer also waits for
-  // every store in flight; a store issued at the end of the layer it was
-  // computed in would stall the next layer, one issued a layer earlier has
-  // had the whole layer to complete.  The same lane reads the record back at
-  // least two layers later (a decoded graph has at least three layers).
+  // With LATE_STORE the record a layer computes is stored at the start of
+  // the next layer, beside that layer's prefetch.  Stores and loads share
+  // one counter, so the wait for the prefetched record at the top of a layer
+  // also waits for every store in flight; a store issued at the end of the
+  // layer it was computed in stalls the next layer, one issued a layer
+  // earlier has had the whole layer to complete.  The same lane reads the
+  // record back at least two layers later (a decoded graph has at least
+  // three layers).  Carrying the record across the degree-specialised
+  // bodies costs register copies, and only the six-wavefront one-code
+  // launch gains (BG1-shaped code at Z = 384: 1.98 -> 1.84 ms; the
+  // persistent mixed launch loses 6 %, the 256-thread BG2 launch 1 %).
   bool pend = false;
   uint32_t pend_off = 0, pend_x = 0, pend_y = 0, pend_z = 0;
   for (int it = 0; it < iters; ++it) {
@@ -205,7 +209,7 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
         }
         pos_n = ld_const(c.layer_pos, np);
         nrec = fetch(pos_n, nit);
-        if (pend) st_rec(st_t, pend_off, pend_x, pend_y, pend_z);
+        if (LATE_STORE && pend) st_rec(st_t, pend_off, pend_x, pend_y, pend_z);
         pend = false;
       }
       const float a1 = __uint_as_float(rec.x), a2 = __uint_as_float(rec.y);
@@ -286,11 +290,16 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
             lds_st<uint4>(rec_b + i * Z * 16,
                           make_uint4(__float_as_uint(b1), __float_as_uint(b2), npk, 0u));
           else if (it < iters - 1 || io.r_out) {  // the last records serve only the export
-            pend = true;
-            pend_off = st_l + (uint32_t)(i * Z3);
-            pend_x = __float_as_uint(b1);
-            pend_y = __float_as_uint(b2);
-            pend_z = npk;
+            if constexpr (LATE_STORE) {
+              pend = true;
+              pend_off = st_l + (uint32_t)(i * Z3);
+              pend_x = __float_as_uint(b1);
+              pend_y = __float_as_uint(b2);
+              pend_z = npk;
+            } else {
+              st_rec(st_t, st_l + (uint32_t)(i * Z3), __float_as_uint(b1), __float_as_uint(b2),
+                     npk);
+            }
           }
           if (PRIV && it == iters - 1) {
             // the private posterior is final: write it out now
@@ -314,7 +323,7 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
     }
   }
 
-  if (pend) st_rec(st_t, pend_off, pend_x, pend_y, pend_z);
+  if (LATE_STORE && pend) st_rec(st_t, pend_off, pend_x, pend_y, pend_z);
 
   // shared posteriors out of LDS (private ones were written in the last
   // iteration)
