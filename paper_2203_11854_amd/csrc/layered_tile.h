@@ -189,8 +189,8 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
   // record back at least two layers later (a decoded graph has at least
   // three layers).  Carrying the record across the degree-specialised
   // bodies costs register copies, and only the six-wavefront one-code
-  // launch gains (BG1-shaped code at Z = 384: 1.98 -> 1.84 ms; the
-  // persistent mixed launch loses 6 %, the 256-thread BG2 launch 1 %).
+  // launch gains (BG1-shaped code at Z = 384: 1.91 -> 1.85 ms; the
+  // persistent mixed launch loses 5 %, the 256-thread BG2 launch 1 %).
   bool pend = false;
   uint32_t pend_off = 0, pend_x = 0, pend_y = 0, pend_z = 0;
   for (int it = 0; it < iters; ++it) {
@@ -208,6 +208,12 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
           ++nit;
         }
         pos_n = ld_const(c.layer_pos, np);
+        // Take this layer's record (loaded a layer ago) before the next
+        // prefetch is issued.  Loads and stores share one counter and the
+        // compiler waits for all of them at once, so a first use after the
+        // next prefetch would wait for that prefetch too (mixed batch 1.23 ->
+        // 1.18 ms).
+        asm volatile("" ::"v"(rec.x), "v"(rec.y), "v"(rec.z), "v"(rec.w));
         nrec = fetch(pos_n, nit);
         if (LATE_STORE && pend) st_rec(st_t, pend_off, pend_x, pend_y, pend_z);
         pend = false;
@@ -283,7 +289,7 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
               pout = out;
             else
               lds_st<float>(addr[q < DL ? q : 0], out);
-            npk |= sg >> (31 - q);
+            npk = (npk << 1) | (sg >> 31);  // descending q: bit q ends at q
           }
           npk |= (uint32_t)i1 << 27;
           if (i < K)

@@ -87,6 +87,8 @@ def test_calls_validate_before_device():
     assert lib.lsim_probe(1, v, v, 20, 1, 1, ctypes.byref(u), None) == INVAL      # not x16
     assert lib.lsim_probe(4, None, v, 0, 0, 1, ctypes.byref(u), None) == INVAL    # rounds < 1
     assert lib.lsim_probe(4, None, v, 0, 1, 0, ctypes.byref(u), None) == INVAL    # empty grid
+    assert lib.lsim_code_set_layer_order(None, 0, None) == INVAL                  # no code
+    assert lib.lsim_code_layer_order(None, None, None) == INVAL
 
 
 def test_binding_fails_loudly_without_device_tensors():
