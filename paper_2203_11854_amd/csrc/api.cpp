@@ -66,11 +66,20 @@ lsim_status dev_status(hipError_t e, const char* what) {
 
 hipStream_t as_stream(lsim_stream s) { return reinterpret_cast<hipStream_t>(s); }
 
-bool rows_meet(const lsim_code& c, int a, int b) {
-  for (int x : c.row_lds_cols[a])
-    for (int y : c.row_lds_cols[b])
-      if (x == y) return true;
-  return false;
+// Conflict graph of the decoded rows: rows that meet a common LDS column,
+// as an n x n byte matrix built from the column lists.
+std::vector<char> row_conflicts(const lsim_code& c) {
+  const int n = (int)c.row_lds_cols.size();
+  const int cols = (int)c.col_ptr.size() - 1;
+  std::vector<std::vector<int>> col_rows(cols);
+  for (int i = 0; i < n; ++i)
+    for (int j : c.row_lds_cols[i]) col_rows[j].push_back(i);
+  std::vector<char> m((size_t)n * n, 0);
+  for (const auto& rs : col_rows)
+    for (int a : rs)
+      for (int b : rs)
+        if (a != b) m[(size_t)a * n + b] = 1;
+  return m;
 }
 
 // The layered schedule table for a visiting order: per position (row,
@@ -81,6 +90,7 @@ bool rows_meet(const lsim_code& c, int a, int b) {
 // iteration starts from the same state of the schedule.
 std::vector<int> layer_table(const lsim_code& c, const std::vector<int>& order) {
   const int n = (int)order.size();
+  const std::vector<char> meet = row_conflicts(c);
   std::vector<int> t(4 * (size_t)n);
   std::vector<int> run;
   for (int p = 0; p < n; ++p) {
@@ -89,7 +99,7 @@ std::vector<int> layer_table(const lsim_code& c, const std::vector<int>& order) 
     bool sync = p == n - 1;
     if (!sync)
       for (int j : run)
-        if (rows_meet(c, j, order[p + 1])) {
+        if (meet[(size_t)j * n + order[p + 1]]) {
           sync = true;
           break;
         }
@@ -108,36 +118,31 @@ std::vector<int> layer_table(const lsim_code& c, const std::vector<int>& order) 
 // between groups.
 std::vector<int> grouped_order(const lsim_code& c) {
   const int n = (int)c.row_lds_cols.size();
+  const std::vector<char> meet = row_conflicts(c);
   std::vector<std::vector<int>> adj(n);
   for (int a = 0; a < n; ++a)
-    for (int b = a + 1; b < n; ++b)
-      if (rows_meet(c, a, b)) {
-        adj[a].push_back(b);
-        adj[b].push_back(a);
-      }
-  std::vector<int> colour(n, -1);
+    for (int b = 0; b < n; ++b)
+      if (meet[(size_t)a * n + b]) adj[a].push_back(b);
+  // saturation: distinct colours among a row's coloured neighbours, kept
+  // with a per-row colour mark (at most n colours)
+  std::vector<int> colour(n, -1), sat(n, 0);
+  std::vector<char> has((size_t)n * n, 0);
   for (int step = 0; step < n; ++step) {
-    int best = -1, best_sat = -1, best_deg = -1;
+    int best = -1;
     for (int i = 0; i < n; ++i) {
       if (colour[i] >= 0) continue;
-      std::vector<int> seen;
-      for (int j : adj[i])
-        if (colour[j] >= 0 && std::find(seen.begin(), seen.end(), colour[j]) == seen.end())
-          seen.push_back(colour[j]);
-      const int sat = (int)seen.size(), deg = (int)adj[i].size();
-      if (sat > best_sat || (sat == best_sat && deg > best_deg)) {
+      if (best < 0 || sat[i] > sat[best] ||
+          (sat[i] == sat[best] && adj[i].size() > adj[best].size()))
         best = i;
-        best_sat = sat;
-        best_deg = deg;
-      }
     }
     int col = 0;
-    for (;; ++col) {
-      bool used = false;
-      for (int j : adj[best]) used |= colour[j] == col;
-      if (!used) break;
-    }
+    while (has[(size_t)best * n + col]) ++col;
     colour[best] = col;
+    for (int j : adj[best])
+      if (!has[(size_t)j * n + col]) {
+        has[(size_t)j * n + col] = 1;
+        ++sat[j];
+      }
   }
   std::vector<int> order;
   const int ng = n ? *std::max_element(colour.begin(), colour.end()) + 1 : 0;
@@ -498,7 +503,11 @@ lsim_status lsim_code_set_layer_order(lsim_code* code, int mode, const int* orde
   }
   const std::vector<int> t = layer_table(*code, ord);
   int* dst = reinterpret_cast<int*>(code->dmem) + code->layer_pos_off;
-  const hipError_t e = hipMemcpy(dst, t.data(), t.size() * sizeof(int), hipMemcpyHostToDevice);
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e == hipSuccess && cur != code->device) e = hipSetDevice(code->device);
+  if (e == hipSuccess) e = hipMemcpy(dst, t.data(), t.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (cur != code->device) (void)hipSetDevice(cur);
   if (e != hipSuccess) return dev_status(e, "layer order upload");
   code->layer_order = ord;
   return LSIM_OK;
