@@ -69,23 +69,16 @@ struct Rec3 {
   uint32_t x, y, z;
 };
 
-// Element `off` of an array at a base common to the workgroup: the byte
-// offset is formed in 32 bits, so the access takes the scalar-base plus
-// 32-bit-lane-offset form.
-template <typename T>
-__device__ __forceinline__ T* at32(T* base, uint32_t off) {
-  using B = std::conditional_t<std::is_const<T>::value, const char, char>;
-  return reinterpret_cast<T*>(reinterpret_cast<B*>(base) + off * (uint32_t)sizeof(T));
-}
-
+// Record at word `off` from a base common to the workgroup (the byte offset
+// is formed in 32 bits: the scalar-base plus lane-offset access form).
 __device__ __forceinline__ uint4 ld_rec(const uint32_t* base, uint32_t off) {
-  const Rec3 v = *reinterpret_cast<const Rec3*>(at32(base, off));
+  const Rec3 v = ldg_at(reinterpret_cast<const Rec3*>(base), off * 4u);
   return make_uint4(v.x, v.y, v.z, 0u);
 }
 
 __device__ __forceinline__ void st_rec(uint32_t* base, uint32_t off, uint32_t x, uint32_t y,
                                        uint32_t z) {
-  *reinterpret_cast<Rec3*>(at32(base, off)) = Rec3{x, y, z};
+  stg_at(reinterpret_cast<Rec3*>(base), off * 4u, Rec3{x, y, z});
 }
 
 __device__ __forceinline__ int rot_lift(int r, int s, int Z) {
@@ -174,7 +167,7 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
       // private column
       const uint32_t xr = (uint32_t)(r + pe.z);
       const int x = pe.y + (int)min(xr, xr - (uint32_t)Z);
-      if ((uint32_t)x < (uint32_t)c.e_tx) v.w = *at32(llr_t, llr_l + (uint32_t)x);
+      if ((uint32_t)x < (uint32_t)c.e_tx) v.w = ldg_at(llr_t, (llr_l + (uint32_t)x) * 4u);
     }
     return v;
   };
@@ -310,8 +303,8 @@ __device__ __forceinline__ void decode_tile(const DevCode& c, int G, int64_t til
           if (PRIV && it == iters - 1) {
             // the private posterior is final: write it out now
             const int v = priv_vn(i);
-            if (bits_t && v < c.k) *at32(bits_t, (uint32_t)(ga * c.k + v)) = pout < 0.f;
-            if (lpost_t) *at32(lpost_t, (uint32_t)(ga * c.n_dec + v)) = -pout;
+            if (bits_t && v < c.k) stg_at(bits_t, (uint32_t)(ga * c.k + v), (uint8_t)(pout < 0.f));
+            if (lpost_t) stg_at(lpost_t, (uint32_t)(ga * c.n_dec + v) * 4u, -pout);
           }
         }
       };
