@@ -234,7 +234,11 @@ def test_nms_layered_few_layers(case):
 
 def test_grouped_order_equals_the_oracles():
     """The library's grouped layer order (its own DSatur colouring) is the
-    oracle's on every workload code and mixed shape."""
+    oracle's on every workload code and mixed shape, and the number of
+    workgroup barriers the schedule table takes per iteration, for the
+    natural, grouped and a shuffled order, is the count of runs of rows
+    with no common column (plus the end of the iteration), recomputed here
+    from the graph."""
     from inputs.workloads import BG1, BG2, SMALL, mixed_specs
     cases = [(BG1, 25344), (BG2, 3840), (SMALL, 648)] + list(mixed_specs())
     for spec, e_tx in cases:
@@ -243,6 +247,25 @@ def test_grouped_order_equals_the_oracles():
         code = lsim.Code.from_qcbase(qb, e_tx)
         code.set_layer_order("grouped")
         assert code.layer_order()[0] == D.grouped_order(g), spec.name
+        # the workgroup barriers the schedule takes: a barrier before a row
+        # that shares a column with a row since the last one, and one at the
+        # end of every iteration
+        cols = [set(g.entries[g.row_entries(i), 1].tolist()) for i in range(g.rows)]
+
+        def barriers(order):
+            n, cur = 1, set()
+            for i in order:
+                if cols[i] & cur:
+                    n, cur = n + 1, set()
+                cur |= cols[i]
+            return n
+
+        assert code.layer_order()[1] == barriers(D.grouped_order(g)), spec.name
+        shuffled = np.random.default_rng(9).permutation(g.rows).tolist()
+        code.set_layer_order(shuffled)
+        assert code.layer_order()[1] == barriers(shuffled), spec.name
+        code.set_layer_order("natural")
+        assert code.layer_order()[1] == barriers(range(g.rows)), spec.name
 
 
 def test_layered_rejects_an_inner_degree_one_column():
