@@ -268,6 +268,25 @@ def test_grouped_order_equals_the_oracles():
         assert code.layer_order()[1] == barriers(range(g.rows)), spec.name
 
 
+@pytest.mark.parametrize("name,B", [("bg2", 4096), ("bg1", 1024)])
+def test_layered_full_batch_is_deterministic_in_both_orders(name, B):
+    """Full-batch decodes repeated in natural and grouped order (whose
+    schedules skip the barriers between layers with disjoint LDS columns)
+    give identical bits and posteriors every time: a missing barrier would
+    show as run-to-run differences."""
+    qb, g, code = gcode(name)
+    gen = torch.Generator(device="cpu").manual_seed(17)
+    llr = (torch.randn((B, g.e_tx), generator=gen) * 3 + 1.0).to(dev)
+    p = lsim.params(lsim.NMS_F32, iters=20, alpha=0.75)
+    for order in ("natural", "grouped"):
+        code.set_layer_order(order)
+        ref = lsim.decode(code, llr, p, want_app=True)
+        for _ in range(6):
+            out = lsim.decode(code, llr, p, want_app=True)
+            assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1]), order
+    code.set_layer_order("natural")
+
+
 def test_layered_rejects_an_inner_degree_one_column():
     """The layered decoder reads a degree-one variable node's message from
     the channel only where the node closes its row; any other degree-one
