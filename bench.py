@@ -56,7 +56,7 @@ LAYERED_TRAFFIC = {"bytes": (2722004 * 2 + 4066563) * 1024,
                    "sha256_16": "d70f9144f73c24f6"}
 FLOOD_SPA_TRAFFIC = {"bytes": (30955 * 2 + 5120) * 1024,
                      "sources": ("k_flood.hip", "spa_math.h", "dispatch.h", "lds.h", "devcode.h"),
-                     "sha256_16": "6ed092d8b835b5bc"}
+                     "sha256_16": "b7c20661452a4d85"}
 
 # Algorithmic VALU work per edge and round:
 # sum-product in the sum / difference form: check side 13 simple ops
