@@ -437,8 +437,10 @@ lsim_status lsim_wbp_forward(const lsim_code* code, int T, const float* d_w, con
  * Weighted BP backward (custom gradient, Sec. IV-A): given d_gpost =
  * dLoss/dL_post f32[B][n_dec] and the forward checkpoints, writes
  * d_gllr = dLoss/dL f32[B][e_tx] and d_gw = dLoss/dw f32[T][E]
- * (overwritten; reduced over the batch in a fixed order).  d_work needs
- * lsim_wbp_workspace() bytes.
+ * (overwritten; reduced over the batch in an order fixed for a given GPU:
+ * each of the workgroups the GPU holds at once adds its codewords in index
+ * order, then their partial sums are added in workgroup order, so repeated
+ * calls give identical bits).  d_work needs lsim_wbp_workspace() bytes.
  */
 lsim_status lsim_wbp_workspace(const lsim_code* code, int T, int64_t B, size_t* bytes);
 lsim_status lsim_wbp_backward(const lsim_code* code, int T, const float* d_w, const float* d_llr,

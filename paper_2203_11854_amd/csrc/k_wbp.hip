@@ -258,6 +258,11 @@ __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
 // the check outputs) at qb_b, LB[n_dec] at lb_b.  ZC: compile-time lift size
 // or 0.  A check output is unclamped, ln((2 - D)/D) <= L, exactly when
 // D >= dth = 2 / (1 + e^L), so the clamp mask needs no logarithm.
+// Workgroup g takes codewords g, g + G, g + 2G, ... (G = gridDim.x) and adds
+// their weight gradients into its own partial gw_part[g][T][E] in that
+// order: the first codeword stores, the later ones load and add.  Each edge
+// of a round is written by one fixed thread (the column task's lane), so a
+// thread only reads back its own earlier stores.
 template <int NT, int ZC>
 __global__ __launch_bounds__(NT) void wbp_backward_kernel(
     DevCode c, int T, const float* __restrict__ w, const float* __restrict__ llr,
@@ -271,11 +276,6 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
   const int zm = Z - 1;
   const bool zpow2 = (Z & zm) == 0;
   const float lmax2 = lmax * kLog2e;
-  const int64_t b = blockIdx.x;
-  const float* llr_b = llr + b * (int64_t)c.e_tx;
-  for (int v = tid; v < c.n_dec; v += NT) lds_st<float>(lb_b + 4 * v, 0.f);
-  for (int e = tid; e < c.E; e += NT) lds_st<float>(qb_b + 4 * e, 0.f);
-  __syncthreads();
 
   auto col_b = [&](auto deg, int cb, int cc, int* off) {
     constexpr int DC = decltype(deg)::value;
@@ -297,148 +297,161 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
     }
   };
 
-  for (int it = T - 1; it >= 0; --it) {
-    const float* ck = ckpt + ((int64_t)it * B + b) * c.E;
-    // A: recompute the clamped check outputs of round it
-    for (int ti = wave; ti < c.n_cn_tasks; ti += NW) {
-      const int task = uni(ld_const(c.cn_tasks, ti));
-      const int i = task >> 16, r = (task & 0xffff) + lane;
-      const int e0 = uni(ld_const(c.row_ptr, i)), d = uni(ld_const(c.row_ptr, i + 1)) - e0;
-      if (r < Z) {
-        with_degree<kDMAX>(d, [&](auto deg) {
-          constexpr int D = decltype(deg)::value;
-          if constexpr (D >= 2)
-            cn_forward<D>(ck, (uint32_t)((e0 * Z + r) * 4), Z * 4, (e0 * Z + r) * 4, lmax2);
-        });
+  for (int64_t b = blockIdx.x; b < B; b += gridDim.x) {
+    const bool first = b == (int64_t)blockIdx.x;
+    const float* llr_b = llr + b * (int64_t)c.e_tx;
+    for (int v = tid; v < c.n_dec; v += NT) lds_st<float>(lb_b + 4 * v, 0.f);
+    for (int e = tid; e < c.E; e += NT) lds_st<float>(qb_b + 4 * e, 0.f);
+    __syncthreads();
+
+    for (int it = T - 1; it >= 0; --it) {
+      const float* ck = ckpt + ((int64_t)it * B + b) * c.E;
+      // A: recompute the clamped check outputs of round it
+      for (int ti = wave; ti < c.n_cn_tasks; ti += NW) {
+        const int task = uni(ld_const(c.cn_tasks, ti));
+        const int i = task >> 16, r = (task & 0xffff) + lane;
+        const int e0 = uni(ld_const(c.row_ptr, i)), d = uni(ld_const(c.row_ptr, i + 1)) - e0;
+        if (r < Z) {
+          with_degree<kDMAX>(d, [&](auto deg) {
+            constexpr int D = decltype(deg)::value;
+            if constexpr (D >= 2)
+              cn_forward<D>(ck, (uint32_t)((e0 * Z + r) * 4), Z * 4, (e0 * Z + r) * 4, lmax2);
+          });
+        }
       }
+      lds_barrier();
+      // B: variable-side adjoint
+      const float* wt = w + (int64_t)it * c.E;
+      float* gwb = gw_part + ((int64_t)blockIdx.x * T + it) * c.E;
+      const bool last = it + 1 == T;
+      for (int ti = wave; ti < c.n_vn_tasks; ti += NW) {
+        const int task = uni(ld_const(c.vn_tasks, ti));
+        const int j = task >> 16, cc = (task & 0xffff) + lane;
+        const int cb = uni(ld_const(c.col_ptr, j)), dc = uni(ld_const(c.col_ptr, j + 1)) - cb;
+        if (cc < Z) {
+          const int v = j * Z + cc;
+          with_degree<kDMAX>(dc, [&](auto deg) {
+            constexpr int DC = decltype(deg)::value;
+            int off[DC];
+            col_b(deg, cb, cc, off);
+            float rr[DC], ww[DC], s[DC], g[DC], gp[DC];
+#pragma unroll
+            for (int q = 0; q < DC; ++q) ww[q] = ldg_at(wt, (uint32_t)off[q]);
+#pragma unroll
+            for (int q = 0; q < DC; ++q) gp[q] = first ? 0.f : ldg_at(gwb, (uint32_t)off[q]);
+#pragma unroll
+            for (int q = 0; q < DC; ++q) rr[q] = lds_ld<float>(off[q]);
+            float acc = chan_lam(c, llr_b, v, lmax);
+#pragma unroll
+            for (int q = 0; q < DC; ++q) {
+              s[q] = ww[q] * rr[q];
+              acc += s[q];
+            }
+            float A = last ? -gpost[b * (int64_t)c.n_dec + v] : 0.f;
+            if (!last) {
+#pragma unroll
+              for (int q = 0; q < DC; ++q) {
+                const float qv = acc - s[q];
+                g[q] = fabsf(qv) <= lmax ? lds_ld<float>(qb_b + off[q]) : 0.f;
+                A += g[q];
+              }
+            } else {
+#pragma unroll
+              for (int q = 0; q < DC; ++q) g[q] = 0.f;
+            }
+            lds_st<float>(lb_b + 4 * v, lds_ld<float>(lb_b + 4 * v) + A);
+#pragma unroll
+            for (int q = 0; q < DC; ++q) {
+              const float sb = A - g[q];
+              const float gq = sb * rr[q];
+              stg_at(gwb, (uint32_t)off[q], first ? gq : gp[q] + gq);
+              lds_st<float>(qb_b + off[q], sb * ww[q]);
+            }
+          });
+        }
+      }
+      lds_barrier();
+      // C: check-side adjoint from the checkpointed inputs
+      for (int ti = wave; ti < c.n_cn_tasks; ti += NW) {
+        const int task = uni(ld_const(c.cn_tasks, ti));
+        const int i = task >> 16, r = (task & 0xffff) + lane;
+        const int e0 = uni(ld_const(c.row_ptr, i)), d = uni(ld_const(c.row_ptr, i + 1)) - e0;
+        if (r < Z) {
+          const uint32_t qin_b = (uint32_t)((e0 * Z + r) * 4);
+          const int qrow_b = qb_b + (e0 * Z + r) * 4;
+          with_degree<kDMAX>(d, [&](auto deg) {
+            constexpr int D = decltype(deg)::value;
+            float x[D], cbar[D];
+#pragma unroll
+            for (int q = 0; q < D; ++q) x[q] = ldg_at(ck, qin_b + (uint32_t)(q * Z * 4));
+#pragma unroll
+            for (int q = 0; q < D; ++q) cbar[q] = lds_ld<float>(qrow_b + q * Z * 4);
+            float mm[D], tt[D], pD[D], pC[D], av[D];
+            SpaAcc pre;
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+              const float m = spa_m(x[q]);
+              mm[q] = m;
+              tt[q] = __uint_as_float(__float_as_uint(1.f - m) |
+                                      (__float_as_uint(x[q]) & 0x80000000u));
+              pD[q] = pre.D;
+              pC[q] = pre.C;
+              pre.add(m);
+            }
+            // a_v = c_v cosh^2(r_v/2) with cosh^2 = 1/(D (2 - D)); zero where clamped
+            SpaAcc suf;
+#pragma unroll
+            for (int q = D - 1; q >= 0; --q) {
+              const float Dx = fmaf(suf.D, pC[q], pD[q]);
+              av[q] = Dx >= dth ? cbar[q] * __builtin_amdgcn_rcpf(Dx * (2.f - Dx)) : 0.f;
+              suf.add(mm[q]);
+            }
+            // S_k = Apre_k Psuf_k + Ppre_k Asuf_k
+            float ap[D], pp[D];
+            float P = 1.f, Aacc = 0.f;
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+              ap[q] = Aacc;
+              pp[q] = P;
+              Aacc = Aacc * tt[q] + av[q] * P;
+              P *= tt[q];
+            }
+            float Ps = 1.f, As = 0.f;
+#pragma unroll
+            for (int q = D - 1; q >= 0; --q) {
+              const float S = ap[q] * Ps + pp[q] * As;
+              lds_st<float>(qrow_b + q * Z * 4, mm[q] * (2.f - mm[q]) * S);
+              As = As * tt[q] + av[q] * Ps;
+              Ps *= tt[q];
+            }
+          });
+        }
+      }
+      lds_barrier();
     }
-    lds_barrier();
-    // B: variable-side adjoint
-    const float* wt = w + (int64_t)it * c.E;
-    float* gwb = gw_part + (b * (int64_t)T + it) * c.E;
-    const bool last = it + 1 == T;
+    // D: q^(1) = lam, then the channel clamp
     for (int ti = wave; ti < c.n_vn_tasks; ti += NW) {
       const int task = uni(ld_const(c.vn_tasks, ti));
       const int j = task >> 16, cc = (task & 0xffff) + lane;
       const int cb = uni(ld_const(c.col_ptr, j)), dc = uni(ld_const(c.col_ptr, j + 1)) - cb;
       if (cc < Z) {
         const int v = j * Z + cc;
+        float acc = lds_ld<float>(lb_b + 4 * v);
         with_degree<kDMAX>(dc, [&](auto deg) {
           constexpr int DC = decltype(deg)::value;
           int off[DC];
           col_b(deg, cb, cc, off);
-          float rr[DC], ww[DC], s[DC], g[DC];
 #pragma unroll
-          for (int q = 0; q < DC; ++q) ww[q] = ldg_at(wt, (uint32_t)off[q]);
-#pragma unroll
-          for (int q = 0; q < DC; ++q) rr[q] = lds_ld<float>(off[q]);
-          float acc = chan_lam(c, llr_b, v, lmax);
-#pragma unroll
-          for (int q = 0; q < DC; ++q) {
-            s[q] = ww[q] * rr[q];
-            acc += s[q];
-          }
-          float A = last ? -gpost[b * (int64_t)c.n_dec + v] : 0.f;
-          if (!last) {
-#pragma unroll
-            for (int q = 0; q < DC; ++q) {
-              const float qv = acc - s[q];
-              g[q] = fabsf(qv) <= lmax ? lds_ld<float>(qb_b + off[q]) : 0.f;
-              A += g[q];
-            }
-          } else {
-#pragma unroll
-            for (int q = 0; q < DC; ++q) g[q] = 0.f;
-          }
-          lds_st<float>(lb_b + 4 * v, lds_ld<float>(lb_b + 4 * v) + A);
-#pragma unroll
-          for (int q = 0; q < DC; ++q) {
-            const float sb = A - g[q];
-            stg_at(gwb, (uint32_t)off[q], sb * rr[q]);
-            lds_st<float>(qb_b + off[q], sb * ww[q]);
-          }
+          for (int q = 0; q < DC; ++q) acc += lds_ld<float>(qb_b + off[q]);
         });
+        const int xx = v - c.tx_lo;
+        if (xx >= 0 && xx < c.e_tx) {
+          const float L = llr_b[xx];
+          gllr[b * (int64_t)c.e_tx + xx] = fabsf(L) <= lmax ? -acc : 0.f;
+        }
       }
     }
-    lds_barrier();
-    // C: check-side adjoint from the checkpointed inputs
-    for (int ti = wave; ti < c.n_cn_tasks; ti += NW) {
-      const int task = uni(ld_const(c.cn_tasks, ti));
-      const int i = task >> 16, r = (task & 0xffff) + lane;
-      const int e0 = uni(ld_const(c.row_ptr, i)), d = uni(ld_const(c.row_ptr, i + 1)) - e0;
-      if (r < Z) {
-        const uint32_t qin_b = (uint32_t)((e0 * Z + r) * 4);
-        const int qrow_b = qb_b + (e0 * Z + r) * 4;
-        with_degree<kDMAX>(d, [&](auto deg) {
-          constexpr int D = decltype(deg)::value;
-          float x[D], cbar[D];
-#pragma unroll
-          for (int q = 0; q < D; ++q) x[q] = ldg_at(ck, qin_b + (uint32_t)(q * Z * 4));
-#pragma unroll
-          for (int q = 0; q < D; ++q) cbar[q] = lds_ld<float>(qrow_b + q * Z * 4);
-          float mm[D], tt[D], pD[D], pC[D], av[D];
-          SpaAcc pre;
-#pragma unroll
-          for (int q = 0; q < D; ++q) {
-            const float m = spa_m(x[q]);
-            mm[q] = m;
-            tt[q] = __uint_as_float(__float_as_uint(1.f - m) | (__float_as_uint(x[q]) & 0x80000000u));
-            pD[q] = pre.D;
-            pC[q] = pre.C;
-            pre.add(m);
-          }
-          // a_v = c_v cosh^2(r_v/2) with cosh^2 = 1/(D (2 - D)); zero where clamped
-          SpaAcc suf;
-#pragma unroll
-          for (int q = D - 1; q >= 0; --q) {
-            const float Dx = fmaf(suf.D, pC[q], pD[q]);
-            av[q] = Dx >= dth ? cbar[q] * __builtin_amdgcn_rcpf(Dx * (2.f - Dx)) : 0.f;
-            suf.add(mm[q]);
-          }
-          // S_k = Apre_k Psuf_k + Ppre_k Asuf_k
-          float ap[D], pp[D];
-          float P = 1.f, Aacc = 0.f;
-#pragma unroll
-          for (int q = 0; q < D; ++q) {
-            ap[q] = Aacc;
-            pp[q] = P;
-            Aacc = Aacc * tt[q] + av[q] * P;
-            P *= tt[q];
-          }
-          float Ps = 1.f, As = 0.f;
-#pragma unroll
-          for (int q = D - 1; q >= 0; --q) {
-            const float S = ap[q] * Ps + pp[q] * As;
-            lds_st<float>(qrow_b + q * Z * 4, mm[q] * (2.f - mm[q]) * S);
-            As = As * tt[q] + av[q] * Ps;
-            Ps *= tt[q];
-          }
-        });
-      }
-    }
-    lds_barrier();
-  }
-  // D: q^(1) = lam, then the channel clamp
-  for (int ti = wave; ti < c.n_vn_tasks; ti += NW) {
-    const int task = uni(ld_const(c.vn_tasks, ti));
-    const int j = task >> 16, cc = (task & 0xffff) + lane;
-    const int cb = uni(ld_const(c.col_ptr, j)), dc = uni(ld_const(c.col_ptr, j + 1)) - cb;
-    if (cc < Z) {
-      const int v = j * Z + cc;
-      float acc = lds_ld<float>(lb_b + 4 * v);
-      with_degree<kDMAX>(dc, [&](auto deg) {
-        constexpr int DC = decltype(deg)::value;
-        int off[DC];
-        col_b(deg, cb, cc, off);
-#pragma unroll
-        for (int q = 0; q < DC; ++q) acc += lds_ld<float>(qb_b + off[q]);
-      });
-      const int xx = v - c.tx_lo;
-      if (xx >= 0 && xx < c.e_tx) {
-        const float L = llr_b[xx];
-        gllr[b * (int64_t)c.e_tx + xx] = fabsf(L) <= lmax ? -acc : 0.f;
-      }
-    }
+    __syncthreads();  // the next codeword clears the LDS this one still reads
   }
 }
 
@@ -553,24 +566,33 @@ hipError_t launch_wbp_backward(const DevCode& c, int T, const float* w, const fl
   if (e == hipSuccess) e = ensure_dyn_lds(k, lds);
   if (e != hipSuccess) return e;
   float* part = reinterpret_cast<float*>(work);
+  // one workgroup per resident slot, each summing its codewords' weight
+  // gradients into one partial; the partials are then added in a fixed order
+  int dev = 0, ncu = 0, occ = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, kBwdNT, lds);
+  if (e != hipSuccess) return e;
+  const int64_t slots = (int64_t)(ncu > 0 ? ncu : 1) * (occ > 0 ? occ : 1);
+  const int64_t G = B < slots ? B : slots;
   // the clamp threshold on D: ln((2 - D) / D) <= L  <=>  D >= 2 / (1 + e^L)
   const float dth = (float)(2.0 / (1.0 + std::exp((double)llr_max)));
   if (c.Z == 128)
-    wbp_backward_kernel<kBwdNT, 128><<<(unsigned)B, kBwdNT, lds, s>>>(
+    wbp_backward_kernel<kBwdNT, 128><<<(unsigned)G, kBwdNT, lds, s>>>(
         c, T, w, llr, ckpt, llr_max, dth, gpost, gllr, part, B);
   else
-    wbp_backward_kernel<kBwdNT, 0><<<(unsigned)B, kBwdNT, lds, s>>>(
+    wbp_backward_kernel<kBwdNT, 0><<<(unsigned)G, kBwdNT, lds, s>>>(
         c, T, w, llr, ckpt, llr_max, dth, gpost, gllr, part, B);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n = (int64_t)T * c.E;
-  float* slices = part + (size_t)B * n;
+  float* slices = part + (size_t)G * n;
   if ((n & 3) == 0) {
     dim3 grid((unsigned)((n / 4 + 255) / 256), kSlices);
-    sum_slices4_kernel<<<grid, 256, 0, s>>>(part, B, n, slices);
+    sum_slices4_kernel<<<grid, 256, 0, s>>>(part, G, n, slices);
   } else {
     dim3 grid((unsigned)((n + 255) / 256), kSlices);
-    sum_slices_kernel<<<grid, 256, 0, s>>>(part, B, n, slices);
+    sum_slices_kernel<<<grid, 256, 0, s>>>(part, G, n, slices);
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
