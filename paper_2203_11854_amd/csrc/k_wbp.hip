@@ -455,9 +455,9 @@ __global__ __launch_bounds__(NT) void wbp_backward_kernel(
   }
 }
 
-// gw[t][e] = sum over b of part[b][t][e], in a fixed order: pass 1 sums
-// kSlices contiguous batch slices into slice partials, pass 2 adds the
-// slices in order.  When rows are a multiple of four floats every thread
+// gw[t][e] = sum over rows b of part[b][t][e] (one row per adjoint
+// workgroup), in a fixed order: pass 1 sums kSlices contiguous runs of rows
+// into slice partials, pass 2 adds the slices in order.  When rows are a multiple of four floats every thread
 // reads four adjacent columns with 16-byte loads.
 constexpr int kSlices = 32;
 
