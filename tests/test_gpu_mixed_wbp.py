@@ -286,23 +286,25 @@ def _elementwise(got, ref, what, tol=1e-3):
     return float(ratio[i])
 
 
-@pytest.mark.parametrize("Tn", [10, 20])
-def test_wbp_adjoint_at_the_training_launch(Tn):
+@pytest.mark.parametrize("Tn,B", [(10, 2048), (20, 2048), (10, 293)])
+def test_wbp_adjoint_at_the_training_launch(Tn, B):
     """The adjoint at the training step's launch (BG2 code, B = 2048, T = 10,
-    and T = 20 as the bench also times): the loss gradient is nonzero only on
-    a few sampled codewords, so dL/dw equals the oracle's float64 autograd
-    over those codewords alone.  dL/dL_ch of the sampled rows and dL/dw are
-    compared element by element; every other row's dL/dL_ch must be exactly
-    zero.  Sampled rows are taken only where no clamped value of the oracle's
-    forward lies within 1e-3 of the clamp threshold (there float32 and
-    float64 may take different sides)."""
+    and T = 20 as the bench also times; and a batch of 293, where the
+    workgroups take unequal numbers of codewords): the loss gradient is
+    nonzero only on a few sampled codewords, so dL/dw equals the oracle's
+    float64 autograd over those codewords alone.  dL/dL_ch of the sampled
+    rows and dL/dw are compared element by element; every other row's
+    dL/dL_ch must be exactly zero.  Sampled rows are taken only where no
+    clamped value of the oracle's forward lies within 1e-3 of the clamp
+    threshold (there float32 and float64 may take different sides)."""
     qb = BG2.load()
     g = qc.graph_from_qcbase(qb, 3840)
     code = lsim.Code.from_qcbase(qb, 3840)
-    B, m = 2048, 4
-    rows = np.array([5, 700, 1401, 2046, 333, 1999])
+    m = 4
+    rows = (np.array([5, 700, 1401, 2046, 333, 1999]) if B == 2048
+            else np.array([5, 270, 141, 292, 33, 199]))
     ebn0 = np.array([1.0, 1.6, 2.2, 2.8, 3.4, 4.0])
-    seed = 0x2203118500000590 + Tn
+    seed = 0x2203118500000590 + Tn + (0 if B == 2048 else 0x40)
     w = rand.uniform(seed + 1, (Tn, g.E), 0.7, 1.3).astype(np.float32)
     pool = [pipeline.transmit(g, qb.family, seed, int(b), 1,
                               np.array([pipeline.n0_for(g, e, m)]), m, "maxlog")
