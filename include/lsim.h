@@ -440,7 +440,10 @@ lsim_status lsim_wbp_forward(const lsim_code* code, int T, const float* d_w, con
  * (overwritten; reduced over the batch in an order fixed for a given GPU:
  * each of the workgroups the GPU holds at once adds its codewords in index
  * order, then their partial sums are added in workgroup order, so repeated
- * calls give identical bits).  d_work needs lsim_wbp_workspace() bytes.
+ * calls give identical bits).  d_work needs lsim_wbp_workspace() bytes:
+ * (min(B, resident workgroups) + 32) * T * E floats, asked of the device
+ * current at the query (run the call on that device); where the device
+ * cannot be asked, the query returns the upper bound (B + 32) * T * E floats.
  */
 lsim_status lsim_wbp_workspace(const lsim_code* code, int T, int64_t B, size_t* bytes);
 lsim_status lsim_wbp_backward(const lsim_code* code, int T, const float* d_w, const float* d_llr,

@@ -512,11 +512,38 @@ size_t bwd_lds(const DevCode& c) {
 constexpr int kFwdNT = 512;
 constexpr int kBwdNT = 1024;
 
+const void* bwd_kernel(const DevCode& c) {
+  return c.Z == 128 ? (const void*)wbp_backward_kernel<kBwdNT, 128>
+                    : (const void*)wbp_backward_kernel<kBwdNT, 0>;
+}
+
+// Adjoint workgroups resident at once on the current device: the launch's
+// grid and the number of weight-gradient partials it writes.
+hipError_t bwd_slots(const DevCode& c, int64_t* slots) {
+  const void* k = bwd_kernel(c);
+  const size_t lds = bwd_lds(c);
+  int dev = 0, ncu = 0, occ = 0;
+  hipError_t e = ensure_dyn_lds(k, lds);
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, kBwdNT, lds);
+  if (e != hipSuccess) return e;
+  *slots = (int64_t)(ncu > 0 ? ncu : 1) * (occ > 0 ? occ : 1);
+  return hipSuccess;
+}
 
 }  // namespace
 
+// min(B, resident workgroups) partial rows plus the slice sums; where the
+// device cannot be asked, one row per codeword (an upper bound)
 size_t wbp_work_bytes(const DevCode& c, int T, int64_t B) {
-  return ((size_t)B + kSlices) * T * c.E * 4;
+  int64_t slots = B;
+  if (bwd_lds(c) > 160 * 1024 || bwd_slots(c, &slots) != hipSuccess) {
+    (void)hipGetLastError();
+    slots = B;
+  }
+  const int64_t G = B < slots ? B : slots;
+  return ((size_t)G + kSlices) * T * c.E * 4;
 }
 
 hipError_t launch_wbp_forward(const DevCode& c, int T, const float* w, const float* llr,
@@ -560,20 +587,17 @@ hipError_t launch_wbp_backward(const DevCode& c, int T, const float* w, const fl
     *why = "weighted BP adjoint state exceeds the 160 KiB LDS";
     return hipSuccess;
   }
-  const void* k = c.Z == 128 ? (const void*)wbp_backward_kernel<kBwdNT, 128>
-                             : (const void*)wbp_backward_kernel<kBwdNT, 0>;
+  const void* k = bwd_kernel(c);
   hipError_t e = require_lds_at_zero(k);
   if (e == hipSuccess) e = ensure_dyn_lds(k, lds);
   if (e != hipSuccess) return e;
   float* part = reinterpret_cast<float*>(work);
   // one workgroup per resident slot, each summing its codewords' weight
   // gradients into one partial; the partials are then added in a fixed order
-  int dev = 0, ncu = 0, occ = 0;
-  e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k, kBwdNT, lds);
+  // (the workspace was sized by wbp_work_bytes from the same query)
+  int64_t slots = 0;
+  e = bwd_slots(c, &slots);
   if (e != hipSuccess) return e;
-  const int64_t slots = (int64_t)(ncu > 0 ? ncu : 1) * (occ > 0 ? occ : 1);
   const int64_t G = B < slots ? B : slots;
   // the clamp threshold on D: ln((2 - D) / D) <= L  <=>  D >= 2 / (1 + e^L)
   const float dth = (float)(2.0 / (1.0 + std::exp((double)llr_max)));

@@ -335,6 +335,12 @@ def test_wbp_adjoint_at_the_training_launch(Tn, B):
     gpost = (gpost * mask).contiguous()
     gllr, gw = lsim.wbp_backward(code, tw, tl, ck, gpost, Tn)
     gllr, gw = gllr.cpu().numpy(), gw.cpu().numpy()
+    # the workspace holds one partial row per resident adjoint workgroup
+    # (at most B) and 32 slice rows
+    parts = lsim.wbp_workspace(code, Tn, B) // (Tn * g.E * 4) - 32
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    print("weight-gradient partial rows", parts)
+    assert 1 <= parts <= B and (parts == B or parts % ncu == 0)
     other = np.ones(B, dtype=bool)
     other[rows] = False
     assert not np.any(gllr[other]), "rows with zero output gradient got a nonzero dL/dL_ch"
