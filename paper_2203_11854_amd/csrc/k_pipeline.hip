@@ -376,14 +376,15 @@ __global__ void quantize_kernel(const float* __restrict__ L, int64_t n, float sc
 
 // ------------------------------------------------------------ error count
 
-// One wavefront per codeword, four codewords per wavefront and sixteen per
-// workgroup.  Bits are bytes holding 0/1, so the population count of the
-// XOR of two words counts 4 bit errors at a time (16-byte loads when both
-// rows are 16-byte aligned, 4-byte when 4-byte aligned, else bytes).  Up to
+// One wavefront per codeword, four codewords per workgroup (a launch of
+// 1024 codewords fills every CU).  Bits are bytes holding 0/1, so the
+// population count of the XOR of two words counts 4 bit errors at a time
+// (16-byte loads when both rows are 16-byte aligned, 4-byte when 4-byte
+// aligned, else bytes).  Up to
 // kLdsBins bins are summed in LDS and added to the device counters once per
 // workgroup; with more bins each codeword adds its own counts.
 constexpr int kCountThreads = 256;
-constexpr int kCwPerWave = 4;
+constexpr int kCwPerWave = 1;
 constexpr int kCwPerBlock = kCountThreads / 64 * kCwPerWave;
 constexpr int kLdsBins = 64;
 
