@@ -90,8 +90,10 @@ __device__ __forceinline__ void cn_forward(const float* ck, uint32_t in_b, int z
 // Forward.  Same schedule and arithmetic as the flooding sum-product
 // decoder (sum / difference check update, messages in log2 units inside
 // the kernel, LDS addressed by byte offset from 0); the weights multiply
-// the check outputs and the checkpoints are stored in natural units.  ZC:
-// compile-time lift size or 0.
+// the check outputs and the checkpoints are stored in natural units, each
+// check writing its inputs as it reads them (coalesced over the lift
+// index; no separate copy pass or barrier).  ZC: compile-time lift size or
+// 0.
 template <int NT, int ZC>
 __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
                                                          const float* __restrict__ w,
@@ -100,7 +102,7 @@ __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
                                                          float* __restrict__ lpost, int64_t B) {
   constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
-  float* msg = reinterpret_cast<float*>(smem);
+  (void)smem;
   const int lam_b = (int)align16((size_t)c.E * 4);
   const int tid = threadIdx.x, lane = tid & 63, wave = uni(tid >> 6);
   const int Z = ZC ? ZC : c.Z;
@@ -109,7 +111,8 @@ __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
   const float lmax2 = lmax * kLog2e;
   const int64_t b = blockIdx.x;
   const float* llr_b = llr + b * (int64_t)c.e_tx;
-  for (int v = tid; v < c.n_dec; v += NT) lds_st<float>(lam_b + 4 * v, chan_lam(c, llr_b, v, lmax) * kLog2e);
+  for (int v = tid; v < c.n_dec; v += NT)
+    lds_st<float>(lam_b + 4 * v, chan_lam(c, llr_b, v, lmax) * kLog2e);
   __syncthreads();
 
   // byte offsets of the DC edges of variable node (j, cc)
@@ -152,23 +155,8 @@ __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
   __syncthreads();
   for (int it = 0; it < T; ++it) {
     const bool last = it + 1 == T;
-    if (ckpt) {
-      float* ck = ckpt + ((int64_t)it * B + b) * c.E;
-      if ((c.E & 3) == 0) {
-        const float4* m4 = reinterpret_cast<const float4*>(msg);
-        for (int e = tid; e < c.E / 4; e += NT) {
-          float4 x = m4[e];
-          x.x *= kLn2;
-          x.y *= kLn2;
-          x.z *= kLn2;
-          x.w *= kLn2;
-          reinterpret_cast<float4*>(ck)[e] = x;
-        }
-      } else {
-        for (int e = tid; e < c.E; e += NT) ck[e] = msg[e] * kLn2;
-      }
-      lds_barrier();  // every wavefront has read q before the checks overwrite it
-    }
+    // the round's checkpoint: each check writes its inputs as it reads them
+    float* ck = ckpt ? ckpt + ((int64_t)it * B + b) * c.E : nullptr;
     for (int ti = wave; ti < c.n_cn_tasks; ti += NW) {
       const int task = uni(ld_const(c.cn_tasks, ti));
       const int i = task >> 16, r = (task & 0xffff) + lane;
@@ -177,10 +165,15 @@ __global__ __launch_bounds__(NT) void wbp_forward_kernel(DevCode c, int T,
         const int row_b = (e0 * Z + r) * 4;
         with_degree<kDMAX>(d, [&](auto deg) {
           constexpr int D = decltype(deg)::value;
-          if constexpr (D >= 2) {  // decoded checks have degree >= 2
-            float x[D], ee[D], pS[D], pA[D];
+          float x[D];
 #pragma unroll
-            for (int q = 0; q < D; ++q) x[q] = lds_ld<float>(row_b + q * Z * 4);
+          for (int q = 0; q < D; ++q) x[q] = lds_ld<float>(row_b + q * Z * 4);
+          if (ck) {
+#pragma unroll
+            for (int q = 0; q < D; ++q) stg_at(ck, (uint32_t)(row_b + q * Z * 4), x[q] * kLn2);
+          }
+          if constexpr (D >= 2) {  // decoded checks have degree >= 2
+            float ee[D], pS[D], pA[D];
             uint32_t sx = 0;
 #pragma unroll
             for (int q = 0; q < D; ++q) sx ^= __float_as_uint(x[q]);
