@@ -251,6 +251,24 @@ def test_wbp_forward_vs_oracle():
     assert ok, worst
 
 
+def test_wbp_checkpoints_are_the_oracles_messages():
+    """Each round's checkpoint is the variable-to-check messages entering
+    that round (q^(1) = lam, then q^(t+1) after the weighted round t), in
+    canonical edge order and natural units, against the oracle's float64
+    iteration with the same weights."""
+    qb, g, L32, w, c = wbp_case()
+    code = lsim.Code.from_qcbase(qb, 3840)
+    _, ck = lsim.wbp_forward(code, T(w).to(dev), T(L32).to(dev), 3)
+    ck = ck.cpu().numpy()
+    lam = np.clip(D.channel_lam(g, L32.astype(np.float64)), -D.LLR_MAX, D.LLR_MAX)
+    q = lam[:, g.edge_vn()]
+    for t in range(3):
+        ok, worst = rel_close(ck[t], q, 1e-4)
+        print(f"checkpoint {t}: worst {worst:.2e}")
+        assert ok, (t, worst)
+        _, _, q = D.spa_iteration(g, lam, q, D.LLR_MAX, w=w[t].astype(np.float64))
+
+
 def test_wbp_gradient_vs_autograd():
     qb, g, L32, w, c = wbp_case()
     code = lsim.Code.from_qcbase(qb, 3840)
